@@ -1,0 +1,169 @@
+"""CPU oracle for the push-relabel additive epsilon-approximation of the
+assignment problem (Lahn, Raghvendra, Zhang, arXiv:2203.03732).
+
+TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark import this package. It shares no code with the GPU
+library: the C file next to this one is compiled by gcc into its own shared
+object and reached through ctypes.
+
+Conventions (Section 2.1): rows of every matrix are supply vertices B,
+columns are demand vertices A; rounded costs k and dual weights are integer
+numbers of epsilon steps.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ORIGIN = {"diag": 0, "zero": 1}
+STATUS = {0: "ok", 1: "partial", -1: "arg", -2: "range", -3: "eps", -7: "nomem"}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction)."""
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "phases", "sum_free", "rounds", "max_rounds", "scanned",
+        "matched_in_phases", "completed_pairs", "sum_k")]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    p, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.orc_round_cost.argtypes = [p, i64, i64, i64, f64, p, i64]
+    lib.orc_round_points_f32.argtypes = [p, p, i64, i64, i32, f64, p, i64, p]
+    lib.orc_points_cost_f64.argtypes = [p, p, i64, i64, i32, f64, p, p, p]
+    lib.orc_solve_rounded.argtypes = [p, i64, i64, i64, i32, i64, i32, i32,
+                                      p, p, p, p, p, p, i64]
+    for fn in (lib.orc_round_cost, lib.orc_round_points_f32,
+               lib.orc_points_cost_f64, lib.orc_solve_rounded):
+        fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise OracleError(f"{what}: {STATUS.get(rc, rc)}")
+    return rc
+
+
+def threshold(eps: float, n: int) -> int:
+    """Integer form of the stop test |B'| <= eps*n (Section 2.2)."""
+    return int(math.floor(eps * n + 1e-9))
+
+
+def round_cost(C: np.ndarray, eps: float) -> np.ndarray:
+    """eq. (1) on a float32 cost matrix scaled to [0, 1]."""
+    C = np.ascontiguousarray(C, dtype=np.float32)
+    nb, na = C.shape
+    k = np.empty((nb, na), dtype=np.int16)
+    _check(_load().orc_round_cost(_ptr(C), nb, na, na, float(eps), _ptr(k), na),
+           "round_cost")
+    return k
+
+
+def round_points_f32(X: np.ndarray, Y: np.ndarray, eps: float):
+    """Squared Euclidean cost in binary32 (fma accumulation in coordinate
+    order), normalised by its maximum and rounded by eq. (1) in binary64.
+    Returns (k, m)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    nb, d = X.shape
+    na, d2 = Y.shape
+    assert d == d2
+    k = np.empty((nb, na), dtype=np.int16)
+    m = np.zeros(1, dtype=np.float32)
+    _check(_load().orc_round_points_f32(_ptr(X), _ptr(Y), nb, na, d, float(eps),
+                                        _ptr(k), na, _ptr(m)), "round_points_f32")
+    return k, float(m[0])
+
+
+def points_cost_f64(X: np.ndarray, Y: np.ndarray, eps: float | None = None,
+                    want_c: bool = True):
+    """Binary64 reference: c64 = d2 / max d2 and k64 = floor(c64 / eps).
+    Returns (c64 or None, k64 or None, m64)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    nb, d = X.shape
+    na = Y.shape[0]
+    c = np.empty((nb, na), dtype=np.float64) if want_c else None
+    k = np.empty((nb, na), dtype=np.int16) if eps is not None else None
+    m = np.zeros(1, dtype=np.float64)
+    _check(_load().orc_points_cost_f64(
+        _ptr(X), _ptr(Y), nb, na, d, float(eps if eps is not None else 0.5),
+        _ptr(c) if c is not None else None, _ptr(k) if k is not None else None,
+        _ptr(m)), "points_cost_f64")
+    return c, k, float(m[0])
+
+
+def solve_rounded(k: np.ndarray, T: int, origin: str = "diag",
+                  max_phases: int = 0, state: dict | None = None,
+                  complete: bool = True, trace: bool = False,
+                  trace_cap: int = 1 << 20) -> dict:
+    """Run the phase loop of Section 2.2 on rounded costs k (rows B).
+
+    state, if given, is a dict with int32 arrays mate_a, mate_b, y_a, y_b to
+    resume from (copied, not modified). Returns a dict with the final arrays,
+    the status ('ok' or 'partial'), the stats and, if asked, the per-phase
+    trace as an (phases, 4) array of (|B'|, rounds, scanned, |M'|)."""
+    k = np.ascontiguousarray(k, dtype=np.int16)
+    n = k.shape[0]
+    assert k.shape == (n, n)
+    if state is None:
+        mate_a = np.full(n, -1, np.int32)
+        mate_b = np.full(n, -1, np.int32)
+        y_a = np.zeros(n, np.int32)
+        y_b = np.ones(n, np.int32)
+        warm = 0
+    else:
+        mate_a = np.array(state["mate_a"], dtype=np.int32, copy=True)
+        mate_b = np.array(state["mate_b"], dtype=np.int32, copy=True)
+        y_a = np.array(state["y_a"], dtype=np.int32, copy=True)
+        y_b = np.array(state["y_b"], dtype=np.int32, copy=True)
+        warm = 1
+    st = _Stats()
+    tr = np.zeros((trace_cap, 4), np.int64) if trace else None
+    rc = _check(_load().orc_solve_rounded(
+        _ptr(k), n, n, int(T), ORIGIN[origin], int(max_phases), warm,
+        1 if complete else 0, _ptr(mate_a), _ptr(mate_b), _ptr(y_a), _ptr(y_b),
+        ctypes.byref(st), _ptr(tr) if tr is not None else None,
+        trace_cap if tr is not None else 0), "solve_rounded")
+    stats = {name: int(getattr(st, name)) for name, _ in _Stats._fields_}
+    out = dict(mate_a=mate_a, mate_b=mate_b, y_a=y_a, y_b=y_b,
+               status=STATUS[rc], stats=stats)
+    if tr is not None:
+        out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
+    return out

@@ -1,0 +1,312 @@
+/*
+ * CPU oracle for the push-relabel additive epsilon-approximation of the
+ * assignment problem (arXiv:2203.03732). TEST INFRASTRUCTURE: see oracle.h.
+ *
+ * Plain single-threaded C, written from the paper's description of the
+ * algorithm (Section 2.2) and its sequential realisation (proof of
+ * Lemma 3.4). Nothing here is tuned; every step is done in the order the
+ * paper states it. Where the paper leaves a choice open, the reading used
+ * is stated at the point where the choice is made.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Section 2.1, eq. (1): cbar(a, b) = eps * floor(c(a, b) / eps).       */
+/* Costs are assumed scaled so that the largest one is 1 (Section 1), */
+/* so a cost outside [0, 1] (or NaN) is rejected.                     */
+/* ------------------------------------------------------------------ */
+
+static int eps_ok(double eps)
+{
+    if (!(eps > 0.0 && eps < 1.0)) return 0;
+    /* the largest rounded cost plus the two dual steps must fit int16 */
+    if (floor(1.0 / eps) + 2.0 > 32767.0) return 0;
+    return 1;
+}
+
+int orc_round_cost(const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                   double eps, int16_t *k, int64_t ldk)
+{
+    if (!C || !k || n_b < 0 || n_a < 0 || ldc < n_a || ldk < n_a)
+        return ORC_E_ARG;
+    if (!eps_ok(eps)) return ORC_E_EPS;
+    for (int64_t b = 0; b < n_b; ++b) {
+        for (int64_t a = 0; a < n_a; ++a) {
+            double c = (double)C[b * ldc + a];
+            if (!(c >= 0.0 && c <= 1.0)) return ORC_E_RANGE;
+            k[b * ldk + a] = (int16_t)floor(c / eps);
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_round_points_f32(const float *X, const float *Y, int64_t n_b,
+                         int64_t n_a, int32_t d, double eps, int16_t *k,
+                         int64_t ldk, float *m_out)
+{
+    if (!X || !Y || !k || n_b < 0 || n_a < 0 || d <= 0 || ldk < n_a)
+        return ORC_E_ARG;
+    if (!eps_ok(eps)) return ORC_E_EPS;
+    float *d2 = (float *)malloc(sizeof(float) * (size_t)(n_b * n_a + 1));
+    if (!d2) return ORC_E_NOMEM;
+    float m = 0.0f;
+    for (int64_t b = 0; b < n_b; ++b) {
+        for (int64_t a = 0; a < n_a; ++a) {
+            float s = 0.0f;
+            for (int32_t j = 0; j < d; ++j) {
+                float t = X[b * d + j] - Y[a * d + j];
+                s = fmaf(t, t, s);
+            }
+            d2[b * n_a + a] = s;
+            if (s > m) m = s;
+        }
+    }
+    for (int64_t b = 0; b < n_b; ++b) {
+        for (int64_t a = 0; a < n_a; ++a) {
+            if (m == 0.0f) {
+                k[b * ldk + a] = 0;
+            } else {
+                double c = (double)d2[b * n_a + a] / (double)m;
+                k[b * ldk + a] = (int16_t)floor(c / eps);
+            }
+        }
+    }
+    if (m_out) *m_out = m;
+    free(d2);
+    return ORC_OK;
+}
+
+int orc_points_cost_f64(const float *X, const float *Y, int64_t n_b,
+                        int64_t n_a, int32_t d, double eps, double *c64,
+                        int16_t *k64, double *m_out)
+{
+    if (!X || !Y || n_b < 0 || n_a < 0 || d <= 0) return ORC_E_ARG;
+    if (k64 && !eps_ok(eps)) return ORC_E_EPS;
+    double *d2 = (double *)malloc(sizeof(double) * (size_t)(n_b * n_a + 1));
+    if (!d2) return ORC_E_NOMEM;
+    double m = 0.0;
+    for (int64_t b = 0; b < n_b; ++b) {
+        for (int64_t a = 0; a < n_a; ++a) {
+            double s = 0.0;
+            for (int32_t j = 0; j < d; ++j) {
+                double t = (double)X[b * d + j] - (double)Y[a * d + j];
+                s += t * t;
+            }
+            d2[b * n_a + a] = s;
+            if (s > m) m = s;
+        }
+    }
+    for (int64_t i = 0; i < n_b * n_a; ++i) {
+        double c = (m == 0.0) ? 0.0 : d2[i] / m;
+        if (c64) c64[i] = c;
+        if (k64) k64[i] = (int16_t)floor(c / eps);
+    }
+    if (m_out) *m_out = m;
+    free(d2);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 2.2: the phase loop.                                        */
+/* ------------------------------------------------------------------ */
+
+/* Column visited at step j of the scan of row b. The paper lets a free b
+ * take "the first" admissible edge (proof of Lemma 3.4) without fixing an
+ * order. Reading used here: DIAG starts row b at column b and wraps around,
+ * ZERO starts every row at column 0. */
+static int64_t scan_col(int32_t origin_mode, int64_t b, int64_t j, int64_t n)
+{
+    if (origin_mode == ORC_ORIGIN_ZERO) return j;
+    int64_t a = b + j;
+    return a >= n ? a - n : a;
+}
+
+/* An edge (a, b) outside M is admissible when its slack is zero. With the
+ * duals and costs in units of eps, the reading that makes the proof of (I2)
+ * go through (a new M' edge must end with y(a) + y(b) = cbar after y(a)
+ * drops by one step) is y(a) + y(b) = cbar(a, b) + eps. */
+static int admissible(const int16_t *k, int64_t ldk, const int32_t *y_a,
+                      const int32_t *y_b, int64_t a, int64_t b)
+{
+    return (int64_t)k[b * ldk + a] + 1 == (int64_t)y_a[a] + (int64_t)y_b[b];
+}
+
+int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
+                      int32_t origin_mode, int64_t max_phases, int32_t warm,
+                      int32_t complete, int32_t *mate_a, int32_t *mate_b,
+                      int32_t *y_a, int32_t *y_b, orc_stats *st,
+                      int64_t *trace, int64_t trace_cap)
+{
+    if (n < 0 || (n > 0 && (!k || ldk < n)) || !mate_a || !mate_b || !y_a ||
+        !y_b || !st)
+        return ORC_E_ARG;
+    if (origin_mode != ORC_ORIGIN_DIAG && origin_mode != ORC_ORIGIN_ZERO)
+        return ORC_E_ARG;
+    memset(st, 0, sizeof(*st));
+
+    /* Initialisation: y(b) = eps, y(a) = 0, M empty. */
+    if (!warm) {
+        for (int64_t v = 0; v < n; ++v) {
+            y_b[v] = 1;
+            y_a[v] = 0;
+            mate_a[v] = -1;
+            mate_b[v] = -1;
+        }
+    }
+
+    size_t sz = (size_t)(n > 0 ? n : 1);
+    int64_t *B_prime = (int64_t *)malloc(sizeof(int64_t) * sz);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * sz);
+    int64_t *target = (int64_t *)malloc(sizeof(int64_t) * sz);
+    char *active = (char *)malloc(sz);
+    char *won = (char *)malloc(sz);
+    int64_t *taken_by = (int64_t *)malloc(sizeof(int64_t) * sz);
+    int64_t *proposer = (int64_t *)malloc(sizeof(int64_t) * sz);
+    if (!B_prime || !pos || !target || !active || !won || !taken_by ||
+        !proposer) {
+        free(B_prime); free(pos); free(target); free(active); free(won);
+        free(taken_by); free(proposer);
+        return ORC_E_NOMEM;
+    }
+
+    int status = ORC_OK;
+    for (;;) {
+        /* B' = the free vertices of B, in ascending order. */
+        int64_t n_i = 0;
+        for (int64_t b = 0; b < n; ++b)
+            if (mate_b[b] < 0) B_prime[n_i++] = b;
+
+        /* Stop once |B'| <= eps n (integer threshold T). */
+        if (n_i <= T) break;
+        if (max_phases > 0 && st->phases == max_phases) {
+            status = ORC_PARTIAL;
+            break;
+        }
+        st->phases += 1;
+        st->sum_free += n_i;
+        int64_t phase_scanned = 0, phase_rounds = 0, phase_matched = 0;
+
+        /* Step (I): a maximal matching M' on the admissible edges incident
+         * on B'. The paper allows any maximal matching. Reading used here:
+         * synchronous proposal rounds. In each round every b of B' that is
+         * still looking proposes to the first column in its scan order that
+         * is admissible and was not taken before the round began; every
+         * column proposed to goes to its lowest-index proposer; losers go on
+         * scanning after the column they lost. A b that finds nothing stays
+         * free in M'. */
+        for (int64_t a = 0; a < n; ++a) taken_by[a] = -1;
+        for (int64_t i = 0; i < n_i; ++i) {
+            pos[i] = 0;
+            active[i] = 1;
+            won[i] = 0;
+        }
+        for (;;) {
+            int64_t proposals = 0;
+            /* (i) propose, against the taken set of the start of the round */
+            for (int64_t i = 0; i < n_i; ++i) {
+                if (!active[i]) continue;
+                int64_t b = B_prime[i];
+                target[i] = -1;
+                int64_t j;
+                for (j = pos[i]; j < n; ++j) {
+                    int64_t a = scan_col(origin_mode, b, j, n);
+                    if (taken_by[a] < 0 && admissible(k, ldk, y_a, y_b, a, b)) {
+                        target[i] = a;
+                        break;
+                    }
+                }
+                if (target[i] < 0) {
+                    phase_scanned += n - pos[i];
+                    active[i] = 0; /* no admissible free column is left */
+                } else {
+                    phase_scanned += j - pos[i] + 1;
+                    pos[i] = j;
+                    proposals += 1;
+                }
+            }
+            if (proposals == 0) break;
+            /* (ii) each proposed-to column goes to its lowest-index proposer */
+            for (int64_t i = 0; i < n_i; ++i)
+                if (active[i]) proposer[target[i]] = -1;
+            for (int64_t i = 0; i < n_i; ++i) {
+                if (!active[i]) continue;
+                int64_t a = target[i], b = B_prime[i];
+                if (proposer[a] < 0 || b < proposer[a]) proposer[a] = b;
+            }
+            /* (iii) winners take their column; losers resume one further */
+            for (int64_t i = 0; i < n_i; ++i) {
+                if (!active[i]) continue;
+                int64_t a = target[i];
+                if (proposer[a] == B_prime[i]) {
+                    taken_by[a] = B_prime[i];
+                    won[i] = 1;
+                    active[i] = 0;
+                    phase_matched += 1;
+                } else {
+                    pos[i] += 1;
+                }
+            }
+            phase_rounds += 1;
+        }
+
+        /* Step (II): add M' to M and delete the M-edges of the columns that
+         * M' re-matches (the set A'' and its edges M''). */
+        for (int64_t a = 0; a < n; ++a) {
+            int64_t b = taken_by[a];
+            if (b < 0) continue;
+            if (mate_a[a] >= 0) mate_b[mate_a[a]] = -1;
+            mate_a[a] = (int32_t)b;
+            mate_b[b] = (int32_t)a;
+        }
+        /* Step (III a): y(a) -= eps for every edge (a, b) of M'. */
+        for (int64_t a = 0; a < n; ++a)
+            if (taken_by[a] >= 0) y_a[a] -= 1;
+        /* Step (III b): y(b) += eps for every b of B' left free by M'. */
+        for (int64_t i = 0; i < n_i; ++i)
+            if (!won[i]) y_b[B_prime[i]] += 1;
+
+        st->rounds += phase_rounds;
+        if (phase_rounds > st->max_rounds) st->max_rounds = phase_rounds;
+        st->scanned += phase_scanned;
+        if (trace && st->phases <= trace_cap) {
+            int64_t *t = trace + 4 * (st->phases - 1);
+            t[0] = n_i;
+            t[1] = phase_rounds;
+            t[2] = phase_scanned;
+            t[3] = phase_matched;
+        }
+    }
+
+    int64_t matched = 0;
+    for (int64_t b = 0; b < n; ++b)
+        if (mate_b[b] >= 0) matched += 1;
+    st->matched_in_phases = matched;
+
+    /* Completion (Section 2.1): match the remaining free vertices
+     * arbitrarily. Reading used here: the i-th free b (ascending) takes the
+     * i-th free a (ascending). */
+    if (complete && status == ORC_OK) {
+        int64_t ia = 0;
+        for (int64_t b = 0; b < n; ++b) {
+            if (mate_b[b] >= 0) continue;
+            while (ia < n && mate_a[ia] >= 0) ++ia;
+            if (ia >= n) break;
+            mate_b[b] = (int32_t)ia;
+            mate_a[ia] = (int32_t)b;
+            st->completed_pairs += 1;
+        }
+    }
+
+    int64_t sum_k = 0;
+    for (int64_t b = 0; b < n; ++b)
+        if (mate_b[b] >= 0) sum_k += k[b * ldk + mate_b[b]];
+    st->sum_k = sum_k;
+
+    free(B_prime); free(pos); free(target); free(active); free(won);
+    free(taken_by); free(proposer);
+    return status;
+}

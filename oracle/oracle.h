@@ -1,0 +1,86 @@
+/*
+ * CPU oracle for the push-relabel additive epsilon-approximation of the
+ * assignment problem (Lahn, Raghvendra and Zhang, "A Push-Relabel Based
+ * Additive Approximation for Optimal Transport", arXiv:2203.03732).
+ *
+ * TEST INFRASTRUCTURE. This library exists only to check the GPU library
+ * against a plain, slow, single-threaded reading of the paper. Only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark load
+ * it. It shares no code, header, table or helper with the GPU library.
+ *
+ * Units: every dual weight is an integer number of epsilon steps, and every
+ * rounded cost k is the integer with cbar = eps * k (Section 2.1, eq. (1)).
+ * Matrices are row-major with rows = supply vertices B and columns = demand
+ * vertices A; k[b*ldk + a] is the rounded cost of edge (a, b).
+ */
+#ifndef PROT_ORACLE_H
+#define PROT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORC_OK = 0,
+    ORC_PARTIAL = 1,      /* stopped after max_phases phases; state is valid */
+    ORC_E_ARG = -1,
+    ORC_E_RANGE = -2,     /* a cost is NaN or outside [0, 1] */
+    ORC_E_EPS = -3,       /* eps outside (0, 1) or 1/eps too large for int16 */
+    ORC_E_NOMEM = -7
+};
+
+enum { ORC_ORIGIN_DIAG = 0, ORC_ORIGIN_ZERO = 1 };
+
+typedef struct {
+    int64_t phases;           /* phases executed by this call */
+    int64_t sum_free;         /* sum over those phases of |B'| */
+    int64_t rounds;           /* proposal rounds that made at least one proposal */
+    int64_t max_rounds;       /* most such rounds in one phase */
+    int64_t scanned;          /* matrix entries examined by the greedy step */
+    int64_t matched_in_phases;/* |M| when the phase loop stopped */
+    int64_t completed_pairs;  /* pairs added by the arbitrary completion */
+    int64_t sum_k;            /* sum of k over the returned matching */
+} orc_stats;
+
+/* eq. (1): k = floor(c / eps), one binary64 division then floor. */
+int orc_round_cost(const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                   double eps, int16_t *k, int64_t ldk);
+
+/* Squared Euclidean cost in binary32, accumulated coordinate by coordinate
+ * with a fused multiply-add: s = fma(x_j - y_j, x_j - y_j, s). The maximum
+ * over all pairs is m; k = floor((d2 / m) / eps) with both divisions in
+ * binary64. If m == 0 every k is 0. Writes m to *m_out. */
+int orc_round_points_f32(const float *X, const float *Y, int64_t n_b,
+                         int64_t n_a, int32_t d, double eps, int16_t *k,
+                         int64_t ldk, float *m_out);
+
+/* Reference squared Euclidean cost in binary64 from the same binary32
+ * points: c64 = d2_64 / max d2_64 (optional output, n_b x n_a), and
+ * k64 = floor(c64 / eps) (optional). Writes the maximum to *m_out. */
+int orc_points_cost_f64(const float *X, const float *Y, int64_t n_b,
+                        int64_t n_a, int32_t d, double eps, double *c64,
+                        int16_t *k64, double *m_out);
+
+/* The integer phase loop of Section 2.2 followed by the arbitrary completion.
+ *   k, ldk      : n x n rounded costs (rows B, columns A)
+ *   T           : stop when |B'| <= T (T = floor(eps * n))
+ *   origin_mode : where the scan of row b starts (ORC_ORIGIN_*)
+ *   max_phases  : stop after this many phases (<= 0: no limit)
+ *   warm        : 0 = start from y(b) = 1, y(a) = 0, M empty; 1 = resume
+ *                 from the given mate/dual arrays
+ *   complete    : 1 = match the last free vertices arbitrarily
+ *   mate_a[a]   : b matched to a, or -1; mate_b[b]: a matched to b, or -1
+ *   y_a, y_b    : dual weights in units of eps
+ *   trace       : optional, 4 int64 per phase (|B'|, rounds, scanned, |M'|)
+ * Returns ORC_OK, ORC_PARTIAL (max_phases reached) or an error. */
+int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
+                      int32_t origin_mode, int64_t max_phases, int32_t warm,
+                      int32_t complete, int32_t *mate_a, int32_t *mate_b,
+                      int32_t *y_a, int32_t *y_b, orc_stats *st,
+                      int64_t *trace, int64_t trace_cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,56 @@
+"""Seeded synthetic inputs.
+
+This module draws the random inputs that both the GPU library and its CPU
+checker consume, so that both see identical arrays. It holds none of the
+solver's arithmetic. All draws use numpy's PCG64 generator and float32.
+
+Workloads (the shapes of the paper's experiments, Section 5):
+  uniform_costs   n x n i.i.d. uniform costs in [0, 1)
+  uniform_points  two sets of n points i.i.d. uniform in the unit cube
+                  (the paper's synthetic workload draws 2-D points)
+  gaussian_batch  independent instances of uneven n with standard normal
+                  points, as in minibatch optimal transport
+  shifted_gaussian_batch  equal-n instances, X ~ N(0, I), Y ~ N(shift, I)
+  random_k        small random integer rounded-cost matrices for tests
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def uniform_costs(n: int, seed: int = 0, n_a: int | None = None) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.random((n, n if n_a is None else n_a), dtype=np.float32)
+
+
+def uniform_points(n: int, d: int = 2, seed: int = 0, n_a: int | None = None):
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, d), dtype=np.float32)
+    Y = rng.random((n if n_a is None else n_a, d), dtype=np.float32)
+    return X, Y
+
+
+def gaussian_batch(batch: int = 512, n_lo: int = 64, n_hi: int = 1024,
+                   d: int = 16, seed: int = 0):
+    """Returns (ns, [X_i], [Y_i]) with n_i uniform in [n_lo, n_hi]."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_lo, n_hi + 1, batch)
+    Xs, Ys = [], []
+    for n in ns:
+        Xs.append(rng.standard_normal((int(n), d), dtype=np.float32))
+        Ys.append(rng.standard_normal((int(n), d), dtype=np.float32))
+    return [int(n) for n in ns], Xs, Ys
+
+
+def shifted_gaussian_batch(batch: int = 64, n: int = 2048, d: int = 64,
+                           shift: float = 0.5, seed: int = 0):
+    """Returns (X, Y) of shape (batch, n, d): X ~ N(0, I), Y ~ N(shift, I)."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((batch, n, d), dtype=np.float32)
+    Y = rng.standard_normal((batch, n, d), dtype=np.float32) + np.float32(shift)
+    return X, Y
+
+
+def random_k(n: int, kmax: int, seed: int = 0, n_a: int | None = None) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, kmax + 1, (n, n if n_a is None else n_a)).astype(np.int16)
