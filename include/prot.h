@@ -1,0 +1,165 @@
+/*
+ * prot — push-relabel additive epsilon-approximation of the assignment
+ * problem on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lahn, Raghvendra and Zhang, "A Push-Relabel Based Additive
+ * Approximation for Optimal Transport" (arXiv:2203.03732), Section 2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Supply vertices B are matrix ROWS (points X), demand vertices A are
+ *    matrix COLUMNS (points Y). n = |A| = |B| (balanced case, Section 2).
+ *  - Rounded costs are int16 units of eps: cbar(a,b) = eps * k[b][a]
+ *    (Section 2.1, eq. (1)). Dual weights are int32 units of eps
+ *    (the duals stay integer multiples of eps, Section 2.2).
+ *  - Every array argument is a DEVICE pointer owned by the caller; the
+ *    library never frees or retains it past the call. Only `prot_stats*`
+ *    arguments and the `*_host` arrays are host pointers.
+ *  - Work is enqueued on the context's HIP stream. A call that fills a
+ *    host `prot_stats` synchronises that stream before returning.
+ *  - Every function returns PROT_OK (0), PROT_PARTIAL (1) or a negative
+ *    error code. No C++ exception crosses this boundary.
+ *    prot_last_error(ctx) returns a message for the last failing call.
+ *  - A context is not thread-safe: use one per host thread / stream.
+ *  - The matrix layout is row-major with a row pitch (in elements) of
+ *    prot_pitch(n): n rounded up to a multiple of 128 (256-byte rows).
+ */
+#ifndef PROT_H
+#define PROT_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct prot_ctx prot_ctx;
+
+enum {
+    PROT_OK = 0,
+    PROT_PARTIAL = 1,          /* stopped at opts->max_phases; state valid */
+    PROT_E_ARG = -1,           /* null pointer, bad size or bad option */
+    PROT_E_RANGE = -2,         /* a cost is NaN or outside [0, 1] */
+    PROT_E_EPS = -3,           /* eps not in (0,1), or 1/eps too big for int16 */
+    PROT_E_STATE = -5,         /* warm-start state violates (I1) or is not a matching */
+    PROT_E_HIP = -6,           /* a HIP runtime call failed */
+    PROT_E_NOMEM = -7,         /* device allocation failed */
+    PROT_E_UNSUPPORTED = -8    /* size beyond this build's limits */
+};
+
+enum { PROT_EPS_ALGORITHMIC = 0, PROT_EPS_STRICT = 1 };
+enum { PROT_ORIGIN_DIAG = 0, PROT_ORIGIN_ZERO = 1 };
+
+typedef struct {
+    /* PROT_EPS_ALGORITHMIC runs with the given eps (additive error 3 eps n,
+     * Section 2.1); PROT_EPS_STRICT runs with eps/3 (error eps n). */
+    int32_t eps_mode;
+    /* Scan order of the greedy step: row b starts at column b and wraps
+     * (PROT_ORIGIN_DIAG, default) or starts at column 0 (PROT_ORIGIN_ZERO). */
+    int32_t origin_mode;
+    /* 1: skip the arbitrary completion (Section 2.1), return the phase-loop
+     * matching as is. */
+    int32_t no_completion;
+    int32_t reserved[5];
+    /* Stop after this many phases (0: run to completion); the call then
+     * returns PROT_PARTIAL and the outputs hold a valid resumable state. */
+    int64_t max_phases;
+} prot_opts;
+
+typedef struct {
+    int64_t phases;            /* phases run (Section 2.2) */
+    int64_t sum_free;          /* sum over phases of |B'| */
+    int64_t rounds;            /* proposal rounds that made a proposal */
+    int64_t max_rounds;        /* most such rounds in one phase */
+    int64_t scanned;           /* matrix entries examined by the greedy step */
+    int64_t matched_in_phases; /* |M| when the phase loop stopped */
+    int64_t completed_pairs;   /* pairs added by the completion */
+    int64_t sum_k;             /* sum of k over the returned matching */
+    int64_t threshold;         /* T: the loop stops when |B'| <= T */
+    int32_t kmax;              /* largest rounded cost */
+    int32_t status;            /* PROT_OK or PROT_PARTIAL */
+    double cost;               /* sum of c(a,b) over the matching (costs scaled to max 1) */
+    double cost_scale;         /* points: the maximum squared distance m (c = d2/m); cost input: 1 */
+    double eps_internal;       /* eps the loop ran with (eps or eps/3) */
+    double ms_build;           /* device time of the cost build (0 if none) */
+    double ms_loop_kernel;     /* device time of the persistent phase-loop kernel */
+    double ms_total;           /* device time from the first kernel to the last */
+} prot_stats;
+
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t
+ * passed as void*, NULL = the null stream). */
+int prot_ctx_create(prot_ctx **out, int device, void *hip_stream);
+int prot_ctx_destroy(prot_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+int prot_set_stream(prot_ctx *ctx, void *hip_stream);
+/* Pre-size the workspace for instances up to n_max (and, if with_matrix,
+ * an n_max x prot_pitch(n_max) int16 cost matrix) so that later calls do
+ * not allocate. */
+int prot_reserve(prot_ctx *ctx, int64_t n_max, int32_t with_matrix);
+
+/* Row pitch in elements used for int16 rounded-cost matrices. */
+int64_t prot_pitch(int64_t n);
+/* Integer stop threshold T = floor(eps * n + 1e-9) (Section 2.2:
+ * stop once |B'| <= eps n). */
+int64_t prot_threshold(double eps, int64_t n);
+/* Largest n the single-instance phase loop accepts on this device. */
+int64_t prot_max_n(prot_ctx *ctx);
+
+/* eq. (1): k[b*ldk + a] = floor(C[b*ldc + a] / eps), the division in
+ * binary64. C: n x n float32 scaled to [0, 1]. Returns PROT_E_RANGE if
+ * any cost is NaN or outside [0, 1] (k is then unspecified). ldk >= n. */
+int prot_round_costs(prot_ctx *ctx, const float *C, int64_t n, int64_t ldc,
+                     double eps, int16_t *k, int64_t ldk);
+
+/* Rounded squared-Euclidean costs from point sets (Section 1 scaling, eq. (1)):
+ * X: n x d (rows B), Y: n x d (columns A), float32 row-major.
+ * d2 = sum_j fma-accumulated (x_j - y_j)^2 in binary32 in coordinate order,
+ * m = max d2, k = floor((d2 / m) / eps) with both divisions in binary64
+ * (k = 0 everywhere if m = 0). k: n x ldk int16 (columns ldk > n are filled
+ * with 0x7FFF). m is written to *m_out (device float) if non-null. */
+int prot_build_costs(prot_ctx *ctx, const float *X, const float *Y, int64_t n,
+                     int32_t d, double eps, int16_t *k, int64_t ldk,
+                     float *m_out);
+
+/* The integer phase loop of Section 2.2 on rounded costs k (n x ldk int16,
+ * 0 <= k <= 32765), stopping once |B'| <= T, then the completion.
+ *  warm = 0: start from y(b) = 1, y(a) = 0, M empty (mate_* and y_* are
+ *            outputs only).
+ *  warm = 1: resume from the state in mate_a, mate_b, y_a, y_b (it must be
+ *            a matching satisfying (I1); PROT_E_STATE otherwise).
+ * Outputs: mate_a[a] (b or -1), mate_b[b] (a or -1), and the duals y_a, y_b
+ * BEFORE the completion (completion edges carry no eq. (3) guarantee).
+ * stats may be NULL (then the call does not synchronise). */
+int prot_solve_rounded(prot_ctx *ctx, const int16_t *k, int64_t n, int64_t ldk,
+                       int64_t T, const prot_opts *opts, int32_t warm,
+                       int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
+                       int32_t *y_b, prot_stats *stats);
+
+/* Cost-matrix input: prot_round_costs into workspace, then the phase loop
+ * with T = prot_threshold(eps_internal, n), then the completion; stats->cost
+ * is sum_b C[b][mate_b[b]] in binary64. */
+int prot_solve_cost(prot_ctx *ctx, const float *C, int64_t n, int64_t ldc,
+                    double eps, const prot_opts *opts, int32_t *mate_a,
+                    int32_t *mate_b, int32_t *y_a, int32_t *y_b,
+                    prot_stats *stats);
+
+/* Point-set input: prot_build_costs into workspace, then as above;
+ * stats->cost is sum_b d2_64(b, mate_b[b]) / m in binary64 (normalised),
+ * stats->cost_scale = m. */
+int prot_solve_points(prot_ctx *ctx, const float *X, const float *Y,
+                      int64_t n, int32_t d, double eps, const prot_opts *opts,
+                      int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
+                      int32_t *y_b, prot_stats *stats);
+
+/* Per-phase record of the last phase loop on this context: for phase i,
+ * out[4i..4i+3] = (|B'|, rounds, scanned entries, |M'|). Copies at most cap
+ * phases and returns the number of phases recorded (<= the trace capacity,
+ * 65536). Synchronises the stream. */
+int64_t prot_get_trace(prot_ctx *ctx, int64_t *out_host, int64_t cap);
+
+const char *prot_status_string(int status);
+const char *prot_last_error(prot_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

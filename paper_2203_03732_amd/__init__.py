@@ -1,1 +1,44 @@
+"""prot: push-relabel additive epsilon-approximation of the assignment problem
+(Lahn, Raghvendra, Zhang, arXiv:2203.03732) on one AMD MI355X.
 
+Python front end of libprot.so (include/prot.h). Typical use:
+
+    import torch, paper_2203_03732_amd as prot
+    res = prot.solve_points(X, Y, eps=0.01)     # X, Y: (n, d) float32 on cuda
+    res.mate_b        # column matched to each row
+    res.y_a, res.y_b  # dual weights in units of eps (before the completion)
+    res.stats         # phases, rounds, scanned entries, cost, timings
+
+The library is loaded lazily, so importing this package on a machine without a
+GPU works; any solver call then needs the built library and a GPU.
+"""
+from __future__ import annotations
+
+from ._lib import (Context, ProtError, Result, context, load, pitch,  # noqa: F401
+                   threshold, EXPORTS)
+
+
+def solve_cost(C, eps, **kw) -> Result:
+    """Cost matrix C (n x n float32, scaled to [0, 1]) -> approximate
+    minimum-cost perfect matching (additive error 3 eps n; eps n with
+    eps_mode='strict')."""
+    return context().solve_cost(C, eps, **kw)
+
+
+def solve_points(X, Y, eps, **kw) -> Result:
+    """Point sets X (rows, supply) and Y (columns, demand), n x d float32, with
+    squared Euclidean cost scaled to max 1."""
+    return context().solve_points(X, Y, eps, **kw)
+
+
+def solve_rounded(k, T, n=None, **kw) -> Result:
+    """The phase loop alone on an int16 rounded-cost matrix (n x ldk)."""
+    return context().solve_rounded(k, T, n, **kw)
+
+
+def round_costs(C, eps, k=None):
+    return context().round_costs(C, eps, k)
+
+
+def build_costs(X, Y, eps, k=None):
+    return context().build_costs(X, Y, eps, k)

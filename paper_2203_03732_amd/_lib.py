@@ -1,0 +1,297 @@
+"""ctypes binding of libprot (include/prot.h). Argument marshalling only:
+every step of the solver runs in the library's HIP kernels. PyTorch supplies
+device memory and the current stream."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libprot.so")
+
+PROT_OK, PROT_PARTIAL = 0, 1
+STATUS_NAMES = {0: "ok", 1: "partial", -1: "arg", -2: "range", -3: "eps", -5: "state",
+                -6: "hip", -7: "nomem", -8: "unsupported"}
+EPS_MODES = {"algorithmic": 0, "strict": 1}
+ORIGINS = {"diag": 0, "zero": 1}
+
+
+class ProtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"prot error {code} ({STATUS_NAMES.get(code, '?')}): {msg}")
+        self.code = code
+        self.name = STATUS_NAMES.get(code, "?")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("eps_mode", ctypes.c_int32), ("origin_mode", ctypes.c_int32),
+                ("no_completion", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+                ("max_phases", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("phases", ctypes.c_int64), ("sum_free", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("max_rounds", ctypes.c_int64),
+                ("scanned", ctypes.c_int64), ("matched_in_phases", ctypes.c_int64),
+                ("completed_pairs", ctypes.c_int64), ("sum_k", ctypes.c_int64),
+                ("threshold", ctypes.c_int64), ("kmax", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("cost", ctypes.c_double),
+                ("cost_scale", ctypes.c_double), ("eps_internal", ctypes.c_double),
+                ("ms_build", ctypes.c_double), ("ms_loop_kernel", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = [
+    "prot_ctx_create", "prot_ctx_destroy", "prot_set_stream", "prot_reserve", "prot_pitch",
+    "prot_threshold", "prot_max_n", "prot_round_costs", "prot_build_costs",
+    "prot_solve_rounded", "prot_solve_cost", "prot_solve_points", "prot_get_trace",
+    "prot_status_string", "prot_last_error",
+]
+
+
+def load():
+    """Load libprot.so (built in-tree by paper_2203_03732_amd.build). There
+    is no fallback: without the library nothing in this package can run."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2203_03732_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "prot_ctx_create": (ctypes.c_int, [ctypes.POINTER(p), ctypes.c_int, p]),
+        "prot_ctx_destroy": (ctypes.c_int, [p]),
+        "prot_set_stream": (ctypes.c_int, [p, p]),
+        "prot_reserve": (ctypes.c_int, [p, i64, i32]),
+        "prot_pitch": (i64, [i64]),
+        "prot_threshold": (i64, [f64, i64]),
+        "prot_max_n": (i64, [p]),
+        "prot_round_costs": (ctypes.c_int, [p, p, i64, i64, f64, p, i64]),
+        "prot_build_costs": (ctypes.c_int, [p, p, p, i64, i32, f64, p, i64, p]),
+        "prot_solve_rounded": (ctypes.c_int, [p, p, i64, i64, i64, ctypes.POINTER(Opts), i32,
+                                              p, p, p, p, ctypes.POINTER(Stats)]),
+        "prot_solve_cost": (ctypes.c_int, [p, p, i64, i64, f64, ctypes.POINTER(Opts),
+                                           p, p, p, p, ctypes.POINTER(Stats)]),
+        "prot_solve_points": (ctypes.c_int, [p, p, p, i64, i32, f64, ctypes.POINTER(Opts),
+                                             p, p, p, p, ctypes.POINTER(Stats)]),
+        "prot_get_trace": (i64, [p, p, i64]),
+        "prot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "prot_last_error": (ctypes.c_char_p, [p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def pitch(n: int) -> int:
+    return int(load().prot_pitch(int(n)))
+
+
+def threshold(eps: float, n: int) -> int:
+    return int(load().prot_threshold(float(eps), int(n)))
+
+
+@dataclass
+class Result:
+    mate_a: object
+    mate_b: object
+    y_a: object
+    y_b: object
+    status: str
+    stats: dict = field(default_factory=dict)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, dtype, name, ndim=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context bound to a device; enqueues on torch's current
+    stream at each call."""
+
+    def __init__(self, device: int | None = None):
+        torch = _torch()
+        lib = load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream().cuda_stream
+            rc = lib.prot_ctx_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream))
+        if rc != 0:
+            raise ProtError(rc, "prot_ctx_create failed")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.prot_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers
+    def _bind_stream(self):
+        torch = _torch()
+        self._lib.prot_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            msg = self._lib.prot_last_error(self._h).decode()
+            raise ProtError(rc, msg)
+        return rc
+
+    @staticmethod
+    def _opts(eps_mode="algorithmic", origin="diag", complete=True, max_phases=0) -> Opts:
+        o = Opts()
+        o.eps_mode = EPS_MODES[eps_mode]
+        o.origin_mode = ORIGINS[origin]
+        o.no_completion = 0 if complete else 1
+        o.max_phases = int(max_phases)
+        return o
+
+    def _outputs(self, n):
+        torch = _torch()
+        kw = dict(dtype=torch.int32, device=f"cuda:{self.device}")
+        return (torch.empty(n, **kw), torch.empty(n, **kw), torch.empty(n, **kw),
+                torch.empty(n, **kw))
+
+    # -- API
+    def reserve(self, n_max: int, with_matrix: bool = True):
+        self._check(self._lib.prot_reserve(self._h, int(n_max), 1 if with_matrix else 0))
+
+    def max_n(self) -> int:
+        return int(self._lib.prot_max_n(self._h))
+
+    def alloc_k(self, n: int):
+        torch = _torch()
+        return torch.empty((n, pitch(n)), dtype=torch.int16, device=f"cuda:{self.device}")
+
+    def round_costs(self, C, eps: float, k=None):
+        torch = _torch()
+        n = C.shape[0]
+        if C.dim() != 2 or C.shape[1] < n or C.stride(1) != 1:
+            raise ValueError("C must be an n x n (row-major) float32 matrix")
+        if k is None:
+            k = self.alloc_k(n)
+        self._bind_stream()
+        self._check(self._lib.prot_round_costs(
+            self._h, _dev_ptr(C, torch.float32, "C", 2), n, C.stride(0), float(eps),
+            _dev_ptr(k, torch.int16, "k", 2), k.stride(0)))
+        return k
+
+    def build_costs(self, X, Y, eps: float, k=None):
+        torch = _torch()
+        n, d = X.shape
+        if Y.shape != (n, d) or not X.is_contiguous() or not Y.is_contiguous():
+            raise ValueError("X and Y must be contiguous n x d float32")
+        if k is None:
+            k = self.alloc_k(n)
+        m = torch.empty(1, dtype=torch.float32, device=f"cuda:{self.device}")
+        self._bind_stream()
+        self._check(self._lib.prot_build_costs(
+            self._h, _dev_ptr(X, torch.float32, "X", 2), _dev_ptr(Y, torch.float32, "Y", 2),
+            n, d, float(eps), _dev_ptr(k, torch.int16, "k", 2), k.stride(0),
+            _dev_ptr(m, torch.float32, "m")))
+        return k, m
+
+    def solve_rounded(self, k, T: int, n: int | None = None, *, state=None, origin="diag",
+                      complete=True, max_phases=0) -> Result:
+        torch = _torch()
+        n = k.shape[0] if n is None else int(n)
+        if k.dim() != 2 or k.stride(1) != 1 or k.shape[1] < n:
+            raise ValueError("k must be a row-major n x ldk int16 matrix")
+        if state is None:
+            mate_a, mate_b, y_a, y_b = self._outputs(n)
+            warm = 0
+        else:
+            mate_a, mate_b, y_a, y_b = (state[x].clone() for x in ("mate_a", "mate_b", "y_a", "y_b"))
+            warm = 1
+        st = Stats()
+        o = self._opts(origin=origin, complete=complete, max_phases=max_phases)
+        self._bind_stream()
+        rc = self._check(self._lib.prot_solve_rounded(
+            self._h, _dev_ptr(k, torch.int16, "k", 2), n, k.stride(0), int(T), ctypes.byref(o),
+            warm, _dev_ptr(mate_a, torch.int32, "mate_a"), _dev_ptr(mate_b, torch.int32, "mate_b"),
+            _dev_ptr(y_a, torch.int32, "y_a"), _dev_ptr(y_b, torch.int32, "y_b"),
+            ctypes.byref(st)))
+        return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
+
+    def solve_cost(self, C, eps: float, *, eps_mode="algorithmic", origin="diag",
+                   complete=True, max_phases=0) -> Result:
+        torch = _torch()
+        n = C.shape[0]
+        if C.dim() != 2 or C.shape[1] < n or C.stride(1) != 1:
+            raise ValueError("C must be an n x n (row-major) float32 matrix")
+        mate_a, mate_b, y_a, y_b = self._outputs(n)
+        st = Stats()
+        o = self._opts(eps_mode, origin, complete, max_phases)
+        self._bind_stream()
+        rc = self._check(self._lib.prot_solve_cost(
+            self._h, _dev_ptr(C, torch.float32, "C", 2), n, C.stride(0), float(eps),
+            ctypes.byref(o), _dev_ptr(mate_a, torch.int32, "mate_a"),
+            _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
+            _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)))
+        return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
+
+    def solve_points(self, X, Y, eps: float, *, eps_mode="algorithmic", origin="diag",
+                     complete=True, max_phases=0) -> Result:
+        torch = _torch()
+        n, d = X.shape
+        if Y.shape != (n, d) or not X.is_contiguous() or not Y.is_contiguous():
+            raise ValueError("X and Y must be contiguous n x d float32")
+        mate_a, mate_b, y_a, y_b = self._outputs(n)
+        st = Stats()
+        o = self._opts(eps_mode, origin, complete, max_phases)
+        self._bind_stream()
+        rc = self._check(self._lib.prot_solve_points(
+            self._h, _dev_ptr(X, torch.float32, "X", 2), _dev_ptr(Y, torch.float32, "Y", 2),
+            n, d, float(eps), ctypes.byref(o), _dev_ptr(mate_a, torch.int32, "mate_a"),
+            _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
+            _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)))
+        return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
+
+    def trace(self, cap: int = 65536):
+        import numpy as np
+        buf = np.zeros((cap, 4), np.int64)
+        m = int(self._lib.prot_get_trace(self._h, buf.ctypes.data_as(ctypes.c_void_p), cap))
+        if m < 0:
+            raise ProtError(m, "prot_get_trace failed")
+        return buf[:m].copy()
+
+
+_default: dict[int, Context] = {}
+
+
+def context(device: int | None = None) -> Context:
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _default:
+        _default[dev] = Context(dev)
+    return _default[dev]

@@ -1,0 +1,537 @@
+// Host runtime and C ABI of libprot (declarations and contracts: include/prot.h).
+//
+// A context owns a stream handle, the device workspace of the phase loop
+// (per-column keys and duals, the free and taken lists, the control block and
+// the phase trace), an optional rounded-cost matrix for the cost and point
+// entry points, and a pinned host staging buffer for the statistics. Each
+// call validates its arguments, enqueues its kernels on the stream and, if
+// it returns statistics, synchronises once at the end.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/prot.h"
+#include "internal.h"
+
+using prot::Ctl;
+
+struct prot_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    int64_t cap_n = 0;               // loop workspace capacity (vertices)
+    unsigned long long *key = nullptr;
+    uint16_t *t = nullptr;
+    int32_t *lists = nullptr;        // F0, F1, L0, L1, scratch(2n)
+    Ctl *ctl = nullptr;
+    int64_t *trace = nullptr;
+    long long *part_k = nullptr;
+    double *part_c = nullptr;
+
+    int64_t cap_mat = 0;             // elements of the rounded-cost matrix
+    int16_t *kmat = nullptr;
+    int32_t cap_th = 0;
+    float *th = nullptr;
+
+    struct Stage {
+        Ctl ctl;
+        long long part_k[prot::kFinalizeBlocks];
+        double part_c[prot::kFinalizeBlocks];
+    } *stage = nullptr;              // pinned host memory
+
+    int grid_npad = -1;
+    int grid_max = 0;
+    // 0 build start, 1 build end, 2 loop start, 3 loop end, 4 all done
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+int fail(prot_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+int hip_fail(prot_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, PROT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                              \
+    do {                                                                \
+        hipError_t e_ = (expr);                                         \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);        \
+    } while (0)
+
+bool eps_valid(double eps)
+{
+    return eps > 0.0 && eps < 1.0 && std::floor(1.0 / eps) + 2.0 <= 32767.0;
+}
+
+double eps_internal(double eps, const prot_opts *o)
+{
+    return (o && o->eps_mode == PROT_EPS_STRICT) ? eps / 3.0 : eps;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+template <class T>
+int dev_alloc(prot_ctx *c, T **p, size_t count)
+{
+    if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, PROT_E_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    return PROT_OK;
+}
+
+int ensure_loop(prot_ctx *c, int64_t n)
+{
+    if (n <= c->cap_n && c->key) return PROT_OK;
+    const int64_t cap = n < 1024 ? 1024 : n;
+    int rc;
+    if ((rc = dev_alloc(c, &c->key, (size_t)cap))) return rc;
+    if ((rc = dev_alloc(c, &c->t, (size_t)round_up(cap, 8)))) return rc;
+    if ((rc = dev_alloc(c, &c->lists, (size_t)cap * 6))) return rc;
+    c->cap_n = cap;
+    return PROT_OK;
+}
+
+int ensure_matrix(prot_ctx *c, int64_t n)
+{
+    const int64_t need = n * prot_pitch(n);
+    if (need <= c->cap_mat && c->kmat) return PROT_OK;
+    int rc = dev_alloc(c, &c->kmat, (size_t)need);
+    if (rc) return rc;
+    c->cap_mat = need;
+    return PROT_OK;
+}
+
+int ensure_thresholds(prot_ctx *c, double eps)
+{
+    const int32_t need = (int32_t)std::floor(1.0 / eps) + 2;
+    if (need <= c->cap_th && c->th) return PROT_OK;
+    int rc = dev_alloc(c, &c->th, (size_t)need);
+    if (rc) return rc;
+    c->cap_th = need;
+    return PROT_OK;
+}
+
+int grid_for(prot_ctx *c, int64_t n, int *grid)
+{
+    const int n_pad = (int)round_up(n, 8);
+    if (c->grid_npad != n_pad) {
+        int gm = 0;
+        hipError_t e = prot::loop_grid(n_pad, &gm);
+        if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
+        if (gm <= 0)
+            return fail(c, PROT_E_UNSUPPORTED, "n=%lld: the column duals do not fit in LDS",
+                        (long long)n);
+        c->grid_npad = n_pad;
+        c->grid_max = gm;
+    }
+    const int wpg = prot::kLoopThreads / 64;
+    // every wave serves at most 64 rows of B' (one per lane)
+    const int64_t min_grid = (n + 64 * wpg - 1) / (64 * wpg);
+    if (min_grid > c->grid_max)
+        return fail(c, PROT_E_UNSUPPORTED, "n=%lld needs %lld resident workgroups, %d fit",
+                    (long long)n, (long long)min_grid, c->grid_max);
+    int64_t g = (n + wpg - 1) / wpg;  // one row per wave when n is small
+    if (g > c->grid_max) g = c->grid_max;
+    if (g < 1) g = 1;
+    *grid = (int)g;
+    return PROT_OK;
+}
+
+prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
+                         const prot_opts *o, int32_t *y_b)
+{
+    prot::LoopArgs a{};
+    a.k = k;
+    a.ldk = ldk;
+    a.n = (int32_t)n;
+    a.n_pad = (int32_t)round_up(n, 8);
+    a.T = T;
+    a.origin = (o && o->origin_mode == PROT_ORIGIN_ZERO) ? 1 : 0;
+    a.max_phases = o ? o->max_phases : 0;
+    a.key = c->key;
+    a.t = c->t;
+    a.y_b = y_b;
+    a.F[0] = c->lists;
+    a.F[1] = c->lists + c->cap_n;
+    a.L[0] = c->lists + 2 * c->cap_n;
+    a.L[1] = c->lists + 3 * c->cap_n;
+    a.ctl = c->ctl;
+    a.trace = c->trace;
+    return a;
+}
+
+// Enqueue init, the phase loop and the completion; returns after enqueueing.
+int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
+             const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
+             int32_t *y_b)
+{
+    int rc = ensure_loop(c, n);
+    if (rc) return rc;
+    int grid = 0;
+    if ((rc = grid_for(c, n, &grid))) return rc;
+    prot::LoopArgs a = loop_args(c, k, n, ldk, T, o, y_b);
+    if (warm) {
+        // (I1) and the matching structure of the given state, O(n).
+        HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
+        HIP_TRY(c, prot::launch_check_state(n, mate_a, mate_b, y_a, y_b, c->ctl, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl.err, &c->ctl->err, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (c->stage->ctl.err & 2)
+            return fail(c, PROT_E_STATE, "warm-start state is not a matching satisfying (I1)");
+    }
+    HIP_TRY(c, prot::launch_init(a, warm, mate_a, mate_b, y_a, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    HIP_TRY(c, prot::launch_loop(a, grid, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    const int32_t complete = (o && o->no_completion) ? 0 : 1;
+    HIP_TRY(c, prot::launch_finish(a, complete, mate_a, mate_b, y_a, c->lists + 4 * c->cap_n,
+                                   c->stream));
+    return PROT_OK;
+}
+
+int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kind,
+            bool timed_build)
+{
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->stage->part_k, c->part_k,
+                              sizeof(long long) * prot::kFinalizeBlocks, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->stage->part_c, c->part_c,
+                              sizeof(double) * prot::kFinalizeBlocks, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const Ctl &h = c->stage->ctl;
+    if (!st) return PROT_OK;
+    std::memset(st, 0, sizeof(*st));
+    st->phases = h.phases;
+    st->sum_free = h.sum_free;
+    st->rounds = h.rounds;
+    st->max_rounds = h.max_rounds;
+    st->scanned = (int64_t)h.scanned;
+    st->threshold = T;
+    st->status = h.status ? PROT_PARTIAL : PROT_OK;
+    st->eps_internal = eps_int;
+    long long sk = 0;
+    double sc = 0.0;
+    for (int i = 0; i < prot::kFinalizeBlocks; ++i) {
+        sk += c->stage->part_k[i];
+        sc += c->stage->part_c[i];
+    }
+    st->sum_k = sk;
+    st->cost_scale = 1.0;
+    if (cost_kind == 1) st->cost = sc;
+    if (cost_kind == 2) {
+        st->cost_scale = (double)h.m;
+        st->cost = h.m > 0.0f ? sc / (double)h.m : 0.0;
+    }
+    st->kmax = h.kmax;
+    float ms = 0.0f;
+    if (timed_build && hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess)
+        st->ms_build = ms;
+    if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) st->ms_loop_kernel = ms;
+    if (hipEventElapsedTime(&ms, c->ev[timed_build ? 0 : 1], c->ev[4]) == hipSuccess)
+        st->ms_total = ms;
+    return PROT_OK;
+}
+
+void fill_match_counts(prot_ctx *c, int64_t n, prot_stats *st, const prot_opts *o)
+{
+    if (!st) return;
+    const int64_t free_after = c->stage->ctl.free_after;
+    st->matched_in_phases = n - free_after;
+    st->completed_pairs = (o && o->no_completion) ? 0 : free_after;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t prot_pitch(int64_t n) { return n <= 0 ? 128 : round_up(n, 128); }
+
+int64_t prot_threshold(double eps, int64_t n) { return (int64_t)std::floor(eps * (double)n + 1e-9); }
+
+const char *prot_status_string(int s)
+{
+    switch (s) {
+    case PROT_OK: return "ok";
+    case PROT_PARTIAL: return "partial (max_phases reached)";
+    case PROT_E_ARG: return "invalid argument";
+    case PROT_E_RANGE: return "cost out of range or not finite";
+    case PROT_E_EPS: return "eps out of range";
+    case PROT_E_STATE: return "invalid warm-start state";
+    case PROT_E_HIP: return "HIP runtime error";
+    case PROT_E_NOMEM: return "out of device memory";
+    case PROT_E_UNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+    }
+}
+
+const char *prot_last_error(prot_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return PROT_E_ARG;
+    *out = nullptr;
+    prot_ctx *c = new (std::nothrow) prot_ctx();
+    if (!c) return PROT_E_NOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        delete c;
+        return PROT_E_HIP;
+    }
+    int rc = dev_alloc(c, &c->ctl, 1);
+    if (!rc) rc = dev_alloc(c, &c->trace, (size_t)4 * prot::kTraceCap);
+    if (!rc) rc = dev_alloc(c, &c->part_k, prot::kFinalizeBlocks);
+    if (!rc) rc = dev_alloc(c, &c->part_c, prot::kFinalizeBlocks);
+    if (!rc && hipHostMalloc((void **)&c->stage, sizeof(prot_ctx::Stage), hipHostMallocDefault) !=
+                   hipSuccess)
+        rc = PROT_E_NOMEM;
+    for (int i = 0; i < 5 && !rc; ++i)
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = PROT_E_HIP;
+    if (rc) {
+        prot_ctx_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return PROT_OK;
+}
+
+int prot_ctx_destroy(prot_ctx *c)
+{
+    if (!c) return PROT_E_ARG;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    (void)hipFree(c->key);
+    (void)hipFree(c->t);
+    (void)hipFree(c->lists);
+    (void)hipFree(c->ctl);
+    (void)hipFree(c->trace);
+    (void)hipFree(c->part_k);
+    (void)hipFree(c->part_c);
+    (void)hipFree(c->kmat);
+    (void)hipFree(c->th);
+    if (c->stage) (void)hipHostFree(c->stage);
+    for (int i = 0; i < 5; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    delete c;
+    return PROT_OK;
+}
+
+int prot_set_stream(prot_ctx *c, void *hip_stream)
+{
+    if (!c) return PROT_E_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return PROT_OK;
+}
+
+int prot_reserve(prot_ctx *c, int64_t n_max, int32_t with_matrix)
+{
+    if (!c || n_max < 0) return fail(c, PROT_E_ARG, "prot_reserve: bad arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = ensure_loop(c, n_max);
+    if (!rc && with_matrix) rc = ensure_matrix(c, n_max);
+    if (!rc) {
+        int grid = 0;
+        rc = grid_for(c, n_max, &grid);
+    }
+    return rc;
+}
+
+int64_t prot_max_n(prot_ctx *c)
+{
+    if (!c) return 0;
+    // LDS holds 2 bytes per column; each wave serves at most 64 rows.
+    int64_t best = 0;
+    for (int64_t n = 4096; n <= (1 << 20); n += 4096) {
+        const int n_pad = (int)round_up(n, 8);
+        int gm = 0;
+        if (prot::loop_grid(n_pad, &gm) != hipSuccess || gm <= 0) break;
+        if ((n + 64 * 8 - 1) / (64 * 8) > gm) break;
+        best = n;
+    }
+    return best;
+}
+
+int prot_round_costs(prot_ctx *c, const float *C, int64_t n, int64_t ldc, double eps,
+                     int16_t *k, int64_t ldk)
+{
+    if (!c) return PROT_E_ARG;
+    if (!C || !k || n < 0 || ldc < n || ldk < n || ldk % 8 || ((uintptr_t)k & 15))
+        return fail(c, PROT_E_ARG, "prot_round_costs: bad pointer, size or alignment");
+    if (!eps_valid(eps)) return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, prot::launch_round_costs(C, n, ldc, eps, k, ldk, c->ctl, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl.err, &c->ctl->err, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a cost is NaN or outside [0,1]");
+    return PROT_OK;
+}
+
+int prot_build_costs(prot_ctx *c, const float *X, const float *Y, int64_t n, int32_t d,
+                     double eps, int16_t *k, int64_t ldk, float *m_out)
+{
+    if (!c) return PROT_E_ARG;
+    if (!X || !Y || !k || n < 0 || d < 1 || ldk < n || ldk % 8 || ((uintptr_t)k & 15))
+        return fail(c, PROT_E_ARG, "prot_build_costs: bad pointer, size or alignment");
+    if (!eps_valid(eps)) return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = ensure_thresholds(c, eps);
+    if (rc) return rc;
+    HIP_TRY(c, prot::launch_build_points(X, Y, n, d, eps, k, ldk, m_out, c->th, c->ctl,
+                                         c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl.err, &c->ctl->err, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");
+    return PROT_OK;
+}
+
+int prot_solve_rounded(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
+                       const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b,
+                       int32_t *y_a, int32_t *y_b, prot_stats *st)
+{
+    if (!c) return PROT_E_ARG;
+    if (n < 0 || T < 0 || (n > 0 && (!k || ldk < n || ldk % 8 || ((uintptr_t)k & 15))) ||
+        (n > 0 && (!mate_a || !mate_b || !y_a || !y_b)))
+        return fail(c, PROT_E_ARG, "prot_solve_rounded: bad pointer, size or alignment");
+    if (n > INT32_MAX / 2) return fail(c, PROT_E_UNSUPPORTED, "n too large");
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (n == 0) return PROT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    int rc = run_loop(c, k, n, ldk, T, o, warm, mate_a, mate_b, y_a, y_b);
+    if (rc) return rc;
+    HIP_TRY(c, prot::launch_finalize(n, mate_b, k, ldk, 0, nullptr, 0, nullptr, nullptr, 0,
+                                     c->part_k, c->part_c, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+    if (!st) return PROT_OK;
+    rc = collect(c, st, T, 0.0, 0, false);
+    if (rc) return rc;
+    fill_match_counts(c, n, st, o);
+    return st->status;
+}
+
+int prot_solve_cost(prot_ctx *c, const float *C, int64_t n, int64_t ldc, double eps,
+                    const prot_opts *o, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
+                    int32_t *y_b, prot_stats *st)
+{
+    if (!c) return PROT_E_ARG;
+    if (n < 0 || (n > 0 && (!C || ldc < n || !mate_a || !mate_b || !y_a || !y_b)))
+        return fail(c, PROT_E_ARG, "prot_solve_cost: bad pointer or size");
+    if (!eps_valid(eps_internal(eps, o)))
+        return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    prot_stats local;
+    if (!st) st = &local;
+    std::memset(st, 0, sizeof(*st));
+    if (n == 0) return PROT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const double ei = eps_internal(eps, o);
+    const int64_t T = prot_threshold(ei, n), ldk = prot_pitch(n);
+    int rc = ensure_matrix(c, n);
+    if (rc) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    HIP_TRY(c, prot::launch_round_costs(C, n, ldc, ei, c->kmat, ldk, c->ctl, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    rc = run_loop(c, c->kmat, n, ldk, T, o, 0, mate_a, mate_b, y_a, y_b);
+    if (rc) return rc;
+    HIP_TRY(c, prot::launch_finalize(n, mate_b, c->kmat, ldk, 1, C, ldc, nullptr, nullptr, 0,
+                                     c->part_k, c->part_c, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+    rc = collect(c, st, T, ei, 1, true);
+    if (rc) return rc;
+    fill_match_counts(c, n, st, o);
+    st->kmax = (int32_t)std::floor(1.0 / ei);
+    if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a cost is NaN or outside [0,1]");
+    return st->status;
+}
+
+int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, int32_t d,
+                      double eps, const prot_opts *o, int32_t *mate_a, int32_t *mate_b,
+                      int32_t *y_a, int32_t *y_b, prot_stats *st)
+{
+    if (!c) return PROT_E_ARG;
+    if (n < 0 || d < 1 || (n > 0 && (!X || !Y || !mate_a || !mate_b || !y_a || !y_b)))
+        return fail(c, PROT_E_ARG, "prot_solve_points: bad pointer or size");
+    if (!eps_valid(eps_internal(eps, o)))
+        return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    prot_stats local;
+    if (!st) st = &local;
+    std::memset(st, 0, sizeof(*st));
+    if (n == 0) return PROT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const double ei = eps_internal(eps, o);
+    const int64_t T = prot_threshold(ei, n), ldk = prot_pitch(n);
+    int rc = ensure_matrix(c, n);
+    if (!rc) rc = ensure_thresholds(c, ei);
+    if (rc) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    HIP_TRY(c, prot::launch_build_points(X, Y, n, d, ei, c->kmat, ldk, nullptr, c->th, c->ctl,
+                                         c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    rc = run_loop(c, c->kmat, n, ldk, T, o, 0, mate_a, mate_b, y_a, y_b);
+    if (rc) return rc;
+    HIP_TRY(c, prot::launch_finalize(n, mate_b, c->kmat, ldk, 2, nullptr, 0, X, Y, d, c->part_k,
+                                     c->part_c, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+    rc = collect(c, st, T, ei, 2, true);
+    if (rc) return rc;
+    fill_match_counts(c, n, st, o);
+    if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");
+    return st->status;
+}
+
+int64_t prot_get_trace(prot_ctx *c, int64_t *out, int64_t cap)
+{
+    if (!c || !out || cap < 0) return PROT_E_ARG;
+    Ctl h;
+    if (hipMemcpyAsync(&c->stage->ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return PROT_E_HIP;
+    h = c->stage->ctl;
+    int64_t m = h.phases;
+    if (m > prot::kTraceCap) m = prot::kTraceCap;
+    if (m > cap) m = cap;
+    if (m > 0) {
+        if (hipMemcpyAsync(out, c->trace, sizeof(int64_t) * 4 * (size_t)m, hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return PROT_E_HIP;
+    }
+    return m;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP translation units of libprot.
+// Not part of the public C ABI (see include/prot.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace prot {
+
+// Device-side control block of one phase loop. Zeroed by the init kernel.
+// Counters that are reused round after round (or phase after phase) live in
+// rings of three: the slot of round r is r % 3. A slot is cleared two rounds
+// before its next use, after every reader of its previous use has passed a
+// grid barrier (see the phase-loop kernel).
+struct alignas(128) Ctl {
+    unsigned long long bar;      // grid-barrier arrivals (monotonic)
+    unsigned long long scanned;  // matrix entries examined
+    uint32_t prop_cnt[3];        // proposals made in round r
+    uint32_t dist_cnt[3];        // distinct columns first proposed to in round r
+    uint32_t f_cnt[3];           // |B'| of phase p
+    uint32_t l_cnt[3];           // columns taken in phase p
+    int32_t status;              // 0 finished, 1 stopped at max_phases
+    int32_t err;                 // bit 0: cost out of range / non-finite
+    int64_t phases;
+    int64_t sum_free;
+    int64_t rounds;
+    int64_t max_rounds;
+    int64_t free_after;          // |free B| when the loop stopped
+    int32_t kmax;                // largest rounded cost produced by a cost build
+    int32_t pad;
+    float m;                     // max squared distance of the last point build
+};
+
+constexpr int kLoopThreads = 512;       // threads per workgroup of the loop
+constexpr int kTraceCap = 65536;        // phases recorded in the trace
+constexpr int kFinalizeBlocks = 256;    // partial sums of the finalize kernel
+
+struct LoopArgs {
+    const int16_t *k;
+    int64_t ldk;
+    int32_t n;
+    int32_t n_pad;          // n rounded up to 8 (LDS dual array length)
+    int64_t T;
+    int32_t origin;         // 0: diagonal, 1: zero
+    int32_t pad;
+    int64_t max_phases;
+    unsigned long long *key;  // per column: (round << 32) | ~b of its last winner
+    uint16_t *t;              // per column: -y(a) (number of phases it was taken in)
+    int32_t *y_b;
+    int32_t *F[2];            // free lists B' (ping-pong by phase parity)
+    int32_t *L[2];            // columns taken in a phase (ping-pong)
+    Ctl *ctl;
+    int64_t *trace;           // 4 int64 per phase
+};
+
+// cost.hip
+hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps,
+                              int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s);
+hipError_t launch_build_points(const float *X, const float *Y, int64_t n, int32_t d,
+                               double eps, int16_t *k, int64_t ldk, float *m_out,
+                               float *thresholds, Ctl *ctl, hipStream_t s);
+
+// solve.hip
+hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
+                       const int32_t *mate_b, const int32_t *y_a, hipStream_t s);
+hipError_t launch_clear_err(Ctl *ctl, hipStream_t s);
+hipError_t launch_check_state(int64_t n, const int32_t *mate_a, const int32_t *mate_b,
+                              const int32_t *y_a, const int32_t *y_b, Ctl *ctl,
+                              hipStream_t s);
+hipError_t loop_grid(int32_t n_pad, int *grid_max);
+hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s);
+hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a,
+                         int32_t *mate_b, int32_t *y_a, int32_t *scratch,
+                         hipStream_t s);
+// cost_kind: 0 none, 1 cost matrix C (ldc), 2 points X, Y (d) with scale m
+hipError_t launch_finalize(int64_t n, const int32_t *mate_b, const int16_t *k,
+                           int64_t ldk, int cost_kind, const float *C, int64_t ldc,
+                           const float *X, const float *Y, int32_t d,
+                           long long *part_k, double *part_c, hipStream_t s);
+
+}  // namespace prot

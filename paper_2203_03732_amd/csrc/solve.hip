@@ -1,0 +1,579 @@
+// The integer phase loop of arXiv:2203.03732, Section 2.2, on one GPU.
+//
+// One cooperative, persistent launch runs every phase. Per phase:
+//   B'  (the free supply rows) is the list F[p & 1];
+//   step (I), a maximal matching M' in the admissible graph of B', is built
+//       by synchronous proposal rounds: every row still looking scans its row
+//       of the rounded-cost matrix (starting at its own column and wrapping,
+//       or at column 0) for the first column that is admissible,
+//       k[b][a] + 1 == y(a) + y(b), and was not taken before the round began;
+//       it proposes with an atomic max on that column's 64-bit key
+//       (round << 32 | ~b), so the lowest-index proposer of the round wins;
+//   step (II) and (III) need no separate pass: the key of a column always
+//       names its current mate, so the first proposal to a column in a
+//       round appends the old mate (if any) to the next free list and the
+//       column to the list of columns taken this phase, and a row that finds
+//       nothing raises its own dual and re-enters the next free list.
+// One grid barrier ends each round. A round with no proposals, or in which
+// every proposal went to a distinct column (no losers), ends the phase.
+//
+// y(a) is stored as t(a) = -y(a) >= 0, the number of phases in which column a
+// was taken. Each workgroup keeps a copy of t in LDS as it stood at the start
+// of the phase (Section 2.2 updates the duals only after the greedy step) and
+// applies the previous phase's taken-column list at each phase start.
+#include "internal.h"
+
+namespace prot {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kChunk = kWave * 8;   // columns examined per wave per load
+constexpr int kPrefetch = 4;        // chunks in flight in a long scan
+
+template <class T>
+__device__ inline T ld_agent(const T *p)
+{
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline void st_agent(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline T add_agent(T *p, T v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All workgroups of the (co-resident) grid meet here. Writes made before the
+// barrier by any workgroup are visible after it.
+__device__ inline void grid_sync(unsigned long long *bar, unsigned long long &target)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        target += gridDim.x;
+        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+            __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// bit e set iff lo <= col0 + e < hi, for e in [0, 8)
+__device__ inline uint32_t range_mask(int col0, int lo, int hi)
+{
+    const int s = lo - col0, t = hi - col0;
+    uint32_t m = 0xFFu;
+    if (s > 0) m = s >= 8 ? 0u : (m << s) & 0xFFu;
+    if (t < 8) m = t <= 0 ? 0u : m & (0xFFu >> (8 - t));
+    return m;
+}
+
+// bit e set iff k[e] + t[e] == need, i.e. k + 1 == y(a) + y(b) with
+// y(a) = -t and need = y(b) - 1.
+__device__ inline uint32_t match_mask(uint4 kv, uint4 tv, int need)
+{
+    const uint32_t kw[4] = {kv.x, kv.y, kv.z, kv.w};
+    const uint32_t tw[4] = {tv.x, tv.y, tv.z, tv.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k0 = (int)(int16_t)(kw[i] & 0xFFFFu), k1 = (int)(int16_t)(kw[i] >> 16);
+        const int t0 = (int)(tw[i] & 0xFFFFu), t1 = (int)(tw[i] >> 16);
+        m |= (uint32_t)(k0 + t0 == need) << (2 * i);
+        m |= (uint32_t)(k1 + t1 == need) << (2 * i + 1);
+    }
+    return m;
+}
+
+// First column of this chunk (wave-wide, lowest column first) that is
+// admissible and not taken in an earlier round of this phase; -1 if none.
+// A column is taken iff its key was written in a round in [r0, r).
+__device__ inline int chunk_hit(int col0, uint4 kv, uint4 tv, int need, int lo, int hi,
+                                const unsigned long long *key, uint32_t r0, uint32_t r)
+{
+    const uint32_t cand = col0 < hi ? (match_mask(kv, tv, need) & range_mask(col0, lo, hi)) : 0u;
+    uint32_t hit = 0;
+    if (cand) {
+        unsigned long long kk[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) kk[e] = ((cand >> e) & 1u) ? ld_agent(key + col0 + e) : 0ull;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t kr = (uint32_t)(kk[e] >> 32);
+            const bool taken = kr >= r0 && kr < r;
+            if (((cand >> e) & 1u) && !taken) hit |= 1u << e;
+        }
+    }
+    const unsigned long long bal = __ballot(hit != 0u);
+    if (bal == 0ull) return -1;
+    const int L = __builtin_ctzll(bal);
+    const uint32_t h = __builtin_amdgcn_readlane(hit, L);
+    const int c = __builtin_amdgcn_readlane(col0, L);
+    return c + __builtin_ctz(h);
+}
+
+struct Hit {
+    int j;  // scan position of the hit, -1 if the row is exhausted
+    int a;  // its column
+};
+
+// Scan row b (wave-cooperative) from scan position pos. Scan position j
+// visits column (origin + j) mod n, so the scan covers the column ranges
+// [origin + pos, n) and then [0, origin), or [origin + pos - n, origin).
+__device__ Hit scan_row(const int16_t *__restrict__ row, const uint16_t *t_lds, int n, int origin,
+                        int pos, int need, const unsigned long long *key, uint32_t r0, uint32_t r,
+                        int lane)
+{
+    int lo[2], hi[2];
+    const int c0 = origin + pos;
+    if (c0 < n) {
+        lo[0] = c0; hi[0] = n; lo[1] = 0; hi[1] = origin;
+    } else {
+        lo[0] = c0 - n; hi[0] = origin; lo[1] = 0; hi[1] = 0;
+    }
+    for (int sg = 0; sg < 2; ++sg) {
+        const int slo = lo[sg], shi = hi[sg];
+        if (slo >= shi) continue;
+        int base = slo & ~7;
+        {   // the first chunk on its own: early rows usually hit in it
+            const int col0 = base + lane * 8;
+            uint4 kv = make_uint4(0u, 0u, 0u, 0u), tv = make_uint4(0u, 0u, 0u, 0u);
+            if (col0 < shi) {
+                kv = *reinterpret_cast<const uint4 *>(row + col0);
+                tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
+            }
+            const int a = chunk_hit(col0, kv, tv, need, slo, shi, key, r0, r);
+            if (a >= 0) return Hit{a >= origin ? a - origin : a - origin + n, a};
+            base += kChunk;
+        }
+        while (base < shi) {
+            uint4 kv[kPrefetch], tv[kPrefetch];
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                const int col0 = base + u * kChunk + lane * 8;
+                kv[u] = make_uint4(0u, 0u, 0u, 0u);
+                tv[u] = make_uint4(0u, 0u, 0u, 0u);
+                if (col0 < shi) {
+                    kv[u] = *reinterpret_cast<const uint4 *>(row + col0);
+                    tv[u] = *reinterpret_cast<const uint4 *>(t_lds + col0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kPrefetch; ++u) {
+                const int col0 = base + u * kChunk + lane * 8;
+                const int a = chunk_hit(col0, kv[u], tv[u], need, slo, shi, key, r0, r);
+                if (a >= 0) return Hit{a >= origin ? a - origin : a - origin + n, a};
+            }
+            base += kPrefetch * kChunk;
+        }
+    }
+    return Hit{-1, -1};
+}
+
+__global__ void loop_reset_kernel(LoopArgs a)
+{
+    Ctl *c = a.ctl;
+    c->bar = 0;
+    c->scanned = 0;
+    for (int i = 0; i < 3; ++i) {
+        c->prop_cnt[i] = 0;
+        c->dist_cnt[i] = 0;
+        c->f_cnt[i] = 0;
+        c->l_cnt[i] = 0;
+    }
+    c->status = 0;
+    c->phases = c->sum_free = c->rounds = c->max_rounds = 0;
+    c->free_after = 0;
+    for (int i = 0; i < 4; ++i) a.trace[i] = 0;
+}
+
+// Initial state: y(b) = 1, y(a) = 0, M empty (Section 2.2), or a warm start.
+__global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
+                            const int32_t *mate_b, const int32_t *y_a)
+{
+    const int n = a.n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_pad; i += gridDim.x * blockDim.x) {
+        if (i >= n) {
+            a.t[i] = 0;
+            continue;
+        }
+        if (!warm) {
+            a.key[i] = 0ull;
+            a.t[i] = 0;
+            a.y_b[i] = 1;
+            a.F[0][i] = i;
+        } else {
+            const int32_t m = mate_a[i];
+            a.key[i] = m >= 0 ? (unsigned long long)(uint32_t)~(uint32_t)m : 0ull;
+            a.t[i] = (uint16_t)(-y_a[i]);
+            if (mate_b[i] < 0) a.F[0][add_agent(&a.ctl->f_cnt[0], 1u)] = i;
+        }
+    }
+    if (!warm && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->f_cnt[0] = (uint32_t)n;
+}
+
+// Warm-start check, O(n): the mate arrays form one matching and (I1) holds.
+__global__ void check_state_kernel(int64_t n, const int32_t *mate_a, const int32_t *mate_b,
+                                   const int32_t *y_a, const int32_t *y_b, Ctl *ctl)
+{
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t ma = mate_a[i], mb = mate_b[i];
+        if (ma >= n || mb >= n) bad = true;
+        else {
+            if (ma >= 0 && mate_b[ma] != i) bad = true;
+            if (mb >= 0 && mate_a[mb] != i) bad = true;
+        }
+        if (y_a[i] > 0 || y_a[i] < -32000 || y_b[i] < 0 || y_b[i] > 32000) bad = true;
+        if (ma < 0 && y_a[i] != 0) bad = true;
+    }
+    if (bad) __hip_atomic_fetch_or(&ctl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
+{
+    extern __shared__ __align__(16) uint16_t t_lds[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wpg = blockDim.x / kWave;
+    const uint32_t W = gridDim.x * wpg;
+    const uint32_t gw = blockIdx.x * wpg + threadIdx.x / kWave;
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    Ctl *ctl = A.ctl;
+    const int n = A.n;
+    unsigned long long bar_target = 0;
+
+    for (int i = threadIdx.x; i < A.n_pad; i += blockDim.x) t_lds[i] = A.t[i];
+    __syncthreads();
+
+    uint32_t r = 0;        // id of the last round (keys carry it)
+    int64_t p = 0;         // phase index within this launch
+    int64_t phase_rounds = 0;
+    for (;;) {
+        // Step (III a) of the previous phase, applied to this copy of y(a).
+        if (p > 0) {
+            const uint32_t nl = ld_agent(&ctl->l_cnt[(p - 1) % 3]);
+            const int32_t *Lp = A.L[(p - 1) & 1];
+            for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) t_lds[Lp[i]] += 1;
+            __syncthreads();
+        }
+        const uint32_t n_i = ld_agent(&ctl->f_cnt[p % 3]);
+        if ((int64_t)n_i <= A.T) break;
+        if (A.max_phases > 0 && p >= A.max_phases) {
+            if (leader) ctl->status = 1;
+            break;
+        }
+        if (leader) {
+            ctl->phases = p + 1;
+            ctl->sum_free += n_i;
+            st_agent(&ctl->f_cnt[(p + 2) % 3], 0u);
+            st_agent(&ctl->l_cnt[(p + 1) % 3], 0u);
+            if (p < kTraceCap) A.trace[4 * p] = n_i;
+            if (p + 1 < kTraceCap)
+                for (int i = 0; i < 4; ++i) st_agent(&A.trace[4 * (p + 1) + i], (int64_t)0);
+        }
+        const uint32_t r0 = r + 1;
+        const int32_t *Fc = A.F[p & 1];
+        int32_t *Fn = A.F[(p + 1) & 1];
+        int32_t *Lc = A.L[p & 1];
+        uint32_t *fcnt_next = &ctl->f_cnt[(p + 1) % 3];
+        uint32_t *lcnt_cur = &ctl->l_cnt[p % 3];
+        int64_t *trace_scanned = p < kTraceCap ? &A.trace[4 * p + 2] : nullptr;
+
+        // Slot s of this wave is entry gw + s*W of B'; lane s holds its state.
+        const uint32_t nslots = gw < n_i ? (n_i - gw + W - 1) / W : 0u;
+        int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0;
+        unsigned long long s_key = 0;
+        if ((uint32_t)lane < nslots) {
+            s_b = Fc[gw + (uint32_t)lane * W];
+            s_yb = A.y_b[s_b];
+        }
+        unsigned long long active = __ballot((uint32_t)lane < nslots);
+
+        for (;;) {
+            r += 1;
+            if (leader) {
+                st_agent(&ctl->prop_cnt[(r + 1) % 3], 0u);
+                st_agent(&ctl->dist_cnt[(r + 1) % 3], 0u);
+            }
+            uint32_t n_prop = 0, n_dist = 0;
+            unsigned long long n_scan = 0;
+            unsigned long long rem = active;
+            while (rem) {
+                const int s = __builtin_ctzll(rem);
+                rem &= rem - 1;
+                const int b = __builtin_amdgcn_readlane(s_b, s);
+                const int pos = __builtin_amdgcn_readlane(s_pos, s);
+                const int yb = __builtin_amdgcn_readlane(s_yb, s);
+                const int origin = A.origin == 0 ? b : 0;
+                const Hit h = scan_row(A.k + (int64_t)b * A.ldk, t_lds, n, origin, pos, yb - 1,
+                                       A.key, r0, r, lane);
+                if (h.j >= 0) {
+                    n_scan += (unsigned long long)(h.j - pos + 1);
+                    const unsigned long long kn =
+                        ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
+                    if (lane == 0) {
+                        const unsigned long long old = __hip_atomic_fetch_max(
+                            A.key + h.a, kn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if ((uint32_t)(old >> 32) < r) {
+                            // first proposal to column a this round: a will be
+                            // matched in M' whoever wins, so (II) evicts its
+                            // old mate and (III a) will lower y(a).
+                            n_dist += 1;
+                            Lc[add_agent(lcnt_cur, 1u)] = h.a;
+                            if (old != 0ull)
+                                Fn[add_agent(fcnt_next, 1u)] = (int32_t)~(uint32_t)old;
+                        }
+                    }
+                    n_prop += 1;
+                    if (lane == s) {
+                        s_pos = h.j;
+                        s_a = h.a;
+                        s_key = kn;
+                    }
+                } else {
+                    // b has no admissible untaken column: free in M', (III b).
+                    n_scan += (unsigned long long)(n - pos);
+                    if (lane == 0) {
+                        A.y_b[b] = yb + 1;
+                        Fn[add_agent(fcnt_next, 1u)] = b;
+                    }
+                    active &= ~(1ull << s);
+                }
+            }
+            if (lane == 0) {
+                if (n_prop) add_agent(&ctl->prop_cnt[r % 3], n_prop);
+                if (n_dist) add_agent(&ctl->dist_cnt[r % 3], n_dist);
+                if (n_scan) {
+                    add_agent(&ctl->scanned, n_scan);
+                    if (trace_scanned) add_agent(trace_scanned, (int64_t)n_scan);
+                }
+            }
+            grid_sync(&ctl->bar, bar_target);
+            const uint32_t P = ld_agent(&ctl->prop_cnt[r % 3]);
+            const uint32_t D = ld_agent(&ctl->dist_cnt[r % 3]);
+            if (leader && P > 0) {
+                ctl->rounds += 1;
+                phase_rounds += 1;
+                if (p < kTraceCap) {
+                    A.trace[4 * p + 1] += 1;
+                    A.trace[4 * p + 3] += D;
+                }
+            }
+            if (P == 0u || P == D) break;  // nobody lost a proposal: M' is maximal
+            bool mine = (active >> lane) & 1ull;
+            if (mine) {
+                if (ld_agent(A.key + s_a) == s_key) mine = false;  // won: matched in M'
+                else s_pos += 1;                                  // lost: resume after
+            }
+            active = __ballot(mine);
+        }
+        if (leader) {
+            if (phase_rounds > ctl->max_rounds) ctl->max_rounds = phase_rounds;
+            phase_rounds = 0;
+        }
+        p += 1;
+    }
+    if (leader) ctl->free_after = ld_agent(&ctl->f_cnt[p % 3]);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) A.t[i] = t_lds[i];
+}
+
+__global__ void clear_err_kernel(Ctl *ctl) { ctl->err = 0; }
+
+__global__ void fill_kernel(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Matching and duals from the per-column keys and t.
+__global__ void decode_kernel(LoopArgs a, int32_t *mate_a, int32_t *mate_b, int32_t *y_a)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
+        const unsigned long long kk = a.key[i];
+        const int32_t m = kk ? (int32_t)~(uint32_t)kk : -1;
+        mate_a[i] = m;
+        if (m >= 0) mate_b[m] = i;
+        y_a[i] = -(int32_t)a.t[i];
+    }
+}
+
+constexpr int kCompleteThreads = 1024;
+
+// Exclusive scan of one flag per element over [0, n), written as the list of
+// flagged indices in ascending order. One workgroup.
+__device__ int list_flags(const int32_t *mate, int n, int32_t *out, int *cnt)
+{
+    const int tid = threadIdx.x;
+    const int per = (n + kCompleteThreads - 1) / kCompleteThreads;
+    const int lo = min(n, tid * per), hi = min(n, lo + per);
+    int c = 0;
+    for (int i = lo; i < hi; ++i) c += mate[i] < 0;
+    cnt[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < kCompleteThreads; off <<= 1) {
+        const int v = tid >= off ? cnt[tid - off] : 0;
+        __syncthreads();
+        cnt[tid] += v;
+        __syncthreads();
+    }
+    int o = cnt[tid] - c;
+    for (int i = lo; i < hi; ++i)
+        if (mate[i] < 0) out[o++] = i;
+    const int total = cnt[kCompleteThreads - 1];
+    __syncthreads();
+    return total;
+}
+
+// Completion (Section 2.1): the i-th free b (ascending) takes the i-th free a.
+__global__ void __launch_bounds__(kCompleteThreads)
+complete_kernel(int n, int32_t *mate_a, int32_t *mate_b, int32_t *scratch, int32_t complete)
+{
+    __shared__ int cnt[kCompleteThreads];
+    const int nb = list_flags(mate_b, n, scratch, cnt);
+    const int na = list_flags(mate_a, n, scratch + n, cnt);
+    if (!complete) return;
+    const int m = min(nb, na);
+    for (int i = threadIdx.x; i < m; i += kCompleteThreads) {
+        const int b = scratch[i], a = scratch[n + i];
+        mate_b[b] = a;
+        mate_a[a] = b;
+    }
+}
+
+constexpr int kFinalizeThreads = 256;
+
+// Per-block partial sums, in a fixed order, of k and of the cost over the
+// matching (deterministic: the host adds the partials in block order).
+__global__ void __launch_bounds__(kFinalizeThreads)
+finalize_kernel(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk, int cost_kind,
+                const float *C, int64_t ldc, const float *X, const float *Y, int32_t d,
+                long long *part_k, double *part_c)
+{
+    __shared__ long long sk[kFinalizeThreads];
+    __shared__ double sc[kFinalizeThreads];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = min<int64_t>(n, blockIdx.x * per), hi = min<int64_t>(n, lo + per);
+    long long ks = 0;
+    double cs = 0.0;
+    for (int64_t b = lo + threadIdx.x; b < hi; b += kFinalizeThreads) {
+        const int32_t a = mate_b[b];
+        if (a < 0) continue;
+        if (k) ks += k[b * ldk + a];
+        if (cost_kind == 1) {
+            cs = __dadd_rn(cs, (double)C[b * ldc + a]);
+        } else if (cost_kind == 2) {
+            double s = 0.0;
+            for (int j = 0; j < d; ++j) {
+                const double t = __dsub_rn((double)X[b * d + j], (double)Y[(int64_t)a * d + j]);
+                s = __dadd_rn(s, __dmul_rn(t, t));
+            }
+            cs = __dadd_rn(cs, s);
+        }
+    }
+    sk[threadIdx.x] = ks;
+    sc[threadIdx.x] = cs;
+    __syncthreads();
+    for (int off = kFinalizeThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            sk[threadIdx.x] += sk[threadIdx.x + off];
+            sc[threadIdx.x] = __dadd_rn(sc[threadIdx.x], sc[threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part_k[blockIdx.x] = sk[0];
+        part_c[blockIdx.x] = sc[0];
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int threads)
+{
+    int64_t b = (n + threads - 1) / threads;
+    return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+}  // namespace
+
+hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
+                       const int32_t *mate_b, const int32_t *y_a, hipStream_t s)
+{
+    hipLaunchKernelGGL(loop_reset_kernel, dim3(1), dim3(1), 0, s, a);
+    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(a.n_pad, 256)), dim3(256), 0, s, a, warm,
+                       mate_a, mate_b, y_a);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_err(Ctl *ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(clear_err_kernel, dim3(1), dim3(1), 0, s, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_state(int64_t n, const int32_t *mate_a, const int32_t *mate_b,
+                              const int32_t *y_a, const int32_t *y_b, Ctl *ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_state_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, mate_a,
+                       mate_b, y_a, y_b, ctl);
+    return hipGetLastError();
+}
+
+hipError_t loop_grid(int32_t n_pad, int *grid_max)
+{
+    const size_t lds = (size_t)n_pad * sizeof(uint16_t);
+    hipError_t e = hipSuccess;
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute((const void *)phase_loop_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel, kLoopThreads, lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (per_cu > 2) per_cu = 2;
+    *grid_max = per_cu * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
+{
+    LoopArgs copy = a;
+    void *args[] = {&copy};
+    const size_t lds = (size_t)a.n_pad * sizeof(uint16_t);
+    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel, dim3(grid),
+                                      dim3(kLoopThreads), args, (unsigned)lds, s);
+}
+
+hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a, int32_t *mate_b,
+                         int32_t *y_a, int32_t *scratch, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, mate_b,
+                       (int64_t)a.n, -1);
+    hipLaunchKernelGGL(decode_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a, mate_a,
+                       mate_b, y_a);
+    hipLaunchKernelGGL(complete_kernel, dim3(1), dim3(kCompleteThreads), 0, s, a.n, mate_a,
+                       mate_b, scratch, complete);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk,
+                           int cost_kind, const float *C, int64_t ldc, const float *X,
+                           const float *Y, int32_t d, long long *part_k, double *part_c,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(kFinalizeThreads), 0, s, n,
+                       mate_b, k, ldk, cost_kind, C, ldc, X, Y, d, part_k, part_c);
+    return hipGetLastError();
+}
+
+}  // namespace prot
