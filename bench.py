@@ -52,6 +52,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after the bench, run 5 plain device copies of this many MiB "
+                         "(reference kernel for scaling memory counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -129,6 +132,14 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, Y, eps, args.cpu_reps)
     print(json.dumps(out), flush=True)
+    if args.copy_calibration_mb:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes}), flush=True)
     ctx.close()
 
 

@@ -156,6 +156,15 @@ int prot_solve_points(prot_ctx *ctx, const float *X, const float *Y,
  * 65536). Synchronises the stream. */
 int64_t prot_get_trace(prot_ctx *ctx, int64_t *out_host, int64_t cap);
 
+/* Diagnostics: per-round device timestamps of the last phase loop, recorded
+ * only when the context was created with PROT_DEBUG_ROUND_TIMES=1 in the
+ * environment. For round r (0-based), out[3r] = latest arrival of any
+ * workgroup at the round's grid barrier, out[3r+1] = the barrier's exit,
+ * out[3r+2] = the phase index; times in ticks of the 100 MHz device clock,
+ * 0 for rounds not run. Returns the number of rounds copied (0 if timing is
+ * off). Synchronises the stream. */
+int64_t prot_get_round_times(prot_ctx *ctx, int64_t *out_host, int64_t cap);
+
 const char *prot_status_string(int status);
 const char *prot_last_error(prot_ctx *ctx);
 

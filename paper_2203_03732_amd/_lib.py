@@ -51,6 +51,7 @@ EXPORTS = [
     "prot_ctx_create", "prot_ctx_destroy", "prot_set_stream", "prot_reserve", "prot_pitch",
     "prot_threshold", "prot_max_n", "prot_round_costs", "prot_build_costs",
     "prot_solve_rounded", "prot_solve_cost", "prot_solve_points", "prot_get_trace",
+    "prot_get_round_times",
     "prot_status_string", "prot_last_error",
 ]
 
@@ -83,6 +84,7 @@ def load():
         "prot_solve_points": (ctypes.c_int, [p, p, p, i64, i32, f64, ctypes.POINTER(Opts),
                                              p, p, p, p, ctypes.POINTER(Stats)]),
         "prot_get_trace": (i64, [p, p, i64]),
+        "prot_get_round_times": (i64, [p, p, i64]),
         "prot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "prot_last_error": (ctypes.c_char_p, [p]),
     }
@@ -276,6 +278,18 @@ class Context:
             _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
             _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)))
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
+
+    def round_times(self, cap: int = 65536):
+        """(rounds, 3) int64: barrier arrival of the last workgroup, barrier
+        exit, phase index; 100 MHz ticks. Empty unless the context was made
+        with PROT_DEBUG_ROUND_TIMES=1."""
+        import numpy as np
+        buf = np.zeros((cap, 3), np.int64)
+        m = int(self._lib.prot_get_round_times(self._h, buf.ctypes.data_as(ctypes.c_void_p), cap))
+        if m < 0:
+            raise ProtError(m, "prot_get_round_times failed")
+        buf = buf[:m]
+        return buf[buf[:, 1] != 0].copy()
 
     def trace(self, cap: int = 65536):
         import numpy as np

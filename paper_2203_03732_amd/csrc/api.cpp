@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -44,6 +45,9 @@ struct prot_ctx {
         double part_c[prot::kFinalizeBlocks];
     } *stage = nullptr;              // pinned host memory
 
+    int64_t *rtime = nullptr;        // round timer (PROT_DEBUG_ROUND_TIMES=1)
+    int64_t rtime_start = 0;
+    int wgs_per_cu = 1;              // PROT_LOOP_WGS_PER_CU (diagnostics)
     int grid_npad = -1;
     int grid_max = 0;
     // 0 build start, 1 build end, 2 loop start, 3 loop end, 4 all done
@@ -142,7 +146,7 @@ int grid_for(prot_ctx *c, int64_t n, int *grid)
     const int n_pad = (int)round_up(n, 8);
     if (c->grid_npad != n_pad) {
         int gm = 0;
-        hipError_t e = prot::loop_grid(n_pad, &gm);
+        hipError_t e = prot::loop_grid(n_pad, c->wgs_per_cu, &gm);
         if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
         if (gm <= 0)
             return fail(c, PROT_E_UNSUPPORTED, "n=%lld: the column duals do not fit in LDS",
@@ -183,6 +187,7 @@ prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, 
     a.L[1] = c->lists + 3 * c->cap_n;
     a.ctl = c->ctl;
     a.trace = c->trace;
+    a.rtime = c->rtime;
     return a;
 }
 
@@ -207,6 +212,7 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
             return fail(c, PROT_E_STATE, "warm-start state is not a matching satisfying (I1)");
     }
     HIP_TRY(c, prot::launch_init(a, warm, mate_a, mate_b, y_a, c->stream));
+    if (c->rtime) HIP_TRY(c, prot::launch_clear_times(c->rtime, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
     HIP_TRY(c, prot::launch_loop(a, grid, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
@@ -318,6 +324,14 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
         rc = PROT_E_NOMEM;
     for (int i = 0; i < 5 && !rc; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = PROT_E_HIP;
+    if (const char *v = std::getenv("PROT_LOOP_WGS_PER_CU")) {
+        const int w = std::atoi(v);
+        if (w >= 1 && w <= 8) c->wgs_per_cu = w;
+    }
+    if (!rc) {
+        const char *v = std::getenv("PROT_DEBUG_ROUND_TIMES");
+        if (v && v[0] == '1') rc = dev_alloc(c, &c->rtime, (size_t)3 * prot::kRoundTimeCap);
+    }
     if (rc) {
         prot_ctx_destroy(c);
         return rc;
@@ -341,6 +355,7 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->part_c);
     (void)hipFree(c->kmat);
     (void)hipFree(c->th);
+    (void)hipFree(c->rtime);
     if (c->stage) (void)hipHostFree(c->stage);
     for (int i = 0; i < 5; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -376,7 +391,7 @@ int64_t prot_max_n(prot_ctx *c)
     for (int64_t n = 4096; n <= (1 << 20); n += 4096) {
         const int n_pad = (int)round_up(n, 8);
         int gm = 0;
-        if (prot::loop_grid(n_pad, &gm) != hipSuccess || gm <= 0) break;
+        if (prot::loop_grid(n_pad, c->wgs_per_cu, &gm) != hipSuccess || gm <= 0) break;
         if ((n + 64 * 8 - 1) / (64 * 8) > gm) break;
         best = n;
     }
@@ -511,6 +526,25 @@ int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, in
     fill_match_counts(c, n, st, o);
     if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");
     return st->status;
+}
+
+int64_t prot_get_round_times(prot_ctx *c, int64_t *out, int64_t cap)
+{
+    if (!c || !out || cap < 0) return PROT_E_ARG;
+    if (!c->rtime) return 0;
+    Ctl h;
+    if (hipMemcpyAsync(&c->stage->ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return PROT_E_HIP;
+    h = c->stage->ctl;
+    (void)h;
+    int64_t m = cap < prot::kRoundTimeCap ? cap : prot::kRoundTimeCap;
+    if (hipMemcpyAsync(out, c->rtime, sizeof(int64_t) * 3 * (size_t)m, hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return PROT_E_HIP;
+    return m;
 }
 
 int64_t prot_get_trace(prot_ctx *c, int64_t *out, int64_t cap)

@@ -82,23 +82,42 @@ __device__ inline float sqdist(const float *__restrict__ x, const float *__restr
     return s;
 }
 
-// Pass 1: m = max over all pairs of the binary32 squared distance.
+// Pass 1: m = max over all pairs of the binary32 squared distance. Block =
+// 256 columns x kMaxRows rows; the rows' coordinates are staged in LDS.
+constexpr int kMaxRows = 256;
+constexpr int kMaxD = 16;   // coordinates staged per row (larger d: read from memory)
+
 template <int D>
 __global__ void __launch_bounds__(kBuildThreads)
 points_max_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_t n,
                   int32_t d, Ctl *ctl)
 {
+    __shared__ float xs[kMaxRows * kMaxD];
     __shared__ float red[kBuildThreads / 64];
     const int64_t a = (int64_t)blockIdx.x * kBuildThreads + threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.y * kMaxRows;
+    const int rows = (int)min<int64_t>(kMaxRows, n - b0);
+    const bool staged = D > 0 || d <= kMaxD;
+    const int dd = D > 0 ? D : d;
+    if (staged)
+        for (int i = threadIdx.x; i < rows * dd; i += kBuildThreads) xs[i] = X[b0 * dd + i];
+    __syncthreads();
     float mx = 0.0f;
     bool bad = false;
     if (a < n) {
-        const float *y = Y + a * d;
-        const int64_t b_end = min<int64_t>(n, ((int64_t)blockIdx.y + 1) * 64);
-        for (int64_t b = (int64_t)blockIdx.y * 64; b < b_end; ++b) {
-            const float s = sqdist<D>(X + b * d, y, d);
-            bad |= !(s <= FLT_MAX);
-            mx = fmaxf(mx, s);
+        const float *y = Y + a * dd;
+        if (staged) {
+            for (int r = 0; r < rows; ++r) {
+                const float s = sqdist<D>(xs + r * dd, y, dd);
+                bad |= !(s <= FLT_MAX);
+                mx = fmaxf(mx, s);
+            }
+        } else {
+            for (int r = 0; r < rows; ++r) {
+                const float s = sqdist<D>(X + (b0 + r) * dd, y, dd);
+                bad |= !(s <= FLT_MAX);
+                mx = fmaxf(mx, s);
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
@@ -140,40 +159,95 @@ __global__ void thresholds_kernel(double eps, Ctl *ctl, float *th, int32_t kcap)
     th[j] = __uint_as_float(lo);
 }
 
-// Pass 2: k for every pair, 8 consecutive columns per thread, a few rows per
-// block; padding columns (n <= col < ldk) get 0x7FFF.
+// k for one entry. v = s * inv in binary32 is within (K + 2) * 2^-22 of the
+// exact s / (m eps) (inv and the product are each rounded once; the exact
+// value is <= K + 1), and the binary64 definition is within 1e-10 of it. So
+// when v is at least delta away from every integer, floor(v) is the
+// definition's k; otherwise the threshold table decides.
+__device__ inline int fast_k(float s, float inv, float delta, int K, bool &exact)
+{
+    const float v = __fmul_rn(s, inv);
+    int g = (int)fminf(v, (float)K);
+    g = g < 0 ? 0 : g;
+    const float f = __fsub_rn(v, (float)g);
+    exact = f >= delta && f <= 1.0f - delta && v < (float)K;
+    return g;
+}
+
+__device__ inline int refine_k(float s, int g, int K, const float *__restrict__ th)
+{
+    while (g < K && s >= th[g + 1]) ++g;
+    while (g > 0 && s < th[g]) --g;
+    return g;
+}
+
+// Pass 2: k for every pair, 8 consecutive columns per thread (their points
+// held in registers), kRowsPerBlock rows per block (coordinates in LDS);
+// padding columns (n <= col < ldk) get 0x7FFF.
 template <int D>
 __global__ void __launch_bounds__(kBuildThreads)
 points_k_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_t n,
                 int32_t d, double eps, int16_t *__restrict__ k, int64_t ldk,
                 const float *__restrict__ th, const Ctl *ctl)
 {
+    constexpr int DR = D > 0 ? D : 1;
+    __shared__ float xs[kRowsPerBlock * kMaxD];
     const int64_t col0 = ((int64_t)blockIdx.x * kBuildThreads + threadIdx.x) * kColsPerThread;
+    const int64_t b0 = (int64_t)blockIdx.y * kRowsPerBlock;
+    const int rows = (int)min<int64_t>(kRowsPerBlock, n - b0);
+    const int dd = D > 0 ? D : d;
+    const bool staged = D > 0 || d <= kMaxD;
+    if (staged)
+        for (int i = threadIdx.x; i < rows * dd; i += kBuildThreads) xs[i] = X[b0 * dd + i];
+    __syncthreads();
     if (col0 >= ldk) return;
     const float mf = ctl->m;
     const int32_t K = ctl->kmax;
     const float inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * eps)) : 0.0f;
-    const int64_t b_end = min<int64_t>(n, ((int64_t)blockIdx.y + 1) * kRowsPerBlock);
-    for (int64_t b = (int64_t)blockIdx.y * kRowsPerBlock; b < b_end; ++b) {
-        const float *x = X + b * d;
-        uint32_t packed[kColsPerThread / 2];
+    const float delta = (float)(K + 2) * 4.8e-7f;   // > (K + 2) * 2^-22 with margin
+    float yv[kColsPerThread][DR];
+#pragma unroll
+    for (int e = 0; e < kColsPerThread; ++e)
+#pragma unroll
+        for (int j = 0; j < DR; ++j)
+            yv[e][j] = (D > 0 && col0 + e < n) ? Y[(col0 + e) * DR + j] : 0.0f;
+    for (int r = 0; r < rows; ++r) {
+        const float *x = staged ? xs + r * dd : X + (b0 + r) * dd;
+        float sv[kColsPerThread];
+        int g[kColsPerThread];
+        uint32_t slow = 0;
 #pragma unroll
         for (int e = 0; e < kColsPerThread; ++e) {
-            const int64_t col = col0 + e;
-            int v = 0x7FFF;
-            if (col < n) {
-                const float s = sqdist<D>(x, Y + col * d, d);
-                int g = (int)fminf(s * inv, (float)K);
-                g = g < 0 ? 0 : g;
-                while (g < K && s >= th[g + 1]) ++g;
-                while (g > 0 && s < th[g]) --g;
-                v = g;
+            float s;
+            if constexpr (D > 0) {
+                s = 0.0f;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const float t = __fsub_rn(x[j], yv[e][j]);
+                    s = __fmaf_rn(t, t, s);
+                }
+            } else {
+                s = col0 + e < n ? sqdist<0>(x, Y + (col0 + e) * dd, dd) : 0.0f;
             }
-            if (e & 1) packed[e >> 1] |= (uint32_t)(uint16_t)v << 16;
-            else packed[e >> 1] = (uint16_t)v;
+            bool ok;
+            g[e] = fast_k(s, inv, delta, K, ok);
+            sv[e] = s;
+            slow |= (uint32_t)!ok << e;
         }
-        *reinterpret_cast<uint4 *>(k + b * ldk + col0) =
-            make_uint4(packed[0], packed[1], packed[2], packed[3]);
+        if (slow) {
+#pragma unroll
+            for (int e = 0; e < kColsPerThread; ++e)
+                if ((slow >> e) & 1u) g[e] = refine_k(sv[e], g[e], K, th);
+        }
+#pragma unroll
+        for (int e = 0; e < kColsPerThread; ++e)
+            if (col0 + e >= n) g[e] = 0x7FFF;
+        uint4 w;
+        w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
+        w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);
+        w.z = (uint32_t)(uint16_t)g[4] | ((uint32_t)(uint16_t)g[5] << 16);
+        w.w = (uint32_t)(uint16_t)g[6] | ((uint32_t)(uint16_t)g[7] << 16);
+        *reinterpret_cast<uint4 *>(k + (b0 + r) * ldk + col0) = w;
     }
 }
 
@@ -197,7 +271,8 @@ hipError_t launch_build_points(const float *X, const float *Y, int64_t n, int32_
 {
     hipLaunchKernelGGL(build_reset_kernel, dim3(1), dim3(1), 0, s, ctl);
     if (n == 0) return hipGetLastError();
-    dim3 gmax((unsigned)((n + kBuildThreads - 1) / kBuildThreads), (unsigned)((n + 63) / 64));
+    dim3 gmax((unsigned)((n + kBuildThreads - 1) / kBuildThreads),
+              (unsigned)((n + kMaxRows - 1) / kMaxRows));
     if (d == 2)
         hipLaunchKernelGGL(points_max_kernel<2>, gmax, dim3(kBuildThreads), 0, s, X, Y, n, d, ctl);
     else if (d == 3)

@@ -6,33 +6,31 @@
 
 namespace prot {
 
-// Device-side control block of one phase loop. Zeroed by the init kernel.
-// Counters that are reused round after round (or phase after phase) live in
-// rings of three: the slot of round r is r % 3. A slot is cleared two rounds
-// before its next use, after every reader of its previous use has passed a
-// grid barrier (see the phase-loop kernel).
+// Device-side control block of one phase loop. Zeroed by the reset kernel.
+// Per-phase words live in a ring of three: the word of phase p is
+// pw[p % 3] and is cleared by the leader during phase p - 1, after every
+// reader of its previous use (phase p - 3) has passed a grid barrier.
 struct alignas(128) Ctl {
-    unsigned long long bar;      // grid-barrier arrivals (monotonic)
-    unsigned long long scanned;  // matrix entries examined
-    uint32_t prop_cnt[3];        // proposals made in round r
-    uint32_t dist_cnt[3];        // distinct columns first proposed to in round r
-    uint32_t f_cnt[3];           // |B'| of phase p
-    uint32_t l_cnt[3];           // columns taken in phase p
-    int32_t status;              // 0 finished, 1 stopped at max_phases
-    int32_t err;                 // bit 0: cost out of range / non-finite
+    unsigned long long arrive;    // this round: (arrivals << 32) | losers
+    unsigned long long flag;      // (round << 1) | 1 if the round ended the phase
+    unsigned long long pw[3];     // phase p: (|B'| of phase p+1 << 32) | columns taken
+    unsigned long long scanned;   // matrix entries examined
+    int32_t status;               // 0 finished, 1 stopped at max_phases
+    int32_t err;                  // bit 0: cost out of range / non-finite; bit 1: bad state
     int64_t phases;
     int64_t sum_free;
     int64_t rounds;
     int64_t max_rounds;
-    int64_t free_after;          // |free B| when the loop stopped
-    int32_t kmax;                // largest rounded cost produced by a cost build
+    int64_t free_after;           // |free B| when the loop stopped
+    int32_t kmax;                 // largest rounded cost produced by a cost build
     int32_t pad;
-    float m;                     // max squared distance of the last point build
+    float m;                      // max squared distance of the last point build
 };
 
-constexpr int kLoopThreads = 512;       // threads per workgroup of the loop
+constexpr int kLoopThreads = 1024;      // threads per workgroup of the loop
 constexpr int kTraceCap = 65536;        // phases recorded in the trace
 constexpr int kFinalizeBlocks = 256;    // partial sums of the finalize kernel
+constexpr int kRoundTimeCap = 65536;    // rounds recorded by the round timer
 
 struct LoopArgs {
     const int16_t *k;
@@ -50,6 +48,7 @@ struct LoopArgs {
     int32_t *L[2];            // columns taken in a phase (ping-pong)
     Ctl *ctl;
     int64_t *trace;           // 4 int64 per phase
+    int64_t *rtime;           // optional: 3 int64 per round (see kRoundTimeCap)
 };
 
 // cost.hip
@@ -66,7 +65,8 @@ hipError_t launch_clear_err(Ctl *ctl, hipStream_t s);
 hipError_t launch_check_state(int64_t n, const int32_t *mate_a, const int32_t *mate_b,
                               const int32_t *y_a, const int32_t *y_b, Ctl *ctl,
                               hipStream_t s);
-hipError_t loop_grid(int32_t n_pad, int *grid_max);
+hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max);
+hipError_t launch_clear_times(int64_t *rtime, hipStream_t s);
 hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s);
 hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a,
                          int32_t *mate_b, int32_t *y_a, int32_t *scratch,

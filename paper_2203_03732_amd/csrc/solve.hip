@@ -28,7 +28,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kChunk = kWave * 8;   // columns examined per wave per load
-constexpr int kPrefetch = 4;        // chunks in flight in a long scan
+constexpr int kPrefetch = 8;        // chunks in flight in a long scan
 
 template <class T>
 __device__ inline T ld_agent(const T *p)
@@ -44,21 +44,6 @@ template <class T>
 __device__ inline T add_agent(T *p, T v)
 {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// All workgroups of the (co-resident) grid meet here. Writes made before the
-// barrier by any workgroup are visible after it.
-__device__ inline void grid_sync(unsigned long long *bar, unsigned long long &target)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        target += gridDim.x;
-        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
-            __builtin_amdgcn_s_sleep(1);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
 }
 
 // bit e set iff lo <= col0 + e < hi, for e in [0, 8)
@@ -150,21 +135,20 @@ __device__ Hit scan_row(const int16_t *__restrict__ row, const uint16_t *t_lds, 
             base += kChunk;
         }
         while (base < shi) {
-            uint4 kv[kPrefetch], tv[kPrefetch];
+            // kPrefetch chunks of the row in flight; the duals come from LDS
+            uint4 kv[kPrefetch];
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) {
                 const int col0 = base + u * kChunk + lane * 8;
                 kv[u] = make_uint4(0u, 0u, 0u, 0u);
-                tv[u] = make_uint4(0u, 0u, 0u, 0u);
-                if (col0 < shi) {
-                    kv[u] = *reinterpret_cast<const uint4 *>(row + col0);
-                    tv[u] = *reinterpret_cast<const uint4 *>(t_lds + col0);
-                }
+                if (col0 < shi) kv[u] = *reinterpret_cast<const uint4 *>(row + col0);
             }
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) {
                 const int col0 = base + u * kChunk + lane * 8;
-                const int a = chunk_hit(col0, kv[u], tv[u], need, slo, shi, key, r0, r);
+                uint4 tv = make_uint4(0u, 0u, 0u, 0u);
+                if (col0 < shi) tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
+                const int a = chunk_hit(col0, kv[u], tv, need, slo, shi, key, r0, r);
                 if (a >= 0) return Hit{a >= origin ? a - origin : a - origin + n, a};
             }
             base += kPrefetch * kChunk;
@@ -176,43 +160,61 @@ __device__ Hit scan_row(const int16_t *__restrict__ row, const uint16_t *t_lds, 
 __global__ void loop_reset_kernel(LoopArgs a)
 {
     Ctl *c = a.ctl;
-    c->bar = 0;
+    c->arrive = 0;
+    c->flag = 0;
+    c->pw[0] = c->pw[1] = c->pw[2] = 0;
     c->scanned = 0;
-    for (int i = 0; i < 3; ++i) {
-        c->prop_cnt[i] = 0;
-        c->dist_cnt[i] = 0;
-        c->f_cnt[i] = 0;
-        c->l_cnt[i] = 0;
-    }
     c->status = 0;
     c->phases = c->sum_free = c->rounds = c->max_rounds = 0;
     c->free_after = 0;
     for (int i = 0; i < 4; ++i) a.trace[i] = 0;
 }
 
+__device__ inline uint32_t lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 // Initial state: y(b) = 1, y(a) = 0, M empty (Section 2.2), or a warm start.
+// The free list of the first phase goes to F[0]; its length to the high
+// half of pw[2] (the word read at the start of phase 0).
 __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
                             const int32_t *mate_b, const int32_t *y_a)
 {
     const int n = a.n;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_pad; i += gridDim.x * blockDim.x) {
-        if (i >= n) {
+    const int lane = threadIdx.x & 63;
+    for (int base = blockIdx.x * blockDim.x; base < a.n_pad; base += gridDim.x * blockDim.x) {
+        const int i = base + threadIdx.x;
+        bool is_free = false;
+        if (i < n) {
+            if (!warm) {
+                a.key[i] = 0ull;
+                a.t[i] = 0;
+                a.y_b[i] = 1;
+                a.F[0][i] = i;
+            } else {
+                const int32_t m = mate_a[i];
+                a.key[i] = m >= 0 ? (unsigned long long)(uint32_t)~(uint32_t)m : 0ull;
+                a.t[i] = (uint16_t)(-y_a[i]);
+                is_free = mate_b[i] < 0;
+            }
+        } else if (i < a.n_pad) {
             a.t[i] = 0;
-            continue;
         }
-        if (!warm) {
-            a.key[i] = 0ull;
-            a.t[i] = 0;
-            a.y_b[i] = 1;
-            a.F[0][i] = i;
-        } else {
-            const int32_t m = mate_a[i];
-            a.key[i] = m >= 0 ? (unsigned long long)(uint32_t)~(uint32_t)m : 0ull;
-            a.t[i] = (uint16_t)(-y_a[i]);
-            if (mate_b[i] < 0) a.F[0][add_agent(&a.ctl->f_cnt[0], 1u)] = i;
+        if (warm) {
+            const unsigned long long bal = __ballot(is_free);
+            if (bal) {
+                uint32_t at = 0;
+                if (lane == 0)
+                    at = (uint32_t)(add_agent(&a.ctl->pw[2],
+                                              (unsigned long long)__popcll(bal) << 32) >> 32);
+                at = __builtin_amdgcn_readfirstlane(at);
+                if (is_free) a.F[0][at + lanes_below(bal)] = i;
+            }
         }
     }
-    if (!warm && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->f_cnt[0] = (uint32_t)n;
+    if (!warm && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->pw[2] = (unsigned long long)n << 32;
 }
 
 // Warm-start check, O(n): the mate arrays form one matching and (I1) holds.
@@ -223,7 +225,7 @@ __global__ void check_state_kernel(int64_t n, const int32_t *mate_a, const int32
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t ma = mate_a[i], mb = mate_b[i];
-        if (ma >= n || mb >= n) bad = true;
+        if (ma >= n || mb >= n || ma < -1 || mb < -1) bad = true;
         else {
             if (ma >= 0 && mate_b[ma] != i) bad = true;
             if (mb >= 0 && mate_a[mb] != i) bad = true;
@@ -237,6 +239,10 @@ __global__ void check_state_kernel(int64_t n, const int32_t *mate_a, const int32
 __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
 {
     extern __shared__ __align__(16) uint16_t t_lds[];
+    __shared__ uint32_t s_n_i, s_nl, s_over;
+    __shared__ uint32_t s_cnt_l, s_cnt_f, s_losers;
+    __shared__ unsigned long long s_base, s_scan;
+
     const int lane = threadIdx.x & (kWave - 1);
     const int wpg = blockDim.x / kWave;
     const uint32_t W = gridDim.x * wpg;
@@ -244,23 +250,34 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
     Ctl *ctl = A.ctl;
     const int n = A.n;
-    unsigned long long bar_target = 0;
 
     for (int i = threadIdx.x; i < A.n_pad; i += blockDim.x) t_lds[i] = A.t[i];
+    if (threadIdx.x == 0) {
+        s_cnt_l = s_cnt_f = s_losers = 0;
+        s_scan = 0;
+    }
     __syncthreads();
 
-    uint32_t r = 0;        // id of the last round (keys carry it)
-    int64_t p = 0;         // phase index within this launch
-    int64_t phase_rounds = 0;
+    uint32_t r = 0;           // id of the last round (keys carry it)
+    int64_t p = 0;            // phase index within this launch
+    int64_t phase_rounds = 0; // leader only
+    uint32_t l_prev = 0;      // leader only
     for (;;) {
-        // Step (III a) of the previous phase, applied to this copy of y(a).
+        // |B'| of this phase and the columns taken in the previous one.
+        if (threadIdx.x == 0) {
+            const unsigned long long w = ld_agent(&ctl->pw[(p + 2) % 3]);
+            s_n_i = (uint32_t)(w >> 32);
+            s_nl = (uint32_t)w;
+        }
+        __syncthreads();
+        const uint32_t n_i = s_n_i;
         if (p > 0) {
-            const uint32_t nl = ld_agent(&ctl->l_cnt[(p - 1) % 3]);
+            // Step (III a) of the previous phase, applied to this copy of y(a).
+            const uint32_t nl = s_nl;
             const int32_t *Lp = A.L[(p - 1) & 1];
             for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) t_lds[Lp[i]] += 1;
-            __syncthreads();
         }
-        const uint32_t n_i = ld_agent(&ctl->f_cnt[p % 3]);
+        __syncthreads();
         if ((int64_t)n_i <= A.T) break;
         if (A.max_phases > 0 && p >= A.max_phases) {
             if (leader) ctl->status = 1;
@@ -269,19 +286,17 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
         if (leader) {
             ctl->phases = p + 1;
             ctl->sum_free += n_i;
-            st_agent(&ctl->f_cnt[(p + 2) % 3], 0u);
-            st_agent(&ctl->l_cnt[(p + 1) % 3], 0u);
+            st_agent(&ctl->pw[(p + 1) % 3], 0ull);
             if (p < kTraceCap) A.trace[4 * p] = n_i;
             if (p + 1 < kTraceCap)
                 for (int i = 0; i < 4; ++i) st_agent(&A.trace[4 * (p + 1) + i], (int64_t)0);
+            l_prev = 0;
         }
         const uint32_t r0 = r + 1;
         const int32_t *Fc = A.F[p & 1];
         int32_t *Fn = A.F[(p + 1) & 1];
         int32_t *Lc = A.L[p & 1];
-        uint32_t *fcnt_next = &ctl->f_cnt[(p + 1) % 3];
-        uint32_t *lcnt_cur = &ctl->l_cnt[p % 3];
-        int64_t *trace_scanned = p < kTraceCap ? &A.trace[4 * p + 2] : nullptr;
+        unsigned long long *pwc = &ctl->pw[p % 3];
 
         // Slot s of this wave is entry gw + s*W of B'; lane s holds its state.
         const uint32_t nslots = gw < n_i ? (n_i - gw + W - 1) / W : 0u;
@@ -292,15 +307,14 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
             s_yb = A.y_b[s_b];
         }
         unsigned long long active = __ballot((uint32_t)lane < nslots);
+        unsigned long long wave_scan = 0;
 
         for (;;) {
             r += 1;
-            if (leader) {
-                st_agent(&ctl->prop_cnt[(r + 1) % 3], 0u);
-                st_agent(&ctl->dist_cnt[(r + 1) % 3], 0u);
-            }
-            uint32_t n_prop = 0, n_dist = 0;
-            unsigned long long n_scan = 0;
+            unsigned long long s_old = 0;  // key a proposal of this lane's slot replaced
+            bool proposed = false;
+            int32_t my_f = -1;             // row this lane's slot puts on the next B'
+            uint32_t n_prop = 0;
             unsigned long long rem = active;
             while (rem) {
                 const int s = __builtin_ctzll(rem);
@@ -312,58 +326,110 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                 const Hit h = scan_row(A.k + (int64_t)b * A.ldk, t_lds, n, origin, pos, yb - 1,
                                        A.key, r0, r, lane);
                 if (h.j >= 0) {
-                    n_scan += (unsigned long long)(h.j - pos + 1);
+                    wave_scan += (unsigned long long)(h.j - pos + 1);
                     const unsigned long long kn =
                         ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
-                    if (lane == 0) {
-                        const unsigned long long old = __hip_atomic_fetch_max(
-                            A.key + h.a, kn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if ((uint32_t)(old >> 32) < r) {
-                            // first proposal to column a this round: a will be
-                            // matched in M' whoever wins, so (II) evicts its
-                            // old mate and (III a) will lower y(a).
-                            n_dist += 1;
-                            Lc[add_agent(lcnt_cur, 1u)] = h.a;
-                            if (old != 0ull)
-                                Fn[add_agent(fcnt_next, 1u)] = (int32_t)~(uint32_t)old;
-                        }
-                    }
-                    n_prop += 1;
                     if (lane == s) {
+                        // the slot's own lane proposes, so proposals of several
+                        // slots are in flight together
+                        s_old = __hip_atomic_fetch_max(A.key + h.a, kn, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                        proposed = true;
                         s_pos = h.j;
                         s_a = h.a;
                         s_key = kn;
                     }
+                    n_prop += 1;
                 } else {
                     // b has no admissible untaken column: free in M', (III b).
-                    n_scan += (unsigned long long)(n - pos);
-                    if (lane == 0) {
+                    wave_scan += (unsigned long long)(n - pos);
+                    if (lane == s) {
                         A.y_b[b] = yb + 1;
-                        Fn[add_agent(fcnt_next, 1u)] = b;
+                        my_f = b;
                     }
                     active &= ~(1ull << s);
                 }
             }
+            // The first proposal to a column in a round: the column is in M'
+            // whoever wins it, so step (II) evicts its old mate (if any) and
+            // the column joins this phase's taken list.
+            int32_t my_l = -1;
+            if (proposed && (uint32_t)(s_old >> 32) < r) {
+                my_l = s_a;
+                if (s_old != 0ull) my_f = (int32_t)~(uint32_t)s_old;
+            }
+            const unsigned long long bl = __ballot(my_l >= 0), bf = __ballot(my_f >= 0);
+            uint32_t off_l = 0, off_f = 0;
             if (lane == 0) {
-                if (n_prop) add_agent(&ctl->prop_cnt[r % 3], n_prop);
-                if (n_dist) add_agent(&ctl->dist_cnt[r % 3], n_dist);
-                if (n_scan) {
-                    add_agent(&ctl->scanned, n_scan);
-                    if (trace_scanned) add_agent(trace_scanned, (int64_t)n_scan);
+                const uint32_t nl = (uint32_t)__popcll(bl), nf = (uint32_t)__popcll(bf);
+                off_l = atomicAdd(&s_cnt_l, nl);
+                off_f = atomicAdd(&s_cnt_f, nf);
+                atomicAdd(&s_losers, n_prop - nl);
+            }
+            off_l = __builtin_amdgcn_readfirstlane(off_l);
+            off_f = __builtin_amdgcn_readfirstlane(off_f);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const uint32_t cl = s_cnt_l, cf = s_cnt_f;
+                unsigned long long base = 0;
+                if (cl | cf) base = add_agent(pwc, ((unsigned long long)cf << 32) | cl);
+                s_base = base;
+            }
+            __syncthreads();
+            {
+                const unsigned long long base = s_base;
+                if (my_l >= 0) Lc[(uint32_t)base + off_l + lanes_below(bl)] = my_l;
+                if (my_f >= 0) Fn[(uint32_t)(base >> 32) + off_f + lanes_below(bf)] = my_f;
+            }
+
+            // Grid barrier. The last workgroup to arrive adds up the losers of
+            // the round and publishes, with the release, whether the phase is
+            // over (no proposal lost: M' is maximal).
+            const bool timed = A.rtime != nullptr && r <= (uint32_t)kRoundTimeCap;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                if (timed)
+                    __hip_atomic_fetch_max(&A.rtime[3 * (r - 1)], (int64_t)wall_clock64(),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t losers = s_losers;
+                s_cnt_l = s_cnt_f = s_losers = 0;
+                const unsigned long long old = __hip_atomic_fetch_add(
+                    &ctl->arrive, (1ull << 32) | losers, __ATOMIC_RELEASE,
+                    __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t over;
+                if ((uint32_t)(old >> 32) + 1u == gridDim.x) {
+                    over = ((uint32_t)old + losers) == 0u;
+                    st_agent(&ctl->arrive, 0ull);
+                    __hip_atomic_store(&ctl->flag, ((unsigned long long)r << 1) | over,
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    unsigned long long f;
+                    while (((f = ld_agent(&ctl->flag)) >> 1) != (unsigned long long)r)
+                        __builtin_amdgcn_s_sleep(1);
+                    over = (uint32_t)(f & 1ull);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_over = over;
+                if (timed && leader) {
+                    A.rtime[3 * (r - 1) + 1] = (int64_t)wall_clock64();
+                    A.rtime[3 * (r - 1) + 2] = p;
                 }
             }
-            grid_sync(&ctl->bar, bar_target);
-            const uint32_t P = ld_agent(&ctl->prop_cnt[r % 3]);
-            const uint32_t D = ld_agent(&ctl->dist_cnt[r % 3]);
-            if (leader && P > 0) {
-                ctl->rounds += 1;
-                phase_rounds += 1;
-                if (p < kTraceCap) {
-                    A.trace[4 * p + 1] += 1;
-                    A.trace[4 * p + 3] += D;
+            __syncthreads();
+            const bool over = s_over != 0u;
+            if (leader) {
+                const uint32_t l_now = (uint32_t)ld_agent(pwc);
+                if (l_now > l_prev) {  // some proposal was made this round
+                    ctl->rounds += 1;
+                    phase_rounds += 1;
+                    if (p < kTraceCap) {
+                        A.trace[4 * p + 1] += 1;
+                        A.trace[4 * p + 3] = l_now;
+                    }
                 }
+                l_prev = l_now;
             }
-            if (P == 0u || P == D) break;  // nobody lost a proposal: M' is maximal
+            if (over) break;
             bool mine = (active >> lane) & 1ull;
             if (mine) {
                 if (ld_agent(A.key + s_a) == s_key) mine = false;  // won: matched in M'
@@ -371,18 +437,36 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
             }
             active = __ballot(mine);
         }
+        // entries examined this phase, one atomic per workgroup
+        if (lane == 0 && wave_scan) atomicAdd(&s_scan, wave_scan);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long sc = s_scan;
+            s_scan = 0;
+            if (sc) {
+                add_agent(&ctl->scanned, sc);
+                if (p < kTraceCap) add_agent(&A.trace[4 * p + 2], (int64_t)sc);
+            }
+        }
         if (leader) {
             if (phase_rounds > ctl->max_rounds) ctl->max_rounds = phase_rounds;
             phase_rounds = 0;
         }
         p += 1;
     }
-    if (leader) ctl->free_after = ld_agent(&ctl->f_cnt[p % 3]);
+    if (leader) ctl->free_after = s_n_i;
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < n; i += blockDim.x) A.t[i] = t_lds[i];
 }
 
 __global__ void clear_err_kernel(Ctl *ctl) { ctl->err = 0; }
+
+__global__ void fill64_kernel(int64_t *p, int64_t n, int64_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
 
 __global__ void fill_kernel(int32_t *p, int64_t n, int32_t v)
 {
@@ -523,7 +607,14 @@ hipError_t launch_check_state(int64_t n, const int32_t *mate_a, const int32_t *m
     return hipGetLastError();
 }
 
-hipError_t loop_grid(int32_t n_pad, int *grid_max)
+hipError_t launch_clear_times(int64_t *rtime, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill64_kernel, dim3(256), dim3(256), 0, s, rtime,
+                       (int64_t)3 * kRoundTimeCap, (int64_t)0);
+    return hipGetLastError();
+}
+
+hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max)
 {
     const size_t lds = (size_t)n_pad * sizeof(uint16_t);
     hipError_t e = hipSuccess;
@@ -540,7 +631,7 @@ hipError_t loop_grid(int32_t n_pad, int *grid_max)
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    if (per_cu > 2) per_cu = 2;
+    if (per_cu > wgs_per_cu) per_cu = wgs_per_cu;
     *grid_max = per_cu * cus;
     return hipSuccess;
 }
