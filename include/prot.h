@@ -150,6 +150,55 @@ int prot_solve_points(prot_ctx *ctx, const float *X, const float *Y,
                       int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
                       int32_t *y_b, prot_stats *stats);
 
+/* ---- Batches of independent instances (minibatch optimal transport) ---- */
+
+/* Per-instance results of a batched solve. */
+typedef struct {
+    int64_t phases, sum_free, rounds, max_rounds, scanned, matched_in_phases,
+        completed_pairs, sum_k, threshold;
+    int32_t status;            /* PROT_OK or PROT_PARTIAL */
+    int32_t kmax;
+    double cost;               /* sum over the matching of d2 / m, binary64 */
+    double cost_scale;         /* m, the instance's max squared distance */
+} prot_instance_stats;
+
+typedef struct prot_batch prot_batch;
+
+/* Largest n of one instance in a batch. */
+int32_t prot_batch_max_n(void);
+
+/* Plan a batch of `batch` independent point-set instances (squared Euclidean
+ * cost scaled per instance to max 1, eq. (1) rounding, the phase loop of
+ * Section 2.2, the completion). Instance i has n_host[i] points
+ * (1 <= n_host[i] <= prot_batch_max_n()) stored in rows [o_i, o_i + n_host[i])
+ * of X and Y (float32, d columns) and of every output array, with
+ * o_i = n_host[0] + ... + n_host[i-1]; output mates are indices local to the
+ * instance. n_host is a host array read during the call. The plan owns its
+ * device workspace (metadata, one rounded-cost matrix per instance). */
+int prot_batch_create(prot_ctx *ctx, int32_t batch, const int64_t *n_host, int32_t d,
+                      double eps, const prot_opts *opts, prot_batch **out);
+int prot_batch_destroy(prot_batch *plan);
+
+/* Enqueue the whole batched solve on the context stream; no synchronisation.
+ * stats: device array of `batch` entries, or NULL. */
+int prot_batch_run(prot_batch *plan, const float *X, const float *Y, int32_t *mate_a,
+                   int32_t *mate_b, int32_t *y_a, int32_t *y_b, prot_instance_stats *stats);
+
+/* Capture the work of prot_batch_run with these pointers into a HIP graph
+ * (replacing any earlier capture of this plan), and replay it on the
+ * context stream. The pointers must stay valid while the graph is used. */
+int prot_batch_capture(prot_batch *plan, const float *X, const float *Y, int32_t *mate_a,
+                       int32_t *mate_b, int32_t *y_a, int32_t *y_b, prot_instance_stats *stats);
+int prot_batch_replay(prot_batch *plan);
+
+/* Convenience: plan, run, synchronise, copy the per-instance statistics to
+ * stats_host (host array of `batch` entries, may be NULL), free the plan.
+ * Returns PROT_E_RANGE if a coordinate is not finite. */
+int prot_solve_batched_points(prot_ctx *ctx, int32_t batch, const int64_t *n_host, int32_t d,
+                              const float *X, const float *Y, double eps,
+                              const prot_opts *opts, int32_t *mate_a, int32_t *mate_b,
+                              int32_t *y_a, int32_t *y_b, prot_instance_stats *stats_host);
+
 /* Per-phase record of the last phase loop on this context: for phase i,
  * out[4i..4i+3] = (|B'|, rounds, scanned entries, |M'|). Copies at most cap
  * phases and returns the number of phases recorded (<= the trace capacity,

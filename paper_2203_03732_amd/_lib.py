@@ -45,13 +45,33 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class InstanceStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "phases", "sum_free", "rounds", "max_rounds", "scanned", "matched_in_phases",
+        "completed_pairs", "sum_k", "threshold")] + [
+        ("status", ctypes.c_int32), ("kmax", ctypes.c_int32), ("cost", ctypes.c_double),
+        ("cost_scale", ctypes.c_double)]
+
+
+def instance_stats_from_bytes(buf) -> list[dict]:
+    """Decode a byte buffer of prot_instance_stats records."""
+    size = ctypes.sizeof(InstanceStats)
+    raw = bytes(buf)
+    out = []
+    for i in range(len(raw) // size):
+        rec = InstanceStats.from_buffer_copy(raw[i * size:(i + 1) * size])
+        out.append({name: getattr(rec, name) for name, _ in InstanceStats._fields_})
+    return out
+
+
 _lib = None
 
 EXPORTS = [
     "prot_ctx_create", "prot_ctx_destroy", "prot_set_stream", "prot_reserve", "prot_pitch",
     "prot_threshold", "prot_max_n", "prot_round_costs", "prot_build_costs",
     "prot_solve_rounded", "prot_solve_cost", "prot_solve_points", "prot_get_trace",
-    "prot_get_round_times",
+    "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
+    "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
     "prot_status_string", "prot_last_error",
 ]
 
@@ -85,6 +105,15 @@ def load():
                                              p, p, p, p, ctypes.POINTER(Stats)]),
         "prot_get_trace": (i64, [p, p, i64]),
         "prot_get_round_times": (i64, [p, p, i64]),
+        "prot_batch_max_n": (i32, []),
+        "prot_batch_create": (ctypes.c_int, [p, i32, p, i32, f64, ctypes.POINTER(Opts),
+                                             ctypes.POINTER(p)]),
+        "prot_batch_destroy": (ctypes.c_int, [p]),
+        "prot_batch_run": (ctypes.c_int, [p, p, p, p, p, p, p, p]),
+        "prot_batch_capture": (ctypes.c_int, [p, p, p, p, p, p, p, p]),
+        "prot_batch_replay": (ctypes.c_int, [p]),
+        "prot_solve_batched_points": (ctypes.c_int, [p, i32, p, i32, p, p, f64,
+                                                     ctypes.POINTER(Opts), p, p, p, p, p]),
         "prot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "prot_last_error": (ctypes.c_char_p, [p]),
     }
@@ -291,6 +320,35 @@ class Context:
         buf = buf[:m]
         return buf[buf[:, 1] != 0].copy()
 
+    def batch(self, ns, d: int, eps: float, *, eps_mode="algorithmic", origin="diag",
+              complete=True, max_phases=0) -> "Batch":
+        return Batch(self, ns, d, eps, eps_mode=eps_mode, origin=origin, complete=complete,
+                     max_phases=max_phases)
+
+    def solve_batched_points(self, ns, X, Y, eps: float, *, eps_mode="algorithmic",
+                             origin="diag", complete=True, max_phases=0):
+        """Instances packed row-wise: instance i is rows [o_i, o_i + ns[i]) of X
+        and Y. Returns (mate_a, mate_b, y_a, y_b, per-instance stats list)."""
+        import numpy as np
+        torch = _torch()
+        ns_arr = np.ascontiguousarray(np.asarray(ns, dtype=np.int64))
+        total = int(ns_arr.sum())
+        if X.shape[0] != total or Y.shape != X.shape or not X.is_contiguous() or not Y.is_contiguous():
+            raise ValueError("X and Y must be contiguous (sum(ns), d) float32")
+        d = X.shape[1]
+        mate_a, mate_b, y_a, y_b = self._outputs(total)
+        st = (InstanceStats * len(ns_arr))()
+        o = self._opts(eps_mode, origin, complete, max_phases)
+        self._bind_stream()
+        self._check(self._lib.prot_solve_batched_points(
+            self._h, len(ns_arr), ns_arr.ctypes.data_as(ctypes.c_void_p), d,
+            _dev_ptr(X, torch.float32, "X", 2), _dev_ptr(Y, torch.float32, "Y", 2), float(eps),
+            ctypes.byref(o), _dev_ptr(mate_a, torch.int32, "mate_a"),
+            _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
+            _dev_ptr(y_b, torch.int32, "y_b"), ctypes.cast(st, ctypes.c_void_p)))
+        stats = [{name: getattr(r, name) for name, _ in InstanceStats._fields_} for r in st]
+        return mate_a, mate_b, y_a, y_b, stats
+
     def trace(self, cap: int = 65536):
         import numpy as np
         buf = np.zeros((cap, 4), np.int64)
@@ -298,6 +356,66 @@ class Context:
         if m < 0:
             raise ProtError(m, "prot_get_trace failed")
         return buf[:m].copy()
+
+
+class Batch:
+    """A planned batch of point-set instances (prot_batch_*): run it directly,
+    or capture it once into a HIP graph and replay it."""
+
+    def __init__(self, ctx: Context, ns, d: int, eps: float, **kw):
+        import numpy as np
+        self.ctx = ctx
+        self.ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int64))
+        self.total = int(self.ns.sum())
+        self.d = int(d)
+        h = ctypes.c_void_p()
+        o = Context._opts(kw.get("eps_mode", "algorithmic"), kw.get("origin", "diag"),
+                          kw.get("complete", True), kw.get("max_phases", 0))
+        ctx._check(ctx._lib.prot_batch_create(ctx._h, len(self.ns),
+                                              self.ns.ctypes.data_as(ctypes.c_void_p), self.d,
+                                              float(eps), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        torch = _torch()
+        self.mate_a, self.mate_b, self.y_a, self.y_b = ctx._outputs(self.total)
+        self.stats_dev = torch.zeros(len(self.ns) * ctypes.sizeof(InstanceStats),
+                                     dtype=torch.uint8, device=f"cuda:{ctx.device}")
+
+    def _ptrs(self, X, Y):
+        torch = _torch()
+        if X.shape != (self.total, self.d) or Y.shape != X.shape or not X.is_contiguous() \
+                or not Y.is_contiguous():
+            raise ValueError("X and Y must be contiguous (sum(ns), d) float32")
+        return (_dev_ptr(X, torch.float32, "X", 2), _dev_ptr(Y, torch.float32, "Y", 2),
+                _dev_ptr(self.mate_a, torch.int32, "mate_a"),
+                _dev_ptr(self.mate_b, torch.int32, "mate_b"),
+                _dev_ptr(self.y_a, torch.int32, "y_a"), _dev_ptr(self.y_b, torch.int32, "y_b"),
+                ctypes.c_void_p(self.stats_dev.data_ptr()))
+
+    def run(self, X, Y):
+        self.ctx._bind_stream()
+        self.ctx._check(self.ctx._lib.prot_batch_run(self._h, *self._ptrs(X, Y)))
+
+    def capture(self, X, Y):
+        self.ctx._bind_stream()
+        self.ctx._check(self.ctx._lib.prot_batch_capture(self._h, *self._ptrs(X, Y)))
+
+    def replay(self):
+        self.ctx._bind_stream()
+        self.ctx._check(self.ctx._lib.prot_batch_replay(self._h))
+
+    def stats(self) -> list[dict]:
+        return instance_stats_from_bytes(self.stats_dev.cpu().numpy().tobytes())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.prot_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default: dict[int, Context] = {}

@@ -13,7 +13,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "../../include/prot.h"
 #include "internal.h"
@@ -167,6 +169,27 @@ int grid_for(prot_ctx *c, int64_t n, int *grid)
     return PROT_OK;
 }
 
+// Single-instance point build into k (thresholds in the context workspace).
+prot::PointsJob points_job(prot_ctx *c, const float *X, const float *Y, int64_t n, int32_t d,
+                           double eps, int16_t *k, int64_t ldk)
+{
+    prot::PointsJob j{};
+    j.X = X;
+    j.Y = Y;
+    j.n_single = n;
+    j.ldk_single = ldk;
+    j.d = d;
+    j.batch = 1;
+    j.eps = eps;
+    j.k = k;
+    j.m = &c->ctl->m;
+    j.th = c->th;
+    j.kcap = (int32_t)std::floor(1.0 / eps) + 2;
+    j.err = &c->ctl->err;
+    j.kmax_out = &c->ctl->kmax;
+    return j;
+}
+
 prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
                          const prot_opts *o, int32_t *y_b)
 {
@@ -277,6 +300,94 @@ void fill_match_counts(prot_ctx *c, int64_t n, prot_stats *st, const prot_opts *
 }
 
 }  // namespace
+
+struct prot_batch {
+    prot_ctx *ctx = nullptr;
+    int32_t batch = 0, d = 0, n_max = 0;
+    int64_t ldk_max = 0;
+    double eps = 0.0;
+    prot_opts opts{};
+    int grid = 1;
+    int32_t *order = nullptr, *n_arr = nullptr, *ldk_arr = nullptr;
+    int64_t *pt_off = nullptr, *k_off = nullptr;
+    int16_t *k = nullptr;
+    float *m = nullptr, *th = nullptr;
+    int32_t kcap = 0;
+    int32_t *err = nullptr;
+    unsigned int *queue = nullptr;
+    prot_instance_stats *stats_tmp = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+template <class T>
+int upload(prot_ctx *c, T **dst, const std::vector<T> &src)
+{
+    int rc = dev_alloc(c, dst, src.size());
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PROT_OK;
+}
+
+int batch_enqueue(prot_batch *bp, hipStream_t s, const float *X, const float *Y, int32_t *mate_a,
+                  int32_t *mate_b, int32_t *y_a, int32_t *y_b, prot_instance_stats *stats)
+{
+    prot_ctx *c = bp->ctx;
+    prot::PointsJob j{};
+    j.X = X;
+    j.Y = Y;
+    j.pt_off = bp->pt_off;
+    j.n_arr = bp->n_arr;
+    j.k_off = bp->k_off;
+    j.ldk_arr = bp->ldk_arr;
+    j.d = bp->d;
+    j.batch = bp->batch;
+    j.eps = bp->eps;
+    j.k = bp->k;
+    j.m = bp->m;
+    j.th = bp->th;
+    j.kcap = bp->kcap;
+    j.err = bp->err;
+    HIP_TRY(c, prot::launch_points(j, bp->n_max, bp->ldk_max, s));
+    prot::BatchArgs a{};
+    a.batch = bp->batch;
+    a.d = bp->d;
+    a.eps = bp->eps;
+    a.max_phases = bp->opts.max_phases;
+    a.origin = bp->opts.origin_mode == PROT_ORIGIN_ZERO ? 1 : 0;
+    a.complete = bp->opts.no_completion ? 0 : 1;
+    a.order = bp->order;
+    a.n_arr = bp->n_arr;
+    a.ldk_arr = bp->ldk_arr;
+    a.pt_off = bp->pt_off;
+    a.k_off = bp->k_off;
+    a.k = bp->k;
+    a.X = X;
+    a.Y = Y;
+    a.m = bp->m;
+    a.mate_a = mate_a;
+    a.mate_b = mate_b;
+    a.y_a = y_a;
+    a.y_b = y_b;
+    a.stats = reinterpret_cast<prot::InstanceStats *>(stats ? stats : bp->stats_tmp);
+    a.queue = bp->queue;
+    HIP_TRY(c, prot::launch_batch_solve(a, bp->n_max, bp->grid, s));
+    return PROT_OK;
+}
+
+bool batch_args_ok(const prot_batch *bp, const float *X, const float *Y, const int32_t *mate_a,
+                   const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b)
+{
+    return bp && X && Y && mate_a && mate_b && y_a && y_b;
+}
+
+}  // namespace
+
+static_assert(sizeof(prot_instance_stats) == sizeof(prot::InstanceStats),
+              "prot_instance_stats and InstanceStats must match");
 
 extern "C" {
 
@@ -424,8 +535,10 @@ int prot_build_costs(prot_ctx *c, const float *X, const float *Y, int64_t n, int
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = ensure_thresholds(c, eps);
     if (rc) return rc;
-    HIP_TRY(c, prot::launch_build_points(X, Y, n, d, eps, k, ldk, m_out, c->th, c->ctl,
-                                         c->stream));
+    HIP_TRY(c, prot::launch_points(points_job(c, X, Y, n, d, eps, k, ldk), n, ldk, c->stream));
+    if (m_out)
+        HIP_TRY(c, hipMemcpyAsync(m_out, &c->ctl->m, sizeof(float), hipMemcpyDeviceToDevice,
+                                  c->stream));
     HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl.err, &c->ctl->err, sizeof(int32_t),
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -513,8 +626,8 @@ int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, in
     if (!rc) rc = ensure_thresholds(c, ei);
     if (rc) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(c, prot::launch_build_points(X, Y, n, d, ei, c->kmat, ldk, nullptr, c->th, c->ctl,
-                                         c->stream));
+    HIP_TRY(c, prot::launch_points(points_job(c, X, Y, n, d, ei, c->kmat, ldk), n, ldk,
+                                   c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     rc = run_loop(c, c->kmat, n, ldk, T, o, 0, mate_a, mate_b, y_a, y_b);
     if (rc) return rc;
@@ -526,6 +639,180 @@ int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, in
     fill_match_counts(c, n, st, o);
     if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");
     return st->status;
+}
+
+
+int32_t prot_batch_max_n(void) { return prot::batch_max_n(); }
+
+int prot_batch_create(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t d, double eps,
+                      const prot_opts *o, prot_batch **out)
+{
+    if (!c) return PROT_E_ARG;
+    if (!out || batch < 0 || (batch > 0 && !n_host) || d < 1)
+        return fail(c, PROT_E_ARG, "prot_batch_create: bad arguments");
+    *out = nullptr;
+    const double ei = eps_internal(eps, o);
+    if (!eps_valid(ei)) return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    HIP_TRY(c, hipSetDevice(c->device));
+    std::vector<int32_t> n_arr(batch), ldk(batch), order(batch);
+    std::vector<int64_t> pt_off(batch), k_off(batch);
+    int64_t pts = 0, kel = 0;
+    int32_t n_max = 0;
+    int64_t ldk_max = 0;
+    for (int32_t i = 0; i < batch; ++i) {
+        if (n_host[i] < 1 || n_host[i] > prot::batch_max_n())
+            return fail(c, PROT_E_UNSUPPORTED, "instance %d: n=%lld outside [1, %d]", i,
+                        (long long)n_host[i], prot::batch_max_n());
+        n_arr[i] = (int32_t)n_host[i];
+        ldk[i] = (int32_t)round_up(n_host[i], 64);
+        pt_off[i] = pts;
+        k_off[i] = kel;
+        pts += n_host[i];
+        kel += n_host[i] * ldk[i];
+        if (n_arr[i] > n_max) n_max = n_arr[i];
+        if (ldk[i] > ldk_max) ldk_max = ldk[i];
+        order[i] = i;
+    }
+    // largest instances first, so the queue ends with short ones
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return n_arr[a] > n_arr[b]; });
+    prot_batch *bp = new (std::nothrow) prot_batch();
+    if (!bp) return PROT_E_NOMEM;
+    bp->ctx = c;
+    bp->batch = batch;
+    bp->d = d;
+    bp->n_max = n_max;
+    bp->ldk_max = ldk_max;
+    bp->eps = ei;
+    if (o) bp->opts = *o;
+    bp->kcap = (int32_t)std::floor(1.0 / ei) + 2;
+    int rc = PROT_OK;
+    if (batch > 0) {
+        if (!rc) rc = upload(c, &bp->order, order);
+        if (!rc) rc = upload(c, &bp->n_arr, n_arr);
+        if (!rc) rc = upload(c, &bp->ldk_arr, ldk);
+        if (!rc) rc = upload(c, &bp->pt_off, pt_off);
+        if (!rc) rc = upload(c, &bp->k_off, k_off);
+        if (!rc) rc = dev_alloc(c, &bp->k, (size_t)kel);
+        if (!rc) rc = dev_alloc(c, &bp->m, (size_t)batch);
+        if (!rc) rc = dev_alloc(c, &bp->th, (size_t)batch * bp->kcap);
+        if (!rc) rc = dev_alloc(c, &bp->stats_tmp, (size_t)batch);
+        if (!rc) {
+            hipError_t e = prot::batch_grid(n_max, batch, &bp->grid);
+            if (e != hipSuccess) rc = hip_fail(c, e, "batch occupancy");
+        }
+    }
+    if (!rc) rc = dev_alloc(c, &bp->err, 1);
+    if (!rc) rc = dev_alloc(c, &bp->queue, 1);
+    if (rc) {
+        prot_batch_destroy(bp);
+        return rc;
+    }
+    *out = bp;
+    return PROT_OK;
+}
+
+int prot_batch_destroy(prot_batch *bp)
+{
+    if (!bp) return PROT_E_ARG;
+    if (bp->ctx) (void)hipSetDevice(bp->ctx->device);
+    if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
+    if (bp->graph) (void)hipGraphDestroy(bp->graph);
+    if (bp->cap_stream) (void)hipStreamDestroy(bp->cap_stream);
+    (void)hipFree(bp->order);
+    (void)hipFree(bp->n_arr);
+    (void)hipFree(bp->ldk_arr);
+    (void)hipFree(bp->pt_off);
+    (void)hipFree(bp->k_off);
+    (void)hipFree(bp->k);
+    (void)hipFree(bp->m);
+    (void)hipFree(bp->th);
+    (void)hipFree(bp->err);
+    (void)hipFree(bp->queue);
+    (void)hipFree(bp->stats_tmp);
+    delete bp;
+    return PROT_OK;
+}
+
+int prot_batch_run(prot_batch *bp, const float *X, const float *Y, int32_t *mate_a,
+                   int32_t *mate_b, int32_t *y_a, int32_t *y_b, prot_instance_stats *stats)
+{
+    if (!bp) return PROT_E_ARG;
+    prot_ctx *c = bp->ctx;
+    if (bp->batch == 0) return PROT_OK;
+    if (!batch_args_ok(bp, X, Y, mate_a, mate_b, y_a, y_b))
+        return fail(c, PROT_E_ARG, "prot_batch_run: null pointer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return batch_enqueue(bp, c->stream, X, Y, mate_a, mate_b, y_a, y_b, stats);
+}
+
+int prot_batch_capture(prot_batch *bp, const float *X, const float *Y, int32_t *mate_a,
+                       int32_t *mate_b, int32_t *y_a, int32_t *y_b, prot_instance_stats *stats)
+{
+    if (!bp) return PROT_E_ARG;
+    prot_ctx *c = bp->ctx;
+    if (bp->batch == 0) return PROT_OK;
+    if (!batch_args_ok(bp, X, Y, mate_a, mate_b, y_a, y_b))
+        return fail(c, PROT_E_ARG, "prot_batch_capture: null pointer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (!bp->cap_stream)
+        HIP_TRY(c, hipStreamCreateWithFlags(&bp->cap_stream, hipStreamNonBlocking));
+    if (bp->exec) {
+        (void)hipGraphExecDestroy(bp->exec);
+        bp->exec = nullptr;
+    }
+    if (bp->graph) {
+        (void)hipGraphDestroy(bp->graph);
+        bp->graph = nullptr;
+    }
+    HIP_TRY(c, hipStreamBeginCapture(bp->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_enqueue(bp, bp->cap_stream, X, Y, mate_a, mate_b, y_a, y_b, stats);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(bp->cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    bp->graph = g;
+    HIP_TRY(c, hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0));
+    return PROT_OK;
+}
+
+int prot_batch_replay(prot_batch *bp)
+{
+    if (!bp) return PROT_E_ARG;
+    prot_ctx *c = bp->ctx;
+    if (bp->batch == 0) return PROT_OK;
+    if (!bp->exec) return fail(c, PROT_E_ARG, "prot_batch_replay: nothing captured");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipGraphLaunch(bp->exec, c->stream));
+    return PROT_OK;
+}
+
+int prot_solve_batched_points(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t d,
+                              const float *X, const float *Y, double eps, const prot_opts *o,
+                              int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,
+                              prot_instance_stats *stats_host)
+{
+    if (!c) return PROT_E_ARG;
+    prot_batch *bp = nullptr;
+    int rc = prot_batch_create(c, batch, n_host, d, eps, o, &bp);
+    if (rc) return rc;
+    rc = prot_batch_run(bp, X, Y, mate_a, mate_b, y_a, y_b, nullptr);
+    int32_t err = 0;
+    if (!rc && batch > 0) {
+        hipError_t e = hipMemcpyAsync(&err, bp->err, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      c->stream);
+        if (e == hipSuccess && stats_host)
+            e = hipMemcpyAsync(stats_host, bp->stats_tmp, sizeof(prot_instance_stats) * batch,
+                               hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = hip_fail(c, e, "batched solve");
+    }
+    prot_batch_destroy(bp);
+    if (!rc && (err & 1)) rc = fail(c, PROT_E_RANGE, "a point coordinate is not finite");
+    return rc;
 }
 
 int64_t prot_get_round_times(prot_ctx *c, int64_t *out, int64_t cap)

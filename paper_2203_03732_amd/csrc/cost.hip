@@ -2,17 +2,18 @@
 //
 // round_costs : a cost matrix already scaled to [0, 1] -> k = floor(c / eps),
 //               the division in binary64. HBM-bound (4 B in, 2 B out).
-// build_points: squared Euclidean costs of two point sets, scaled so the
-//               largest is 1 (Section 1), then rounded. For the low
-//               dimensions of the paper's synthetic workload (d = 2, 3) the
-//               work is bound by the 2 B/entry write, so the distance is a
-//               direct difference on the vector ALUs in binary32:
-//               s = fma(x_j - y_j, x_j - y_j, s) in coordinate order.
-//               k = floor((s / m) / eps) needs two binary64 divisions per
-//               entry; instead, since that map is monotone in s, a small
-//               table of the smallest binary32 s reaching each k is built
-//               once per instance and each entry is classified against it,
-//               which yields the identical integer.
+// points      : squared Euclidean costs of point sets, scaled so the largest
+//               is 1 (Section 1), then rounded; one instance or a batch of
+//               independent instances (grid z = instance). The distance is a
+//               direct difference on the vector ALUs in binary32,
+//               s = fma(x_j - y_j, x_j - y_j, s) in coordinate order, so the
+//               result is reproducible bit for bit. k = floor((s / m) / eps)
+//               needs two binary64 divisions per entry; instead each entry is
+//               classified by a binary32 product whose error is bounded, and
+//               only entries within that bound of an integer are resolved
+//               against a per-instance table of the smallest s reaching each
+//               k (the map s -> k is monotone), giving the identical integer.
+#include "cost_common.h"
 #include "internal.h"
 
 #include <float.h>
@@ -24,6 +25,8 @@ namespace {
 constexpr int kColsPerThread = 8;
 constexpr int kBuildThreads = 256;
 constexpr int kRowsPerBlock = 16;
+constexpr int kMaxRows = 256;   // rows per block of the max pass
+constexpr int kMaxD = 16;       // coordinates staged per row (larger d: read from memory)
 
 __global__ void __launch_bounds__(kBuildThreads)
 round_costs_kernel(const float *__restrict__ C, int64_t n, int64_t ldc, double eps,
@@ -56,68 +59,42 @@ round_costs_kernel(const float *__restrict__ C, int64_t n, int64_t ldc, double e
     if (bad) __hip_atomic_fetch_or(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void build_reset_kernel(Ctl *ctl)
+__global__ void build_reset_kernel(PointsJob j)
 {
-    ctl->m = 0.0f;
-    ctl->err = 0;
-    ctl->kmax = 0;
-}
-
-template <int D>
-__device__ inline float sqdist(const float *__restrict__ x, const float *__restrict__ y, int d)
-{
-    float s = 0.0f;
-    if constexpr (D > 0) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const float t = __fsub_rn(x[j], y[j]);
-            s = __fmaf_rn(t, t, s);
-        }
-    } else {
-        for (int j = 0; j < d; ++j) {
-            const float t = __fsub_rn(x[j], y[j]);
-            s = __fmaf_rn(t, t, s);
-        }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < j.batch; i += gridDim.x * blockDim.x)
+        j.m[i] = 0.0f;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *j.err = 0;
+        if (j.kmax_out) *j.kmax_out = 0;
     }
-    return s;
 }
 
 // Pass 1: m = max over all pairs of the binary32 squared distance. Block =
-// 256 columns x kMaxRows rows; the rows' coordinates are staged in LDS.
-constexpr int kMaxRows = 256;
-constexpr int kMaxD = 16;   // coordinates staged per row (larger d: read from memory)
-
+// 256 columns x kMaxRows rows of one instance; the rows' coordinates are
+// staged in LDS.
 template <int D>
-__global__ void __launch_bounds__(kBuildThreads)
-points_max_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_t n,
-                  int32_t d, Ctl *ctl)
+__global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
 {
     __shared__ float xs[kMaxRows * kMaxD];
     __shared__ float red[kBuildThreads / 64];
+    const Instance in = j.instance(blockIdx.z);
     const int64_t a = (int64_t)blockIdx.x * kBuildThreads + threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.y * kMaxRows;
-    const int rows = (int)min<int64_t>(kMaxRows, n - b0);
-    const bool staged = D > 0 || d <= kMaxD;
-    const int dd = D > 0 ? D : d;
+    if (b0 >= in.n || (int64_t)blockIdx.x * kBuildThreads >= in.n) return;
+    const int rows = (int)min<int64_t>(kMaxRows, in.n - b0);
+    const int dd = D > 0 ? D : j.d;
+    const bool staged = D > 0 || j.d <= kMaxD;
     if (staged)
-        for (int i = threadIdx.x; i < rows * dd; i += kBuildThreads) xs[i] = X[b0 * dd + i];
+        for (int i = threadIdx.x; i < rows * dd; i += kBuildThreads) xs[i] = in.X[b0 * dd + i];
     __syncthreads();
     float mx = 0.0f;
     bool bad = false;
-    if (a < n) {
-        const float *y = Y + a * dd;
-        if (staged) {
-            for (int r = 0; r < rows; ++r) {
-                const float s = sqdist<D>(xs + r * dd, y, dd);
-                bad |= !(s <= FLT_MAX);
-                mx = fmaxf(mx, s);
-            }
-        } else {
-            for (int r = 0; r < rows; ++r) {
-                const float s = sqdist<D>(X + (b0 + r) * dd, y, dd);
-                bad |= !(s <= FLT_MAX);
-                mx = fmaxf(mx, s);
-            }
+    if (a < in.n) {
+        const float *y = in.Y + a * dd;
+        for (int r = 0; r < rows; ++r) {
+            const float s = sqdist<D>(staged ? xs + r * dd : in.X + (b0 + r) * dd, y, dd);
+            bad |= !(s <= FLT_MAX);
+            mx = fmaxf(mx, s);
         }
     }
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
@@ -127,92 +104,56 @@ points_max_kernel(const float *__restrict__ X, const float *__restrict__ Y, int6
         float m = red[0];
         for (int i = 1; i < kBuildThreads / 64; ++i) m = fmaxf(m, red[i]);
         // squared distances are >= 0, so their bit patterns order as floats do
-        __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(&ctl->m), __float_as_uint(m),
+        __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(&j.m[blockIdx.z]), __float_as_uint(m),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (bad) __hip_atomic_fetch_or(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// k(s) = floor((s / m) / eps), both divisions binary64 (the definition).
-__device__ inline double k_of(float s, double m, double eps)
-{
-    return floor(((double)s / m) / eps);
+    if (bad) __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // th[j] = smallest binary32 s >= 0 with k(s) >= j, for j = 0..K; th[K+1] = +inf.
-// k(s) is non-decreasing in s, and so in the bit pattern of s >= 0.
-__global__ void thresholds_kernel(double eps, Ctl *ctl, float *th, int32_t kcap)
+__global__ void thresholds_kernel(PointsJob j)
 {
-    const float mf = ctl->m;
-    const double m = (double)mf;
-    const int32_t K = (mf > 0.0f) ? (int32_t)floor(1.0 / eps) : 0;
-    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0) ctl->kmax = K;
-    if (j > K + 1 || j >= kcap) return;
-    if (j == 0) { th[0] = 0.0f; return; }
-    if (j == K + 1) { th[j] = __int_as_float(0x7f800000); return; }
-    uint32_t lo = 0, hi = __float_as_uint(mf);  // k(m) = K >= j
-    while (lo < hi) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        if (k_of(__uint_as_float(mid), m, eps) >= (double)j) hi = mid; else lo = mid + 1;
-    }
-    th[j] = __uint_as_float(lo);
-}
-
-// k for one entry. v = s * inv in binary32 is within (K + 2) * 2^-22 of the
-// exact s / (m eps) (inv and the product are each rounded once; the exact
-// value is <= K + 1), and the binary64 definition is within 1e-10 of it. So
-// when v is at least delta away from every integer, floor(v) is the
-// definition's k; otherwise the threshold table decides.
-__device__ inline int fast_k(float s, float inv, float delta, int K, bool &exact)
-{
-    const float v = __fmul_rn(s, inv);
-    int g = (int)fminf(v, (float)K);
-    g = g < 0 ? 0 : g;
-    const float f = __fsub_rn(v, (float)g);
-    exact = f >= delta && f <= 1.0f - delta && v < (float)K;
-    return g;
-}
-
-__device__ inline int refine_k(float s, int g, int K, const float *__restrict__ th)
-{
-    while (g < K && s >= th[g + 1]) ++g;
-    while (g > 0 && s < th[g]) --g;
-    return g;
+    const float mf = j.m[blockIdx.z];
+    const int32_t K = (mf > 0.0f) ? (int32_t)floor(1.0 / j.eps) : 0;
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && j.kmax_out && blockIdx.z == 0) *j.kmax_out = K;
+    if (i > K + 1 || i >= j.kcap) return;
+    j.th[(int64_t)blockIdx.z * j.kcap + i] = threshold_of(i, K, mf, j.eps);
 }
 
 // Pass 2: k for every pair, 8 consecutive columns per thread (their points
 // held in registers), kRowsPerBlock rows per block (coordinates in LDS);
 // padding columns (n <= col < ldk) get 0x7FFF.
 template <int D>
-__global__ void __launch_bounds__(kBuildThreads)
-points_k_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_t n,
-                int32_t d, double eps, int16_t *__restrict__ k, int64_t ldk,
-                const float *__restrict__ th, const Ctl *ctl)
+__global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
 {
     constexpr int DR = D > 0 ? D : 1;
     __shared__ float xs[kRowsPerBlock * kMaxD];
+    const Instance in = j.instance(blockIdx.z);
     const int64_t col0 = ((int64_t)blockIdx.x * kBuildThreads + threadIdx.x) * kColsPerThread;
     const int64_t b0 = (int64_t)blockIdx.y * kRowsPerBlock;
-    const int rows = (int)min<int64_t>(kRowsPerBlock, n - b0);
-    const int dd = D > 0 ? D : d;
-    const bool staged = D > 0 || d <= kMaxD;
+    if (b0 >= in.n || (int64_t)blockIdx.x * kBuildThreads * kColsPerThread >= in.ldk) return;
+    const int rows = (int)min<int64_t>(kRowsPerBlock, in.n - b0);
+    const int dd = D > 0 ? D : j.d;
+    const bool staged = D > 0 || j.d <= kMaxD;
     if (staged)
-        for (int i = threadIdx.x; i < rows * dd; i += kBuildThreads) xs[i] = X[b0 * dd + i];
+        for (int i = threadIdx.x; i < rows * dd; i += kBuildThreads) xs[i] = in.X[b0 * dd + i];
     __syncthreads();
-    if (col0 >= ldk) return;
-    const float mf = ctl->m;
-    const int32_t K = ctl->kmax;
-    const float inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * eps)) : 0.0f;
-    const float delta = (float)(K + 2) * 4.8e-7f;   // > (K + 2) * 2^-22 with margin
+    if (col0 >= in.ldk) return;
+    const int64_t n = in.n;
+    const float mf = j.m[blockIdx.z];
+    const int32_t K = (mf > 0.0f) ? (int32_t)floor(1.0 / j.eps) : 0;
+    const float inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * j.eps)) : 0.0f;
+    const float delta = classify_margin(K);
+    const float *th = j.th + (int64_t)blockIdx.z * j.kcap;
     float yv[kColsPerThread][DR];
 #pragma unroll
     for (int e = 0; e < kColsPerThread; ++e)
 #pragma unroll
-        for (int j = 0; j < DR; ++j)
-            yv[e][j] = (D > 0 && col0 + e < n) ? Y[(col0 + e) * DR + j] : 0.0f;
+        for (int q = 0; q < DR; ++q)
+            yv[e][q] = (D > 0 && col0 + e < n) ? in.Y[(col0 + e) * DR + q] : 0.0f;
     for (int r = 0; r < rows; ++r) {
-        const float *x = staged ? xs + r * dd : X + (b0 + r) * dd;
+        const float *x = staged ? xs + r * dd : in.X + (b0 + r) * dd;
         float sv[kColsPerThread];
         int g[kColsPerThread];
         uint32_t slow = 0;
@@ -222,12 +163,12 @@ points_k_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_
             if constexpr (D > 0) {
                 s = 0.0f;
 #pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    const float t = __fsub_rn(x[j], yv[e][j]);
+                for (int q = 0; q < D; ++q) {
+                    const float t = __fsub_rn(x[q], yv[e][q]);
                     s = __fmaf_rn(t, t, s);
                 }
             } else {
-                s = col0 + e < n ? sqdist<0>(x, Y + (col0 + e) * dd, dd) : 0.0f;
+                s = col0 + e < n ? sqdist<0>(x, in.Y + (col0 + e) * dd, dd) : 0.0f;
             }
             bool ok;
             g[e] = fast_k(s, inv, delta, K, ok);
@@ -247,8 +188,22 @@ points_k_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_
         w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);
         w.z = (uint32_t)(uint16_t)g[4] | ((uint32_t)(uint16_t)g[5] << 16);
         w.w = (uint32_t)(uint16_t)g[6] | ((uint32_t)(uint16_t)g[7] << 16);
-        *reinterpret_cast<uint4 *>(k + (b0 + r) * ldk + col0) = w;
+        *reinterpret_cast<uint4 *>(in.k + (b0 + r) * in.ldk + col0) = w;
     }
+}
+
+template <int D>
+void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s)
+{
+    dim3 gmax((unsigned)((n_max + kBuildThreads - 1) / kBuildThreads),
+              (unsigned)((n_max + kMaxRows - 1) / kMaxRows), (unsigned)j.batch);
+    hipLaunchKernelGGL(points_max_kernel<D>, gmax, dim3(kBuildThreads), 0, s, j);
+    hipLaunchKernelGGL(thresholds_kernel, dim3((j.kcap + 255) / 256, 1, j.batch), dim3(256), 0,
+                       s, j);
+    const int64_t per_block = (int64_t)kBuildThreads * kColsPerThread;
+    dim3 gk((unsigned)((ldk_max + per_block - 1) / per_block),
+            (unsigned)((n_max + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned)j.batch);
+    hipLaunchKernelGGL(points_k_kernel<D>, gk, dim3(kBuildThreads), 0, s, j);
 }
 
 }  // namespace
@@ -256,7 +211,12 @@ points_k_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_
 hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps,
                               int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s)
 {
-    hipLaunchKernelGGL(build_reset_kernel, dim3(1), dim3(1), 0, s, ctl);
+    PointsJob j{};
+    j.batch = 1;
+    j.m = &ctl->m;
+    j.err = &ctl->err;
+    j.kmax_out = &ctl->kmax;
+    hipLaunchKernelGGL(build_reset_kernel, dim3(1), dim3(64), 0, s, j);
     const int64_t per_block = (int64_t)kBuildThreads * kColsPerThread;
     dim3 grid((unsigned)((ldk + per_block - 1) / per_block), (unsigned)(n < 65535 ? n : 65535));
     if (n > 0)
@@ -265,39 +225,13 @@ hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps
     return hipGetLastError();
 }
 
-hipError_t launch_build_points(const float *X, const float *Y, int64_t n, int32_t d,
-                               double eps, int16_t *k, int64_t ldk, float *m_out,
-                               float *th, Ctl *ctl, hipStream_t s)
+hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s)
 {
-    hipLaunchKernelGGL(build_reset_kernel, dim3(1), dim3(1), 0, s, ctl);
-    if (n == 0) return hipGetLastError();
-    dim3 gmax((unsigned)((n + kBuildThreads - 1) / kBuildThreads),
-              (unsigned)((n + kMaxRows - 1) / kMaxRows));
-    if (d == 2)
-        hipLaunchKernelGGL(points_max_kernel<2>, gmax, dim3(kBuildThreads), 0, s, X, Y, n, d, ctl);
-    else if (d == 3)
-        hipLaunchKernelGGL(points_max_kernel<3>, gmax, dim3(kBuildThreads), 0, s, X, Y, n, d, ctl);
-    else
-        hipLaunchKernelGGL(points_max_kernel<0>, gmax, dim3(kBuildThreads), 0, s, X, Y, n, d, ctl);
-    const int32_t kcap = (int32_t)floor(1.0 / eps) + 2;
-    hipLaunchKernelGGL(thresholds_kernel, dim3((kcap + 255) / 256), dim3(256), 0, s, eps, ctl,
-                       th, kcap);
-    const int64_t per_block = (int64_t)kBuildThreads * kColsPerThread;
-    dim3 gk((unsigned)((ldk + per_block - 1) / per_block),
-            (unsigned)((n + kRowsPerBlock - 1) / kRowsPerBlock));
-    if (d == 2)
-        hipLaunchKernelGGL(points_k_kernel<2>, gk, dim3(kBuildThreads), 0, s, X, Y, n, d, eps, k,
-                           ldk, th, ctl);
-    else if (d == 3)
-        hipLaunchKernelGGL(points_k_kernel<3>, gk, dim3(kBuildThreads), 0, s, X, Y, n, d, eps, k,
-                           ldk, th, ctl);
-    else
-        hipLaunchKernelGGL(points_k_kernel<0>, gk, dim3(kBuildThreads), 0, s, X, Y, n, d, eps, k,
-                           ldk, th, ctl);
-    if (m_out) {
-        hipError_t e = hipMemcpyAsync(m_out, &ctl->m, sizeof(float), hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
-    }
+    hipLaunchKernelGGL(build_reset_kernel, dim3((j.batch + 255) / 256), dim3(256), 0, s, j);
+    if (n_max == 0 || j.batch == 0) return hipGetLastError();
+    if (j.d == 2) launch_points_d<2>(j, n_max, ldk_max, s);
+    else if (j.d == 3) launch_points_d<3>(j, n_max, ldk_max, s);
+    else launch_points_d<0>(j, n_max, ldk_max, s);
     return hipGetLastError();
 }
 

@@ -1,0 +1,113 @@
+// Device helpers for the rounded-cost definitions of the point-set builds
+// (arXiv:2203.03732, Section 2.1, eq. (1), on costs scaled to max 1).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace prot {
+
+// One instance of a (possibly batched) point-set cost build.
+struct Instance {
+    const float *X;   // n x d rows (supply B)
+    const float *Y;   // n x d columns (demand A)
+    int64_t n;
+    int64_t ldk;      // row pitch of its rounded-cost matrix
+    int16_t *k;
+};
+
+struct PointsJob {
+    const float *X, *Y;        // packed points; instance i starts at row pt_off[i]
+    const int64_t *pt_off;     // device, per instance (null: one instance at row 0)
+    const int32_t *n_arr;      // device, per instance (null: n_single)
+    const int64_t *k_off;      // device, element offset of each instance's matrix
+    const int32_t *ldk_arr;    // device, row pitch per instance (null: ldk_single)
+    int64_t n_single, ldk_single;
+    int32_t d;
+    int32_t batch;
+    double eps;
+    int16_t *k;
+    float *m;                  // per instance: max squared distance
+    float *th;                 // per instance: kcap thresholds
+    int32_t kcap;              // floor(1 / eps) + 2
+    int32_t *err;              // bit 0 set on a non-finite distance
+    int32_t *kmax_out;         // optional: K of instance 0
+
+    __device__ Instance instance(int i) const
+    {
+        Instance in;
+        const int64_t off = pt_off ? pt_off[i] : 0;
+        in.X = X + off * d;
+        in.Y = Y + off * d;
+        in.n = n_arr ? n_arr[i] : n_single;
+        in.ldk = ldk_arr ? ldk_arr[i] : ldk_single;
+        in.k = k + (k_off ? k_off[i] : 0);
+        return in;
+    }
+};
+
+template <int D>
+__device__ inline float sqdist(const float *__restrict__ x, const float *__restrict__ y, int d)
+{
+    float s = 0.0f;
+    if constexpr (D > 0) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float t = __fsub_rn(x[j], y[j]);
+            s = __fmaf_rn(t, t, s);
+        }
+    } else {
+        for (int j = 0; j < d; ++j) {
+            const float t = __fsub_rn(x[j], y[j]);
+            s = __fmaf_rn(t, t, s);
+        }
+    }
+    return s;
+}
+
+// k(s) = floor((s / m) / eps), both divisions binary64 (the definition).
+__device__ inline double k_of(float s, double m, double eps)
+{
+    return floor(((double)s / m) / eps);
+}
+
+// Smallest binary32 s >= 0 with k(s) >= j (0 < j <= K); j = 0 gives 0 and
+// j = K + 1 gives +inf. k(s) is non-decreasing in s, hence in the bit
+// pattern of s >= 0, and k(m) = K.
+__device__ inline float threshold_of(int32_t j, int32_t K, float mf, double eps)
+{
+    if (j == 0) return 0.0f;
+    if (j > K) return __int_as_float(0x7f800000);
+    const double m = (double)mf;
+    uint32_t lo = 0, hi = __float_as_uint(mf);
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (k_of(__uint_as_float(mid), m, eps) >= (double)j) hi = mid; else lo = mid + 1;
+    }
+    return __uint_as_float(lo);
+}
+
+// v = s * inv in binary32 is within (K + 2) * 2^-22 of the exact s / (m eps)
+// (inv and the product are each rounded once; the exact value is <= K + 1),
+// and the binary64 definition is within 1e-10 of it. So when v is at least
+// this margin away from every integer, floor(v) is the definition's k.
+__device__ inline float classify_margin(int32_t K) { return (float)(K + 2) * 4.8e-7f; }
+
+__device__ inline int fast_k(float s, float inv, float delta, int K, bool &exact)
+{
+    const float v = __fmul_rn(s, inv);
+    int g = (int)fminf(v, (float)K);
+    g = g < 0 ? 0 : g;
+    const float f = __fsub_rn(v, (float)g);
+    exact = f >= delta && f <= 1.0f - delta && v < (float)K;
+    return g;
+}
+
+// Exact k from a starting guess and the threshold table th[0..K+1].
+__device__ inline int refine_k(float s, int g, int K, const float *th)
+{
+    while (g < K && s >= th[g + 1]) ++g;
+    while (g > 0 && s < th[g]) --g;
+    return g;
+}
+
+}  // namespace prot

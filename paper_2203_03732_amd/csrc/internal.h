@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cost_common.h"
+
 namespace prot {
 
 // Device-side control block of one phase loop. Zeroed by the reset kernel.
@@ -51,12 +53,42 @@ struct LoopArgs {
     int64_t *rtime;           // optional: 3 int64 per round (see kRoundTimeCap)
 };
 
+// Per-instance results of the batched solver (layout of prot_instance_stats).
+struct InstanceStats {
+    int64_t phases, sum_free, rounds, max_rounds, scanned, matched_in_phases,
+        completed_pairs, sum_k, threshold;
+    int32_t status, kmax;
+    double cost, cost_scale;
+};
+
+struct BatchArgs {
+    int32_t batch;
+    int32_t d;
+    double eps;
+    int64_t max_phases;
+    int32_t origin;
+    int32_t complete;
+    const int32_t *order;     // instance ids, largest n first
+    const int32_t *n_arr;
+    const int32_t *ldk_arr;
+    const int64_t *pt_off;    // first row of each instance in X, Y and the outputs
+    const int64_t *k_off;     // element offset of each instance's rounded costs
+    const int16_t *k;
+    const float *X, *Y, *m;
+    int32_t *mate_a, *mate_b, *y_a, *y_b;
+    InstanceStats *stats;
+    unsigned int *queue;
+};
+
 // cost.hip
 hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps,
                               int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s);
-hipError_t launch_build_points(const float *X, const float *Y, int64_t n, int32_t d,
-                               double eps, int16_t *k, int64_t ldk, float *m_out,
-                               float *thresholds, Ctl *ctl, hipStream_t s);
+hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s);
+
+// batch.hip
+int32_t batch_max_n();
+hipError_t batch_grid(int32_t n_max, int32_t batch, int *grid);
+hipError_t launch_batch_solve(const BatchArgs &a, int32_t n_max, int grid, hipStream_t s);
 
 // solve.hip
 hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,

@@ -1,0 +1,131 @@
+"""GPU parity of the batched solver: every instance of a batch must be
+bit-exact with the CPU oracle run on that instance alone (rounded costs from
+the binary32 definition, matching, duals and statistics), and graph replays
+must reproduce the direct run."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_03732_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+STAT_KEYS = ("phases", "sum_free", "rounds", "max_rounds", "scanned",
+             "matched_in_phases", "completed_pairs", "sum_k")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2203_03732_amd as prot
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = prot.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def pack(Xs):
+    return torch.from_numpy(np.ascontiguousarray(np.concatenate(Xs, 0))).cuda()
+
+
+def check_instances(ns, Xs, Ys, eps, out, stats, origin="diag", which=None, complete=True):
+    mate_a, mate_b, y_a, y_b = (t.cpu().numpy() for t in out)
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    idx = range(len(ns)) if which is None else which
+    for i in idx:
+        n, o = ns[i], offs[i]
+        k, m = oracle.round_points_f32(Xs[i], Ys[i], eps)
+        ref = oracle.solve_rounded(k, oracle.threshold(eps, n), origin=origin, complete=complete)
+        for name, arr in (("mate_a", mate_a), ("mate_b", mate_b), ("y_a", y_a), ("y_b", y_b)):
+            assert np.array_equal(arr[o:o + n], ref[name]), f"instance {i} (n={n}): {name}"
+        for s in STAT_KEYS:
+            assert stats[i][s] == ref["stats"][s], f"instance {i}: {s}"
+        assert stats[i]["cost_scale"] == m
+        if complete:
+            d2 = ((Xs[i].astype(np.float64) - Ys[i].astype(np.float64)[ref["mate_b"]]) ** 2).sum(1)
+            assert math.isclose(stats[i]["cost"], d2.sum() / m, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("origin", ["diag", "zero"])
+@pytest.mark.parametrize("d,eps", [(2, 0.05), (16, 0.05), (3, 0.1)])
+def test_batched_small_bit_exact(ctx, d, eps, origin):
+    rng = np.random.default_rng(d * 10 + int(eps * 100))
+    ns = [1, 2, 7, 64] + [int(x) for x in rng.integers(8, 300, 12)]
+    Xs = [rng.standard_normal((n, d)).astype(np.float32) for n in ns]
+    Ys = [rng.standard_normal((n, d)).astype(np.float32) for n in ns]
+    mate_a, mate_b, y_a, y_b, stats = ctx.solve_batched_points(ns, pack(Xs), pack(Ys), eps,
+                                                               origin=origin)
+    check_instances(ns, Xs, Ys, eps, (mate_a, mate_b, y_a, y_b), stats, origin)
+
+
+def test_batched_large_instances(ctx):
+    """Instances up to the batched limit (n = 2048) use the larger LDS layout."""
+    rng = np.random.default_rng(3)
+    ns = [2048, 1500, 1025, 33]
+    Xs = [rng.random((n, 2), dtype=np.float32) for n in ns]
+    Ys = [rng.random((n, 2), dtype=np.float32) for n in ns]
+    out = ctx.solve_batched_points(ns, pack(Xs), pack(Ys), 0.02)
+    check_instances(ns, Xs, Ys, 0.02, out[:4], out[4])
+
+
+def test_batched_no_completion(ctx):
+    rng = np.random.default_rng(4)
+    ns = [100, 250, 31]
+    Xs = [rng.standard_normal((n, 4)).astype(np.float32) for n in ns]
+    Ys = [rng.standard_normal((n, 4)).astype(np.float32) for n in ns]
+    out = ctx.solve_batched_points(ns, pack(Xs), pack(Ys), 0.1, complete=False)
+    check_instances(ns, Xs, Ys, 0.1, out[:4], out[4], complete=False)
+
+
+def test_minibatch_512_instances_d16_eps005(ctx):
+    """512 instances, n uniform in [64, 1024], standard normal points in R^16,
+    eps = 0.05: every instance bit-exact with the oracle."""
+    ns, Xs, Ys = synth.gaussian_batch(512, 64, 1024, 16, seed=0)
+    X, Y = pack(Xs), pack(Ys)
+    b = ctx.batch(ns, 16, 0.05)
+    b.run(X, Y)
+    torch.cuda.synchronize()
+    stats = b.stats()
+    out = (b.mate_a, b.mate_b, b.y_a, b.y_b)
+    check_instances(ns, Xs, Ys, 0.05, out, stats)
+    b.close()
+
+
+def test_graph_replay_matches_direct_run(ctx):
+    rng = np.random.default_rng(8)
+    ns = [int(x) for x in rng.integers(64, 700, 40)]
+    Xs = [rng.standard_normal((n, 16)).astype(np.float32) for n in ns]
+    Ys = [rng.standard_normal((n, 16)).astype(np.float32) for n in ns]
+    X, Y = pack(Xs), pack(Ys)
+    b = ctx.batch(ns, 16, 0.05)
+    b.run(X, Y)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (b.mate_a, b.mate_b, b.y_a, b.y_b)]
+    ref_stats = b.stats()
+    b.capture(X, Y)
+    for rep in range(3):
+        for t in (b.mate_a, b.mate_b, b.y_a, b.y_b):
+            t.fill_(-7)
+        b.stats_dev.zero_()
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        for got, want in zip((b.mate_a, b.mate_b, b.y_a, b.y_b), ref):
+            assert torch.equal(got, want), f"replay {rep}"
+        assert b.stats() == ref_stats
+        # eager work between replays
+        (X * 2.0).sum().item()
+    b.close()
+
+
+def test_batched_rejects_oversized_instance(ctx):
+    import paper_2203_03732_amd as prot
+    n = prot.load().prot_batch_max_n() + 1
+    X = torch.zeros((n, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(prot.ProtError) as e:
+        ctx.solve_batched_points([n], X, X.clone(), 0.1)
+    assert e.value.name == "unsupported"
