@@ -41,6 +41,67 @@ def cpu_baseline(X, Y, eps, reps):
                       f"+ phase loop + completion), single-threaded C"}
 
 
+def bench_batched(prot, synth, torch, reps=10):
+    """512 independent instances (n uniform in [64, 1024], standard normal
+    points in R^16, eps = 0.05): one graph replay of the batched solve vs a
+    host loop of single-instance solves on the same stream."""
+    import numpy as np
+    ns, Xs, Ys = synth.gaussian_batch(512, 64, 1024, 16, seed=0)
+    X = torch.from_numpy(np.concatenate(Xs)).cuda()
+    Y = torch.from_numpy(np.concatenate(Ys)).cuda()
+    ctx = prot.Context(0)
+    plan = ctx.batch(ns, 16, 0.05)
+    plan.run(X, Y)
+    plan.capture(X, Y)
+    plan.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.replay()
+    torch.cuda.synchronize()
+    replay_ms = 1e3 * (time.perf_counter() - t0) / reps
+    Xl = [torch.from_numpy(x).cuda() for x in Xs]
+    Yl = [torch.from_numpy(y).cuda() for y in Ys]
+    ctx.reserve(max(ns), with_matrix=True)
+    for x, y in zip(Xl[:8], Yl[:8]):
+        ctx.solve_points(x, y, 0.05)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x, y in zip(Xl, Yl):
+        ctx.solve_points(x, y, 0.05)
+    torch.cuda.synchronize()
+    loop_ms = 1e3 * (time.perf_counter() - t0)
+    st = plan.stats()
+    plan.close()
+    ctx.close()
+    return {"workload": "512 instances, n~U[64,1024], N(0,I) in R^16, eps=0.05",
+            "graph_replay_ms": round(replay_ms, 4),
+            "solves_per_s": round(512 / (replay_ms * 1e-3), 1),
+            "plain_loop_ms": round(loop_ms, 3),
+            "plain_loop_solves_per_s": round(512 / (loop_ms * 1e-3), 1),
+            "ratio_vs_plain_loop": round(loop_ms / replay_ms, 2),
+            "mean_phases": round(float(np.mean([s["phases"] for s in st])), 2)}
+
+
+def bench_ot_loss(prot, synth, torch, reps=5):
+    """64 instances, n = 2048, X ~ N(0, I_64), Y ~ N(0.5, I_64), eps = 0.01:
+    forward (batched solve + loss) and hand-written backward."""
+    X, Y = synth.shifted_gaussian_batch(64, 2048, 64, 0.5, seed=0)
+    Xd = torch.from_numpy(X).cuda().requires_grad_(True)
+    Yd = torch.from_numpy(Y).cuda().requires_grad_(True)
+    prot.ot_match_loss(Xd, Yd, 0.01).sum().backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Xd.grad = None
+        Yd.grad = None
+        prot.ot_match_loss(Xd, Yd, 0.01).sum().backward()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    return {"workload": "64 x n=2048, R^64, X~N(0,I), Y~N(0.5,I), eps=0.01",
+            "fwd_bwd_ms": round(ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +113,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-reps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and OT-loss measurements")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the bench, run 5 plain device copies of this many MiB "
                          "(reference kernel for scaling memory counters)")
@@ -129,6 +192,10 @@ def main():
                                      "completed_pairs", "sum_k")} | {"cost": st["cost"]},
         "roofline": roofline,
     }
+    ctx.close()
+    if not args.no_extras:
+        out["batched"] = bench_batched(prot, synth, torch)
+        out["ot_loss"] = bench_ot_loss(prot, synth, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, Y, eps, args.cpu_reps)
     print(json.dumps(out), flush=True)
@@ -140,7 +207,6 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes}), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -199,6 +199,21 @@ int prot_solve_batched_points(prot_ctx *ctx, int32_t batch, const int64_t *n_hos
                               const prot_opts *opts, int32_t *mate_a, int32_t *mate_b,
                               int32_t *y_a, int32_t *y_b, prot_instance_stats *stats_host);
 
+/* Matching-based OT loss of every instance of a plan, from its matching:
+ * L_i = (1/n_i) * sum_b ||x_b - y_{mate_b[b]}||^2 (float32 result of a
+ * binary64 sum; unmatched rows add nothing). X, Y and mate_b use the plan's
+ * packed layout; loss: device float[batch]. */
+int prot_batch_loss_fwd(prot_batch *plan, const float *X, const float *Y,
+                        const int32_t *mate_b, float *loss);
+
+/* Gradient of sum_i g_i * L_i for the fixed matching (the matching is
+ * piecewise constant in X and Y): dX_b = (2 g_i / n_i)(x_b - y_{mate_b[b]}),
+ * dY_a = (2 g_i / n_i)(y_a - x_{mate_a[a]}), 0 where unmatched. grad_loss:
+ * device float[batch]; dX, dY: device, same layout as X, Y. */
+int prot_batch_loss_bwd(prot_batch *plan, const float *X, const float *Y,
+                        const int32_t *mate_a, const int32_t *mate_b,
+                        const float *grad_loss, float *dX, float *dY);
+
 /* Per-phase record of the last phase loop on this context: for phase i,
  * out[4i..4i+3] = (|B'|, rounds, scanned entries, |M'|). Copies at most cap
  * phases and returns the number of phases recorded (<= the trace capacity,

@@ -167,3 +167,41 @@ def solve_rounded(k: np.ndarray, T: int, origin: str = "diag",
     if tr is not None:
         out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
     return out
+
+
+# ---------------------------------------------------------------------------
+# Matching-based OT loss (not in the paper; the paper motivates using the
+# transport plan and duals in learning, Section 1). For one instance with
+# matching mate_b (row b -> column a):
+#     L = (1/n) * sum_b ||x_b - y_{mate(b)}||^2
+# The matching is piecewise constant in X and Y, so the gradient is that of
+# the fixed plan P = (1/n) * permutation:
+#     dL/dx_b = (2/n) (x_b - y_{mate(b)}),  dL/dy_a = (2/n) (y_a - x_{mate^-1(a)}).
+# Rows left unmatched (no completion) contribute nothing.
+
+def ot_loss(X: np.ndarray, Y: np.ndarray, mate_b: np.ndarray) -> float:
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    n = X.shape[0]
+    total = 0.0
+    for b in range(n):
+        a = int(mate_b[b])
+        if a >= 0:
+            diff = X[b] - Y[a]
+            total += float(diff @ diff)
+    return total / n if n else 0.0
+
+
+def ot_loss_grad(X: np.ndarray, Y: np.ndarray, mate_b: np.ndarray, g: float = 1.0):
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    n = X.shape[0]
+    dX = np.zeros_like(X)
+    dY = np.zeros_like(Y)
+    for b in range(n):
+        a = int(mate_b[b])
+        if a >= 0:
+            diff = X[b] - Y[a]
+            dX[b] = 2.0 * g * diff / n
+            dY[a] = -2.0 * g * diff / n
+    return dX, dY

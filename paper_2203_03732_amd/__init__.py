@@ -42,3 +42,10 @@ def round_costs(C, eps, k=None):
 
 def build_costs(X, Y, eps, k=None):
     return context().build_costs(X, Y, eps, k)
+
+
+def ot_match_loss(X, Y, eps, eps_mode="algorithmic"):
+    """Differentiable per-instance loss (1/n) sum ||x_b - y_mate(b)||^2 for
+    X, Y of shape (batch, n, d); see paper_2203_03732_amd.autograd."""
+    from .autograd import ot_match_loss as f
+    return f(X, Y, eps, eps_mode)

@@ -72,6 +72,7 @@ EXPORTS = [
     "prot_solve_rounded", "prot_solve_cost", "prot_solve_points", "prot_get_trace",
     "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
     "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
+    "prot_batch_loss_fwd", "prot_batch_loss_bwd",
     "prot_status_string", "prot_last_error",
 ]
 
@@ -112,6 +113,8 @@ def load():
         "prot_batch_run": (ctypes.c_int, [p, p, p, p, p, p, p, p]),
         "prot_batch_capture": (ctypes.c_int, [p, p, p, p, p, p, p, p]),
         "prot_batch_replay": (ctypes.c_int, [p]),
+        "prot_batch_loss_fwd": (ctypes.c_int, [p, p, p, p, p]),
+        "prot_batch_loss_bwd": (ctypes.c_int, [p, p, p, p, p, p, p, p]),
         "prot_solve_batched_points": (ctypes.c_int, [p, i32, p, i32, p, p, f64,
                                                      ctypes.POINTER(Opts), p, p, p, p, p]),
         "prot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -177,6 +180,8 @@ class Context:
         self._lib = lib
 
     def close(self):
+        for plan in self.__dict__.pop("_plans", {}).values():
+            plan.close()
         if getattr(self, "_h", None):
             self._lib.prot_ctx_destroy(self._h)
             self._h = None
@@ -320,6 +325,14 @@ class Context:
         buf = buf[:m]
         return buf[buf[:, 1] != 0].copy()
 
+    def cached_batch(self, ns, d: int, eps: float, **kw) -> "Batch":
+        """A plan reused across calls with the same shapes and options."""
+        key = (tuple(int(x) for x in ns), int(d), float(eps), tuple(sorted(kw.items())))
+        cache = self.__dict__.setdefault("_plans", {})
+        if key not in cache:
+            cache[key] = Batch(self, ns, d, eps, **kw)
+        return cache[key]
+
     def batch(self, ns, d: int, eps: float, *, eps_mode="algorithmic", origin="diag",
               complete=True, max_phases=0) -> "Batch":
         return Batch(self, ns, d, eps, eps_mode=eps_mode, origin=origin, complete=complete,
@@ -405,6 +418,32 @@ class Batch:
 
     def stats(self) -> list[dict]:
         return instance_stats_from_bytes(self.stats_dev.cpu().numpy().tobytes())
+
+    def loss(self, X, Y, mate_b=None):
+        """Per-instance (1/n) sum ||x_b - y_mate(b)||^2 as a float32 tensor."""
+        torch = _torch()
+        mate_b = self.mate_b if mate_b is None else mate_b
+        out = torch.empty(len(self.ns), dtype=torch.float32, device=X.device)
+        self.ctx._bind_stream()
+        self.ctx._check(self.ctx._lib.prot_batch_loss_fwd(
+            self._h, _dev_ptr(X, torch.float32, "X"), _dev_ptr(Y, torch.float32, "Y"),
+            _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(out, torch.float32, "loss")))
+        return out
+
+    def loss_grad(self, X, Y, grad_loss, mate_a=None, mate_b=None):
+        """(dX, dY) of sum_i grad_loss[i] * L_i for the fixed matching."""
+        torch = _torch()
+        mate_a = self.mate_a if mate_a is None else mate_a
+        mate_b = self.mate_b if mate_b is None else mate_b
+        grad_loss = grad_loss.to(torch.float32).contiguous()
+        dX, dY = torch.empty_like(X), torch.empty_like(Y)
+        self.ctx._bind_stream()
+        self.ctx._check(self.ctx._lib.prot_batch_loss_bwd(
+            self._h, _dev_ptr(X, torch.float32, "X"), _dev_ptr(Y, torch.float32, "Y"),
+            _dev_ptr(mate_a, torch.int32, "mate_a"), _dev_ptr(mate_b, torch.int32, "mate_b"),
+            _dev_ptr(grad_loss, torch.float32, "grad_loss"), _dev_ptr(dX, torch.float32, "dX"),
+            _dev_ptr(dY, torch.float32, "dY")))
+        return dX, dY
 
     def close(self):
         if getattr(self, "_h", None):

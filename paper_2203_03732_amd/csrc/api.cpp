@@ -790,6 +790,33 @@ int prot_batch_replay(prot_batch *bp)
     return PROT_OK;
 }
 
+int prot_batch_loss_fwd(prot_batch *bp, const float *X, const float *Y, const int32_t *mate_b,
+                        float *loss)
+{
+    if (!bp) return PROT_E_ARG;
+    prot_ctx *c = bp->ctx;
+    if (bp->batch == 0) return PROT_OK;
+    if (!X || !Y || !mate_b || !loss) return fail(c, PROT_E_ARG, "prot_batch_loss_fwd: null pointer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    prot::LossArgs a{bp->batch, bp->d, bp->n_arr, bp->pt_off, X, Y, nullptr, mate_b};
+    HIP_TRY(c, prot::launch_loss_fwd(a, loss, c->stream));
+    return PROT_OK;
+}
+
+int prot_batch_loss_bwd(prot_batch *bp, const float *X, const float *Y, const int32_t *mate_a,
+                        const int32_t *mate_b, const float *grad_loss, float *dX, float *dY)
+{
+    if (!bp) return PROT_E_ARG;
+    prot_ctx *c = bp->ctx;
+    if (bp->batch == 0) return PROT_OK;
+    if (!X || !Y || !mate_a || !mate_b || !grad_loss || !dX || !dY)
+        return fail(c, PROT_E_ARG, "prot_batch_loss_bwd: null pointer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    prot::LossArgs a{bp->batch, bp->d, bp->n_arr, bp->pt_off, X, Y, mate_a, mate_b};
+    HIP_TRY(c, prot::launch_loss_bwd(a, bp->n_max, grad_loss, dX, dY, c->stream));
+    return PROT_OK;
+}
+
 int prot_solve_batched_points(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t d,
                               const float *X, const float *Y, double eps, const prot_opts *o,
                               int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,

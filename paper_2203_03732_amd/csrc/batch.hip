@@ -31,6 +31,7 @@ struct BatchShared {
     int32_t at[NMAX];              // column proposed to this round (-1: exhausted)
     int32_t L[NMAX];               // columns taken this phase
     uint16_t t[NMAX];              // -y(a)
+    uint16_t skip[NMAX];           // phases row b is known to find nothing in
     long long red_k[kBatchThreads];
     double red_c[kBatchThreads];
     uint32_t nF[2], nact[2], nL, P, D;
@@ -41,11 +42,15 @@ struct BatchShared {
 // First admissible column not taken before round r, scanning row b from
 // position pos with a group of GS lanes (all lanes of the group get the
 // result). Keys and duals are in LDS.
+// When the row is exhausted, *slack_out is the smallest k + t - need over the
+// columns scanned if none of them was admissible, else 0.
 template <int GS>
 __device__ Hit group_scan(const int16_t *__restrict__ row, const uint16_t *t,
                           const unsigned long long *key, int n, int origin, int pos, int need,
-                          uint32_t r0, uint32_t r, int gl, int gbase)
+                          uint32_t r0, uint32_t r, int gl, int gbase, int *slack_out)
 {
+    int mn = 0x7FFFFFFF;  // smallest k + t seen by this lane
+    bool any_adm = false; // some scanned column was admissible (taken or not)
     constexpr int CH = GS * 8;
     constexpr int U = GS >= 16 ? 4 : 8;
     constexpr unsigned long long GM = GS == 64 ? ~0ull : ((1ull << GS) - 1ull);
@@ -76,8 +81,11 @@ __device__ Hit group_scan(const int16_t *__restrict__ row, const uint16_t *t,
                 uint32_t cand = 0;
                 if (col0 < shi) {
                     const uint4 tv = *reinterpret_cast<const uint4 *>(t + col0);
-                    cand = match_mask(kv[u], tv, need) & range_mask(col0, slo, shi);
+                    const uint32_t rm = range_mask(col0, slo, shi);
+                    cand = match_mask(kv[u], tv, need) & rm;
+                    mn = min(mn, min_sum_masked(kv[u], tv, rm));
                 }
+                any_adm |= cand != 0u;
                 uint32_t hit = 0;
                 for (uint32_t c = cand; c; c &= c - 1) {
                     const int e = __builtin_ctz(c);
@@ -96,6 +104,10 @@ __device__ Hit group_scan(const int16_t *__restrict__ row, const uint16_t *t,
             depth = U;
         }
     }
+#pragma unroll
+    for (int off = GS / 2; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off));
+    const bool adm = ((__ballot(any_adm) >> gbase) & GM) != 0ull;
+    *slack_out = adm ? 0 : mn - need;
     return Hit{-1, -1};
 }
 
@@ -116,9 +128,23 @@ __device__ void round_pass(BatchShared<NMAX> &S, const int16_t *k, int64_t ldk, 
         const int pos = S.ap[ac][i];
         const int yb = S.yb[b];
         const int origin = origin_mode == 0 ? b : 0;
-        const Hit h = group_scan<GS>(k + (int64_t)b * ldk, S.t, S.key, n, origin, pos, yb - 1,
-                                     r0, r, gl, gbase);
+        Hit h{-1, -1};
+        int slack = 0;
+        const int skip = S.skip[b];
+        if (skip == 0)
+            h = group_scan<GS>(k + (int64_t)b * ldk, S.t, S.key, n, origin, pos, yb - 1, r0, r,
+                               gl, gbase, &slack);
         if (gl != 0) continue;
+        if (skip > 0) {
+            // Exact fast-forward: an earlier full scan of this row found no
+            // admissible column, every slack k + t - (y(b) - 1) was >= skip + 1
+            // then, and since y(b) has grown by one per phase while t only
+            // grows, no column can be admissible yet; the scan would exhaust.
+            S.skip[b] = (uint16_t)(skip - 1);
+        } else if (pos == 0 && slack >= 2) {
+            // the row's first scan of this phase covered every column
+            S.skip[b] = (uint16_t)min(slack - 1, 65535);
+        }
         if (h.j >= 0) {
             scanned += (unsigned long long)(h.j - pos + 1);
             const unsigned long long kn = ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
@@ -187,6 +213,7 @@ __device__ void solve_instance(const BatchArgs &A, int inst, BatchShared<NMAX> &
         S.t[i] = 0;
         S.yb[i] = 1;
         S.F[0][i] = i;
+        S.skip[i] = 0;
     }
     for (int i = n + tid; i < ((n + 7) & ~7); i += kBatchThreads) S.t[i] = 0;
     if (tid == 0) {

@@ -26,7 +26,7 @@ constexpr int kColsPerThread = 8;
 constexpr int kBuildThreads = 256;
 constexpr int kRowsPerBlock = 16;
 constexpr int kMaxRows = 256;   // rows per block of the max pass
-constexpr int kMaxD = 16;       // coordinates staged per row (larger d: read from memory)
+constexpr int kMaxD = 3;        // largest d of the low-dimensional kernels
 
 __global__ void __launch_bounds__(kBuildThreads)
 round_costs_kernel(const float *__restrict__ C, int64_t n, int64_t ldc, double eps,
@@ -69,30 +69,32 @@ __global__ void build_reset_kernel(PointsJob j)
     }
 }
 
+// Low dimensions (d = 2, 3): the work is bound by the 2-byte writes of pass
+// 2, so pairs are computed straight from registers and LDS.
 // Pass 1: m = max over all pairs of the binary32 squared distance. Block =
 // 256 columns x kMaxRows rows of one instance; the rows' coordinates are
 // staged in LDS.
 template <int D>
 __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
 {
-    __shared__ float xs[kMaxRows * kMaxD];
+    static_assert(D > 0 && D <= kMaxD, "low-dimensional kernel");
+    __shared__ float xs[kMaxRows * D];
     __shared__ float red[kBuildThreads / 64];
     const Instance in = j.instance(blockIdx.z);
     const int64_t a = (int64_t)blockIdx.x * kBuildThreads + threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.y * kMaxRows;
     if (b0 >= in.n || (int64_t)blockIdx.x * kBuildThreads >= in.n) return;
     const int rows = (int)min<int64_t>(kMaxRows, in.n - b0);
-    const int dd = D > 0 ? D : j.d;
-    const bool staged = D > 0 || j.d <= kMaxD;
-    if (staged)
-        for (int i = threadIdx.x; i < rows * dd; i += kBuildThreads) xs[i] = in.X[b0 * dd + i];
+    for (int i = threadIdx.x; i < rows * D; i += kBuildThreads) xs[i] = in.X[b0 * D + i];
     __syncthreads();
     float mx = 0.0f;
     bool bad = false;
     if (a < in.n) {
-        const float *y = in.Y + a * dd;
+        float y[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) y[q] = in.Y[a * D + q];
         for (int r = 0; r < rows; ++r) {
-            const float s = sqdist<D>(staged ? xs + r * dd : in.X + (b0 + r) * dd, y, dd);
+            const float s = sqdist<D>(xs + r * D, y, D);
             bad |= !(s <= FLT_MAX);
             mx = fmaxf(mx, s);
         }
@@ -127,17 +129,14 @@ __global__ void thresholds_kernel(PointsJob j)
 template <int D>
 __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
 {
-    constexpr int DR = D > 0 ? D : 1;
-    __shared__ float xs[kRowsPerBlock * kMaxD];
+    static_assert(D > 0 && D <= kMaxD, "low-dimensional kernel");
+    __shared__ float xs[kRowsPerBlock * D];
     const Instance in = j.instance(blockIdx.z);
     const int64_t col0 = ((int64_t)blockIdx.x * kBuildThreads + threadIdx.x) * kColsPerThread;
     const int64_t b0 = (int64_t)blockIdx.y * kRowsPerBlock;
     if (b0 >= in.n || (int64_t)blockIdx.x * kBuildThreads * kColsPerThread >= in.ldk) return;
     const int rows = (int)min<int64_t>(kRowsPerBlock, in.n - b0);
-    const int dd = D > 0 ? D : j.d;
-    const bool staged = D > 0 || j.d <= kMaxD;
-    if (staged)
-        for (int i = threadIdx.x; i < rows * dd; i += kBuildThreads) xs[i] = in.X[b0 * dd + i];
+    for (int i = threadIdx.x; i < rows * D; i += kBuildThreads) xs[i] = in.X[b0 * D + i];
     __syncthreads();
     if (col0 >= in.ldk) return;
     const int64_t n = in.n;
@@ -146,30 +145,19 @@ __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
     const float inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * j.eps)) : 0.0f;
     const float delta = classify_margin(K);
     const float *th = j.th + (int64_t)blockIdx.z * j.kcap;
-    float yv[kColsPerThread][DR];
+    float yv[kColsPerThread][D];
 #pragma unroll
     for (int e = 0; e < kColsPerThread; ++e)
 #pragma unroll
-        for (int q = 0; q < DR; ++q)
-            yv[e][q] = (D > 0 && col0 + e < n) ? in.Y[(col0 + e) * DR + q] : 0.0f;
+        for (int q = 0; q < D; ++q) yv[e][q] = col0 + e < n ? in.Y[(col0 + e) * D + q] : 0.0f;
     for (int r = 0; r < rows; ++r) {
-        const float *x = staged ? xs + r * dd : in.X + (b0 + r) * dd;
+        const float *x = xs + r * D;
         float sv[kColsPerThread];
         int g[kColsPerThread];
         uint32_t slow = 0;
 #pragma unroll
         for (int e = 0; e < kColsPerThread; ++e) {
-            float s;
-            if constexpr (D > 0) {
-                s = 0.0f;
-#pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    const float t = __fsub_rn(x[q], yv[e][q]);
-                    s = __fmaf_rn(t, t, s);
-                }
-            } else {
-                s = col0 + e < n ? sqdist<0>(x, in.Y + (col0 + e) * dd, dd) : 0.0f;
-            }
+            const float s = sqdist<D>(x, yv[e], D);
             bool ok;
             g[e] = fast_k(s, inv, delta, K, ok);
             sv[e] = s;
@@ -190,6 +178,118 @@ __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
         w.w = (uint32_t)(uint16_t)g[6] | ((uint32_t)(uint16_t)g[7] << 16);
         *reinterpret_cast<uint4 *>(in.k + (b0 + r) * in.ldk + col0) = w;
     }
+}
+
+// General d: a 64 x 64 block of pairs, 4 x 4 pairs per thread, coordinates
+// staged through LDS 16 at a time (coordinate-major, so each thread reads its
+// 4 rows and its 4 columns with one 16-byte LDS load each). Every pair still
+// accumulates fma(x_j - y_j, x_j - y_j, s) in coordinate order; coordinates
+// past d are staged as 0 and add exactly nothing. PASS 0 takes the maximum,
+// PASS 1 writes the rounded costs.
+constexpr int kTile = 64;
+constexpr int kTj = 16;
+
+template <int PASS>
+__global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
+{
+    __shared__ __align__(16) float xs[kTj][kTile + 4];
+    __shared__ __align__(16) float ys[kTj][kTile + 4];
+    __shared__ float red[4];
+    const Instance in = j.instance(blockIdx.z);
+    const int64_t n = in.n;
+    const int64_t b0 = (int64_t)blockIdx.y * kTile, a0 = (int64_t)blockIdx.x * kTile;
+    if (b0 >= n || a0 >= (PASS ? in.ldk : n)) return;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int d = j.d;
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[i][c] = 0.0f;
+    for (int j0 = 0; j0 < d; j0 += kTj) {
+        for (int q = tid; q < kTile * kTj; q += 256) {
+            const int r = q / kTj, jj = q - r * kTj;
+            const bool cj = j0 + jj < d;
+            xs[jj][r] = (cj && b0 + r < n) ? in.X[(b0 + r) * d + j0 + jj] : 0.0f;
+            ys[jj][r] = (cj && a0 + r < n) ? in.Y[(a0 + r) * d + j0 + jj] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < kTj; ++jj) {
+            const float4 xv = *reinterpret_cast<const float4 *>(&xs[jj][ty * 4]);
+            const float4 yv = *reinterpret_cast<const float4 *>(&ys[jj][tx * 4]);
+            const float xr[4] = {xv.x, xv.y, xv.z, xv.w};
+            const float yc[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float t = __fsub_rn(xr[i], yc[c]);
+                    acc[i][c] = __fmaf_rn(t, t, acc[i][c]);
+                }
+        }
+        __syncthreads();
+    }
+    if constexpr (PASS == 0) {
+        float mx = 0.0f;
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (b0 + ty * 4 + i < n && a0 + tx * 4 + c < n) {
+                    bad |= !(acc[i][c] <= FLT_MAX);
+                    mx = fmaxf(mx, acc[i][c]);
+                }
+        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+        if ((tid & 63) == 0) red[tid >> 6] = mx;
+        __syncthreads();
+        if (tid == 0) {
+            const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+            __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(&j.m[blockIdx.z]),
+                                   __float_as_uint(m), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (bad) __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        const float mf = j.m[blockIdx.z];
+        const int32_t K = (mf > 0.0f) ? (int32_t)floor(1.0 / j.eps) : 0;
+        const float inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * j.eps)) : 0.0f;
+        const float delta = classify_margin(K);
+        const float *th = j.th + (int64_t)blockIdx.z * j.kcap;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = b0 + ty * 4 + i;
+            if (row >= n) continue;
+            int g[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int64_t col = a0 + tx * 4 + c;
+                if (col >= n) {
+                    g[c] = 0x7FFF;
+                    continue;
+                }
+                bool ok;
+                g[c] = fast_k(acc[i][c], inv, delta, K, ok);
+                if (!ok) g[c] = refine_k(acc[i][c], g[c], K, th);
+            }
+            uint2 w;
+            w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
+            w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);
+            *reinterpret_cast<uint2 *>(in.k + row * in.ldk + a0 + tx * 4) = w;
+        }
+    }
+}
+
+void launch_points_tiled(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s)
+{
+    const unsigned rows = (unsigned)((n_max + kTile - 1) / kTile);
+    hipLaunchKernelGGL(points_tile_kernel<0>, dim3(rows, rows, j.batch), dim3(256), 0, s, j);
+    hipLaunchKernelGGL(thresholds_kernel, dim3((j.kcap + 255) / 256, 1, j.batch), dim3(256), 0,
+                       s, j);
+    hipLaunchKernelGGL(points_tile_kernel<1>,
+                       dim3((unsigned)((ldk_max + kTile - 1) / kTile), rows, j.batch), dim3(256),
+                       0, s, j);
 }
 
 template <int D>
@@ -231,7 +331,7 @@ hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hip
     if (n_max == 0 || j.batch == 0) return hipGetLastError();
     if (j.d == 2) launch_points_d<2>(j, n_max, ldk_max, s);
     else if (j.d == 3) launch_points_d<3>(j, n_max, ldk_max, s);
-    else launch_points_d<0>(j, n_max, ldk_max, s);
+    else launch_points_tiled(j, n_max, ldk_max, s);
     return hipGetLastError();
 }
 

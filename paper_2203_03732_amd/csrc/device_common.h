@@ -48,6 +48,23 @@ __device__ inline uint32_t match_mask(uint4 kv, uint4 tv, int need)
     return m;
 }
 
+// Smallest k[e] + t[e] over the elements e whose bit is set in mask (a large
+// value if none).
+__device__ inline int min_sum_masked(uint4 kv, uint4 tv, uint32_t mask)
+{
+    const uint32_t kw[4] = {kv.x, kv.y, kv.z, kv.w};
+    const uint32_t tw[4] = {tv.x, tv.y, tv.z, tv.w};
+    int m = 0x7FFFFFFF;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int s0 = (int)(int16_t)(kw[i] & 0xFFFFu) + (int)(tw[i] & 0xFFFFu);
+        const int s1 = (int)(int16_t)(kw[i] >> 16) + (int)(tw[i] >> 16);
+        if ((mask >> (2 * i)) & 1u) m = min(m, s0);
+        if ((mask >> (2 * i + 1)) & 1u) m = min(m, s1);
+    }
+    return m;
+}
+
 __device__ inline uint32_t lanes_below(unsigned long long mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

@@ -80,6 +80,15 @@ struct BatchArgs {
     unsigned int *queue;
 };
 
+struct LossArgs {
+    int32_t batch;
+    int32_t d;
+    const int32_t *n_arr;
+    const int64_t *pt_off;
+    const float *X, *Y;
+    const int32_t *mate_a, *mate_b;
+};
+
 // cost.hip
 hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps,
                               int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s);
@@ -89,6 +98,11 @@ hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hip
 int32_t batch_max_n();
 hipError_t batch_grid(int32_t n_max, int32_t batch, int *grid);
 hipError_t launch_batch_solve(const BatchArgs &a, int32_t n_max, int grid, hipStream_t s);
+
+// loss.hip
+hipError_t launch_loss_fwd(const LossArgs &a, float *loss, hipStream_t s);
+hipError_t launch_loss_bwd(const LossArgs &a, int64_t n_max, const float *grad_loss, float *dX,
+                           float *dY, hipStream_t s);
 
 // solve.hip
 hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,

@@ -84,7 +84,8 @@ def test_round_costs_rejects_nan_and_range(ctx):
 
 
 @pytest.mark.parametrize("n,d,eps", [(1, 2, 0.1), (50, 2, 0.01), (1000, 2, 0.01),
-                                     (513, 3, 0.005), (200, 5, 0.05), (300, 16, 0.05)])
+                                     (513, 3, 0.005), (200, 5, 0.05), (300, 16, 0.05),
+                                     (150, 17, 0.02), (130, 64, 0.01), (65, 4, 0.3)])
 def test_build_costs_bit_exact(ctx, n, d, eps):
     X, Y = synth.uniform_points(n, d, seed=7 + d)
     k, m = ctx.build_costs(dev(X), dev(Y), eps)

@@ -323,3 +323,51 @@ def test_deterministic():
     for x in ("mate_b", "y_a", "y_b", "trace"):
         assert np.array_equal(r1[x], r2[x])
     assert r1["stats"] == r2["stats"]
+
+
+# ------------------------------------------------------- matching-based loss
+
+def _exact_ot(X, Y):
+    """min over permutations of (1/n) sum ||x_b - y_sigma(b)||^2, brute force."""
+    import itertools
+    n = X.shape[0]
+    best, arg = None, None
+    for perm in itertools.permutations(range(n)):
+        v = sum(float(((X[b] - Y[perm[b]]) ** 2).sum()) for b in range(n)) / n
+        if best is None or v < best:
+            best, arg = v, perm
+    return best, np.array(arg)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_loss_gradient_equals_finite_differences_of_exact_ot(seed):
+    """At generic points the optimal permutation is locally constant, so the
+    gradient of the exact OT cost W(X, Y) equals the fixed-plan gradient; the
+    oracle's formula must match central differences of W."""
+    rng = np.random.default_rng(seed)
+    n, d, h = 5, 2, 1e-5
+    X = rng.standard_normal((n, d))
+    Y = rng.standard_normal((n, d))
+    w, perm = _exact_ot(X, Y)
+    assert math.isclose(oracle.ot_loss(X, Y, perm), w, rel_tol=1e-12)
+    dX, dY = oracle.ot_loss_grad(X, Y, perm)
+    for M, G in ((X, dX), (Y, dY)):
+        for idx in np.ndindex(M.shape):
+            old = M[idx]
+            M[idx] = old + h
+            wp, _ = _exact_ot(X, Y)
+            M[idx] = old - h
+            wm, _ = _exact_ot(X, Y)
+            M[idx] = old
+            assert abs((wp - wm) / (2 * h) - G[idx]) < 1e-6
+
+
+def test_loss_gradient_scales_with_upstream_gradient():
+    rng = np.random.default_rng(1)
+    X, Y = rng.standard_normal((6, 3)), rng.standard_normal((6, 3))
+    mb = rng.permutation(6)
+    a1, b1 = oracle.ot_loss_grad(X, Y, mb, 1.0)
+    a3, b3 = oracle.ot_loss_grad(X, Y, mb, -3.0)
+    assert np.allclose(a3, -3.0 * a1) and np.allclose(b3, -3.0 * b1)
+    # the two gradients are opposite on matched pairs: sum over all is zero
+    assert np.allclose(a1.sum(0) + b1.sum(0), 0.0)
