@@ -13,8 +13,7 @@ namespace prot {
 // pw[p % 3] and is cleared by the leader during phase p - 1, after every
 // reader of its previous use (phase p - 3) has passed a grid barrier.
 struct alignas(128) Ctl {
-    unsigned long long arrive;    // this round: (arrivals << 32) | losers
-    unsigned long long flag;      // (round << 1) | 1 if the round ended the phase
+    unsigned long long arrive[3]; // round r -> [r % 3]: (arrivals << 32) | losers
     unsigned long long pw[3];     // phase p: (|B'| of phase p+1 << 32) | columns taken
     unsigned long long scanned;   // matrix entries examined
     int32_t status;               // 0 finished, 1 stopped at max_phases

@@ -30,25 +30,39 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kChunk = kWave * 8;   // columns examined per wave per load
 constexpr int kPrefetch = 8;        // chunks in flight in a long scan
+constexpr int kSlotBatch = 4;       // rows whose first chunks are loaded together
+
+__device__ inline bool taken_in_phase(unsigned long long key, uint32_t r0, uint32_t r)
+{
+    const uint32_t kr = (uint32_t)(key >> 32);
+    return kr >= r0 && kr < r;
+}
 
 // First column of this chunk (wave-wide, lowest column first) that is
 // admissible and not taken in an earlier round of this phase; -1 if none.
-// A column is taken iff its key was written in a round in [r0, r).
+// A column is taken iff its key was written in a round in [r0, r). The
+// first admissible column is checked alone first (usually it is free); only
+// if it was taken are all candidates of the chunk checked.
 __device__ inline int chunk_hit(int col0, uint4 kv, uint4 tv, int need, int lo, int hi,
                                 const unsigned long long *key, uint32_t r0, uint32_t r)
 {
     const uint32_t cand = col0 < hi ? (match_mask(kv, tv, need) & range_mask(col0, lo, hi)) : 0u;
+    const unsigned long long cb = __ballot(cand != 0u);
+    if (cb == 0ull) return -1;
+    {
+        const int L = __builtin_ctzll(cb);
+        const int a0 = __builtin_amdgcn_readlane(col0, L) +
+                       __builtin_ctz(__builtin_amdgcn_readlane(cand, L));
+        if (!taken_in_phase(ld_agent(key + a0), r0, r)) return a0;
+    }
     uint32_t hit = 0;
     if (cand) {
         unsigned long long kk[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) kk[e] = ((cand >> e) & 1u) ? ld_agent(key + col0 + e) : 0ull;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const uint32_t kr = (uint32_t)(kk[e] >> 32);
-            const bool taken = kr >= r0 && kr < r;
-            if (((cand >> e) & 1u) && !taken) hit |= 1u << e;
-        }
+        for (int e = 0; e < 8; ++e)
+            if (((cand >> e) & 1u) && !taken_in_phase(kk[e], r0, r)) hit |= 1u << e;
     }
     const unsigned long long bal = __ballot(hit != 0u);
     if (bal == 0ull) return -1;
@@ -58,38 +72,68 @@ __device__ inline int chunk_hit(int col0, uint4 kv, uint4 tv, int need, int lo, 
     return c + __builtin_ctz(h);
 }
 
+// Scan position j of row b visits column (origin + j) mod n, so a scan from
+// position pos covers the column ranges [origin + pos, n) and then
+// [0, origin), or only [origin + pos - n, origin).
+// (Two named ranges rather than an array, so that selecting one with a
+// runtime index stays in registers.)
+struct Segs {
+    int lo0, hi0, lo1, hi1;
+    __device__ int lo(int sg) const { return sg ? lo1 : lo0; }
+    __device__ int hi(int sg) const { return sg ? hi1 : hi0; }
+};
 
-// Scan row b (wave-cooperative) from scan position pos. Scan position j
-// visits column (origin + j) mod n, so the scan covers the column ranges
-// [origin + pos, n) and then [0, origin), or [origin + pos - n, origin).
-__device__ Hit scan_row(const int16_t *__restrict__ row, const uint16_t *t_lds, int n, int origin,
-                        int pos, int need, const unsigned long long *key, uint32_t r0, uint32_t r,
-                        int lane)
+__device__ inline Segs segments(int n, int origin, int pos)
 {
-    int lo[2], hi[2];
+    Segs s;
     const int c0 = origin + pos;
     if (c0 < n) {
-        lo[0] = c0; hi[0] = n; lo[1] = 0; hi[1] = origin;
+        s.lo0 = c0; s.hi0 = n; s.lo1 = 0; s.hi1 = origin;
     } else {
-        lo[0] = c0 - n; hi[0] = origin; lo[1] = 0; hi[1] = 0;
+        s.lo0 = c0 - n; s.hi0 = origin; s.lo1 = 0; s.hi1 = 0;
     }
-    for (int sg = 0; sg < 2; ++sg) {
-        const int slo = lo[sg], shi = hi[sg];
-        if (slo >= shi) continue;
-        int base = slo & ~7;
-        {   // the first chunk on its own: early rows usually hit in it
-            const int col0 = base + lane * 8;
-            uint4 kv = make_uint4(0u, 0u, 0u, 0u), tv = make_uint4(0u, 0u, 0u, 0u);
-            if (col0 < shi) {
-                kv = *reinterpret_cast<const uint4 *>(row + col0);
-                tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
-            }
-            const int a = chunk_hit(col0, kv, tv, need, slo, shi, key, r0, r);
-            if (a >= 0) return Hit{a >= origin ? a - origin : a - origin + n, a};
-            base += kChunk;
+    return s;
+}
+
+// Where the scan of slot s (held by lane s of the wave) starts this round.
+struct SlotView {
+    int b, pos, yb, origin;
+    Segs S;
+    int sg, base;   // first nonempty segment (1 if none) and its first chunk
+};
+
+__device__ inline SlotView slot_view(int s, int s_b, int s_pos, int s_yb, int origin_mode, int n)
+{
+    SlotView v;
+    v.b = __builtin_amdgcn_readlane(s_b, s);
+    v.pos = __builtin_amdgcn_readlane(s_pos, s);
+    v.yb = __builtin_amdgcn_readlane(s_yb, s);
+    v.origin = origin_mode == 0 ? v.b : 0;
+    v.S = segments(n, v.origin, v.pos);
+    v.sg = v.S.lo0 < v.S.hi0 ? 0 : 1;
+    v.base = v.S.lo(v.sg) & ~7;
+    return v;
+}
+
+__device__ inline Hit hit_at(int a, int origin, int n)
+{
+    return Hit{a >= origin ? a - origin : a - origin + n, a};
+}
+
+// Continue the wave-cooperative scan of a row in segment sg at column base
+// (a multiple of 8), kPrefetch chunks in flight; the duals come from LDS.
+__device__ Hit scan_from(const int16_t *__restrict__ row, const uint16_t *t_lds, int n, int origin,
+                         const Segs &S, int sg, int base, int need,
+                         const unsigned long long *key, uint32_t r0, uint32_t r, int lane)
+{
+    for (; sg < 2; ++sg) {
+        const int slo = S.lo(sg), shi = S.hi(sg);
+        if (slo >= shi) {
+            base = -1;
+            continue;
         }
+        if (base < 0) base = slo & ~7;
         while (base < shi) {
-            // kPrefetch chunks of the row in flight; the duals come from LDS
             uint4 kv[kPrefetch];
 #pragma unroll
             for (int u = 0; u < kPrefetch; ++u) {
@@ -103,10 +147,11 @@ __device__ Hit scan_row(const int16_t *__restrict__ row, const uint16_t *t_lds, 
                 uint4 tv = make_uint4(0u, 0u, 0u, 0u);
                 if (col0 < shi) tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
                 const int a = chunk_hit(col0, kv[u], tv, need, slo, shi, key, r0, r);
-                if (a >= 0) return Hit{a >= origin ? a - origin : a - origin + n, a};
+                if (a >= 0) return hit_at(a, origin, n);
             }
             base += kPrefetch * kChunk;
         }
+        base = -1;
     }
     return Hit{-1, -1};
 }
@@ -114,8 +159,7 @@ __device__ Hit scan_row(const int16_t *__restrict__ row, const uint16_t *t_lds, 
 __global__ void loop_reset_kernel(LoopArgs a)
 {
     Ctl *c = a.ctl;
-    c->arrive = 0;
-    c->flag = 0;
+    c->arrive[0] = c->arrive[1] = c->arrive[2] = 0;
     c->pw[0] = c->pw[1] = c->pw[2] = 0;
     c->scanned = 0;
     c->status = 0;
@@ -264,39 +308,96 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
             bool proposed = false;
             int32_t my_f = -1;             // row this lane's slot puts on the next B'
             uint32_t n_prop = 0;
+            // Rows are taken kSlotBatch at a time: their first chunks and the
+            // key of each chunk's first admissible column are loaded together,
+            // so the usual case (a free admissible column early in the row)
+            // costs two memory round trips for the whole batch.
             unsigned long long rem = active;
             while (rem) {
-                const int s = __builtin_ctzll(rem);
-                rem &= rem - 1;
-                const int b = __builtin_amdgcn_readlane(s_b, s);
-                const int pos = __builtin_amdgcn_readlane(s_pos, s);
-                const int yb = __builtin_amdgcn_readlane(s_yb, s);
-                const int origin = A.origin == 0 ? b : 0;
-                const Hit h = scan_row(A.k + (int64_t)b * A.ldk, t_lds, n, origin, pos, yb - 1,
-                                       A.key, r0, r, lane);
-                if (h.j >= 0) {
-                    wave_scan += (unsigned long long)(h.j - pos + 1);
-                    const unsigned long long kn =
-                        ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
-                    if (lane == s) {
-                        // the slot's own lane proposes, so proposals of several
-                        // slots are in flight together
-                        s_old = __hip_atomic_fetch_max(A.key + h.a, kn, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                        proposed = true;
-                        s_pos = h.j;
-                        s_a = h.a;
-                        s_key = kn;
+                int sl[kSlotBatch], a0q[kSlotBatch];
+                uint4 kvq[kSlotBatch];
+                unsigned long long k0q[kSlotBatch];
+#pragma unroll
+                for (int q = 0; q < kSlotBatch; ++q) {
+                    sl[q] = -1;
+                    a0q[q] = -1;
+                    k0q[q] = 0ull;
+                    kvq[q] = make_uint4(0u, 0u, 0u, 0u);
+                    if (!rem) continue;
+                    sl[q] = __builtin_ctzll(rem);
+                    rem &= rem - 1;
+                    const SlotView v = slot_view(sl[q], s_b, s_pos, s_yb, A.origin, n);
+                    const int col0 = v.base + lane * 8;
+                    if (col0 < v.S.hi(v.sg))
+                        kvq[q] = *reinterpret_cast<const uint4 *>(A.k + (int64_t)v.b * A.ldk + col0);
+                }
+#pragma unroll
+                for (int q = 0; q < kSlotBatch; ++q) {
+                    if (sl[q] < 0) continue;
+                    const SlotView v = slot_view(sl[q], s_b, s_pos, s_yb, A.origin, n);
+                    const int slo = v.S.lo(v.sg), shi = v.S.hi(v.sg);
+                    const int col0 = v.base + lane * 8;
+                    uint32_t cand = 0;
+                    if (col0 < shi) {
+                        const uint4 tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
+                        cand = match_mask(kvq[q], tv, v.yb - 1) & range_mask(col0, slo, shi);
                     }
-                    n_prop += 1;
-                } else {
-                    // b has no admissible untaken column: free in M', (III b).
-                    wave_scan += (unsigned long long)(n - pos);
-                    if (lane == s) {
-                        A.y_b[b] = yb + 1;
-                        my_f = b;
+                    const unsigned long long cb = __ballot(cand != 0u);
+                    if (cb) {
+                        const int L = __builtin_ctzll(cb);
+                        a0q[q] = __builtin_amdgcn_readlane(col0, L) +
+                                 __builtin_ctz(__builtin_amdgcn_readlane(cand, L));
+                        k0q[q] = ld_agent(A.key + a0q[q]);
                     }
-                    active &= ~(1ull << s);
+                }
+#pragma unroll
+                for (int q = 0; q < kSlotBatch; ++q) {
+                    if (sl[q] < 0) continue;
+                    const int s = sl[q];
+                    const SlotView v = slot_view(s, s_b, s_pos, s_yb, A.origin, n);
+                    const int b = v.b, pos = v.pos, yb = v.yb;
+                    Hit h{-1, -1};
+                    if (a0q[q] >= 0 && !taken_in_phase(k0q[q], r0, r)) {
+                        h = hit_at(a0q[q], v.origin, n);
+                    } else {
+                        const int slo = v.S.lo(v.sg), shi = v.S.hi(v.sg);
+                        int a = -1;
+                        if (a0q[q] >= 0) {  // the first admissible column was taken
+                            const int col0 = v.base + lane * 8;
+                            const uint4 tv = col0 < shi
+                                ? *reinterpret_cast<const uint4 *>(t_lds + col0)
+                                : make_uint4(0u, 0u, 0u, 0u);
+                            a = chunk_hit(col0, kvq[q], tv, yb - 1, slo, shi, A.key, r0, r);
+                        }
+                        if (a >= 0) h = hit_at(a, v.origin, n);
+                        else if (slo < shi)
+                            h = scan_from(A.k + (int64_t)b * A.ldk, t_lds, n, v.origin, v.S, v.sg,
+                                          v.base + kChunk, yb - 1, A.key, r0, r, lane);
+                    }
+                    if (h.j >= 0) {
+                        wave_scan += (unsigned long long)(h.j - pos + 1);
+                        const unsigned long long kn =
+                            ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
+                        if (lane == s) {
+                            // the slot's own lane proposes, so proposals of several
+                            // slots are in flight together
+                            s_old = __hip_atomic_fetch_max(A.key + h.a, kn, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                            proposed = true;
+                            s_pos = h.j;
+                            s_a = h.a;
+                            s_key = kn;
+                        }
+                        n_prop += 1;
+                    } else {
+                        // b has no admissible untaken column: free in M', (III b).
+                        wave_scan += (unsigned long long)(n - pos);
+                        if (lane == s) {
+                            A.y_b[b] = yb + 1;
+                            my_f = b;
+                        }
+                        active &= ~(1ull << s);
+                    }
                 }
             }
             // The first proposal to a column in a round: the column is in M'
@@ -331,9 +432,9 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                 if (my_f >= 0) Fn[(uint32_t)(base >> 32) + off_f + lanes_below(bf)] = my_f;
             }
 
-            // Grid barrier. The last workgroup to arrive adds up the losers of
-            // the round and publishes, with the release, whether the phase is
-            // over (no proposal lost: M' is maximal).
+            // Grid barrier on the round's word (arrivals << 32 | losers): when
+            // every workgroup has arrived it also holds the round's losers; the
+            // phase is over when nobody lost a proposal (M' is maximal).
             const bool timed = A.rtime != nullptr && r <= (uint32_t)kRoundTimeCap;
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -342,21 +443,16 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t losers = s_losers;
                 s_cnt_l = s_cnt_f = s_losers = 0;
-                const unsigned long long old = __hip_atomic_fetch_add(
-                    &ctl->arrive, (1ull << 32) | losers, __ATOMIC_RELEASE,
-                    __HIP_MEMORY_SCOPE_AGENT);
-                uint32_t over;
-                if ((uint32_t)(old >> 32) + 1u == gridDim.x) {
-                    over = ((uint32_t)old + losers) == 0u;
-                    st_agent(&ctl->arrive, 0ull);
-                    __hip_atomic_store(&ctl->flag, ((unsigned long long)r << 1) | over,
-                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                } else {
-                    unsigned long long f;
-                    while (((f = ld_agent(&ctl->flag)) >> 1) != (unsigned long long)r)
-                        __builtin_amdgcn_s_sleep(1);
-                    over = (uint32_t)(f & 1ull);
-                }
+                // the word of round r + 1 was last read at the barrier of
+                // round r - 2, which every workgroup has left
+                if (leader) st_agent(&ctl->arrive[(r + 1) % 3], 0ull);
+                unsigned long long *word = &ctl->arrive[r % 3];
+                __hip_atomic_fetch_add(word, (1ull << 32) | losers, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                unsigned long long w;
+                while (((w = ld_agent(word)) >> 32) != (unsigned long long)gridDim.x)
+                    __builtin_amdgcn_s_sleep(1);
+                const uint32_t over = (uint32_t)w == 0u;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 s_over = over;
                 if (timed && leader) {
