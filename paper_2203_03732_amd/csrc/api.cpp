@@ -48,6 +48,9 @@ struct prot_ctx {
     } *stage = nullptr;              // pinned host memory
 
     int64_t *rtime = nullptr;        // round timer (PROT_DEBUG_ROUND_TIMES=1)
+    bool force_tiled = false;        // PROT_COST_PATH=tiled: no matrix cores (diagnostics)
+    float *mfma_buf = nullptr;       // amax, emax, tile maxima of the matrix-core build
+    int64_t mfma_cap = 0;
     int64_t rtime_start = 0;
     int wgs_per_cu = 1;              // PROT_LOOP_WGS_PER_CU (diagnostics)
     int grid_npad = -1;
@@ -166,6 +169,28 @@ int grid_for(prot_ctx *c, int64_t n, int *grid)
     if (g > c->grid_max) g = c->grid_max;
     if (g < 1) g = 1;
     *grid = (int)g;
+    return PROT_OK;
+}
+
+// Workspace of the matrix-core build for `batch` instances of at most n_max
+// points; leaves j.mfma unset (tiled path) when d is small or it is disabled.
+int setup_mfma(prot_ctx *c, prot::PointsJob &j, int64_t n_max, float **buf, int64_t *cap)
+{
+    j.mfma = prot::MfmaAux{};
+    if (j.d < prot::kMfmaMinD || c->force_tiled) return PROT_OK;
+    const int64_t tx = (n_max + prot::kMfmaTile - 1) / prot::kMfmaTile;
+    const int64_t need = 2 * (int64_t)j.batch + (int64_t)j.batch * tx * tx;
+    if (need > *cap || !*buf) {
+        int rc = dev_alloc(c, buf, (size_t)need);
+        if (rc) return rc;
+        *cap = need;
+    }
+    j.mfma.amax = *buf;
+    j.mfma.emax = *buf + j.batch;
+    j.mfma.tile_max = *buf + 2 * j.batch;
+    j.mfma.tiles_x = (int32_t)tx;
+    j.mfma.tiles_per_inst = tx * tx;
+    j.mfma.cE = prot::mfma_error_constant(j.d);
     return PROT_OK;
 }
 
@@ -316,6 +341,9 @@ struct prot_batch {
     int32_t *err = nullptr;
     unsigned int *queue = nullptr;
     prot_instance_stats *stats_tmp = nullptr;
+    float *mfma_buf = nullptr;
+    int64_t mfma_cap = 0;
+    prot::MfmaAux mfma{};
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -351,6 +379,7 @@ int batch_enqueue(prot_batch *bp, hipStream_t s, const float *X, const float *Y,
     j.th = bp->th;
     j.kcap = bp->kcap;
     j.err = bp->err;
+    j.mfma = bp->mfma;
     HIP_TRY(c, prot::launch_points(j, bp->n_max, bp->ldk_max, s));
     prot::BatchArgs a{};
     a.batch = bp->batch;
@@ -374,6 +403,7 @@ int batch_enqueue(prot_batch *bp, hipStream_t s, const float *X, const float *Y,
     a.y_b = y_b;
     a.stats = reinterpret_cast<prot::InstanceStats *>(stats ? stats : bp->stats_tmp);
     a.queue = bp->queue;
+    a.rtime = c->rtime;
     HIP_TRY(c, prot::launch_batch_solve(a, bp->n_max, bp->grid, s));
     return PROT_OK;
 }
@@ -435,6 +465,7 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
         rc = PROT_E_NOMEM;
     for (int i = 0; i < 5 && !rc; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = PROT_E_HIP;
+    if (const char *v = std::getenv("PROT_COST_PATH")) c->force_tiled = std::strcmp(v, "tiled") == 0;
     if (const char *v = std::getenv("PROT_LOOP_WGS_PER_CU")) {
         const int w = std::atoi(v);
         if (w >= 1 && w <= 8) c->wgs_per_cu = w;
@@ -467,6 +498,7 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->kmat);
     (void)hipFree(c->th);
     (void)hipFree(c->rtime);
+    (void)hipFree(c->mfma_buf);
     if (c->stage) (void)hipHostFree(c->stage);
     for (int i = 0; i < 5; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -535,7 +567,9 @@ int prot_build_costs(prot_ctx *c, const float *X, const float *Y, int64_t n, int
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = ensure_thresholds(c, eps);
     if (rc) return rc;
-    HIP_TRY(c, prot::launch_points(points_job(c, X, Y, n, d, eps, k, ldk), n, ldk, c->stream));
+    prot::PointsJob j = points_job(c, X, Y, n, d, eps, k, ldk);
+    if ((rc = setup_mfma(c, j, n, &c->mfma_buf, &c->mfma_cap))) return rc;
+    HIP_TRY(c, prot::launch_points(j, n, ldk, c->stream));
     if (m_out)
         HIP_TRY(c, hipMemcpyAsync(m_out, &c->ctl->m, sizeof(float), hipMemcpyDeviceToDevice,
                                   c->stream));
@@ -626,8 +660,9 @@ int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, in
     if (!rc) rc = ensure_thresholds(c, ei);
     if (rc) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(c, prot::launch_points(points_job(c, X, Y, n, d, ei, c->kmat, ldk), n, ldk,
-                                   c->stream));
+    prot::PointsJob j = points_job(c, X, Y, n, d, ei, c->kmat, ldk);
+    if ((rc = setup_mfma(c, j, n, &c->mfma_buf, &c->mfma_cap))) return rc;
+    HIP_TRY(c, prot::launch_points(j, n, ldk, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     rc = run_loop(c, c->kmat, n, ldk, T, o, 0, mate_a, mate_b, y_a, y_b);
     if (rc) return rc;
@@ -704,6 +739,13 @@ int prot_batch_create(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t
     }
     if (!rc) rc = dev_alloc(c, &bp->err, 1);
     if (!rc) rc = dev_alloc(c, &bp->queue, 1);
+    if (!rc && batch > 0) {
+        prot::PointsJob j{};
+        j.d = d;
+        j.batch = batch;
+        rc = setup_mfma(c, j, n_max, &bp->mfma_buf, &bp->mfma_cap);
+        bp->mfma = j.mfma;
+    }
     if (rc) {
         prot_batch_destroy(bp);
         return rc;
@@ -730,6 +772,7 @@ int prot_batch_destroy(prot_batch *bp)
     (void)hipFree(bp->err);
     (void)hipFree(bp->queue);
     (void)hipFree(bp->stats_tmp);
+    (void)hipFree(bp->mfma_buf);
     delete bp;
     return PROT_OK;
 }

@@ -198,7 +198,7 @@ __device__ int ordered_list(BatchShared<NMAX> &S, int n, Flag flag, int32_t *out
 }
 
 template <int NMAX>
-__device__ void solve_instance(const BatchArgs &A, int inst, BatchShared<NMAX> &S)
+__device__ void solve_instance(const BatchArgs &A, int inst, BatchShared<NMAX> &S, bool timed)
 {
     const int tid = threadIdx.x;
     const int n = A.n_arr[inst];
@@ -253,6 +253,7 @@ __device__ void solve_instance(const BatchArgs &A, int inst, BatchShared<NMAX> &
             if (tid == 0) S.P = S.D = 0;
             __syncthreads();
             const uint32_t nact = S.nact[ac];
+            const int64_t t_start = timed ? (int64_t)wall_clock64() : 0;
             // widest lane groups that still give every active row its own group
             if (nact > (uint32_t)kBatchThreads / 16)
                 round_pass<4, NMAX>(S, k, ldk, n, A.origin, r0, r, ac, nx);
@@ -261,6 +262,12 @@ __device__ void solve_instance(const BatchArgs &A, int inst, BatchShared<NMAX> &
             else
                 round_pass<64, NMAX>(S, k, ldk, n, A.origin, r0, r, ac, nx);
             __syncthreads();
+            if (timed && tid == 0 && 4u * r <= 3u * (uint32_t)kRoundTimeCap) {
+                A.rtime[4 * (r - 1)] = t_start;
+                A.rtime[4 * (r - 1) + 1] = (int64_t)wall_clock64();
+                A.rtime[4 * (r - 1) + 2] = nact;
+                A.rtime[4 * (r - 1) + 3] = phases;
+            }
             const uint32_t P = S.P, D = S.D;
             if (P > 0) phase_rounds += 1;
             if (P == D) break;  // nobody lost a proposal: M' is maximal
@@ -380,7 +387,7 @@ __global__ void __launch_bounds__(kBatchThreads) batch_solve_kernel(BatchArgs A)
         const int job = S.job;
         __syncthreads();
         if (job >= A.batch) break;
-        solve_instance<NMAX>(A, A.order[job], S);
+        solve_instance<NMAX>(A, A.order[job], S, A.rtime != nullptr && job == 0);
     }
 }
 

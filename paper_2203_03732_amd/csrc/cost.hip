@@ -331,6 +331,7 @@ hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hip
     if (n_max == 0 || j.batch == 0) return hipGetLastError();
     if (j.d == 2) launch_points_d<2>(j, n_max, ldk_max, s);
     else if (j.d == 3) launch_points_d<3>(j, n_max, ldk_max, s);
+    else if (j.mfma.tile_max) return launch_points_mfma(j, j.mfma, n_max, ldk_max, s);
     else launch_points_tiled(j, n_max, ldk_max, s);
     return hipGetLastError();
 }

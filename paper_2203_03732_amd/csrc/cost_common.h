@@ -15,6 +15,16 @@ struct Instance {
     int16_t *k;
 };
 
+// Workspace of the matrix-core path (d >= 16), per instance.
+struct MfmaAux {
+    float *amax;              // largest approximate squared distance
+    float *emax;              // largest error bound
+    float *tile_max;          // per 64 x 64 tile: largest approximate value
+    int64_t tiles_per_inst;   // tiles_x * tiles_x
+    int32_t tiles_x;          // 64-wide tiles along n_max
+    float cE;                 // error-bound constant for this d
+};
+
 struct PointsJob {
     const float *X, *Y;        // packed points; instance i starts at row pt_off[i]
     const int64_t *pt_off;     // device, per instance (null: one instance at row 0)
@@ -31,6 +41,7 @@ struct PointsJob {
     int32_t kcap;              // floor(1 / eps) + 2
     int32_t *err;              // bit 0 set on a non-finite distance
     int32_t *kmax_out;         // optional: K of instance 0
+    MfmaAux mfma;              // used when mfma.tile_max is set (d >= 16)
 
     __device__ Instance instance(int i) const
     {

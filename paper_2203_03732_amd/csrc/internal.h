@@ -77,6 +77,7 @@ struct BatchArgs {
     int32_t *mate_a, *mate_b, *y_a, *y_b;
     InstanceStats *stats;
     unsigned int *queue;
+    int64_t *rtime;           // optional diagnostics: 4 int64 per round of the first job
 };
 
 struct LossArgs {
@@ -92,6 +93,13 @@ struct LossArgs {
 hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps,
                               int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s);
 hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s);
+
+// cost_mfma.hip
+constexpr int32_t kMfmaMinD = 16;          // d from which the matrix cores are used
+constexpr int64_t kMfmaTile = 64;
+float mfma_error_constant(int32_t d);
+hipError_t launch_points_mfma(const PointsJob &j, const MfmaAux &x, int64_t n_max,
+                              int64_t ldk_max, hipStream_t s);
 
 // batch.hip
 int32_t batch_max_n();

@@ -97,6 +97,22 @@ def test_build_costs_bit_exact(ctx, n, d, eps):
     assert (kg[:, n:] == 0x7FFF).all()
 
 
+def test_build_costs_matrix_core_path_far_from_origin(ctx):
+    """Points far from the origin make the matrix-core approximation's error
+    bound large relative to the distances, so most entries take the exact
+    fallback; the result must still equal the definition bit for bit."""
+    rng = np.random.default_rng(12)
+    n, d = 300, 24
+    X = (100.0 + rng.standard_normal((n, d))).astype(np.float32)
+    Y = (100.0 + rng.standard_normal((n, d))).astype(np.float32)
+    for eps in (0.05, 0.003):
+        k, m = ctx.build_costs(dev(X), dev(Y), eps)
+        torch.cuda.synchronize()
+        ko, mo = oracle.round_points_f32(X, Y, eps)
+        assert float(host(m)[0]) == mo
+        assert np.array_equal(host(k)[:, :n], ko)
+
+
 def test_build_costs_within_tolerance_of_binary64(ctx):
     """The binary32 cost is within 1e-5 of the binary64 cost (normalised),
     and every rounded-cost flip against binary64 is one step at a boundary."""
