@@ -30,7 +30,8 @@ struct prot_ctx {
     int64_t cap_n = 0;               // loop workspace capacity (vertices)
     unsigned long long *key = nullptr;
     uint16_t *t = nullptr;
-    int32_t *lists = nullptr;        // F0, F1, L0, L1, scratch(2n)
+    int32_t *lists = nullptr;        // completion scratch (2n)
+    unsigned long long *tlists = nullptr;  // tagged F0, F1, L0, L1 of the phase loop
     Ctl *ctl = nullptr;
     int64_t *trace = nullptr;
     long long *part_k = nullptr;
@@ -121,7 +122,10 @@ int ensure_loop(prot_ctx *c, int64_t n)
     int rc;
     if ((rc = dev_alloc(c, &c->key, (size_t)cap))) return rc;
     if ((rc = dev_alloc(c, &c->t, (size_t)round_up(cap, 8)))) return rc;
-    if ((rc = dev_alloc(c, &c->lists, (size_t)cap * 6))) return rc;
+    if ((rc = dev_alloc(c, &c->lists, (size_t)cap * 2))) return rc;
+    if ((rc = dev_alloc(c, &c->tlists, (size_t)cap * 4))) return rc;
+    // list entries carry tags; fresh memory must not hold one by chance
+    HIP_TRY(c, prot::launch_fill_u64(c->tlists, cap * 4, 0ull, c->stream));
     c->cap_n = cap;
     return PROT_OK;
 }
@@ -229,10 +233,10 @@ prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, 
     a.key = c->key;
     a.t = c->t;
     a.y_b = y_b;
-    a.F[0] = c->lists;
-    a.F[1] = c->lists + c->cap_n;
-    a.L[0] = c->lists + 2 * c->cap_n;
-    a.L[1] = c->lists + 3 * c->cap_n;
+    a.F[0] = c->tlists;
+    a.F[1] = c->tlists + c->cap_n;
+    a.L[0] = c->tlists + 2 * c->cap_n;
+    a.L[1] = c->tlists + 3 * c->cap_n;
     a.ctl = c->ctl;
     a.trace = c->trace;
     a.rtime = c->rtime;
@@ -265,8 +269,7 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
     HIP_TRY(c, prot::launch_loop(a, grid, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
     const int32_t complete = (o && o->no_completion) ? 0 : 1;
-    HIP_TRY(c, prot::launch_finish(a, complete, mate_a, mate_b, y_a, c->lists + 4 * c->cap_n,
-                                   c->stream));
+    HIP_TRY(c, prot::launch_finish(a, complete, mate_a, mate_b, y_a, c->lists, c->stream));
     return PROT_OK;
 }
 
@@ -283,6 +286,8 @@ int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kin
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const Ctl &h = c->stage->ctl;
+    if (h.err & 4) return fail(c, PROT_E_HIP, "phase loop: a list entry was not published in time");
+    if (h.err & 8) return fail(c, PROT_E_UNSUPPORTED, "phase loop: more than 2^32 rounds");
     if (!st) return PROT_OK;
     std::memset(st, 0, sizeof(*st));
     st->phases = h.phases;
@@ -457,6 +462,7 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
         return PROT_E_HIP;
     }
     int rc = dev_alloc(c, &c->ctl, 1);
+    if (!rc && hipMemset(c->ctl, 0, sizeof(Ctl)) != hipSuccess) rc = PROT_E_HIP;
     if (!rc) rc = dev_alloc(c, &c->trace, (size_t)4 * prot::kTraceCap);
     if (!rc) rc = dev_alloc(c, &c->part_k, prot::kFinalizeBlocks);
     if (!rc) rc = dev_alloc(c, &c->part_c, prot::kFinalizeBlocks);
@@ -491,6 +497,7 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->key);
     (void)hipFree(c->t);
     (void)hipFree(c->lists);
+    (void)hipFree(c->tlists);
     (void)hipFree(c->ctl);
     (void)hipFree(c->trace);
     (void)hipFree(c->part_k);

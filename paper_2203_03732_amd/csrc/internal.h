@@ -9,15 +9,19 @@
 namespace prot {
 
 // Device-side control block of one phase loop. Zeroed by the reset kernel.
-// Per-phase words live in a ring of three: the word of phase p is
-// pw[p % 3] and is cleared by the leader during phase p - 1, after every
-// reader of its previous use (phase p - 3) has passed a grid barrier.
+// Round r uses the word arrive[r % 3]; the leader clears the word of round
+// r + 1 during round r, after every reader of its previous use (round r - 2)
+// has passed a grid barrier.
 struct alignas(128) Ctl {
-    unsigned long long arrive[3]; // round r -> [r % 3]: (arrivals << 32) | losers
-    unsigned long long pw[3];     // phase p: (|B'| of phase p+1 << 32) | columns taken
+    unsigned long long arrive[3]; // per round: packed arrivals, losing workgroups, list counts
+    uint32_t free0;               // |B'| of the first phase (set by the init kernel)
+    uint32_t tag_last;            // last list tag used by a launch (kept across launches,
+                                  // so that no entry of an earlier launch matches a tag)
+    unsigned long long pad1[2];
     unsigned long long scanned;   // matrix entries examined
     int32_t status;               // 0 finished, 1 stopped at max_phases
-    int32_t err;                  // bit 0: cost out of range / non-finite; bit 1: bad state
+    int32_t err;                  // bit 0: cost out of range / non-finite; bit 1: bad state;
+                                  // bit 2: a list entry did not arrive; bit 3: round ids exhausted
     int64_t phases;
     int64_t sum_free;
     int64_t rounds;
@@ -45,8 +49,8 @@ struct LoopArgs {
     unsigned long long *key;  // per column: (round << 32) | ~b of its last winner
     uint16_t *t;              // per column: -y(a) (number of phases it was taken in)
     int32_t *y_b;
-    int32_t *F[2];            // free lists B' (ping-pong by phase parity)
-    int32_t *L[2];            // columns taken in a phase (ping-pong)
+    unsigned long long *F[2]; // free lists B', (phase tag << 32) | row (ping-pong by parity)
+    unsigned long long *L[2]; // columns taken in a phase, (phase tag << 32) | column
     Ctl *ctl;
     int64_t *trace;           // 4 int64 per phase
     int64_t *rtime;           // optional: 3 int64 per round (see kRoundTimeCap)
@@ -120,6 +124,7 @@ hipError_t launch_check_state(int64_t n, const int32_t *mate_a, const int32_t *m
                               hipStream_t s);
 hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max);
 hipError_t launch_clear_times(int64_t *rtime, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s);
 hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a,
                          int32_t *mate_b, int32_t *y_a, int32_t *scratch,

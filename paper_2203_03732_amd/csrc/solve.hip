@@ -14,13 +14,29 @@
 //       round appends the old mate (if any) to the next free list and the
 //       column to the list of columns taken this phase, and a row that finds
 //       nothing raises its own dual and re-enters the next free list.
-// One grid barrier ends each round. A round with no proposals, or in which
-// every proposal went to a distinct column (no losers), ends the phase.
+// One grid barrier ends each round. A round in which no workgroup saw a lost
+// proposal (or no proposal was made) ends the phase: M' is maximal.
 //
 // y(a) is stored as t(a) = -y(a) >= 0, the number of phases in which column a
-// was taken. Each workgroup keeps a copy of t in LDS as it stood at the start
-// of the phase (Section 2.2 updates the duals only after the greedy step) and
-// applies the previous phase's taken-column list at each phase start.
+// was taken. Each workgroup keeps t in LDS. The columns taken in a round are
+// read back by every workgroup at the start of the next round and marked
+// there (bit 15 of t, which makes k + t exceed any y(b) - 1), so the scan
+// itself needs no global memory besides the matrix row; their t is raised by
+// one at the same time (Section 2.2 lowers y(a) after the greedy step, and a
+// marked column is not looked at again in the phase), and the marks are
+// cleared when the phase ends.
+//
+// Communication between workgroups uses device-scope atomics and loads and
+// write-through stores only, so a round needs no L2 write-back or invalidate:
+//   * each round has one 64-bit word that every workgroup adds to once; the
+//     sum packs the arrivals, the workgroups that lost a proposal and the
+//     numbers of taken columns and freed rows, and the value returned to a
+//     workgroup is the prefix of the workgroups that arrived before it, which
+//     places its list entries;
+//   * list entries are written after the arrival, tagged with the phase, and
+//     a reader waits (bounded) until the entry carries the expected tag;
+//   * y(b) of a row that found nothing is stored before the arrival, and each
+//     wave waits for its stores to complete before the workgroup arrives.
 #include "device_common.h"
 #include "internal.h"
 
@@ -32,44 +48,52 @@ constexpr int kChunk = kWave * 8;   // columns examined per wave per load
 constexpr int kPrefetch = 8;        // chunks in flight in a long scan
 constexpr int kSlotBatch = 4;       // rows whose first chunks are loaded together
 
-__device__ inline bool taken_in_phase(unsigned long long key, uint32_t r0, uint32_t r)
+// Round word: sums over the workgroups that arrived.
+constexpr int kShiftFree = 21, kShiftLose = 42, kShiftArrive = 53;
+constexpr unsigned long long kField = (1ull << 21) - 1;
+constexpr uint16_t kTaken = 0x8000;            // mark: column taken earlier in the phase
+constexpr int kSpinLimit = 1 << 22;            // bounded waits for list entries
+constexpr uint32_t kRoundLimit = 0xFFFFFF00u;  // round ids must fit the key's 32 bits
+
+// Waits until this wave's earlier stores and atomics have completed.
+__device__ inline void wait_memory()
 {
-    const uint32_t kr = (uint32_t)(key >> 32);
-    return kr >= r0 && kr < r;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// First column of this chunk (wave-wide, lowest column first) that is
-// admissible and not taken in an earlier round of this phase; -1 if none.
-// A column is taken iff its key was written in a round in [r0, r). The
-// first admissible column is checked alone first (usually it is free); only
-// if it was taken are all candidates of the chunk checked.
-__device__ inline int chunk_hit(int col0, uint4 kv, uint4 tv, int need, int lo, int hi,
-                                const unsigned long long *key, uint32_t r0, uint32_t r)
+// Value of a tagged list entry ((tag << 32) | value) once it carries `tag`.
+// The wait is bounded: on time-out bit 2 of the error word is raised and the
+// value is used as found. The value is clamped to [0, n) either way.
+__device__ inline int32_t take_entry(const unsigned long long *p, uint32_t tag, int n, int32_t *err)
+{
+    unsigned long long v = ld_agent(p);
+    for (int spins = 0; (uint32_t)(v >> 32) != tag; v = ld_agent(p)) {
+        if (++spins > kSpinLimit) {
+            __hip_atomic_fetch_or(err, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    const int32_t x = (int32_t)(uint32_t)v;
+    return x < 0 ? 0 : (x >= n ? n - 1 : x);
+}
+
+__device__ inline unsigned long long tagged(uint32_t tag, int32_t v)
+{
+    return ((unsigned long long)tag << 32) | (uint32_t)v;
+}
+
+// First admissible, unmarked column of this chunk (wave-wide, lowest column
+// first); -1 if none.
+__device__ inline int chunk_hit(int col0, uint4 kv, uint4 tv, int need, int lo, int hi)
 {
     const uint32_t cand = col0 < hi ? (match_mask(kv, tv, need) & range_mask(col0, lo, hi)) : 0u;
     const unsigned long long cb = __ballot(cand != 0u);
     if (cb == 0ull) return -1;
-    {
-        const int L = __builtin_ctzll(cb);
-        const int a0 = __builtin_amdgcn_readlane(col0, L) +
-                       __builtin_ctz(__builtin_amdgcn_readlane(cand, L));
-        if (!taken_in_phase(ld_agent(key + a0), r0, r)) return a0;
-    }
-    uint32_t hit = 0;
-    if (cand) {
-        unsigned long long kk[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) kk[e] = ((cand >> e) & 1u) ? ld_agent(key + col0 + e) : 0ull;
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-            if (((cand >> e) & 1u) && !taken_in_phase(kk[e], r0, r)) hit |= 1u << e;
-    }
-    const unsigned long long bal = __ballot(hit != 0u);
-    if (bal == 0ull) return -1;
-    const int L = __builtin_ctzll(bal);
-    const uint32_t h = __builtin_amdgcn_readlane(hit, L);
-    const int c = __builtin_amdgcn_readlane(col0, L);
-    return c + __builtin_ctz(h);
+    const int L = __builtin_ctzll(cb);
+    return __builtin_amdgcn_readlane(col0, L) + __builtin_ctz(__builtin_amdgcn_readlane(cand, L));
 }
 
 // Scan position j of row b visits column (origin + j) mod n, so a scan from
@@ -123,8 +147,7 @@ __device__ inline Hit hit_at(int a, int origin, int n)
 // Continue the wave-cooperative scan of a row in segment sg at column base
 // (a multiple of 8), kPrefetch chunks in flight; the duals come from LDS.
 __device__ Hit scan_from(const int16_t *__restrict__ row, const uint16_t *t_lds, int n, int origin,
-                         const Segs &S, int sg, int base, int need,
-                         const unsigned long long *key, uint32_t r0, uint32_t r, int lane)
+                         const Segs &S, int sg, int base, int need, int lane)
 {
     for (; sg < 2; ++sg) {
         const int slo = S.lo(sg), shi = S.hi(sg);
@@ -146,7 +169,7 @@ __device__ Hit scan_from(const int16_t *__restrict__ row, const uint16_t *t_lds,
                 const int col0 = base + u * kChunk + lane * 8;
                 uint4 tv = make_uint4(0u, 0u, 0u, 0u);
                 if (col0 < shi) tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
-                const int a = chunk_hit(col0, kv[u], tv, need, slo, shi, key, r0, r);
+                const int a = chunk_hit(col0, kv[u], tv, need, slo, shi);
                 if (a >= 0) return hit_at(a, origin, n);
             }
             base += kPrefetch * kChunk;
@@ -160,7 +183,7 @@ __global__ void loop_reset_kernel(LoopArgs a)
 {
     Ctl *c = a.ctl;
     c->arrive[0] = c->arrive[1] = c->arrive[2] = 0;
-    c->pw[0] = c->pw[1] = c->pw[2] = 0;
+    c->free0 = 0;
     c->scanned = 0;
     c->status = 0;
     c->phases = c->sum_free = c->rounds = c->max_rounds = 0;
@@ -170,13 +193,14 @@ __global__ void loop_reset_kernel(LoopArgs a)
 
 
 // Initial state: y(b) = 1, y(a) = 0, M empty (Section 2.2), or a warm start.
-// The free list of the first phase goes to F[0]; its length to the high
-// half of pw[2] (the word read at the start of phase 0).
+// The free list of the first phase goes to F[0] with the launch's first tag
+// (one past the last tag of the previous launch), its length to ctl->free0.
 __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
                             const int32_t *mate_b, const int32_t *y_a)
 {
     const int n = a.n;
     const int lane = threadIdx.x & 63;
+    const uint32_t tag0 = a.ctl->tag_last + 1u;
     for (int base = blockIdx.x * blockDim.x; base < a.n_pad; base += gridDim.x * blockDim.x) {
         const int i = base + threadIdx.x;
         bool is_free = false;
@@ -185,7 +209,7 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
                 a.key[i] = 0ull;
                 a.t[i] = 0;
                 a.y_b[i] = 1;
-                a.F[0][i] = i;
+                a.F[0][i] = tagged(tag0, i);
             } else {
                 const int32_t m = mate_a[i];
                 a.key[i] = m >= 0 ? (unsigned long long)(uint32_t)~(uint32_t)m : 0ull;
@@ -199,15 +223,13 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
             const unsigned long long bal = __ballot(is_free);
             if (bal) {
                 uint32_t at = 0;
-                if (lane == 0)
-                    at = (uint32_t)(add_agent(&a.ctl->pw[2],
-                                              (unsigned long long)__popcll(bal) << 32) >> 32);
+                if (lane == 0) at = add_agent(&a.ctl->free0, (uint32_t)__popcll(bal));
                 at = __builtin_amdgcn_readfirstlane(at);
-                if (is_free) a.F[0][at + lanes_below(bal)] = i;
+                if (is_free) a.F[0][at + lanes_below(bal)] = tagged(tag0, i);
             }
         }
     }
-    if (!warm && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->pw[2] = (unsigned long long)n << 32;
+    if (!warm && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->free0 = (uint32_t)n;
 }
 
 // Warm-start check, O(n): the mate arrays form one matching and (I1) holds.
@@ -232,9 +254,8 @@ __global__ void check_state_kernel(int64_t n, const int32_t *mate_a, const int32
 __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
 {
     extern __shared__ __align__(16) uint16_t t_lds[];
-    __shared__ uint32_t s_n_i, s_nl, s_over;
-    __shared__ uint32_t s_cnt_l, s_cnt_f, s_losers;
-    __shared__ unsigned long long s_base, s_scan;
+    __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose;
+    __shared__ unsigned long long s_old_word, s_word, s_scan;
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wpg = blockDim.x / kWave;
@@ -246,82 +267,87 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
 
     for (int i = threadIdx.x; i < A.n_pad; i += blockDim.x) t_lds[i] = A.t[i];
     if (threadIdx.x == 0) {
-        s_cnt_l = s_cnt_f = s_losers = 0;
+        s_cnt_l = s_cnt_f = s_lose = 0;
         s_scan = 0;
     }
     __syncthreads();
 
-    uint32_t r = 0;           // id of the last round (keys carry it)
-    int64_t p = 0;            // phase index within this launch
-    int64_t phase_rounds = 0; // leader only
-    uint32_t l_prev = 0;      // leader only
+    uint32_t n_i = ld_agent(&ctl->free0);  // |B'| of the current phase
+    // List entries written in phase p carry tag0 + p + 1; the free list of
+    // the first phase carries tag0.
+    const uint32_t tag0 = ld_agent(&ctl->tag_last) + 1u;
+    uint32_t r = 0;                        // id of the last round (keys carry it)
+    int64_t p = 0;                         // phase index within this launch
+    // statistics, kept by the leader
+    int64_t st_rounds = 0, st_max_rounds = 0, st_sum_free = 0;
     for (;;) {
-        // |B'| of this phase and the columns taken in the previous one.
-        if (threadIdx.x == 0) {
-            const unsigned long long w = ld_agent(&ctl->pw[(p + 2) % 3]);
-            s_n_i = (uint32_t)(w >> 32);
-            s_nl = (uint32_t)w;
-        }
-        __syncthreads();
-        const uint32_t n_i = s_n_i;
-        if (p > 0) {
-            // Step (III a) of the previous phase, applied to this copy of y(a).
-            const uint32_t nl = s_nl;
-            const int32_t *Lp = A.L[(p - 1) & 1];
-            for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) t_lds[Lp[i]] += 1;
-        }
-        __syncthreads();
         if ((int64_t)n_i <= A.T) break;
         if (A.max_phases > 0 && p >= A.max_phases) {
             if (leader) ctl->status = 1;
             break;
         }
+        if (r >= kRoundLimit) {
+            if (leader) __hip_atomic_fetch_or(&ctl->err, 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
         if (leader) {
-            ctl->phases = p + 1;
-            ctl->sum_free += n_i;
-            st_agent(&ctl->pw[(p + 1) % 3], 0ull);
+            st_sum_free += n_i;
             if (p < kTraceCap) A.trace[4 * p] = n_i;
             if (p + 1 < kTraceCap)
                 for (int i = 0; i < 4; ++i) st_agent(&A.trace[4 * (p + 1) + i], (int64_t)0);
-            l_prev = 0;
         }
-        const uint32_t r0 = r + 1;
-        const int32_t *Fc = A.F[p & 1];
-        int32_t *Fn = A.F[(p + 1) & 1];
-        int32_t *Lc = A.L[p & 1];
-        unsigned long long *pwc = &ctl->pw[p % 3];
+        const uint32_t tag = tag0 + (uint32_t)(p + 1);  // entries written in this phase
+        const unsigned long long *Fc = A.F[p & 1];
+        unsigned long long *Fn = A.F[(p + 1) & 1];
+        unsigned long long *Lc = A.L[p & 1];
+        uint32_t lcount = 0, fcount = 0;  // list lengths after the last finished round
+        uint32_t l_new = 0;               // columns taken in the last finished round
+        int64_t phase_rounds = 0;
 
         // Slot s of this wave is entry gw + s*W of B'; lane s holds its state.
         const uint32_t nslots = gw < n_i ? (n_i - gw + W - 1) / W : 0u;
         int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0;
         unsigned long long s_key = 0;
         if ((uint32_t)lane < nslots) {
-            s_b = Fc[gw + (uint32_t)lane * W];
-            s_yb = A.y_b[s_b];
+            s_b = take_entry(Fc + gw + (uint32_t)lane * W, tag0 + (uint32_t)p, n, &ctl->err);
+            s_yb = ld_agent(A.y_b + s_b);
         }
         unsigned long long active = __ballot((uint32_t)lane < nslots);
         unsigned long long wave_scan = 0;
 
         for (;;) {
             r += 1;
+            if (l_new) {
+                // Columns taken in the previous round: marked for the rest of
+                // the phase, t raised now (step (III a)).
+                const uint32_t lb = lcount - l_new;
+                for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
+                    const int32_t a = take_entry(Lc + lb + i, tag, n, &ctl->err);
+                    t_lds[a] = (uint16_t)((t_lds[a] + 1) | kTaken);
+                }
+                // the rows of this wave that proposed: won (matched in M') or
+                // lost (resume one position after the column)
+                bool mine = (active >> lane) & 1ull;
+                if (mine) {
+                    if (ld_agent(A.key + s_a) == s_key) mine = false;
+                    else s_pos += 1;
+                }
+                active = __ballot(mine);
+                __syncthreads();
+            }
             unsigned long long s_old = 0;  // key a proposal of this lane's slot replaced
             bool proposed = false;
             int32_t my_f = -1;             // row this lane's slot puts on the next B'
             uint32_t n_prop = 0;
-            // Rows are taken kSlotBatch at a time: their first chunks and the
-            // key of each chunk's first admissible column are loaded together,
-            // so the usual case (a free admissible column early in the row)
-            // costs two memory round trips for the whole batch.
+            // Rows are taken kSlotBatch at a time so that their first chunks
+            // are loaded together.
             unsigned long long rem = active;
             while (rem) {
-                int sl[kSlotBatch], a0q[kSlotBatch];
+                int sl[kSlotBatch];
                 uint4 kvq[kSlotBatch];
-                unsigned long long k0q[kSlotBatch];
 #pragma unroll
                 for (int q = 0; q < kSlotBatch; ++q) {
                     sl[q] = -1;
-                    a0q[q] = -1;
-                    k0q[q] = 0ull;
                     kvq[q] = make_uint4(0u, 0u, 0u, 0u);
                     if (!rem) continue;
                     sl[q] = __builtin_ctzll(rem);
@@ -334,46 +360,19 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
 #pragma unroll
                 for (int q = 0; q < kSlotBatch; ++q) {
                     if (sl[q] < 0) continue;
-                    const SlotView v = slot_view(sl[q], s_b, s_pos, s_yb, A.origin, n);
-                    const int slo = v.S.lo(v.sg), shi = v.S.hi(v.sg);
-                    const int col0 = v.base + lane * 8;
-                    uint32_t cand = 0;
-                    if (col0 < shi) {
-                        const uint4 tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
-                        cand = match_mask(kvq[q], tv, v.yb - 1) & range_mask(col0, slo, shi);
-                    }
-                    const unsigned long long cb = __ballot(cand != 0u);
-                    if (cb) {
-                        const int L = __builtin_ctzll(cb);
-                        a0q[q] = __builtin_amdgcn_readlane(col0, L) +
-                                 __builtin_ctz(__builtin_amdgcn_readlane(cand, L));
-                        k0q[q] = ld_agent(A.key + a0q[q]);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kSlotBatch; ++q) {
-                    if (sl[q] < 0) continue;
                     const int s = sl[q];
                     const SlotView v = slot_view(s, s_b, s_pos, s_yb, A.origin, n);
                     const int b = v.b, pos = v.pos, yb = v.yb;
+                    const int slo = v.S.lo(v.sg), shi = v.S.hi(v.sg);
+                    const int col0 = v.base + lane * 8;
+                    const uint4 tv = col0 < shi ? *reinterpret_cast<const uint4 *>(t_lds + col0)
+                                                : make_uint4(0u, 0u, 0u, 0u);
                     Hit h{-1, -1};
-                    if (a0q[q] >= 0 && !taken_in_phase(k0q[q], r0, r)) {
-                        h = hit_at(a0q[q], v.origin, n);
-                    } else {
-                        const int slo = v.S.lo(v.sg), shi = v.S.hi(v.sg);
-                        int a = -1;
-                        if (a0q[q] >= 0) {  // the first admissible column was taken
-                            const int col0 = v.base + lane * 8;
-                            const uint4 tv = col0 < shi
-                                ? *reinterpret_cast<const uint4 *>(t_lds + col0)
-                                : make_uint4(0u, 0u, 0u, 0u);
-                            a = chunk_hit(col0, kvq[q], tv, yb - 1, slo, shi, A.key, r0, r);
-                        }
-                        if (a >= 0) h = hit_at(a, v.origin, n);
-                        else if (slo < shi)
-                            h = scan_from(A.k + (int64_t)b * A.ldk, t_lds, n, v.origin, v.S, v.sg,
-                                          v.base + kChunk, yb - 1, A.key, r0, r, lane);
-                    }
+                    const int a = chunk_hit(col0, kvq[q], tv, yb - 1, slo, shi);
+                    if (a >= 0) h = hit_at(a, v.origin, n);
+                    else if (slo < shi)
+                        h = scan_from(A.k + (int64_t)b * A.ldk, t_lds, n, v.origin, v.S, v.sg,
+                                      v.base + kChunk, yb - 1, lane);
                     if (h.j >= 0) {
                         wave_scan += (unsigned long long)(h.j - pos + 1);
                         const unsigned long long kn =
@@ -393,7 +392,7 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                         // b has no admissible untaken column: free in M', (III b).
                         wave_scan += (unsigned long long)(n - pos);
                         if (lane == s) {
-                            A.y_b[b] = yb + 1;
+                            st_agent(A.y_b + b, yb + 1);
                             my_f = b;
                         }
                         active &= ~(1ull << s);
@@ -414,73 +413,82 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                 const uint32_t nl = (uint32_t)__popcll(bl), nf = (uint32_t)__popcll(bf);
                 off_l = atomicAdd(&s_cnt_l, nl);
                 off_f = atomicAdd(&s_cnt_f, nf);
-                atomicAdd(&s_losers, n_prop - nl);
+                if (n_prop > nl) s_lose = 1;  // a proposal of this wave lost
             }
             off_l = __builtin_amdgcn_readfirstlane(off_l);
             off_f = __builtin_amdgcn_readfirstlane(off_f);
+            wait_memory();  // y(b) stores of this wave are complete
             __syncthreads();
-            if (threadIdx.x == 0) {
-                const uint32_t cl = s_cnt_l, cf = s_cnt_f;
-                unsigned long long base = 0;
-                if (cl | cf) base = add_agent(pwc, ((unsigned long long)cf << 32) | cl);
-                s_base = base;
-            }
-            __syncthreads();
-            {
-                const unsigned long long base = s_base;
-                if (my_l >= 0) Lc[(uint32_t)base + off_l + lanes_below(bl)] = my_l;
-                if (my_f >= 0) Fn[(uint32_t)(base >> 32) + off_f + lanes_below(bf)] = my_f;
-            }
 
-            // Grid barrier on the round's word (arrivals << 32 | losers): when
-            // every workgroup has arrived it also holds the round's losers; the
-            // phase is over when nobody lost a proposal (M' is maximal).
+            // Arrival: the returned word is the sum over the workgroups that
+            // arrived before this one, which places this workgroup's entries.
             const bool timed = A.rtime != nullptr && r <= (uint32_t)kRoundTimeCap;
-            __syncthreads();
+            unsigned long long *word = &ctl->arrive[r % 3];
             if (threadIdx.x == 0) {
                 if (timed)
                     __hip_atomic_fetch_max(&A.rtime[3 * (r - 1)], (int64_t)wall_clock64(),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t losers = s_losers;
-                s_cnt_l = s_cnt_f = s_losers = 0;
-                // the word of round r + 1 was last read at the barrier of
-                // round r - 2, which every workgroup has left
-                if (leader) st_agent(&ctl->arrive[(r + 1) % 3], 0ull);
-                unsigned long long *word = &ctl->arrive[r % 3];
-                __hip_atomic_fetch_add(word, (1ull << 32) | losers, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                // the word of round r + 1 was last read in round r - 2, which
+                // every workgroup has left
+                if (leader) {
+                    st_agent(&ctl->arrive[(r + 1) % 3], 0ull);
+                    wait_memory();
+                }
+                const unsigned long long add = (1ull << kShiftArrive) |
+                                               ((unsigned long long)s_lose << kShiftLose) |
+                                               ((unsigned long long)s_cnt_f << kShiftFree) |
+                                               (unsigned long long)s_cnt_l;
+                s_cnt_l = s_cnt_f = s_lose = 0;
+                s_old_word = __hip_atomic_fetch_add(word, add, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+            {
+                const unsigned long long o = s_old_word;
+                if (my_l >= 0)
+                    st_agent(Lc + lcount + (uint32_t)(o & kField) + off_l + lanes_below(bl),
+                             tagged(tag, my_l));
+                if (my_f >= 0)
+                    st_agent(Fn + fcount + (uint32_t)((o >> kShiftFree) & kField) + off_f +
+                                 lanes_below(bf),
+                             tagged(tag, my_f));
+            }
+            if (threadIdx.x == 0) {
                 unsigned long long w;
-                while (((w = ld_agent(word)) >> 32) != (unsigned long long)gridDim.x)
+                while (((w = ld_agent(word)) >> kShiftArrive) != (unsigned long long)gridDim.x)
                     __builtin_amdgcn_s_sleep(1);
-                const uint32_t over = (uint32_t)w == 0u;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                s_over = over;
+                s_word = w;
                 if (timed && leader) {
                     A.rtime[3 * (r - 1) + 1] = (int64_t)wall_clock64();
                     A.rtime[3 * (r - 1) + 2] = p;
                 }
             }
             __syncthreads();
-            const bool over = s_over != 0u;
-            if (leader) {
-                const uint32_t l_now = (uint32_t)ld_agent(pwc);
-                if (l_now > l_prev) {  // some proposal was made this round
-                    ctl->rounds += 1;
-                    phase_rounds += 1;
-                    if (p < kTraceCap) {
-                        A.trace[4 * p + 1] += 1;
-                        A.trace[4 * p + 3] = l_now;
-                    }
-                }
-                l_prev = l_now;
+            const unsigned long long w = s_word;
+            l_new = (uint32_t)(w & kField);
+            lcount += l_new;
+            fcount += (uint32_t)((w >> kShiftFree) & kField);
+            if (l_new) phase_rounds += 1;  // some proposal was made this round
+            if (((w >> kShiftLose) & 0x7FFull) == 0) break;
+        }
+        // Columns taken in the last round get their t raised; then the marks
+        // of the phase are cleared.
+        {
+            const uint32_t lb = lcount - l_new;
+            for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
+                const int32_t a = take_entry(Lc + lb + i, tag, n, &ctl->err);
+                t_lds[a] = (uint16_t)(t_lds[a] + 1);
             }
-            if (over) break;
-            bool mine = (active >> lane) & 1ull;
-            if (mine) {
-                if (ld_agent(A.key + s_a) == s_key) mine = false;  // won: matched in M'
-                else s_pos += 1;                                  // lost: resume after
-            }
-            active = __ballot(mine);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x * 8; i < A.n_pad; i += blockDim.x * 8) {
+            uint4 *q = reinterpret_cast<uint4 *>(t_lds + i);
+            uint4 v = *q;
+            v.x &= 0x7FFF7FFFu;
+            v.y &= 0x7FFF7FFFu;
+            v.z &= 0x7FFF7FFFu;
+            v.w &= 0x7FFF7FFFu;
+            *q = v;
         }
         // entries examined this phase, one atomic per workgroup
         if (lane == 0 && wave_scan) atomicAdd(&s_scan, wave_scan);
@@ -494,12 +502,25 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
             }
         }
         if (leader) {
-            if (phase_rounds > ctl->max_rounds) ctl->max_rounds = phase_rounds;
-            phase_rounds = 0;
+            st_rounds += phase_rounds;
+            if (phase_rounds > st_max_rounds) st_max_rounds = phase_rounds;
+            if (p < kTraceCap) {
+                A.trace[4 * p + 1] = phase_rounds;
+                A.trace[4 * p + 3] = lcount;
+            }
         }
+        n_i = fcount;
         p += 1;
     }
-    if (leader) ctl->free_after = s_n_i;
+    if (leader) {
+        // after a phase every workgroup has read tag_last (before arriving)
+        if (p > 0) ctl->tag_last = tag0 + (uint32_t)p;
+        ctl->phases = p;
+        ctl->sum_free = st_sum_free;
+        ctl->rounds = st_rounds;
+        ctl->max_rounds = st_max_rounds;
+        ctl->free_after = n_i;
+    }
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < n; i += blockDim.x) A.t[i] = t_lds[i];
 }
@@ -659,6 +680,13 @@ hipError_t launch_clear_times(int64_t *rtime, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, (int64_t *)p, n,
+                       (int64_t)v);
+    return hipGetLastError();
+}
+
 hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max)
 {
     const size_t lds = (size_t)n_pad * sizeof(uint16_t);
@@ -678,6 +706,8 @@ hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max)
     if (e != hipSuccess) return e;
     if (per_cu > wgs_per_cu) per_cu = wgs_per_cu;
     *grid_max = per_cu * cus;
+    // arrivals and losing workgroups are 11-bit fields of the round word
+    if (*grid_max > 2047) *grid_max = 2047;
     return hipSuccess;
 }
 
