@@ -32,6 +32,7 @@ struct prot_ctx {
     uint16_t *t = nullptr;
     int32_t *lists = nullptr;        // completion scratch (2n)
     unsigned long long *tlists = nullptr;  // tagged F0, F1, L0, L1 of the phase loop
+    unsigned long long *words = nullptr;   // round words of the phase loop barrier
     Ctl *ctl = nullptr;
     int64_t *trace = nullptr;
     long long *part_k = nullptr;
@@ -50,6 +51,7 @@ struct prot_ctx {
 
     int64_t *rtime = nullptr;        // round timer (PROT_DEBUG_ROUND_TIMES=1)
     bool force_tiled = false;        // PROT_COST_PATH=tiled: no matrix cores (diagnostics)
+    int loop_groups = 8;             // barrier groups of the phase loop (PROT_LOOP_GROUPS)
     float *mfma_buf = nullptr;       // amax, emax, tile maxima of the matrix-core build
     int64_t mfma_cap = 0;
     int64_t rtime_start = 0;
@@ -123,9 +125,9 @@ int ensure_loop(prot_ctx *c, int64_t n)
     if ((rc = dev_alloc(c, &c->key, (size_t)cap))) return rc;
     if ((rc = dev_alloc(c, &c->t, (size_t)round_up(cap, 8)))) return rc;
     if ((rc = dev_alloc(c, &c->lists, (size_t)cap * 2))) return rc;
-    if ((rc = dev_alloc(c, &c->tlists, (size_t)cap * 4))) return rc;
+    if ((rc = dev_alloc(c, &c->tlists, (size_t)cap * 4 * prot::kMaxGroups))) return rc;
     // list entries carry tags; fresh memory must not hold one by chance
-    HIP_TRY(c, prot::launch_fill_u64(c->tlists, cap * 4, 0ull, c->stream));
+    HIP_TRY(c, prot::launch_fill_u64(c->tlists, cap * 4 * prot::kMaxGroups, 0ull, c->stream));
     c->cap_n = cap;
     return PROT_OK;
 }
@@ -233,10 +235,13 @@ prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, 
     a.key = c->key;
     a.t = c->t;
     a.y_b = y_b;
+    const int64_t region = c->cap_n * prot::kMaxGroups;
     a.F[0] = c->tlists;
-    a.F[1] = c->tlists + c->cap_n;
-    a.L[0] = c->tlists + 2 * c->cap_n;
-    a.L[1] = c->tlists + 3 * c->cap_n;
+    a.F[1] = c->tlists + region;
+    a.L[0] = c->tlists + 2 * region;
+    a.L[1] = c->tlists + 3 * region;
+    a.list_cap = c->cap_n;
+    a.words = c->words;
     a.ctl = c->ctl;
     a.trace = c->trace;
     a.rtime = c->rtime;
@@ -253,6 +258,7 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
     int grid = 0;
     if ((rc = grid_for(c, n, &grid))) return rc;
     prot::LoopArgs a = loop_args(c, k, n, ldk, T, o, y_b);
+    a.groups = std::min(c->loop_groups, grid);
     if (warm) {
         // (I1) and the matching structure of the given state, O(n).
         HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
@@ -463,6 +469,7 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
     }
     int rc = dev_alloc(c, &c->ctl, 1);
     if (!rc && hipMemset(c->ctl, 0, sizeof(Ctl)) != hipSuccess) rc = PROT_E_HIP;
+    if (!rc) rc = dev_alloc(c, &c->words, (size_t)3 * prot::kMaxGroups * prot::kWordStride);
     if (!rc) rc = dev_alloc(c, &c->trace, (size_t)4 * prot::kTraceCap);
     if (!rc) rc = dev_alloc(c, &c->part_k, prot::kFinalizeBlocks);
     if (!rc) rc = dev_alloc(c, &c->part_c, prot::kFinalizeBlocks);
@@ -472,6 +479,10 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
     for (int i = 0; i < 5 && !rc; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = PROT_E_HIP;
     if (const char *v = std::getenv("PROT_COST_PATH")) c->force_tiled = std::strcmp(v, "tiled") == 0;
+    if (const char *v = std::getenv("PROT_LOOP_GROUPS")) {
+        const int g = std::atoi(v);
+        if (g >= 1 && g <= prot::kMaxGroups) c->loop_groups = g;
+    }
     if (const char *v = std::getenv("PROT_LOOP_WGS_PER_CU")) {
         const int w = std::atoi(v);
         if (w >= 1 && w <= 8) c->wgs_per_cu = w;
@@ -498,6 +509,7 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->t);
     (void)hipFree(c->lists);
     (void)hipFree(c->tlists);
+    (void)hipFree(c->words);
     (void)hipFree(c->ctl);
     (void)hipFree(c->trace);
     (void)hipFree(c->part_k);

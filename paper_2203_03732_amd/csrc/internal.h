@@ -9,11 +9,8 @@
 namespace prot {
 
 // Device-side control block of one phase loop. Zeroed by the reset kernel.
-// Round r uses the word arrive[r % 3]; the leader clears the word of round
-// r + 1 during round r, after every reader of its previous use (round r - 2)
-// has passed a grid barrier.
 struct alignas(128) Ctl {
-    unsigned long long arrive[3]; // per round: packed arrivals, losing workgroups, list counts
+    unsigned long long pad2[3];
     uint32_t free0;               // |B'| of the first phase (set by the init kernel)
     uint32_t tag_last;            // last list tag used by a launch (kept across launches,
                                   // so that no entry of an earlier launch matches a tag)
@@ -33,6 +30,15 @@ struct alignas(128) Ctl {
 };
 
 constexpr int kLoopThreads = 1024;      // threads per workgroup of the loop
+// Round barrier: the workgroups are split into up to kMaxGroups groups
+// (blockIdx % G); each round has one word per group, kWordStride words
+// apart (one 128-byte line each), in a ring of three rounds: round r uses
+// words[(r % 3) * kMaxGroups * kWordStride + g * kWordStride]. Workgroup 0
+// clears the words of round r + 1 during round r, after every reader of
+// their previous use (round r - 2) has passed a barrier. Each list of the
+// loop is split into G regions of list_cap entries, one per group.
+constexpr int kMaxGroups = 32;
+constexpr int kWordStride = 16;
 constexpr int kTraceCap = 65536;        // phases recorded in the trace
 constexpr int kFinalizeBlocks = 256;    // partial sums of the finalize kernel
 constexpr int kRoundTimeCap = 65536;    // rounds recorded by the round timer
@@ -51,6 +57,10 @@ struct LoopArgs {
     int32_t *y_b;
     unsigned long long *F[2]; // free lists B', (phase tag << 32) | row (ping-pong by parity)
     unsigned long long *L[2]; // columns taken in a phase, (phase tag << 32) | column
+    int64_t list_cap;         // entries per group region of F and L (>= n)
+    int32_t groups;           // G, 1 <= G <= min(kMaxGroups, grid)
+    int32_t pad2;
+    unsigned long long *words;  // round words, 3 * kMaxGroups * kWordStride
     Ctl *ctl;
     int64_t *trace;           // 4 int64 per phase
     int64_t *rtime;           // optional: 3 int64 per round (see kRoundTimeCap)

@@ -48,7 +48,8 @@ constexpr int kChunk = kWave * 8;   // columns examined per wave per load
 constexpr int kPrefetch = 8;        // chunks in flight in a long scan
 constexpr int kSlotBatch = 4;       // rows whose first chunks are loaded together
 
-// Round word: sums over the workgroups that arrived.
+// Round words: workgroup w adds to word w % G of the round; each word sums
+// over the workgroups of its group that arrived.
 constexpr int kShiftFree = 21, kShiftLose = 42, kShiftArrive = 53;
 constexpr unsigned long long kField = (1ull << 21) - 1;
 constexpr uint16_t kTaken = 0x8000;            // mark: column taken earlier in the phase
@@ -78,6 +79,33 @@ __device__ inline int32_t take_entry(const unsigned long long *p, uint32_t tag, 
     }
     const int32_t x = (int32_t)(uint32_t)v;
     return x < 0 ? 0 : (x >= n ? n - 1 : x);
+}
+
+// Group j holding position i of a list split into group regions, given the
+// exclusive prefix sums pre[0..G) of the region lengths.
+__device__ inline int group_of(const uint32_t *pre, int G, uint32_t i)
+{
+    int j = 0;
+    while (j + 1 < G && pre[j + 1] <= i) ++j;
+    return j;
+}
+
+__device__ inline uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ inline uint32_t wave_exclusive_scan(uint32_t v, int lane)
+{
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    return x - v;
 }
 
 __device__ inline unsigned long long tagged(uint32_t tag, int32_t v)
@@ -179,10 +207,65 @@ __device__ Hit scan_from(const int16_t *__restrict__ row, const uint16_t *t_lds,
     return Hit{-1, -1};
 }
 
+// Team scan: R waves of one workgroup share a row. The row's chunks (kChunk
+// columns, segment 0 first, then segment 1, each aligned down to 8 columns)
+// are dealt out round-robin, chunk c to wave c mod R; wave k = this wave's
+// rank. Returns the scan position of this wave's first hit (its chunks are
+// visited in order), or kNoHit. The first pass loads one chunk per wave;
+// later passes kPrefetch each, and stop once the team's best hit so far
+// (*best, in LDS) precedes them.
+constexpr int kNoHit = 0x7FFFFFFF;
+
+__device__ int team_scan(const int16_t *__restrict__ row, const uint16_t *t_lds, int n, int origin,
+                         const Segs &S, int need, int k, int R, int lane, const int *best)
+{
+    const int b0 = S.lo0 & ~7, b1 = S.lo1 & ~7;
+    const int nc0 = S.lo0 < S.hi0 ? (S.hi0 - b0 + kChunk - 1) / kChunk : 0;
+    const int nc1 = S.lo1 < S.hi1 ? (S.hi1 - b1 + kChunk - 1) / kChunk : 0;
+    const int nc = nc0 + nc1;
+    int c = k;
+    int depth = 1;
+    while (c < nc) {
+        uint4 kv[kPrefetch];
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u) {
+            const int cc = c + u * R;
+            kv[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (u < depth && cc < nc) {
+                const bool s1 = cc >= nc0;
+                const int col0 = (s1 ? b1 + (cc - nc0) * kChunk : b0 + cc * kChunk) + lane * 8;
+                if (col0 < (s1 ? S.hi1 : S.hi0)) kv[u] = *reinterpret_cast<const uint4 *>(row + col0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u) {
+            const int cc = c + u * R;
+            if (u >= depth || cc >= nc) break;
+            const bool s1 = cc >= nc0;
+            const int lo = s1 ? S.lo1 : S.lo0, hi = s1 ? S.hi1 : S.hi0;
+            const int col0 = (s1 ? b1 + (cc - nc0) * kChunk : b0 + cc * kChunk) + lane * 8;
+            uint4 tv = make_uint4(0u, 0u, 0u, 0u);
+            if (col0 < hi) tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
+            const int a = chunk_hit(col0, kv[u], tv, need, lo, hi);
+            if (a >= 0) return hit_at(a, origin, n).j;
+        }
+        c += depth * R;
+        depth = kPrefetch;
+        if (c < nc) {
+            // first scan position of chunk c
+            const bool s1 = c >= nc0;
+            const int col = s1 ? max(S.lo1, b1 + (c - nc0) * kChunk) : max(S.lo0, b0 + c * kChunk);
+            const int j = hit_at(col, origin, n).j;
+            if (__hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < j) break;
+        }
+    }
+    return kNoHit;
+}
+
 __global__ void loop_reset_kernel(LoopArgs a)
 {
     Ctl *c = a.ctl;
-    c->arrive[0] = c->arrive[1] = c->arrive[2] = 0;
+    for (int i = 0; i < 3 * kMaxGroups; ++i) a.words[i * kWordStride] = 0ull;
     c->free0 = 0;
     c->scanned = 0;
     c->status = 0;
@@ -255,7 +338,14 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
 {
     extern __shared__ __align__(16) uint16_t t_lds[];
     __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose;
-    __shared__ unsigned long long s_old_word, s_word, s_scan;
+    __shared__ uint32_t s_base_l, s_base_f, s_ltot, s_over;
+    __shared__ unsigned long long s_scan;
+    // per group: list lengths of the phase so far, last round's new taken
+    // columns (start, count, prefix over groups), free-list prefix
+    __shared__ uint32_t s_lcum[kMaxGroups], s_fcum[kMaxGroups], s_lstart[kMaxGroups],
+        s_lnew[kMaxGroups], s_lpre[kMaxGroups], s_fpre[kMaxGroups];
+    // team mode: best hit position of each team's row, by round parity
+    __shared__ int s_best[2][kLoopThreads / kWave];
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wpg = blockDim.x / kWave;
@@ -265,14 +355,23 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
     Ctl *ctl = A.ctl;
     const int n = A.n;
 
+    const int G = A.groups;
+    const int grp = blockIdx.x % G;
+    const int64_t cap = A.list_cap;  // entries per group region of a list
+
     for (int i = threadIdx.x; i < A.n_pad; i += blockDim.x) t_lds[i] = A.t[i];
+    uint32_t n_i = ld_agent(&ctl->free0);  // |B'| of the current phase
     if (threadIdx.x == 0) {
         s_cnt_l = s_cnt_f = s_lose = 0;
         s_scan = 0;
     }
+    if (threadIdx.x < kMaxGroups) {
+        // the first free list is one region (group 0)
+        s_fpre[threadIdx.x] = threadIdx.x == 0 ? 0u : n_i;
+        s_lcum[threadIdx.x] = s_fcum[threadIdx.x] = 0;
+    }
     __syncthreads();
 
-    uint32_t n_i = ld_agent(&ctl->free0);  // |B'| of the current phase
     // List entries written in phase p carry tag0 + p + 1; the free list of
     // the first phase carries tag0.
     const uint32_t tag0 = ld_agent(&ctl->tag_last) + 1u;
@@ -300,16 +399,33 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
         const unsigned long long *Fc = A.F[p & 1];
         unsigned long long *Fn = A.F[(p + 1) & 1];
         unsigned long long *Lc = A.L[p & 1];
-        uint32_t lcount = 0, fcount = 0;  // list lengths after the last finished round
-        uint32_t l_new = 0;               // columns taken in the last finished round
+        uint32_t lcount = 0;  // length of the taken list after the last finished round
+        uint32_t l_new = 0;   // columns taken in the last finished round
         int64_t phase_rounds = 0;
 
-        // Slot s of this wave is entry gw + s*W of B'; lane s holds its state.
-        const uint32_t nslots = gw < n_i ? (n_i - gw + W - 1) / W : 0u;
+        // Slot mode (R = 1): slot s of this wave is entry gw + s*W of B' and
+        // lane s holds its state. Team mode (|B'| <= W/2): R waves of a
+        // workgroup (R a power of two, R <= W / |B'|, R <= 16) share one row,
+        // entry `team`, and lane 0 of each of them holds its state.
+        int R = 1;
+        if (2 * n_i <= W) {
+            const uint32_t q = W / n_i;
+            R = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : 2));
+        }
+        const int wv = threadIdx.x / kWave;
+        const int team_local = wv / R, k_rank = wv % R;
+        const uint32_t team = blockIdx.x * (uint32_t)(wpg / R) + (uint32_t)team_local;
+        const uint32_t nslots = R == 1 ? (gw < n_i ? (n_i - gw + W - 1) / W : 0u)
+                                       : (team < n_i ? 1u : 0u);
+        if (threadIdx.x < 2 * (kLoopThreads / kWave))
+            (&s_best[0][0])[threadIdx.x] = kNoHit;
+        __syncthreads();
         int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0;
         unsigned long long s_key = 0;
         if ((uint32_t)lane < nslots) {
-            s_b = take_entry(Fc + gw + (uint32_t)lane * W, tag0 + (uint32_t)p, n, &ctl->err);
+            const uint32_t e = R == 1 ? gw + (uint32_t)lane * W : team;
+            const int j = group_of(s_fpre, G, e);
+            s_b = take_entry(Fc + j * cap + (e - s_fpre[j]), tag0 + (uint32_t)p, n, &ctl->err);
             s_yb = ld_agent(A.y_b + s_b);
         }
         unsigned long long active = __ballot((uint32_t)lane < nslots);
@@ -320,9 +436,10 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
             if (l_new) {
                 // Columns taken in the previous round: marked for the rest of
                 // the phase, t raised now (step (III a)).
-                const uint32_t lb = lcount - l_new;
                 for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
-                    const int32_t a = take_entry(Lc + lb + i, tag, n, &ctl->err);
+                    const int j = group_of(s_lpre, G, i);
+                    const int32_t a =
+                        take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, n, &ctl->err);
                     t_lds[a] = (uint16_t)((t_lds[a] + 1) | kTaken);
                 }
                 // the rows of this wave that proposed: won (matched in M') or
@@ -339,9 +456,59 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
             bool proposed = false;
             int32_t my_f = -1;             // row this lane's slot puts on the next B'
             uint32_t n_prop = 0;
-            // Rows are taken kSlotBatch at a time so that their first chunks
-            // are loaded together.
-            unsigned long long rem = active;
+            if (R > 1) {
+                // team mode: every wave of the team scans its share of the row;
+                // the team's first hit is the smallest position found
+                int* best = &s_best[r & 1][team_local];
+                if (active & 1ull) {
+                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, n);
+                    const int j = team_scan(A.k + (int64_t)v.b * A.ldk, t_lds, n, v.origin, v.S,
+                                            v.yb - 1, k_rank, R, lane, best);
+                    if (lane == 0 && j != kNoHit) atomicMin(best, j);
+                }
+                __syncthreads();
+                if (active & 1ull) {
+                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, n);
+                    const int j = *best;
+                    const int b = v.b, pos = v.pos, yb = v.yb;
+                    const bool lead = k_rank == 0;
+                    if (j != kNoHit) {
+                        const int a = v.origin + j < n ? v.origin + j : v.origin + j - n;
+                        const unsigned long long kn =
+                            ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
+                        if (lead) {
+                            wave_scan += (unsigned long long)(j - pos + 1);
+                            if (lane == 0) {
+                                s_old = __hip_atomic_fetch_max(A.key + a, kn, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                                proposed = true;
+                            }
+                            n_prop = 1;
+                        }
+                        if (lane == 0) {
+                            s_pos = j;
+                            s_a = a;
+                            s_key = kn;
+                        }
+                    } else {
+                        // b has no admissible untaken column: free in M', (III b).
+                        if (lead) {
+                            wave_scan += (unsigned long long)(n - pos);
+                            if (lane == 0) {
+                                st_agent(A.y_b + b, yb + 1);
+                                my_f = b;
+                            }
+                        }
+                        active = 0ull;
+                    }
+                    // the other buffer is cleared for the next round; every wave
+                    // read it in the previous round, before this round's barriers
+                    if (lead && lane == 0) s_best[(r + 1) & 1][team_local] = kNoHit;
+                }
+            }
+            // Slot mode: rows are taken kSlotBatch at a time so that their
+            // first chunks are loaded together.
+            unsigned long long rem = R == 1 ? active : 0ull;
             while (rem) {
                 int sl[kSlotBatch];
                 uint4 kvq[kSlotBatch];
@@ -420,65 +587,86 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
             wait_memory();  // y(b) stores of this wave are complete
             __syncthreads();
 
-            // Arrival: the returned word is the sum over the workgroups that
-            // arrived before this one, which places this workgroup's entries.
+            // Arrival: the returned word is the sum over the workgroups of this
+            // group that arrived before this one, which places this
+            // workgroup's entries in the group's list regions.
             const bool timed = A.rtime != nullptr && r <= (uint32_t)kRoundTimeCap;
-            unsigned long long *word = &ctl->arrive[r % 3];
-            if (threadIdx.x == 0) {
-                if (timed)
+            unsigned long long *words = A.words + (r % 3) * kMaxGroups * kWordStride;
+            if (threadIdx.x < kWave) {
+                if (timed && threadIdx.x == 0)
                     __hip_atomic_fetch_max(&A.rtime[3 * (r - 1)], (int64_t)wall_clock64(),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // the word of round r + 1 was last read in round r - 2, which
+                // the words of round r + 1 were last read in round r - 2, which
                 // every workgroup has left
-                if (leader) {
-                    st_agent(&ctl->arrive[(r + 1) % 3], 0ull);
+                if (blockIdx.x == 0) {
+                    if (lane < G)
+                        st_agent(A.words + ((r + 1) % 3) * kMaxGroups * kWordStride +
+                                     lane * kWordStride,
+                                 0ull);
                     wait_memory();
                 }
-                const unsigned long long add = (1ull << kShiftArrive) |
-                                               ((unsigned long long)s_lose << kShiftLose) |
-                                               ((unsigned long long)s_cnt_f << kShiftFree) |
-                                               (unsigned long long)s_cnt_l;
-                s_cnt_l = s_cnt_f = s_lose = 0;
-                s_old_word = __hip_atomic_fetch_add(word, add, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
+                if (threadIdx.x == 0) {
+                    const unsigned long long add = (1ull << kShiftArrive) |
+                                                   ((unsigned long long)s_lose << kShiftLose) |
+                                                   ((unsigned long long)s_cnt_f << kShiftFree) |
+                                                   (unsigned long long)s_cnt_l;
+                    s_cnt_l = s_cnt_f = s_lose = 0;
+                    const unsigned long long o = __hip_atomic_fetch_add(
+                        words + grp * kWordStride, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_base_l = s_lcum[grp] + (uint32_t)(o & kField);
+                    s_base_f = s_fcum[grp] + (uint32_t)((o >> kShiftFree) & kField);
+                }
             }
             __syncthreads();
             {
-                const unsigned long long o = s_old_word;
+                const uint32_t bl0 = s_base_l, bf0 = s_base_f;
                 if (my_l >= 0)
-                    st_agent(Lc + lcount + (uint32_t)(o & kField) + off_l + lanes_below(bl),
-                             tagged(tag, my_l));
+                    st_agent(Lc + grp * cap + bl0 + off_l + lanes_below(bl), tagged(tag, my_l));
                 if (my_f >= 0)
-                    st_agent(Fn + fcount + (uint32_t)((o >> kShiftFree) & kField) + off_f +
-                                 lanes_below(bf),
-                             tagged(tag, my_f));
+                    st_agent(Fn + grp * cap + bf0 + off_f + lanes_below(bf), tagged(tag, my_f));
             }
-            if (threadIdx.x == 0) {
-                unsigned long long w;
-                while (((w = ld_agent(word)) >> kShiftArrive) != (unsigned long long)gridDim.x)
+            if (threadIdx.x < kWave) {
+                // lane j < G polls the word of group j until every workgroup arrived
+                unsigned long long v;
+                for (;;) {
+                    v = lane < G ? ld_agent(words + lane * kWordStride) : 0ull;
+                    if (wave_sum((uint32_t)(v >> kShiftArrive)) == gridDim.x) break;
                     __builtin_amdgcn_s_sleep(1);
-                s_word = w;
+                }
+                const uint32_t nl = (uint32_t)(v & kField);
+                const uint32_t nf = (uint32_t)((v >> kShiftFree) & kField);
+                const uint32_t lose = (uint32_t)((v >> kShiftLose) & 0x7FFull);
+                const uint32_t lpre = wave_exclusive_scan(nl, lane);
+                const uint32_t ltot = wave_sum(nl), losers = wave_sum(lose);
+                if (lane < G) {
+                    s_lnew[lane] = nl;
+                    s_lpre[lane] = lpre;
+                    s_lstart[lane] = s_lcum[lane];
+                    s_lcum[lane] += nl;
+                    s_fcum[lane] += nf;
+                }
+                if (lane == 0) {
+                    s_ltot = ltot;
+                    s_over = losers == 0u;
+                }
                 if (timed && leader) {
                     A.rtime[3 * (r - 1) + 1] = (int64_t)wall_clock64();
                     A.rtime[3 * (r - 1) + 2] = p;
                 }
             }
             __syncthreads();
-            const unsigned long long w = s_word;
-            l_new = (uint32_t)(w & kField);
+            l_new = s_ltot;
             lcount += l_new;
-            fcount += (uint32_t)((w >> kShiftFree) & kField);
             if (l_new) phase_rounds += 1;  // some proposal was made this round
-            if (((w >> kShiftLose) & 0x7FFull) == 0) break;
+            if (s_over) break;
         }
         // Columns taken in the last round get their t raised; then the marks
         // of the phase are cleared.
-        {
-            const uint32_t lb = lcount - l_new;
-            for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
-                const int32_t a = take_entry(Lc + lb + i, tag, n, &ctl->err);
-                t_lds[a] = (uint16_t)(t_lds[a] + 1);
-            }
+        for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
+            const int j = group_of(s_lpre, G, i);
+            const int32_t a =
+                take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, n, &ctl->err);
+            t_lds[a] = (uint16_t)(t_lds[a] + 1);
         }
         __syncthreads();
         for (int i = threadIdx.x * 8; i < A.n_pad; i += blockDim.x * 8) {
@@ -509,7 +697,21 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                 A.trace[4 * p + 3] = lcount;
             }
         }
-        n_i = fcount;
+        // the next free list: group regions of Fn, in group order
+        if (threadIdx.x < kWave) {
+            const uint32_t f = lane < G ? s_fcum[lane] : 0u;
+            const uint32_t pre = wave_exclusive_scan(f, lane);
+            const uint32_t total = wave_sum(f);  // all lanes take part in the shuffles
+            if (lane < G) {
+                s_fpre[lane] = pre;
+                s_fcum[lane] = 0;
+                s_lcum[lane] = 0;
+            }
+            if (lane == 0) s_ltot = total;
+        }
+        __syncthreads();
+        n_i = s_ltot;
+        __syncthreads();
         p += 1;
     }
     if (leader) {
