@@ -47,6 +47,7 @@ enum {
 };
 
 enum { PROT_EPS_ALGORITHMIC = 0, PROT_EPS_STRICT = 1 };
+enum { PROT_COST_DIRECT = 0, PROT_COST_MATRIX_CORES = 1 };
 enum { PROT_ORIGIN_DIAG = 0, PROT_ORIGIN_ZERO = 1 };
 
 typedef struct {
@@ -91,6 +92,18 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream);
 int prot_ctx_destroy(prot_ctx *ctx);
 /* Change the stream later calls enqueue on. */
 int prot_set_stream(prot_ctx *ctx, void *hip_stream);
+
+/* How later point-set cost builds on ctx (and batches created afterwards)
+ * compute the squared distances; both give the same result, bit for bit.
+ * PROT_COST_DIRECT (default): every distance as the fma-accumulated sum of
+ * squared coordinate differences, the definition itself (Section 2.1 rounds
+ * these costs by eq. (1)). PROT_COST_MATRIX_CORES: for d >= 16,
+ * |x|^2 + |y|^2 - 2 x.y with FP32 matrix-core products plus a rounding-error
+ * bound; entries the bound cannot place in their rounding cell, and the
+ * tiles that may hold the maximum, are recomputed directly. On MI355X the FP32
+ * matrix rate equals the FP32 vector rate, so this path is not faster; it is
+ * kept for comparison. Returns PROT_E_ARG for an unknown path. */
+int prot_set_cost_path(prot_ctx *ctx, int32_t path);
 /* Pre-size the workspace for instances up to n_max (and, if with_matrix,
  * an n_max x prot_pitch(n_max) int16 cost matrix) so that later calls do
  * not allocate. */

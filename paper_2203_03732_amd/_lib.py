@@ -67,7 +67,8 @@ def instance_stats_from_bytes(buf) -> list[dict]:
 _lib = None
 
 EXPORTS = [
-    "prot_ctx_create", "prot_ctx_destroy", "prot_set_stream", "prot_reserve", "prot_pitch",
+    "prot_ctx_create", "prot_ctx_destroy", "prot_set_stream", "prot_set_cost_path",
+    "prot_reserve", "prot_pitch",
     "prot_threshold", "prot_max_n", "prot_round_costs", "prot_build_costs",
     "prot_solve_rounded", "prot_solve_cost", "prot_solve_points", "prot_get_trace",
     "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
@@ -92,6 +93,7 @@ def load():
         "prot_ctx_create": (ctypes.c_int, [ctypes.POINTER(p), ctypes.c_int, p]),
         "prot_ctx_destroy": (ctypes.c_int, [p]),
         "prot_set_stream": (ctypes.c_int, [p, p]),
+        "prot_set_cost_path": (ctypes.c_int, [p, i32]),
         "prot_reserve": (ctypes.c_int, [p, i64, i32]),
         "prot_pitch": (i64, [i64]),
         "prot_threshold": (i64, [f64, i64]),
@@ -241,6 +243,13 @@ class Context:
             self._h, _dev_ptr(C, torch.float32, "C", 2), n, C.stride(0), float(eps),
             _dev_ptr(k, torch.int16, "k", 2), k.stride(0)))
         return k
+
+    COST_PATHS = {"direct": 0, "matrix_cores": 1}
+
+    def set_cost_path(self, path: str) -> None:
+        """'direct' (default) or 'matrix_cores' for later point-set builds;
+        both give the same result (include/prot.h, prot_set_cost_path)."""
+        self._check(self._lib.prot_set_cost_path(self._h, self.COST_PATHS[path]))
 
     def build_costs(self, X, Y, eps: float, k=None):
         torch = _torch()

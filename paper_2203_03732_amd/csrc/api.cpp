@@ -50,7 +50,7 @@ struct prot_ctx {
     } *stage = nullptr;              // pinned host memory
 
     int64_t *rtime = nullptr;        // round timer (PROT_DEBUG_ROUND_TIMES=1)
-    bool force_tiled = false;        // PROT_COST_PATH=tiled: no matrix cores (diagnostics)
+    int32_t cost_path = PROT_COST_DIRECT;  // prot_set_cost_path
     int loop_groups = 8;             // barrier groups of the phase loop (PROT_LOOP_GROUPS)
     float *mfma_buf = nullptr;       // amax, emax, tile maxima of the matrix-core build
     int64_t mfma_cap = 0;
@@ -183,7 +183,7 @@ int grid_for(prot_ctx *c, int64_t n, int *grid)
 int setup_mfma(prot_ctx *c, prot::PointsJob &j, int64_t n_max, float **buf, int64_t *cap)
 {
     j.mfma = prot::MfmaAux{};
-    if (j.d < prot::kMfmaMinD || c->force_tiled) return PROT_OK;
+    if (j.d < prot::kMfmaMinD || c->cost_path != PROT_COST_MATRIX_CORES) return PROT_OK;
     const int64_t tx = (n_max + prot::kMfmaTile - 1) / prot::kMfmaTile;
     const int64_t need = 2 * (int64_t)j.batch + (int64_t)j.batch * tx * tx;
     if (need > *cap || !*buf) {
@@ -478,7 +478,8 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
         rc = PROT_E_NOMEM;
     for (int i = 0; i < 5 && !rc; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = PROT_E_HIP;
-    if (const char *v = std::getenv("PROT_COST_PATH")) c->force_tiled = std::strcmp(v, "tiled") == 0;
+    if (const char *v = std::getenv("PROT_COST_PATH"))
+        if (std::strcmp(v, "mfma") == 0) c->cost_path = PROT_COST_MATRIX_CORES;
     if (const char *v = std::getenv("PROT_LOOP_GROUPS")) {
         const int g = std::atoi(v);
         if (g >= 1 && g <= prot::kMaxGroups) c->loop_groups = g;
@@ -522,6 +523,15 @@ int prot_ctx_destroy(prot_ctx *c)
     for (int i = 0; i < 5; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     delete c;
+    return PROT_OK;
+}
+
+int prot_set_cost_path(prot_ctx *c, int32_t path)
+{
+    if (!c) return PROT_E_ARG;
+    if (path != PROT_COST_DIRECT && path != PROT_COST_MATRIX_CORES)
+        return fail(c, PROT_E_ARG, "unknown cost path %d", (int)path);
+    c->cost_path = path;
     return PROT_OK;
 }
 

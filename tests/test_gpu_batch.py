@@ -62,6 +62,21 @@ def test_batched_small_bit_exact(ctx, d, eps, origin):
     check_instances(ns, Xs, Ys, eps, (mate_a, mate_b, y_a, y_b), stats, origin)
 
 
+def test_batched_matrix_core_build_bit_exact(ctx):
+    """The matrix-core build of a batch (d >= 16) gives the same instances."""
+    rng = np.random.default_rng(77)
+    d, eps = 24, 0.05
+    ns = [1, 5, 64, 65, 200, 333]
+    Xs = [rng.standard_normal((n, d)).astype(np.float32) for n in ns]
+    Ys = [(0.3 + rng.standard_normal((n, d))).astype(np.float32) for n in ns]
+    ctx.set_cost_path("matrix_cores")
+    try:
+        out = ctx.solve_batched_points(ns, pack(Xs), pack(Ys), eps)
+    finally:
+        ctx.set_cost_path("direct")
+    check_instances(ns, Xs, Ys, eps, out[:4], out[4])
+
+
 def test_batched_large_instances(ctx):
     """Instances up to the batched limit (n = 2048) use the larger LDS layout."""
     rng = np.random.default_rng(3)

@@ -83,12 +83,17 @@ def test_round_costs_rejects_nan_and_range(ctx):
     assert e.value.name == "eps"
 
 
+@pytest.mark.parametrize("path", ["direct", "matrix_cores"])
 @pytest.mark.parametrize("n,d,eps", [(1, 2, 0.1), (50, 2, 0.01), (1000, 2, 0.01),
                                      (513, 3, 0.005), (200, 5, 0.05), (300, 16, 0.05),
                                      (150, 17, 0.02), (130, 64, 0.01), (65, 4, 0.3)])
-def test_build_costs_bit_exact(ctx, n, d, eps):
+def test_build_costs_bit_exact(ctx, n, d, eps, path):
     X, Y = synth.uniform_points(n, d, seed=7 + d)
-    k, m = ctx.build_costs(dev(X), dev(Y), eps)
+    ctx.set_cost_path(path)
+    try:
+        k, m = ctx.build_costs(dev(X), dev(Y), eps)
+    finally:
+        ctx.set_cost_path("direct")
     torch.cuda.synchronize()
     ko, mo = oracle.round_points_f32(X, Y, eps)
     assert float(host(m)[0]) == mo
@@ -106,7 +111,11 @@ def test_build_costs_matrix_core_path_far_from_origin(ctx):
     X = (100.0 + rng.standard_normal((n, d))).astype(np.float32)
     Y = (100.0 + rng.standard_normal((n, d))).astype(np.float32)
     for eps in (0.05, 0.003):
-        k, m = ctx.build_costs(dev(X), dev(Y), eps)
+        ctx.set_cost_path("matrix_cores")
+        try:
+            k, m = ctx.build_costs(dev(X), dev(Y), eps)
+        finally:
+            ctx.set_cost_path("direct")
         torch.cuda.synchronize()
         ko, mo = oracle.round_points_f32(X, Y, eps)
         assert float(host(m)[0]) == mo
