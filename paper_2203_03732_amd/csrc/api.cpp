@@ -358,6 +358,16 @@ struct prot_batch {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // Teams (instances above the LDS-resident limit of 1024): `team`
+    // phase-loop workgroups per instance, per_launch instances per launch.
+    int team = 0;
+    int per_launch = 0;
+    int32_t n_pad_max = 0;
+    prot::LoopArgs *loops = nullptr;
+    unsigned long long *t_key = nullptr, *t_lists = nullptr, *t_words = nullptr;
+    uint16_t *t_t = nullptr;
+    Ctl *t_ctl = nullptr;
+    int32_t *t_scratch = nullptr;
 };
 
 namespace {
@@ -369,6 +379,86 @@ int upload(prot_ctx *c, T **dst, const std::vector<T> &src)
     if (rc) return rc;
     HIP_TRY(c, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
     return PROT_OK;
+}
+
+// Chooses between the LDS-resident batched kernel (instances up to n = 1024)
+// and teams of phase-loop workgroups (larger instances), and for teams builds
+// every instance's loop arguments and workspace. PROT_BATCH_TEAM=<w> forces
+// w workgroups per instance (0: never use teams).
+int setup_teams(prot_ctx *c, prot_batch *bp, const std::vector<int32_t> &n_arr,
+                const std::vector<int32_t> &ldk, const std::vector<int64_t> &pt_off,
+                const std::vector<int64_t> &k_off)
+{
+    int forced = -1;
+    if (const char *v = std::getenv("PROT_BATCH_TEAM")) forced = std::atoi(v);
+    if (forced == 0 || (forced < 0 && bp->n_max <= 1024)) return PROT_OK;
+    const int32_t n_pad_max = (int32_t)round_up(bp->n_max, 8);
+    int gm = 0;
+    hipError_t e = prot::loop_grid_multi(n_pad_max, c->wgs_per_cu, &gm);
+    if (e != hipSuccess) return hip_fail(c, e, "team occupancy");
+    if (gm < 1) return PROT_OK;  // keep the LDS-resident kernel
+    // each wave serves at most 64 rows of B' (one per lane): a team needs
+    // ceil(n_max / (64 * 16)) workgroups at least
+    const int wpg = prot::kLoopThreads / 64;
+    const int team_min = (int)((bp->n_max + 64 * wpg - 1) / (64 * wpg));
+    int team = forced > 0 ? forced : gm / bp->batch;
+    team = std::max(team_min, std::min(team, 8));
+    if (team > gm) return PROT_OK;  // keep the LDS-resident kernel
+    bp->team = team;
+    bp->per_launch = gm / team;
+    bp->n_pad_max = n_pad_max;
+    const int32_t batch = bp->batch;
+    const int G = std::min(team, 8);
+    int64_t nk = 0, nt = 0, nl = 0, ns = 0;
+    for (int32_t i = 0; i < batch; ++i) {
+        nk += n_arr[i];
+        nt += round_up(n_arr[i], 8);
+        nl += (int64_t)4 * G * n_arr[i];
+        ns += 2 * (int64_t)n_arr[i];
+    }
+    const int64_t words_per = (int64_t)3 * prot::kMaxGroups * prot::kWordStride;
+    int rc = dev_alloc(c, &bp->t_key, (size_t)nk);
+    if (!rc) rc = dev_alloc(c, &bp->t_t, (size_t)nt);
+    if (!rc) rc = dev_alloc(c, &bp->t_lists, (size_t)nl);
+    if (!rc) rc = dev_alloc(c, &bp->t_words, (size_t)(words_per * batch));
+    if (!rc) rc = dev_alloc(c, &bp->t_ctl, (size_t)batch);
+    if (!rc) rc = dev_alloc(c, &bp->t_scratch, (size_t)ns);
+    if (rc) return rc;
+    // list entries carry tags, so fresh memory must hold none by chance
+    HIP_TRY(c, hipMemset(bp->t_lists, 0, sizeof(unsigned long long) * (size_t)nl));
+    HIP_TRY(c, hipMemset(bp->t_ctl, 0, sizeof(Ctl) * (size_t)batch));
+    std::vector<prot::LoopArgs> la(batch);
+    const int origin = bp->opts.origin_mode == PROT_ORIGIN_ZERO ? 1 : 0;
+    int64_t ok = 0, ot = 0, ol = 0;
+    for (int32_t i = 0; i < batch; ++i) {
+        prot::LoopArgs &a = la[i];
+        const int64_t n = n_arr[i];
+        a.k = bp->k + k_off[i];
+        a.ldk = ldk[i];
+        a.n = (int32_t)n;
+        a.n_pad = (int32_t)round_up(n, 8);
+        a.T = prot_threshold(bp->eps, n);
+        a.origin = origin;
+        a.max_phases = bp->opts.max_phases;
+        a.key = bp->t_key + ok;
+        a.t = bp->t_t + ot;
+        a.y_b = nullptr;  // the launch's y_b base + y_off
+        for (int q = 0; q < 2; ++q) {
+            a.F[q] = bp->t_lists + ol + (int64_t)q * G * n;
+            a.L[q] = bp->t_lists + ol + (int64_t)(2 + q) * G * n;
+        }
+        a.list_cap = n;
+        a.groups = G;
+        a.words = bp->t_words + words_per * i;
+        a.ctl = bp->t_ctl + i;
+        a.trace = nullptr;
+        a.rtime = nullptr;
+        a.y_off = pt_off[i];
+        ok += n;
+        ot += round_up(n, 8);
+        ol += (int64_t)4 * G * n;
+    }
+    return upload(c, &bp->loops, la);
 }
 
 int batch_enqueue(prot_batch *bp, hipStream_t s, const float *X, const float *Y, int32_t *mate_a,
@@ -392,6 +482,33 @@ int batch_enqueue(prot_batch *bp, hipStream_t s, const float *X, const float *Y,
     j.err = bp->err;
     j.mfma = bp->mfma;
     HIP_TRY(c, prot::launch_points(j, bp->n_max, bp->ldk_max, s));
+    if (bp->team > 0) {
+        prot::TeamArgs t{};
+        t.batch = bp->batch;
+        t.d = bp->d;
+        t.complete = bp->opts.no_completion ? 0 : 1;
+        t.eps = bp->eps;
+        t.loops = bp->loops;
+        t.pt_off = bp->pt_off;
+        t.X = X;
+        t.Y = Y;
+        t.m = bp->m;
+        t.mate_a = mate_a;
+        t.mate_b = mate_b;
+        t.y_a = y_a;
+        t.y_b = y_b;
+        t.scratch = bp->t_scratch;
+        t.stats = reinterpret_cast<prot::InstanceStats *>(stats ? stats : bp->stats_tmp);
+        t.err = bp->err;
+        HIP_TRY(c, prot::launch_team_init(t, bp->n_pad_max, s));
+        for (int first = 0; first < bp->batch; first += bp->per_launch) {
+            const int count = std::min(bp->per_launch, bp->batch - first);
+            HIP_TRY(c, prot::launch_loop_multi(bp->loops + first, count, bp->team, bp->n_pad_max,
+                                               y_b, s));
+        }
+        HIP_TRY(c, prot::launch_team_finish(t, s));
+        return PROT_OK;
+    }
     prot::BatchArgs a{};
     a.batch = bp->batch;
     a.d = bp->d;
@@ -775,6 +892,7 @@ int prot_batch_create(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t
         rc = setup_mfma(c, j, n_max, &bp->mfma_buf, &bp->mfma_cap);
         bp->mfma = j.mfma;
     }
+    if (!rc && batch > 0) rc = setup_teams(c, bp, n_arr, ldk, pt_off, k_off);
     if (rc) {
         prot_batch_destroy(bp);
         return rc;
@@ -802,6 +920,13 @@ int prot_batch_destroy(prot_batch *bp)
     (void)hipFree(bp->queue);
     (void)hipFree(bp->stats_tmp);
     (void)hipFree(bp->mfma_buf);
+    (void)hipFree(bp->loops);
+    (void)hipFree(bp->t_key);
+    (void)hipFree(bp->t_lists);
+    (void)hipFree(bp->t_words);
+    (void)hipFree(bp->t_t);
+    (void)hipFree(bp->t_ctl);
+    (void)hipFree(bp->t_scratch);
     delete bp;
     return PROT_OK;
 }
@@ -911,6 +1036,8 @@ int prot_solve_batched_points(prot_ctx *c, int32_t batch, const int64_t *n_host,
     }
     prot_batch_destroy(bp);
     if (!rc && (err & 1)) rc = fail(c, PROT_E_RANGE, "a point coordinate is not finite");
+    if (!rc && (err & 4)) rc = fail(c, PROT_E_HIP, "phase loop: a list entry was not published in time");
+    if (!rc && (err & 8)) rc = fail(c, PROT_E_UNSUPPORTED, "phase loop: more than 2^32 rounds");
     return rc;
 }
 

@@ -61,6 +61,7 @@ struct LoopArgs {
     int32_t groups;           // G, 1 <= G <= min(kMaxGroups, grid)
     int32_t pad2;
     unsigned long long *words;  // round words, 3 * kMaxGroups * kWordStride
+    int64_t y_off;            // batched teams: y_b is the launch's y_b base + y_off
     Ctl *ctl;
     int64_t *trace;           // 4 int64 per phase
     int64_t *rtime;           // optional: 3 int64 per round (see kRoundTimeCap)
@@ -92,6 +93,23 @@ struct BatchArgs {
     InstanceStats *stats;
     unsigned int *queue;
     int64_t *rtime;           // optional diagnostics: 4 int64 per round of the first job
+};
+
+// Batched instances solved by teams of phase-loop workgroups: per-instance
+// loop arguments on the device, plus what the set-up and the finish need.
+struct TeamArgs {
+    int32_t batch;
+    int32_t d;
+    int32_t complete;
+    int32_t pad;
+    double eps;
+    const LoopArgs *loops;    // per instance
+    const int64_t *pt_off;    // first row of each instance in X, Y and the outputs
+    const float *X, *Y, *m;
+    int32_t *mate_a, *mate_b, *y_a, *y_b;
+    int32_t *scratch;         // 2 * (sum of n) ints; instance i at 2 * pt_off[i]
+    InstanceStats *stats;
+    int32_t *err;             // bits 2 and 3 of a loop's error word are collected here
 };
 
 struct LossArgs {
@@ -136,6 +154,12 @@ hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max);
 hipError_t launch_clear_times(int64_t *rtime, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s);
+// Teams: workgroups a cooperative launch of the multi-instance loop can hold.
+hipError_t loop_grid_multi(int32_t n_pad_max, int wgs_per_cu, int *grid_max);
+hipError_t launch_team_init(const TeamArgs &t, int32_t n_pad_max, hipStream_t s);
+hipError_t launch_loop_multi(const LoopArgs *arr, int count, int team, int32_t n_pad_max,
+                             int32_t *y_base, hipStream_t s);
+hipError_t launch_team_finish(const TeamArgs &t, hipStream_t s);
 hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a,
                          int32_t *mate_b, int32_t *y_a, int32_t *scratch,
                          hipStream_t s);

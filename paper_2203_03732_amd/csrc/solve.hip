@@ -45,8 +45,9 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kChunk = kWave * 8;   // columns examined per wave per load
-constexpr int kPrefetch = 8;        // chunks in flight in a long scan
+constexpr int kPrefetch = 6;        // chunks in flight in a long scan
 constexpr int kSlotBatch = 4;       // rows whose first chunks are loaded together
+constexpr int kTeamPrefetch = 4;    // chunks in flight per wave of a team scan
 
 // Round words: workgroup w adds to word w % G of the round; each word sums
 // over the workgroups of its group that arrived.
@@ -212,7 +213,7 @@ __device__ Hit scan_from(const int16_t *__restrict__ row, const uint16_t *t_lds,
 // are dealt out round-robin, chunk c to wave c mod R; wave k = this wave's
 // rank. Returns the scan position of this wave's first hit (its chunks are
 // visited in order), or kNoHit. The first pass loads one chunk per wave;
-// later passes kPrefetch each, and stop once the team's best hit so far
+// later passes kTeamPrefetch each, and stop once the team's best hit so far
 // (*best, in LDS) precedes them.
 constexpr int kNoHit = 0x7FFFFFFF;
 
@@ -226,9 +227,9 @@ __device__ int team_scan(const int16_t *__restrict__ row, const uint16_t *t_lds,
     int c = k;
     int depth = 1;
     while (c < nc) {
-        uint4 kv[kPrefetch];
+        uint4 kv[kTeamPrefetch];
 #pragma unroll
-        for (int u = 0; u < kPrefetch; ++u) {
+        for (int u = 0; u < kTeamPrefetch; ++u) {
             const int cc = c + u * R;
             kv[u] = make_uint4(0u, 0u, 0u, 0u);
             if (u < depth && cc < nc) {
@@ -238,7 +239,7 @@ __device__ int team_scan(const int16_t *__restrict__ row, const uint16_t *t_lds,
             }
         }
 #pragma unroll
-        for (int u = 0; u < kPrefetch; ++u) {
+        for (int u = 0; u < kTeamPrefetch; ++u) {
             const int cc = c + u * R;
             if (u >= depth || cc >= nc) break;
             const bool s1 = cc >= nc0;
@@ -250,7 +251,7 @@ __device__ int team_scan(const int16_t *__restrict__ row, const uint16_t *t_lds,
             if (a >= 0) return hit_at(a, origin, n).j;
         }
         c += depth * R;
-        depth = kPrefetch;
+        depth = kTeamPrefetch;
         if (c < nc) {
             // first scan position of chunk c
             const bool s1 = c >= nc0;
@@ -334,8 +335,20 @@ __global__ void check_state_kernel(int64_t n, const int32_t *mate_a, const int32
     if (bad) __hip_atomic_fetch_or(&ctl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
+// kMulti: many instances in one launch, `team` consecutive workgroups per
+// instance, the instance's arguments in arr[blockIdx.x / team]; the barrier,
+// lists and statistics of each instance involve only its own team.
+template <bool kMulti>
+__global__ void __launch_bounds__(kLoopThreads)
+phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32_t *y_base)
 {
+    // the instance's arguments stay where they are (kernel arguments, or the
+    // array in global memory), read through the scalar cache when needed
+    const LoopArgs &A = kMulti ? arr[blockIdx.x / team] : A0;
+    int32_t *const y_b = kMulti ? y_base + A.y_off : A.y_b;
+    // workgroups of this instance, and this workgroup's rank among them
+    const uint32_t nwg = kMulti ? (uint32_t)team : gridDim.x;
+    const uint32_t wg = kMulti ? blockIdx.x % (uint32_t)team : blockIdx.x;
     extern __shared__ __align__(16) uint16_t t_lds[];
     __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose;
     __shared__ uint32_t s_base_l, s_base_f, s_ltot, s_over;
@@ -349,14 +362,14 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wpg = blockDim.x / kWave;
-    const uint32_t W = gridDim.x * wpg;
-    const uint32_t gw = blockIdx.x * wpg + threadIdx.x / kWave;
-    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    const uint32_t W = nwg * wpg;
+    const uint32_t gw = wg * wpg + threadIdx.x / kWave;
+    const bool leader = wg == 0 && threadIdx.x == 0;
     Ctl *ctl = A.ctl;
     const int n = A.n;
 
     const int G = A.groups;
-    const int grp = blockIdx.x % G;
+    const int grp = (int)(wg % (uint32_t)G);
     const int64_t cap = A.list_cap;  // entries per group region of a list
 
     for (int i = threadIdx.x; i < A.n_pad; i += blockDim.x) t_lds[i] = A.t[i];
@@ -391,8 +404,8 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
         }
         if (leader) {
             st_sum_free += n_i;
-            if (p < kTraceCap) A.trace[4 * p] = n_i;
-            if (p + 1 < kTraceCap)
+            if (A.trace && p < kTraceCap) A.trace[4 * p] = n_i;
+            if (A.trace && p + 1 < kTraceCap)
                 for (int i = 0; i < 4; ++i) st_agent(&A.trace[4 * (p + 1) + i], (int64_t)0);
         }
         const uint32_t tag = tag0 + (uint32_t)(p + 1);  // entries written in this phase
@@ -414,19 +427,19 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
         }
         const int wv = threadIdx.x / kWave;
         const int team_local = wv / R, k_rank = wv % R;
-        const uint32_t team = blockIdx.x * (uint32_t)(wpg / R) + (uint32_t)team_local;
+        const uint32_t team_id = wg * (uint32_t)(wpg / R) + (uint32_t)team_local;
         const uint32_t nslots = R == 1 ? (gw < n_i ? (n_i - gw + W - 1) / W : 0u)
-                                       : (team < n_i ? 1u : 0u);
+                                       : (team_id < n_i ? 1u : 0u);
         if (threadIdx.x < 2 * (kLoopThreads / kWave))
             (&s_best[0][0])[threadIdx.x] = kNoHit;
         __syncthreads();
         int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0;
         unsigned long long s_key = 0;
         if ((uint32_t)lane < nslots) {
-            const uint32_t e = R == 1 ? gw + (uint32_t)lane * W : team;
+            const uint32_t e = R == 1 ? gw + (uint32_t)lane * W : team_id;
             const int j = group_of(s_fpre, G, e);
             s_b = take_entry(Fc + j * cap + (e - s_fpre[j]), tag0 + (uint32_t)p, n, &ctl->err);
-            s_yb = ld_agent(A.y_b + s_b);
+            s_yb = ld_agent(y_b + s_b);
         }
         unsigned long long active = __ballot((uint32_t)lane < nslots);
         unsigned long long wave_scan = 0;
@@ -495,7 +508,7 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                         if (lead) {
                             wave_scan += (unsigned long long)(n - pos);
                             if (lane == 0) {
-                                st_agent(A.y_b + b, yb + 1);
+                                st_agent(y_b + b, yb + 1);
                                 my_f = b;
                             }
                         }
@@ -559,7 +572,7 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                         // b has no admissible untaken column: free in M', (III b).
                         wave_scan += (unsigned long long)(n - pos);
                         if (lane == s) {
-                            st_agent(A.y_b + b, yb + 1);
+                            st_agent(y_b + b, yb + 1);
                             my_f = b;
                         }
                         active &= ~(1ull << s);
@@ -598,7 +611,7 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 // the words of round r + 1 were last read in round r - 2, which
                 // every workgroup has left
-                if (blockIdx.x == 0) {
+                if (wg == 0) {
                     if (lane < G)
                         st_agent(A.words + ((r + 1) % 3) * kMaxGroups * kWordStride +
                                      lane * kWordStride,
@@ -630,7 +643,7 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
                 unsigned long long v;
                 for (;;) {
                     v = lane < G ? ld_agent(words + lane * kWordStride) : 0ull;
-                    if (wave_sum((uint32_t)(v >> kShiftArrive)) == gridDim.x) break;
+                    if (wave_sum((uint32_t)(v >> kShiftArrive)) == nwg) break;
                     __builtin_amdgcn_s_sleep(1);
                 }
                 const uint32_t nl = (uint32_t)(v & kField);
@@ -686,13 +699,13 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
             s_scan = 0;
             if (sc) {
                 add_agent(&ctl->scanned, sc);
-                if (p < kTraceCap) add_agent(&A.trace[4 * p + 2], (int64_t)sc);
+                if (A.trace && p < kTraceCap) add_agent(&A.trace[4 * p + 2], (int64_t)sc);
             }
         }
         if (leader) {
             st_rounds += phase_rounds;
             if (phase_rounds > st_max_rounds) st_max_rounds = phase_rounds;
-            if (p < kTraceCap) {
+            if (A.trace && p < kTraceCap) {
                 A.trace[4 * p + 1] = phase_rounds;
                 A.trace[4 * p + 3] = lcount;
             }
@@ -723,7 +736,7 @@ __global__ void __launch_bounds__(kLoopThreads) phase_loop_kernel(LoopArgs A)
         ctl->max_rounds = st_max_rounds;
         ctl->free_after = n_i;
     }
-    if (blockIdx.x == 0)
+    if (wg == 0)
         for (int i = threadIdx.x; i < n; i += blockDim.x) A.t[i] = t_lds[i];
 }
 
@@ -844,6 +857,120 @@ finalize_kernel(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk,
     }
 }
 
+// Batched teams, set-up of every instance: the cold start of the init
+// kernel plus the reset of its control block and round words.
+__global__ void team_init_kernel(TeamArgs T)
+{
+    const LoopArgs a = T.loops[blockIdx.y];
+    int32_t *y_b = T.y_b + a.y_off;
+    const uint32_t tag0 = a.ctl->tag_last + 1u;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_pad; i += gridDim.x * blockDim.x) {
+        if (i < a.n) {
+            a.key[i] = 0ull;
+            a.t[i] = 0;
+            y_b[i] = 1;
+            a.F[0][i] = tagged(tag0, i);
+        } else {
+            a.t[i] = 0;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctl *c = a.ctl;
+        for (int i = 0; i < 3 * kMaxGroups; ++i) a.words[i * kWordStride] = 0ull;
+        c->free0 = (uint32_t)a.n;
+        c->scanned = 0;
+        c->status = 0;
+        c->err = 0;
+        c->phases = c->sum_free = c->rounds = c->max_rounds = 0;
+        c->free_after = 0;
+    }
+}
+
+// Batched teams, one workgroup per instance after the loop: matching and
+// duals from the keys and t, the completion (Section 2.1: the i-th free b in
+// ascending order takes the i-th free a), and the instance's statistics
+// (fixed-order reductions, binary64 cost).
+__global__ void __launch_bounds__(kCompleteThreads) team_finish_kernel(TeamArgs T)
+{
+    __shared__ int cnt[kCompleteThreads];
+    __shared__ long long red_k[kCompleteThreads];
+    __shared__ double red_c[kCompleteThreads];
+    const int inst = blockIdx.x;
+    const int tid = threadIdx.x;
+    const LoopArgs a = T.loops[inst];
+    const int n = a.n;
+    const int64_t off = T.pt_off[inst];
+    int32_t *ma = T.mate_a + off, *mb = T.mate_b + off, *ya = T.y_a + off;
+    for (int i = tid; i < n; i += kCompleteThreads) mb[i] = -1;
+    __syncthreads();
+    for (int i = tid; i < n; i += kCompleteThreads) {
+        const unsigned long long kk = a.key[i];
+        const int32_t b = kk ? (int32_t)~(uint32_t)kk : -1;
+        ma[i] = b;
+        if (b >= 0) mb[b] = i;
+        ya[i] = -(int32_t)a.t[i];
+    }
+    __syncthreads();
+    int32_t *sc = T.scratch + 2 * off;
+    const int nb = list_flags(mb, n, sc, cnt);
+    const int na = list_flags(ma, n, sc + n, cnt);
+    if (T.complete) {
+        const int m = min(nb, na);
+        for (int i = tid; i < m; i += kCompleteThreads) {
+            mb[sc[i]] = sc[n + i];
+            ma[sc[n + i]] = sc[i];
+        }
+    }
+    __syncthreads();
+    const float *X = T.X + off * T.d, *Y = T.Y + off * T.d;
+    long long ks = 0;
+    double cs = 0.0;
+    for (int b = tid; b < n; b += kCompleteThreads) {
+        const int32_t c = mb[b];
+        if (c < 0) continue;
+        ks += a.k[(int64_t)b * a.ldk + c];
+        double s = 0.0;
+        for (int q = 0; q < T.d; ++q) {
+            const double dq =
+                __dsub_rn((double)X[(int64_t)b * T.d + q], (double)Y[(int64_t)c * T.d + q]);
+            s = __dadd_rn(s, __dmul_rn(dq, dq));
+        }
+        cs = __dadd_rn(cs, s);
+    }
+    red_k[tid] = ks;
+    red_c[tid] = cs;
+    __syncthreads();
+    for (int o = kCompleteThreads / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            red_k[tid] += red_k[tid + o];
+            red_c[tid] = __dadd_rn(red_c[tid], red_c[tid + o]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const Ctl &c = *a.ctl;
+        InstanceStats &st = T.stats[inst];
+        const float m = T.m[inst];
+        st.phases = c.phases;
+        st.sum_free = c.sum_free;
+        st.rounds = c.rounds;
+        st.max_rounds = c.max_rounds;
+        st.scanned = (int64_t)c.scanned;
+        st.matched_in_phases = n - c.free_after;
+        st.completed_pairs = T.complete ? c.free_after : 0;
+        st.sum_k = red_k[0];
+        st.threshold = a.T;
+        st.status = c.status ? 1 : 0;
+        st.kmax = m > 0.0f ? (int32_t)floor(1.0 / T.eps) : 0;
+        st.cost_scale = (double)m;
+        st.cost = m > 0.0f ? red_c[0] / (double)m : 0.0;
+        if (c.err & 12) {
+            st.status = -6;
+            __hip_atomic_fetch_or(T.err, c.err & 12, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 inline unsigned blocks_for(int64_t n, int threads)
 {
     int64_t b = (n + threads - 1) / threads;
@@ -894,12 +1021,13 @@ hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max)
     const size_t lds = (size_t)n_pad * sizeof(uint16_t);
     hipError_t e = hipSuccess;
     if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)phase_loop_kernel,
+        e = hipFuncSetAttribute((const void *)phase_loop_kernel<false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel, kLoopThreads, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<false>,
+                                                     kLoopThreads, lds);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
     e = hipGetDevice(&dev);
@@ -916,10 +1044,61 @@ hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max)
 hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
 {
     LoopArgs copy = a;
-    void *args[] = {&copy};
+    const LoopArgs *none = nullptr;
+    int team = 1;
+    int32_t *no_base = nullptr;
+    void *args[] = {&copy, &none, &team, &no_base};
     const size_t lds = (size_t)a.n_pad * sizeof(uint16_t);
-    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel, dim3(grid),
+    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel<false>, dim3(grid),
                                       dim3(kLoopThreads), args, (unsigned)lds, s);
+}
+
+hipError_t loop_grid_multi(int32_t n_pad_max, int wgs_per_cu, int *grid_max)
+{
+    const size_t lds = (size_t)n_pad_max * sizeof(uint16_t);
+    hipError_t e = hipSuccess;
+    if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute((const void *)phase_loop_kernel<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0, dev = 0, cus = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<true>,
+                                                     kLoopThreads, lds);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    if (per_cu > wgs_per_cu) per_cu = wgs_per_cu;
+    *grid_max = per_cu * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_team_init(const TeamArgs &t, int32_t n_pad_max, hipStream_t s)
+{
+    if (t.batch > 0)
+        hipLaunchKernelGGL(team_init_kernel, dim3(blocks_for(n_pad_max, 256), (unsigned)t.batch),
+                           dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_loop_multi(const LoopArgs *arr, int count, int team, int32_t n_pad_max,
+                             int32_t *y_base, hipStream_t s)
+{
+    LoopArgs none{};
+    void *args[] = {&none, &arr, &team, &y_base};
+    const size_t lds = (size_t)n_pad_max * sizeof(uint16_t);
+    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel<true>,
+                                      dim3((unsigned)(count * team)), dim3(kLoopThreads), args,
+                                      (unsigned)lds, s);
+}
+
+hipError_t launch_team_finish(const TeamArgs &t, hipStream_t s)
+{
+    if (t.batch > 0)
+        hipLaunchKernelGGL(team_finish_kernel, dim3((unsigned)t.batch), dim3(kCompleteThreads), 0,
+                           s, t);
+    return hipGetLastError();
 }
 
 hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a, int32_t *mate_b,

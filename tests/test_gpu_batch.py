@@ -77,6 +77,53 @@ def test_batched_matrix_core_build_bit_exact(ctx):
     check_instances(ns, Xs, Ys, eps, out[:4], out[4])
 
 
+@pytest.mark.parametrize("origin", ["diag", "zero"])
+def test_batched_teams_bit_exact(ctx, origin):
+    """Instances above n = 1024 are solved by teams of phase-loop workgroups;
+    every instance must still match the oracle, including uneven sizes."""
+    rng = np.random.default_rng(11)
+    ns = [2048, 1100, 1025, 64, 3, 1800]
+    Xs = [rng.standard_normal((n, 8)).astype(np.float32) for n in ns]
+    Ys = [(0.2 + rng.standard_normal((n, 8))).astype(np.float32) for n in ns]
+    out = ctx.solve_batched_points(ns, pack(Xs), pack(Ys), 0.02, origin=origin)
+    check_instances(ns, Xs, Ys, 0.02, out[:4], out[4], origin)
+
+
+def test_batched_teams_partial_and_replay(ctx):
+    """Teams honour max_phases and no completion, and a captured graph of a
+    team batch replays to the direct result."""
+    rng = np.random.default_rng(12)
+    ns = [1500, 1200, 2000]
+    Xs = [rng.random((n, 2), dtype=np.float32) for n in ns]
+    Ys = [rng.random((n, 2), dtype=np.float32) for n in ns]
+    X, Y = pack(Xs), pack(Ys)
+    plan = ctx.batch(ns, 2, 0.01, max_phases=3, complete=False)
+    plan.run(X, Y)
+    torch.cuda.synchronize()
+    direct = [t.clone() for t in (plan.mate_a, plan.mate_b, plan.y_a, plan.y_b)]
+    st = plan.stats()
+    mate_a, mate_b, y_a, y_b = (t.cpu().numpy() for t in direct)
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    for i, n in enumerate(ns):
+        k, _ = oracle.round_points_f32(Xs[i], Ys[i], 0.01)
+        ref = oracle.solve_rounded(k, oracle.threshold(0.01, n), max_phases=3, complete=False)
+        o = offs[i]
+        for name, arr in (("mate_a", mate_a), ("mate_b", mate_b), ("y_a", y_a), ("y_b", y_b)):
+            assert np.array_equal(arr[o:o + n], ref[name]), f"instance {i}: {name}"
+        assert st[i]["phases"] == ref["stats"]["phases"]
+        assert st[i]["status"] == (1 if ref["status"] == "partial" else 0)
+    plan.capture(X, Y)
+    for _ in range(3):
+        for t in (plan.mate_a, plan.mate_b, plan.y_a, plan.y_b):
+            t.fill_(-7)
+        torch.cuda.synchronize()
+        plan.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((plan.mate_a, plan.mate_b, plan.y_a, plan.y_b), direct):
+            assert torch.equal(a, b)
+    plan.close()
+
+
 def test_batched_large_instances(ctx):
     """Instances up to the batched limit (n = 2048) use the larger LDS layout."""
     rng = np.random.default_rng(3)
