@@ -85,19 +85,26 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
     const int64_t b0 = (int64_t)blockIdx.y * kMaxRows;
     if (b0 >= in.n || (int64_t)blockIdx.x * kBuildThreads >= in.n) return;
     const int rows = (int)min<int64_t>(kMaxRows, in.n - b0);
-    for (int i = threadIdx.x; i < rows * D; i += kBuildThreads) xs[i] = in.X[b0 * D + i];
+    // A non-finite coordinate is caught where it is loaded; with finite
+    // coordinates a distance can only overflow to +inf, which the maximum
+    // keeps, so no per-pair test is needed.
+    bool bad = false;
+    for (int i = threadIdx.x; i < rows * D; i += kBuildThreads) {
+        const float v = in.X[b0 * D + i];
+        bad |= !(fabsf(v) <= FLT_MAX);
+        xs[i] = v;
+    }
     __syncthreads();
     float mx = 0.0f;
-    bool bad = false;
     if (a < in.n) {
         float y[D];
 #pragma unroll
-        for (int q = 0; q < D; ++q) y[q] = in.Y[a * D + q];
-        for (int r = 0; r < rows; ++r) {
-            const float s = sqdist<D>(xs + r * D, y, D);
-            bad |= !(s <= FLT_MAX);
-            mx = fmaxf(mx, s);
+        for (int q = 0; q < D; ++q) {
+            y[q] = in.Y[a * D + q];
+            bad |= !(fabsf(y[q]) <= FLT_MAX);
         }
+        for (int r = 0; r < rows; ++r) mx = fmaxf(mx, sqdist<D>(xs + r * D, y, D));
+        bad |= !(mx <= FLT_MAX);
     }
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
@@ -150,27 +157,36 @@ __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
     for (int e = 0; e < kColsPerThread; ++e)
 #pragma unroll
         for (int q = 0; q < D; ++q) yv[e][q] = col0 + e < n ? in.Y[(col0 + e) * D + q] : 0.0f;
+    uint32_t pad = 0;  // padding columns of this thread
+#pragma unroll
+    for (int e = 0; e < kColsPerThread; ++e) pad |= (uint32_t)(col0 + e >= n) << e;
     for (int r = 0; r < rows; ++r) {
         const float *x = xs + r * D;
         float sv[kColsPerThread];
         int g[kColsPerThread];
-        uint32_t slow = 0;
+        bool all_ok = true;
 #pragma unroll
         for (int e = 0; e < kColsPerThread; ++e) {
             const float s = sqdist<D>(x, yv[e], D);
             bool ok;
             g[e] = fast_k(s, inv, delta, K, ok);
             sv[e] = s;
-            slow |= (uint32_t)!ok << e;
+            all_ok &= ok;
         }
-        if (slow) {
+        if (!all_ok) {
+            // rare: entries within the margin of a rounding boundary
+#pragma unroll
+            for (int e = 0; e < kColsPerThread; ++e) {
+                bool ok;
+                fast_k(sv[e], inv, delta, K, ok);
+                if (!ok) g[e] = refine_k(sv[e], g[e], K, th);
+            }
+        }
+        if (pad) {
 #pragma unroll
             for (int e = 0; e < kColsPerThread; ++e)
-                if ((slow >> e) & 1u) g[e] = refine_k(sv[e], g[e], K, th);
+                if ((pad >> e) & 1u) g[e] = 0x7FFF;
         }
-#pragma unroll
-        for (int e = 0; e < kColsPerThread; ++e)
-            if (col0 + e >= n) g[e] = 0x7FFF;
         uint4 w;
         w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
         w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);

@@ -98,24 +98,28 @@ __device__ inline float threshold_of(int32_t j, int32_t K, float mf, double eps)
 }
 
 // v = s * inv in binary32 is within (K + 2) * 2^-22 of the exact s / (m eps)
-// (inv and the product are each rounded once; the exact value is <= K + 1),
-// and the binary64 definition is within 1e-10 of it. So when v is at least
-// this margin away from every integer, floor(v) is the definition's k.
+// for every 0 <= s <= m (inv and the product are each rounded once; the exact
+// value is <= K + 1), and the binary64 definition is within 1e-10 of it. So
+// when v is at least this margin away from every integer, floor(v) is the
+// definition's k (at most K, since s <= m).
 __device__ inline float classify_margin(int32_t K) { return (float)(K + 2) * 4.8e-7f; }
 
 __device__ inline int fast_k(float s, float inv, float delta, int K, bool &exact)
 {
     const float v = __fmul_rn(s, inv);
-    int g = (int)fminf(v, (float)K);
-    g = g < 0 ? 0 : g;
-    const float f = __fsub_rn(v, (float)g);
-    exact = f >= delta && f <= 1.0f - delta && v < (float)K;
+    // v - floor(v), exact for 0 <= v < 2^23; floor(v) by truncation (v >= 0)
+    const float f = __builtin_amdgcn_fractf(v);
+    const int g = (int)v;
+    exact = f >= delta && f <= 1.0f - delta;
+    (void)K;
     return g;
 }
 
-// Exact k from a starting guess and the threshold table th[0..K+1].
+// Exact k from a starting guess (clamped to [0, K]) and the threshold table
+// th[0..K+1].
 __device__ inline int refine_k(float s, int g, int K, const float *th)
 {
+    g = g > K ? K : (g < 0 ? 0 : g);
     while (g < K && s >= th[g + 1]) ++g;
     while (g > 0 && s < th[g]) --g;
     return g;
