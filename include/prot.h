@@ -48,6 +48,7 @@ enum {
 
 enum { PROT_EPS_ALGORITHMIC = 0, PROT_EPS_STRICT = 1 };
 enum { PROT_COST_DIRECT = 0, PROT_COST_MATRIX_CORES = 1 };
+enum { PROT_COSTS_AUTO = 0, PROT_COSTS_MATRIX = 1, PROT_COSTS_ON_THE_FLY = 2 };
 enum { PROT_ORIGIN_DIAG = 0, PROT_ORIGIN_ZERO = 1 };
 
 typedef struct {
@@ -60,7 +61,14 @@ typedef struct {
     /* 1: skip the arbitrary completion (Section 2.1), return the phase-loop
      * matching as is. */
     int32_t no_completion;
-    int32_t reserved[5];
+    /* Point-set solves: where the rounded costs live. PROT_COSTS_AUTO picks;
+     * PROT_COSTS_MATRIX builds the n x n int16 matrix and scans it;
+     * PROT_COSTS_ON_THE_FLY (d = 2, 3) builds only the maximum and the
+     * threshold table and lets the greedy step recompute each k it examines
+     * from the points with the build's own operations (identical integers,
+     * no n^2 memory). */
+    int32_t cost_storage;
+    int32_t reserved[4];
     /* Stop after this many phases (0: run to completion); the call then
      * returns PROT_PARTIAL and the outputs hold a valid resumable state. */
     int64_t max_phases;

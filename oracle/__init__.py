@@ -63,8 +63,11 @@ def _load():
     lib.orc_points_cost_f64.argtypes = [p, p, i64, i64, i32, f64, p, p, p]
     lib.orc_solve_rounded.argtypes = [p, i64, i64, i64, i32, i64, i32, i32,
                                       p, p, p, p, p, p, i64]
+    lib.orc_points_max_f32.argtypes = [p, p, i64, i64, i32, p]
+    lib.orc_points_pairs_f32.argtypes = [p, p, i32, f64, ctypes.c_float, p, p, i64, p]
     for fn in (lib.orc_round_cost, lib.orc_round_points_f32,
-               lib.orc_points_cost_f64, lib.orc_solve_rounded):
+               lib.orc_points_cost_f64, lib.orc_solve_rounded, lib.orc_points_max_f32,
+               lib.orc_points_pairs_f32):
         fn.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -109,6 +112,31 @@ def round_points_f32(X: np.ndarray, Y: np.ndarray, eps: float):
     _check(_load().orc_round_points_f32(_ptr(X), _ptr(Y), nb, na, d, float(eps),
                                         _ptr(k), na, _ptr(m)), "round_points_f32")
     return k, float(m[0])
+
+
+def points_max_f32(X: np.ndarray, Y: np.ndarray) -> float:
+    """The binary32 maximum squared distance of round_points_f32, without the
+    matrix (for large n)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    m = np.zeros(1, dtype=np.float32)
+    _check(_load().orc_points_max_f32(_ptr(X), _ptr(Y), X.shape[0], Y.shape[0], X.shape[1],
+                                      _ptr(m)), "points_max_f32")
+    return float(m[0])
+
+
+def points_pairs_f32(X: np.ndarray, Y: np.ndarray, eps: float, m: float, b_idx, a_idx):
+    """Eq. (1) of round_points_f32 for the pairs (b_idx[i], a_idx[i]) only,
+    given the maximum m."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    b_idx = np.ascontiguousarray(b_idx, dtype=np.int64)
+    a_idx = np.ascontiguousarray(a_idx, dtype=np.int64)
+    out = np.empty(len(b_idx), dtype=np.int16)
+    _check(_load().orc_points_pairs_f32(_ptr(X), _ptr(Y), X.shape[1], float(eps),
+                                        ctypes.c_float(m), _ptr(b_idx), _ptr(a_idx),
+                                        len(b_idx), _ptr(out)), "points_pairs_f32")
+    return out
 
 
 def points_cost_f64(X: np.ndarray, Y: np.ndarray, eps: float | None = None,

@@ -80,6 +80,50 @@ int orc_round_points_f32(const float *X, const float *Y, int64_t n_b,
     return ORC_OK;
 }
 
+/* The same binary32 squared distance as orc_round_points_f32, for large
+ * instances whose n^2 matrix is not wanted: the maximum over all pairs, then
+ * eq. (1) for chosen pairs (b_i, a_i) only. */
+static float sq_f32(const float *x, const float *y, int32_t d)
+{
+    float s = 0.0f;
+    for (int32_t j = 0; j < d; ++j) {
+        float t = x[j] - y[j];
+        s = fmaf(t, t, s);
+    }
+    return s;
+}
+
+int orc_points_max_f32(const float *X, const float *Y, int64_t n_b, int64_t n_a, int32_t d,
+                       float *m_out)
+{
+    if (!X || !Y || !m_out || n_b < 0 || n_a < 0 || d <= 0) return ORC_E_ARG;
+    float m = 0.0f;
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) {
+            float s = sq_f32(X + b * d, Y + a * d, d);
+            if (s > m) m = s;
+        }
+    *m_out = m;
+    return ORC_OK;
+}
+
+int orc_points_pairs_f32(const float *X, const float *Y, int32_t d, double eps, float m,
+                         const int64_t *b_idx, const int64_t *a_idx, int64_t count,
+                         int16_t *k_out)
+{
+    if (!X || !Y || !b_idx || !a_idx || !k_out || count < 0 || d <= 0) return ORC_E_ARG;
+    if (!eps_ok(eps)) return ORC_E_EPS;
+    for (int64_t i = 0; i < count; ++i) {
+        if (m == 0.0f) {
+            k_out[i] = 0;
+        } else {
+            double c = (double)sq_f32(X + b_idx[i] * d, Y + a_idx[i] * d, d) / (double)m;
+            k_out[i] = (int16_t)floor(c / eps);
+        }
+    }
+    return ORC_OK;
+}
+
 int orc_points_cost_f64(const float *X, const float *Y, int64_t n_b,
                         int64_t n_a, int32_t d, double eps, double *c64,
                         int16_t *k64, double *m_out)

@@ -55,6 +55,15 @@ int orc_round_points_f32(const float *X, const float *Y, int64_t n_b,
                          int64_t n_a, int32_t d, double eps, int16_t *k,
                          int64_t ldk, float *m_out);
 
+/* Large instances: the binary32 maximum squared distance over all pairs, and
+ * eq. (1) for the chosen pairs (b_idx[i], a_idx[i]) given that maximum. Same
+ * arithmetic as orc_round_points_f32. */
+int orc_points_max_f32(const float *X, const float *Y, int64_t n_b, int64_t n_a, int32_t d,
+                       float *m_out);
+int orc_points_pairs_f32(const float *X, const float *Y, int32_t d, double eps, float m,
+                         const int64_t *b_idx, const int64_t *a_idx, int64_t count,
+                         int16_t *k_out);
+
 /* Reference squared Euclidean cost in binary64 from the same binary32
  * points: c64 = d2_64 / max d2_64 (optional output, n_b x n_a), and
  * k64 = floor(c64 / eps) (optional). Writes the maximum to *m_out. */

@@ -26,8 +26,11 @@ class ProtError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("eps_mode", ctypes.c_int32), ("origin_mode", ctypes.c_int32),
-                ("no_completion", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
-                ("max_phases", ctypes.c_int64)]
+                ("no_completion", ctypes.c_int32), ("cost_storage", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4), ("max_phases", ctypes.c_int64)]
+
+
+COST_STORAGE = {"auto": 0, "matrix": 1, "on_the_fly": 2}
 
 
 class Stats(ctypes.Structure):
@@ -206,11 +209,13 @@ class Context:
         return rc
 
     @staticmethod
-    def _opts(eps_mode="algorithmic", origin="diag", complete=True, max_phases=0) -> Opts:
+    def _opts(eps_mode="algorithmic", origin="diag", complete=True, max_phases=0,
+              storage="auto") -> Opts:
         o = Opts()
         o.eps_mode = EPS_MODES[eps_mode]
         o.origin_mode = ORIGINS[origin]
         o.no_completion = 0 if complete else 1
+        o.cost_storage = COST_STORAGE[storage]
         o.max_phases = int(max_phases)
         return o
 
@@ -306,14 +311,17 @@ class Context:
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
 
     def solve_points(self, X, Y, eps: float, *, eps_mode="algorithmic", origin="diag",
-                     complete=True, max_phases=0) -> Result:
+                     complete=True, max_phases=0, storage="auto") -> Result:
+        """storage: 'auto', 'matrix' (build and scan the n x n int16 matrix) or
+        'on_the_fly' (d = 2, 3: no matrix, each examined cost recomputed from
+        the points); all give the same result."""
         torch = _torch()
         n, d = X.shape
         if Y.shape != (n, d) or not X.is_contiguous() or not Y.is_contiguous():
             raise ValueError("X and Y must be contiguous n x d float32")
         mate_a, mate_b, y_a, y_b = self._outputs(n)
         st = Stats()
-        o = self._opts(eps_mode, origin, complete, max_phases)
+        o = self._opts(eps_mode, origin, complete, max_phases, storage)
         self._bind_stream()
         rc = self._check(self._lib.prot_solve_points(
             self._h, _dev_ptr(X, torch.float32, "X", 2), _dev_ptr(Y, torch.float32, "Y", 2),

@@ -152,10 +152,27 @@ int ensure_thresholds(prot_ctx *c, double eps)
     return PROT_OK;
 }
 
+// PROT_COSTS_AUTO: where the costs of a point-set solve live. A matrix that
+// fits the 256 MiB Infinity Cache is built and scanned (its reads are cheaper
+// than recomputing); a larger one costs more to write than the recomputation
+// in the greedy step, so d = 2, 3 computes costs on the fly.
+bool auto_on_the_fly(int32_t d, int64_t n)
+{
+    return (d == 2 || d == 3) && 2 * n * prot_pitch(n) > ((int64_t)256 << 20);
+}
+
 int grid_for(prot_ctx *c, int64_t n, int *grid)
 {
     const int n_pad = (int)round_up(n, 8);
     if (c->grid_npad != n_pad) {
+        int lds_max = 0;
+        HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                         c->device));
+        // the column duals live in LDS, 2 bytes per column (plus ~1 KB of state)
+        if ((int64_t)n_pad * 2 + 2048 > lds_max)
+            return fail(c, PROT_E_UNSUPPORTED,
+                        "n=%lld: the column duals (2 bytes each) exceed the %d bytes of LDS",
+                        (long long)n, lds_max);
         int gm = 0;
         hipError_t e = prot::loop_grid(n_pad, c->wgs_per_cu, &gm);
         if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
@@ -249,9 +266,16 @@ prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, 
 }
 
 // Enqueue init, the phase loop and the completion; returns after enqueueing.
+// Costs computed on the fly from points of dimension d (d = 0: read k).
+struct OnTheFly {
+    int32_t d = 0;
+    const float *X = nullptr, *Y = nullptr;
+    double eps = 0.0;
+};
+
 int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
              const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
-             int32_t *y_b)
+             int32_t *y_b, const OnTheFly &otf = OnTheFly())
 {
     int rc = ensure_loop(c, n);
     if (rc) return rc;
@@ -259,6 +283,14 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
     if ((rc = grid_for(c, n, &grid))) return rc;
     prot::LoopArgs a = loop_args(c, k, n, ldk, T, o, y_b);
     a.groups = std::min(c->loop_groups, grid);
+    if (otf.d) {
+        a.pd = otf.d;
+        a.px = otf.X;
+        a.py = otf.Y;
+        a.pm = &c->ctl->m;
+        a.pth = c->th;
+        a.peps = otf.eps;
+    }
     if (warm) {
         // (I1) and the matching structure of the given state, O(n).
         HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
@@ -802,18 +834,39 @@ int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, in
     HIP_TRY(c, hipSetDevice(c->device));
     const double ei = eps_internal(eps, o);
     const int64_t T = prot_threshold(ei, n), ldk = prot_pitch(n);
-    int rc = ensure_matrix(c, n);
+    const int32_t storage = o ? o->cost_storage : PROT_COSTS_AUTO;
+    if (storage < PROT_COSTS_AUTO || storage > PROT_COSTS_ON_THE_FLY)
+        return fail(c, PROT_E_ARG, "unknown cost_storage %d", (int)storage);
+    if (storage == PROT_COSTS_ON_THE_FLY && d != 2 && d != 3)
+        return fail(c, PROT_E_UNSUPPORTED, "costs on the fly need d = 2 or 3 (d = %d)", (int)d);
+    const bool on_the_fly =
+        storage == PROT_COSTS_ON_THE_FLY || (storage == PROT_COSTS_AUTO && auto_on_the_fly(d, n));
+    int rc = on_the_fly ? PROT_OK : ensure_matrix(c, n);
     if (!rc) rc = ensure_thresholds(c, ei);
     if (rc) return rc;
+    int16_t *kmat = on_the_fly ? nullptr : c->kmat;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    prot::PointsJob j = points_job(c, X, Y, n, d, ei, c->kmat, ldk);
-    if ((rc = setup_mfma(c, j, n, &c->mfma_buf, &c->mfma_cap))) return rc;
+    prot::PointsJob j = points_job(c, X, Y, n, d, ei, kmat, ldk);
+    j.no_matrix = on_the_fly ? 1 : 0;
+    if (!on_the_fly && (rc = setup_mfma(c, j, n, &c->mfma_buf, &c->mfma_cap))) return rc;
     HIP_TRY(c, prot::launch_points(j, n, ldk, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-    rc = run_loop(c, c->kmat, n, ldk, T, o, 0, mate_a, mate_b, y_a, y_b);
+    OnTheFly otf;
+    if (on_the_fly) {
+        otf.d = d;
+        otf.X = X;
+        otf.Y = Y;
+        otf.eps = ei;
+    }
+    rc = run_loop(c, kmat, n, on_the_fly ? round_up(n, 8) : ldk, T, o, 0, mate_a, mate_b, y_a,
+                  y_b, otf);
     if (rc) return rc;
-    HIP_TRY(c, prot::launch_finalize(n, mate_b, c->kmat, ldk, 2, nullptr, 0, X, Y, d, c->part_k,
-                                     c->part_c, c->stream));
+    if (on_the_fly)
+        HIP_TRY(c, prot::launch_finalize(n, mate_b, nullptr, 0, 2, nullptr, 0, X, Y, d,
+                                         c->part_k, c->part_c, c->stream, &c->ctl->m, ei, c->th));
+    else
+        HIP_TRY(c, prot::launch_finalize(n, mate_b, c->kmat, ldk, 2, nullptr, 0, X, Y, d,
+                                         c->part_k, c->part_c, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
     rc = collect(c, st, T, ei, 2, true);
     if (rc) return rc;

@@ -316,6 +316,7 @@ void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStre
     hipLaunchKernelGGL(points_max_kernel<D>, gmax, dim3(kBuildThreads), 0, s, j);
     hipLaunchKernelGGL(thresholds_kernel, dim3((j.kcap + 255) / 256, 1, j.batch), dim3(256), 0,
                        s, j);
+    if (j.no_matrix) return;
     const int64_t per_block = (int64_t)kBuildThreads * kColsPerThread;
     dim3 gk((unsigned)((ldk_max + per_block - 1) / per_block),
             (unsigned)((n_max + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned)j.batch);

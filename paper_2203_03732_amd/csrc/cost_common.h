@@ -42,6 +42,7 @@ struct PointsJob {
     int32_t *err;              // bit 0 set on a non-finite distance
     int32_t *kmax_out;         // optional: K of instance 0
     MfmaAux mfma;              // used when mfma.tile_max is set (d >= 16)
+    int32_t no_matrix;         // 1: maximum and thresholds only (costs computed on the fly)
 
     __device__ Instance instance(int i) const
     {

@@ -65,6 +65,14 @@ struct LoopArgs {
     Ctl *ctl;
     int64_t *trace;           // 4 int64 per phase
     int64_t *rtime;           // optional: 3 int64 per round (see kRoundTimeCap)
+    // Matrix-free (pd = 2 or 3): k is computed from the points instead of read
+    // from k; m, the threshold table and eps are those of the cost build.
+    int32_t pd;               // 0: read k
+    int32_t pad3;
+    const float *px, *py;     // n x pd rows (supply) and columns (demand)
+    const float *pm;          // device: max squared distance
+    const float *pth;         // device: threshold table th[0..K+1]
+    double peps;
 };
 
 // Per-instance results of the batched solver (layout of prot_instance_stats).
@@ -163,10 +171,14 @@ hipError_t launch_team_finish(const TeamArgs &t, hipStream_t s);
 hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a,
                          int32_t *mate_b, int32_t *y_a, int32_t *scratch,
                          hipStream_t s);
-// cost_kind: 0 none, 1 cost matrix C (ldc), 2 points X, Y (d) with scale m
+// cost_kind: 0 none, 1 cost matrix C (ldc), 2 points X, Y (d) with scale m.
+// With k == nullptr (points, costs on the fly) the rounded cost of each
+// matched pair is recomputed from the points, *m_dev, eps and th.
 hipError_t launch_finalize(int64_t n, const int32_t *mate_b, const int16_t *k,
                            int64_t ldk, int cost_kind, const float *C, int64_t ldc,
                            const float *X, const float *Y, int32_t d,
-                           long long *part_k, double *part_c, hipStream_t s);
+                           long long *part_k, double *part_c, hipStream_t s,
+                           const float *m_dev = nullptr, double eps = 0.0,
+                           const float *th = nullptr);
 
 }  // namespace prot

@@ -173,10 +173,117 @@ __device__ inline Hit hit_at(int a, int origin, int n)
     return Hit{a >= origin ? a - origin : a - origin + n, a};
 }
 
+// Where the loop's rounded costs come from. MatrixSrc reads the int16 matrix;
+// PointsSrc<D> (point sets of dimension D) computes the same integers from
+// the points with the cost build's operations (sqdist, fast_k, refine_k with
+// the instance's threshold table), so no n x n matrix is stored or read.
+// chunk(row, col0) gives k for columns col0 .. col0 + 7 (col0 a multiple of
+// 8, col0 < n), 0x7FFF past n.
+struct MatrixSrc {
+    static constexpr int kAhead = kPrefetch;      // chunks in flight in a long scan
+    static constexpr int kTeamAhead = kTeamPrefetch;
+    static constexpr int kBatch = kSlotBatch;     // rows whose first chunks go together
+    const int16_t *k;
+    int64_t ldk;
+    using Row = const int16_t *;
+    __device__ Row row(int b) const { return k + (int64_t)b * ldk; }
+    __device__ uint4 chunk(const Row &r, int col0) const
+    {
+        return *reinterpret_cast<const uint4 *>(r + col0);
+    }
+};
+
+template <int D>
+struct PointsSrc {
+    // computing ahead buys less than loading ahead and costs 8 * D registers
+    // per chunk
+    static constexpr int kAhead = 2;
+    static constexpr int kTeamAhead = 2;
+    static constexpr int kBatch = 2;
+    const float *X, *Y, *th;
+    float inv, delta;
+    int K, n;
+    struct Row {
+        float x[D];
+    };
+    __device__ Row row(int b) const
+    {
+        Row r;
+#pragma unroll
+        for (int q = 0; q < D; ++q) r.x[q] = X[(int64_t)b * D + q];
+        return r;
+    }
+    __device__ uint4 chunk(const Row &r, int col0) const
+    {
+        float y[8 * D];
+        if (col0 + 8 <= n) {
+            // 8 points = 2D float4 (col0 is a multiple of 8, so aligned)
+            const float4 *p = reinterpret_cast<const float4 *>(Y + (int64_t)col0 * D);
+#pragma unroll
+            for (int i = 0; i < 2 * D; ++i) {
+                const float4 v = p[i];
+                y[4 * i] = v.x;
+                y[4 * i + 1] = v.y;
+                y[4 * i + 2] = v.z;
+                y[4 * i + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8 * D; ++i) y[i] = col0 + i / D < n ? Y[(int64_t)col0 * D + i] : 0.0f;
+        }
+        int g[8];
+        float sv[8];
+        bool all_ok = true;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            bool ok;
+            sv[e] = sqdist<D>(r.x, y + e * D, D);
+            g[e] = fast_k(sv[e], inv, delta, K, ok);
+            all_ok &= ok;
+        }
+        if (!all_ok) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                bool ok;
+                fast_k(sv[e], inv, delta, K, ok);
+                if (!ok) g[e] = refine_k(sv[e], g[e], K, th);
+            }
+        }
+        if (col0 + 8 > n) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (col0 + e >= n) g[e] = 0x7FFF;
+        }
+        uint4 w;
+        w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
+        w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);
+        w.z = (uint32_t)(uint16_t)g[4] | ((uint32_t)(uint16_t)g[5] << 16);
+        w.w = (uint32_t)(uint16_t)g[6] | ((uint32_t)(uint16_t)g[7] << 16);
+        return w;
+    }
+};
+
+template <int D>
+__device__ inline PointsSrc<D> points_src(const LoopArgs &A)
+{
+    // the same m, K, 1/(m eps) and margin as the cost build's pass 2
+    PointsSrc<D> s;
+    const float mf = *A.pm;
+    s.X = A.px;
+    s.Y = A.py;
+    s.th = A.pth;
+    s.K = (mf > 0.0f) ? (int32_t)floor(1.0 / A.peps) : 0;
+    s.inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * A.peps)) : 0.0f;
+    s.delta = classify_margin(s.K);
+    s.n = A.n;
+    return s;
+}
+
 // Continue the wave-cooperative scan of a row in segment sg at column base
 // (a multiple of 8), kPrefetch chunks in flight; the duals come from LDS.
-__device__ Hit scan_from(const int16_t *__restrict__ row, const uint16_t *t_lds, int n, int origin,
-                         const Segs &S, int sg, int base, int need, int lane)
+template <class Src>
+__device__ Hit scan_from(const Src &src, const typename Src::Row &row, const uint16_t *t_lds,
+                         int n, int origin, const Segs &S, int sg, int base, int need, int lane)
 {
     for (; sg < 2; ++sg) {
         const int slo = S.lo(sg), shi = S.hi(sg);
@@ -186,22 +293,22 @@ __device__ Hit scan_from(const int16_t *__restrict__ row, const uint16_t *t_lds,
         }
         if (base < 0) base = slo & ~7;
         while (base < shi) {
-            uint4 kv[kPrefetch];
+            uint4 kv[Src::kAhead];
 #pragma unroll
-            for (int u = 0; u < kPrefetch; ++u) {
+            for (int u = 0; u < Src::kAhead; ++u) {
                 const int col0 = base + u * kChunk + lane * 8;
                 kv[u] = make_uint4(0u, 0u, 0u, 0u);
-                if (col0 < shi) kv[u] = *reinterpret_cast<const uint4 *>(row + col0);
+                if (col0 < shi) kv[u] = src.chunk(row, col0);
             }
 #pragma unroll
-            for (int u = 0; u < kPrefetch; ++u) {
+            for (int u = 0; u < Src::kAhead; ++u) {
                 const int col0 = base + u * kChunk + lane * 8;
                 uint4 tv = make_uint4(0u, 0u, 0u, 0u);
                 if (col0 < shi) tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
                 const int a = chunk_hit(col0, kv[u], tv, need, slo, shi);
                 if (a >= 0) return hit_at(a, origin, n);
             }
-            base += kPrefetch * kChunk;
+            base += Src::kAhead * kChunk;
         }
         base = -1;
     }
@@ -217,8 +324,10 @@ __device__ Hit scan_from(const int16_t *__restrict__ row, const uint16_t *t_lds,
 // (*best, in LDS) precedes them.
 constexpr int kNoHit = 0x7FFFFFFF;
 
-__device__ int team_scan(const int16_t *__restrict__ row, const uint16_t *t_lds, int n, int origin,
-                         const Segs &S, int need, int k, int R, int lane, const int *best)
+template <class Src>
+__device__ int team_scan(const Src &src, const typename Src::Row &row, const uint16_t *t_lds,
+                         int n, int origin, const Segs &S, int need, int k, int R, int lane,
+                         const int *best)
 {
     const int b0 = S.lo0 & ~7, b1 = S.lo1 & ~7;
     const int nc0 = S.lo0 < S.hi0 ? (S.hi0 - b0 + kChunk - 1) / kChunk : 0;
@@ -227,19 +336,19 @@ __device__ int team_scan(const int16_t *__restrict__ row, const uint16_t *t_lds,
     int c = k;
     int depth = 1;
     while (c < nc) {
-        uint4 kv[kTeamPrefetch];
+        uint4 kv[Src::kTeamAhead];
 #pragma unroll
-        for (int u = 0; u < kTeamPrefetch; ++u) {
+        for (int u = 0; u < Src::kTeamAhead; ++u) {
             const int cc = c + u * R;
             kv[u] = make_uint4(0u, 0u, 0u, 0u);
             if (u < depth && cc < nc) {
                 const bool s1 = cc >= nc0;
                 const int col0 = (s1 ? b1 + (cc - nc0) * kChunk : b0 + cc * kChunk) + lane * 8;
-                if (col0 < (s1 ? S.hi1 : S.hi0)) kv[u] = *reinterpret_cast<const uint4 *>(row + col0);
+                if (col0 < (s1 ? S.hi1 : S.hi0)) kv[u] = src.chunk(row, col0);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kTeamPrefetch; ++u) {
+        for (int u = 0; u < Src::kTeamAhead; ++u) {
             const int cc = c + u * R;
             if (u >= depth || cc >= nc) break;
             const bool s1 = cc >= nc0;
@@ -251,7 +360,7 @@ __device__ int team_scan(const int16_t *__restrict__ row, const uint16_t *t_lds,
             if (a >= 0) return hit_at(a, origin, n).j;
         }
         c += depth * R;
-        depth = kTeamPrefetch;
+        depth = Src::kTeamAhead;
         if (c < nc) {
             // first scan position of chunk c
             const bool s1 = c >= nc0;
@@ -338,7 +447,20 @@ __global__ void check_state_kernel(int64_t n, const int32_t *mate_a, const int32
 // kMulti: many instances in one launch, `team` consecutive workgroups per
 // instance, the instance's arguments in arr[blockIdx.x / team]; the barrier,
 // lists and statistics of each instance involve only its own team.
-template <bool kMulti>
+template <int D>
+struct SrcOf {
+    using type = PointsSrc<D>;
+    static __device__ type make(const LoopArgs &A) { return points_src<D>(A); }
+};
+template <>
+struct SrcOf<0> {
+    using type = MatrixSrc;
+    static __device__ type make(const LoopArgs &A) { return MatrixSrc{A.k, A.ldk}; }
+};
+
+// kSrcD: 0 reads the rounded-cost matrix; 2 or 3 computes it from points of
+// that dimension (matrix-free).
+template <bool kMulti, int kSrcD>
 __global__ void __launch_bounds__(kLoopThreads)
 phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32_t *y_base)
 {
@@ -346,6 +468,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     // array in global memory), read through the scalar cache when needed
     const LoopArgs &A = kMulti ? arr[blockIdx.x / team] : A0;
     int32_t *const y_b = kMulti ? y_base + A.y_off : A.y_b;
+    const typename SrcOf<kSrcD>::type src = SrcOf<kSrcD>::make(A);
     // workgroups of this instance, and this workgroup's rank among them
     const uint32_t nwg = kMulti ? (uint32_t)team : gridDim.x;
     const uint32_t wg = kMulti ? blockIdx.x % (uint32_t)team : blockIdx.x;
@@ -475,7 +598,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 int* best = &s_best[r & 1][team_local];
                 if (active & 1ull) {
                     const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, n);
-                    const int j = team_scan(A.k + (int64_t)v.b * A.ldk, t_lds, n, v.origin, v.S,
+                    const int j = team_scan(src, src.row(v.b), t_lds, n, v.origin, v.S,
                                             v.yb - 1, k_rank, R, lane, best);
                     if (lane == 0 && j != kNoHit) atomicMin(best, j);
                 }
@@ -519,14 +642,14 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     if (lead && lane == 0) s_best[(r + 1) & 1][team_local] = kNoHit;
                 }
             }
-            // Slot mode: rows are taken kSlotBatch at a time so that their
+            // Slot mode: rows are taken a few at a time (kBatch) so that their
             // first chunks are loaded together.
             unsigned long long rem = R == 1 ? active : 0ull;
             while (rem) {
-                int sl[kSlotBatch];
-                uint4 kvq[kSlotBatch];
+                int sl[SrcOf<kSrcD>::type::kBatch];
+                uint4 kvq[SrcOf<kSrcD>::type::kBatch];
 #pragma unroll
-                for (int q = 0; q < kSlotBatch; ++q) {
+                for (int q = 0; q < SrcOf<kSrcD>::type::kBatch; ++q) {
                     sl[q] = -1;
                     kvq[q] = make_uint4(0u, 0u, 0u, 0u);
                     if (!rem) continue;
@@ -535,10 +658,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     const SlotView v = slot_view(sl[q], s_b, s_pos, s_yb, A.origin, n);
                     const int col0 = v.base + lane * 8;
                     if (col0 < v.S.hi(v.sg))
-                        kvq[q] = *reinterpret_cast<const uint4 *>(A.k + (int64_t)v.b * A.ldk + col0);
+                        kvq[q] = src.chunk(src.row(v.b), col0);
                 }
 #pragma unroll
-                for (int q = 0; q < kSlotBatch; ++q) {
+                for (int q = 0; q < SrcOf<kSrcD>::type::kBatch; ++q) {
                     if (sl[q] < 0) continue;
                     const int s = sl[q];
                     const SlotView v = slot_view(s, s_b, s_pos, s_yb, A.origin, n);
@@ -551,7 +674,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     const int a = chunk_hit(col0, kvq[q], tv, yb - 1, slo, shi);
                     if (a >= 0) h = hit_at(a, v.origin, n);
                     else if (slo < shi)
-                        h = scan_from(A.k + (int64_t)b * A.ldk, t_lds, n, v.origin, v.S, v.sg,
+                        h = scan_from(src, src.row(b), t_lds, n, v.origin, v.S, v.sg,
                                       v.base + kChunk, yb - 1, lane);
                     if (h.j >= 0) {
                         wave_scan += (unsigned long long)(h.j - pos + 1);
@@ -818,8 +941,18 @@ constexpr int kFinalizeThreads = 256;
 __global__ void __launch_bounds__(kFinalizeThreads)
 finalize_kernel(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk, int cost_kind,
                 const float *C, int64_t ldc, const float *X, const float *Y, int32_t d,
-                long long *part_k, double *part_c)
+                long long *part_k, double *part_c, const float *m_dev, double eps,
+                const float *th)
 {
+    // costs on the fly: the cost build's rounding of each matched pair
+    int K = 0;
+    float inv = 0.0f, delta = 0.0f;
+    if (!k && m_dev) {
+        const float mf = *m_dev;
+        K = (mf > 0.0f) ? (int32_t)floor(1.0 / eps) : 0;
+        inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * eps)) : 0.0f;
+        delta = classify_margin(K);
+    }
     __shared__ long long sk[kFinalizeThreads];
     __shared__ double sc[kFinalizeThreads];
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -829,7 +962,15 @@ finalize_kernel(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk,
     for (int64_t b = lo + threadIdx.x; b < hi; b += kFinalizeThreads) {
         const int32_t a = mate_b[b];
         if (a < 0) continue;
-        if (k) ks += k[b * ldk + a];
+        if (k) {
+            ks += k[b * ldk + a];
+        } else if (m_dev) {
+            const float sq = sqdist<0>(X + b * d, Y + (int64_t)a * d, d);
+            bool ok;
+            int g = fast_k(sq, inv, delta, K, ok);
+            if (!ok) g = refine_k(sq, g, K, th);
+            ks += g;
+        }
         if (cost_kind == 1) {
             cs = __dadd_rn(cs, (double)C[b * ldc + a]);
         } else if (cost_kind == 2) {
@@ -1021,12 +1162,12 @@ hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max)
     const size_t lds = (size_t)n_pad * sizeof(uint16_t);
     hipError_t e = hipSuccess;
     if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)phase_loop_kernel<false>,
+        e = hipFuncSetAttribute((const void *)phase_loop_kernel<false, 0>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<false>,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<false, 0>,
                                                      kLoopThreads, lds);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
@@ -1049,8 +1190,15 @@ hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
     int32_t *no_base = nullptr;
     void *args[] = {&copy, &none, &team, &no_base};
     const size_t lds = (size_t)a.n_pad * sizeof(uint16_t);
-    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel<false>, dim3(grid),
-                                      dim3(kLoopThreads), args, (unsigned)lds, s);
+    const void *fn = a.pd == 2   ? (const void *)phase_loop_kernel<false, 2>
+                     : a.pd == 3 ? (const void *)phase_loop_kernel<false, 3>
+                                 : (const void *)phase_loop_kernel<false, 0>;
+    if (a.pd && lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kLoopThreads), args, (unsigned)lds, s);
 }
 
 hipError_t loop_grid_multi(int32_t n_pad_max, int wgs_per_cu, int *grid_max)
@@ -1058,12 +1206,12 @@ hipError_t loop_grid_multi(int32_t n_pad_max, int wgs_per_cu, int *grid_max)
     const size_t lds = (size_t)n_pad_max * sizeof(uint16_t);
     hipError_t e = hipSuccess;
     if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)phase_loop_kernel<true>,
+        e = hipFuncSetAttribute((const void *)phase_loop_kernel<true, 0>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     int per_cu = 0, dev = 0, cus = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<true>,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<true, 0>,
                                                      kLoopThreads, lds);
     if (e != hipSuccess) return e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
@@ -1088,7 +1236,7 @@ hipError_t launch_loop_multi(const LoopArgs *arr, int count, int team, int32_t n
     LoopArgs none{};
     void *args[] = {&none, &arr, &team, &y_base};
     const size_t lds = (size_t)n_pad_max * sizeof(uint16_t);
-    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel<true>,
+    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel<true, 0>,
                                       dim3((unsigned)(count * team)), dim3(kLoopThreads), args,
                                       (unsigned)lds, s);
 }
@@ -1116,10 +1264,11 @@ hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a, i
 hipError_t launch_finalize(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk,
                            int cost_kind, const float *C, int64_t ldc, const float *X,
                            const float *Y, int32_t d, long long *part_k, double *part_c,
-                           hipStream_t s)
+                           hipStream_t s, const float *m_dev, double eps, const float *th)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(kFinalizeThreads), 0, s, n,
-                       mate_b, k, ldk, cost_kind, C, ldc, X, Y, d, part_k, part_c);
+                       mate_b, k, ldk, cost_kind, C, ldc, X, Y, d, part_k, part_c, m_dev, eps,
+                       th);
     return hipGetLastError();
 }
 

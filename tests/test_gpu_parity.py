@@ -271,25 +271,98 @@ def test_solve_cost_modes(ctx, eps_mode):
     assert gpu.stats["eps_internal"] == ei
 
 
-def _points_case(ctx, n, d, eps, seed=0):
-    X, Y = synth.uniform_points(n, d, seed=seed)
-    gpu = ctx.solve_points(dev(X), dev(Y), eps)
+def _points_case(ctx, n, d, eps, seed=0, storage="matrix", origin="diag", X=None, Y=None):
+    if X is None:
+        X, Y = synth.uniform_points(n, d, seed=seed)
+    gpu = ctx.solve_points(dev(X), dev(Y), eps, storage=storage, origin=origin)
     k, m = oracle.round_points_f32(X, Y, eps)
-    orc = oracle.solve_rounded(k, oracle.threshold(eps, n), trace=True)
-    assert_same(gpu, orc, f"points n={n}")
+    orc = oracle.solve_rounded(k, oracle.threshold(eps, n), trace=True, origin=origin)
+    assert_same(gpu, orc, f"points n={n} {storage} {origin}")
+    for key in ("phases", "rounds", "scanned", "sum_free", "sum_k"):
+        assert gpu.stats[key] == orc["stats"][key], key
     assert gpu.stats["cost_scale"] == m
     d2 = ((X.astype(np.float64) - Y.astype(np.float64)[orc["mate_b"]]) ** 2).sum(1)
-    assert math.isclose(gpu.stats["cost"], d2.sum() / m, rel_tol=1e-12)
+    want = d2.sum() / m if m > 0 else 0.0  # all points equal: every cost is 0
+    assert math.isclose(gpu.stats["cost"], want, rel_tol=1e-12, abs_tol=1e-300)
     return gpu, orc, k
 
 
-def test_points_small(ctx):
-    _points_case(ctx, 2000, 2, 0.01, seed=4)
-    _points_case(ctx, 1500, 3, 0.005, seed=5)
+@pytest.mark.parametrize("storage", ["matrix", "on_the_fly"])
+def test_points_small(ctx, storage):
+    _points_case(ctx, 2000, 2, 0.01, seed=4, storage=storage)
+    _points_case(ctx, 1500, 3, 0.005, seed=5, storage=storage)
 
 
-def test_points_n10000_eps001(ctx):
+@pytest.mark.parametrize("origin", ["diag", "zero"])
+@pytest.mark.parametrize("n,d,eps", [(1, 2, 0.1), (7, 3, 0.2), (13, 2, 0.05), (1001, 3, 0.01),
+                                     (4099, 2, 0.02)])
+def test_points_on_the_fly_ragged(ctx, n, d, eps, origin):
+    """Costs recomputed in the greedy step: sizes that leave partial chunks,
+    both scan origins; bit-exact with the matrix-free definition."""
+    _points_case(ctx, n, d, eps, seed=n + d, storage="on_the_fly", origin=origin)
+
+
+def test_points_on_the_fly_degenerate(ctx):
+    """All points equal (m = 0, every k = 0) and clustered duplicates."""
+    n = 300
+    X = np.full((n, 2), 0.25, np.float32)
+    _points_case(ctx, n, 2, 0.05, storage="on_the_fly", X=X, Y=X.copy())
+    rng = np.random.default_rng(5)
+    X = np.repeat(rng.random((30, 3), dtype=np.float32), 10, axis=0)
+    Y = np.repeat(rng.random((30, 3), dtype=np.float32), 10, axis=0)
+    _points_case(ctx, n, 3, 0.02, storage="on_the_fly", X=X, Y=Y)
+
+
+def test_points_on_the_fly_rejects_high_d(ctx):
+    import paper_2203_03732_amd as prot
+    X, Y = synth.uniform_points(64, 5, seed=1)
+    with pytest.raises(prot.ProtError) as e:
+        ctx.solve_points(dev(X), dev(Y), 0.1, storage="on_the_fly")
+    assert e.value.name == "unsupported"
+
+
+@pytest.mark.parametrize("storage", ["matrix", "on_the_fly"])
+def test_points_n10000_eps001(ctx, storage):
     """Two sets of 10k uniform points in the unit square, squared Euclidean
     cost scaled to max 1, eps = 0.01: bit-exact with the oracle end to end."""
-    gpu, orc, k = _points_case(ctx, 10000, 2, 0.01, seed=0)
+    gpu, orc, k = _points_case(ctx, 10000, 2, 0.01, seed=0, storage=storage)
     assert np.array_equal(ctx.trace(), orc["trace"])
+
+
+def test_points_n50000_d3_full_size_on_the_fly(ctx):
+    """The 3-D instance at full size (n = 50,000, eps = 0.005) as the default
+    runs it (costs on the fly): the maximum and every matched pair's rounded
+    cost from the oracle, (I1), eq. (3) on the matching, (I2) on sampled full
+    rows, Sigma k, and the dual certificate c(M) <= eps (Sigma y - n) + 3 eps n
+    (c(OPT) >= eps (Sigma y - n) by eq. (2)); the matrix storage gives the
+    identical result."""
+    n, d, eps = 50000, 3, 0.005
+    X, Y = synth.uniform_points(n, d, seed=0)
+    Xd, Yd = dev(X), dev(Y)
+    loop = ctx.solve_points(Xd, Yd, eps, complete=False)
+    full = ctx.solve_points(Xd, Yd, eps)
+    m = oracle.points_max_f32(X, Y)
+    assert loop.stats["cost_scale"] == m and full.stats["cost_scale"] == m
+    mate_a, mate_b = host(loop.mate_a), host(loop.mate_b)
+    ya, yb = host(loop.y_a).astype(np.int64), host(loop.y_b).astype(np.int64)
+    matched = np.nonzero(mate_b >= 0)[0]
+    assert np.array_equal(mate_a[mate_b[matched]], matched)
+    assert n - len(matched) <= oracle.threshold(eps, n)
+    assert (yb >= 0).all() and (ya <= 0).all() and (ya[mate_a < 0] == 0).all()
+    kp = oracle.points_pairs_f32(X, Y, eps, m, matched, mate_b[matched]).astype(np.int64)
+    assert np.array_equal(ya[mate_b[matched]] + yb[matched], kp)  # eq. (3) on M
+    assert loop.stats["sum_k"] == kp.sum()
+    rng = np.random.default_rng(1)
+    cols = np.arange(n)
+    for b in rng.choice(n, 12, replace=False):
+        kr = oracle.points_pairs_f32(X, Y, eps, m, np.full(n, b), cols).astype(np.int64)
+        assert (ya + yb[b] <= kr + 1).all(), f"(I2) fails on row {b}"  # eq. (2)
+    for x in ("y_a", "y_b"):
+        assert torch.equal(getattr(loop, x), getattr(full, x))
+    lb = eps * (ya.sum() + yb.sum() - n)
+    assert full.stats["cost"] <= lb + 3 * eps * n + 1e-9
+    same = ctx.solve_points(Xd, Yd, eps, storage="matrix")
+    for x in ("mate_a", "mate_b", "y_a", "y_b"):
+        assert torch.equal(getattr(same, x), getattr(full, x))
+    for key in ("phases", "rounds", "scanned", "sum_k"):
+        assert same.stats[key] == full.stats[key]

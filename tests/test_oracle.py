@@ -371,3 +371,19 @@ def test_loss_gradient_scales_with_upstream_gradient():
     assert np.allclose(a3, -3.0 * a1) and np.allclose(b3, -3.0 * b1)
     # the two gradients are opposite on matched pairs: sum over all is zero
     assert np.allclose(a1.sum(0) + b1.sum(0), 0.0)
+
+
+def test_points_max_and_pairs_equal_full_matrix():
+    """The large-instance helpers reproduce round_points_f32 exactly."""
+    rng = np.random.default_rng(21)
+    for n, d, eps in [(1, 2, 0.1), (37, 3, 0.01), (200, 2, 0.005), (64, 5, 0.05)]:
+        X = rng.random((n, d), dtype=np.float32)
+        Y = rng.random((n, d), dtype=np.float32)
+        k, m = oracle.round_points_f32(X, Y, eps)
+        assert oracle.points_max_f32(X, Y) == m
+        b = rng.integers(0, n, 300)
+        a = rng.integers(0, n, 300)
+        assert np.array_equal(oracle.points_pairs_f32(X, Y, eps, m, b, a), k[b, a])
+    X = np.full((5, 2), 0.5, np.float32)
+    assert oracle.points_max_f32(X, X) == 0.0
+    assert (oracle.points_pairs_f32(X, X, 0.1, 0.0, [0, 4], [3, 1]) == 0).all()
