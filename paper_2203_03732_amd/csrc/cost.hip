@@ -14,8 +14,10 @@
 //               against a per-instance table of the smallest s reaching each
 //               k (the map s -> k is monotone), giving the identical integer.
 #include "cost_common.h"
+#include "device_common.h"
 #include "internal.h"
 
+#include <algorithm>
 #include <float.h>
 #include <math.h>
 
@@ -117,6 +119,216 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (bad) __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Pruned exact maximum (one instance, d = 2, 3). The maximum of the binary32
+// distances over all pairs is attained by a pair whose real distance is
+// within a relative 2^-21 of it. (1) For each of the 2^d diagonal directions
+// u, the point of X furthest along u and the point of Y furthest along -u;
+// the largest binary32 distance among these pairs is a lower bound L <= m.
+// (2) A point x can be in a pair of binary32 distance >= L only if the
+// furthest corner of Y's bounding box is at real distance >= L (1 - 2^-21);
+// that bound is evaluated in binary64 (exact differences and squares) and
+// tested against L (1 - 1e-5); the same for y against X's box. (3) Every pair
+// of surviving candidates is evaluated in binary32 and the maximum taken, so m
+// is the maximum of the definition bit for bit; with no pruning possible (all
+// pairs near the maximum) step 3 is the full n^2 pass.
+__device__ inline uint32_t order_of(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float float_of(uint32_t o)
+{
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+
+__global__ void prune_reset_kernel(PruneAux a)
+{
+    const int t = threadIdx.x;
+    if (t < 16) a.ext[t] = 0ull;
+    if (t < 12) a.bb[t] = ((t / 3) & 1) ? 0u : 0xFFFFFFFFu;  // min slots start high
+    if (t < 2) a.cnt[t] = 0u;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) extent_kernel(PointsJob j)
+{
+    constexpr int U = 1 << D;
+    const PruneAux &P = j.prune;
+    const int64_t n = j.n_single;
+    unsigned long long ex[U], ey[U];
+    float lo[2][D], hi[2][D];
+#pragma unroll
+    for (int u = 0; u < U; ++u) ex[u] = ey[u] = 0ull;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        lo[0][q] = lo[1][q] = FLT_MAX;
+        hi[0][q] = hi[1][q] = -FLT_MAX;
+    }
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float x[D], y[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            x[q] = j.X[i * D + q];
+            y[q] = j.Y[i * D + q];
+            bad |= !(fabsf(x[q]) <= FLT_MAX) || !(fabsf(y[q]) <= FLT_MAX);
+            lo[0][q] = fminf(lo[0][q], x[q]);
+            hi[0][q] = fmaxf(hi[0][q], x[q]);
+            lo[1][q] = fminf(lo[1][q], y[q]);
+            hi[1][q] = fmaxf(hi[1][q], y[q]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float px = 0.0f, py = 0.0f;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                px += ((u >> q) & 1) ? x[q] : -x[q];
+                py += ((u >> q) & 1) ? -y[q] : y[q];
+            }
+            const unsigned long long kx = ((unsigned long long)order_of(px) << 32) | (uint32_t)i;
+            const unsigned long long ky = ((unsigned long long)order_of(py) << 32) | (uint32_t)i;
+            ex[u] = kx > ex[u] ? kx : ex[u];
+            ey[u] = ky > ey[u] ? ky : ey[u];
+        }
+    }
+    // wave reductions, then one atomic per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned long long ox = __shfl_xor(ex[u], off), oy = __shfl_xor(ey[u], off);
+            ex[u] = ox > ex[u] ? ox : ex[u];
+            ey[u] = oy > ey[u] ? oy : ey[u];
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                lo[w][q] = fminf(lo[w][q], __shfl_xor(lo[w][q], off));
+                hi[w][q] = fmaxf(hi[w][q], __shfl_xor(hi[w][q], off));
+            }
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            __hip_atomic_fetch_max(&P.ext[u], ex[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(&P.ext[8 + u], ey[u], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                __hip_atomic_fetch_min(&P.bb[6 * w + q], order_of(lo[w][q]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_max(&P.bb[6 * w + 3 + q], order_of(hi[w][q]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+    }
+    if (bad) __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int D>
+__device__ inline float prune_lower_bound(const PointsJob &j)
+{
+    // the largest binary32 distance among the directional extreme points
+    constexpr int U = 1 << D;
+    const PruneAux &P = j.prune;
+    float L = 0.0f;
+    for (int u1 = 0; u1 < U; ++u1)
+        for (int u2 = 0; u2 < U; ++u2) {
+            const int64_t bi = (int64_t)(uint32_t)P.ext[u1], ai = (int64_t)(uint32_t)P.ext[8 + u2];
+            L = fmaxf(L, sqdist<D>(j.X + bi * D, j.Y + ai * D, D));
+        }
+    return L;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) prune_kernel(PointsJob j)
+{
+    const PruneAux &P = j.prune;
+    const int64_t n = j.n_single;
+    const double L = (double)prune_lower_bound<D>(j) * (1.0 - 1e-5);
+    double blo[2][D], bhi[2][D];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            blo[w][q] = (double)float_of(P.bb[6 * w + q]);
+            bhi[w][q] = (double)float_of(P.bb[6 * w + 3 + q]);
+        }
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        bool cx = false, cy = false;
+        if (i < n) {
+            // furthest corner of the other set's box, per coordinate
+            double ux = 0.0, uy = 0.0;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                const double x = (double)j.X[i * D + q], y = (double)j.Y[i * D + q];
+                const double a0 = x - blo[1][q], a1 = x - bhi[1][q];
+                const double b0 = y - blo[0][q], b1 = y - bhi[0][q];
+                ux += fmax(a0 * a0, a1 * a1);
+                uy += fmax(b0 * b0, b1 * b1);
+            }
+            cx = ux >= L;
+            cy = uy >= L;
+        }
+        const unsigned long long bx = __ballot(cx), by = __ballot(cy);
+        uint32_t ox = 0, oy = 0;
+        if (lane == 0) {
+            if (bx) ox = atomicAdd(&P.cnt[0], (uint32_t)__popcll(bx));
+            if (by) oy = atomicAdd(&P.cnt[1], (uint32_t)__popcll(by));
+        }
+        ox = __builtin_amdgcn_readfirstlane(ox);
+        oy = __builtin_amdgcn_readfirstlane(oy);
+        if (cx) P.cx[ox + lanes_below(bx)] = (int32_t)i;
+        if (cy) P.cy[oy + lanes_below(by)] = (int32_t)i;
+    }
+}
+
+// Every candidate pair: tiles of kMaxRows x-candidates (staged in LDS) by 256
+// y-candidates, visited by a fixed grid.
+template <int D>
+__global__ void __launch_bounds__(kBuildThreads) pairs_max_kernel(PointsJob j)
+{
+    __shared__ float xs[kMaxRows * D];
+    __shared__ float red[kBuildThreads / 64];
+    const PruneAux &P = j.prune;
+    const int64_t nx = P.cnt[0], ny = P.cnt[1];
+    const int64_t tx = (nx + kMaxRows - 1) / kMaxRows, ty = (ny + kBuildThreads - 1) / kBuildThreads;
+    float mx = 0.0f;
+    for (int64_t t = blockIdx.x; t < tx * ty; t += gridDim.x) {
+        const int64_t r0 = (t / ty) * kMaxRows, c = (t % ty) * kBuildThreads + threadIdx.x;
+        const int rows = (int)min<int64_t>(kMaxRows, nx - r0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < rows * D; i += kBuildThreads)
+            xs[i] = j.X[(int64_t)P.cx[r0 + i / D] * D + i % D];
+        __syncthreads();
+        if (c < ny) {
+            float y[D];
+            const int64_t a = P.cy[c];
+#pragma unroll
+            for (int q = 0; q < D; ++q) y[q] = j.Y[a * D + q];
+            for (int r = 0; r < rows; ++r) mx = fmaxf(mx, sqdist<D>(xs + r * D, y, D));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = red[0];
+        for (int i = 1; i < kBuildThreads / 64; ++i) m = fmaxf(m, red[i]);
+        if (!(m <= FLT_MAX))
+            __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(j.m), __float_as_uint(m),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // th[j] = smallest binary32 s >= 0 with k(s) >= j, for j = 0..K; th[K+1] = +inf.
@@ -311,9 +523,17 @@ void launch_points_tiled(const PointsJob &j, int64_t n_max, int64_t ldk_max, hip
 template <int D>
 void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s)
 {
-    dim3 gmax((unsigned)((n_max + kBuildThreads - 1) / kBuildThreads),
-              (unsigned)((n_max + kMaxRows - 1) / kMaxRows), (unsigned)j.batch);
-    hipLaunchKernelGGL(points_max_kernel<D>, gmax, dim3(kBuildThreads), 0, s, j);
+    if (j.prune.cx && j.batch == 1) {
+        const unsigned g = (unsigned)std::min<int64_t>(1024, (n_max + 255) / 256);
+        hipLaunchKernelGGL(prune_reset_kernel, dim3(1), dim3(64), 0, s, j.prune);
+        hipLaunchKernelGGL(extent_kernel<D>, dim3(g), dim3(256), 0, s, j);
+        hipLaunchKernelGGL(prune_kernel<D>, dim3(g), dim3(256), 0, s, j);
+        hipLaunchKernelGGL(pairs_max_kernel<D>, dim3(1024), dim3(kBuildThreads), 0, s, j);
+    } else {
+        dim3 gmax((unsigned)((n_max + kBuildThreads - 1) / kBuildThreads),
+                  (unsigned)((n_max + kMaxRows - 1) / kMaxRows), (unsigned)j.batch);
+        hipLaunchKernelGGL(points_max_kernel<D>, gmax, dim3(kBuildThreads), 0, s, j);
+    }
     hipLaunchKernelGGL(thresholds_kernel, dim3((j.kcap + 255) / 256, 1, j.batch), dim3(256), 0,
                        s, j);
     if (j.no_matrix) return;

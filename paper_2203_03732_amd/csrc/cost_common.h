@@ -25,6 +25,14 @@ struct MfmaAux {
     float cE;                 // error-bound constant for this d
 };
 
+// Workspace of the pruned maximum (one instance, d <= 3).
+struct PruneAux {
+    unsigned long long *ext;  // [16]: X then Y, per direction u: (order(u . p) << 32) | index
+    uint32_t *bb;             // [12]: order-encoded min X, max X, min Y, max Y per coordinate
+    uint32_t *cnt;            // [2]: candidate counts of X and Y
+    int32_t *cx, *cy;         // candidate indices (n each)
+};
+
 struct PointsJob {
     const float *X, *Y;        // packed points; instance i starts at row pt_off[i]
     const int64_t *pt_off;     // device, per instance (null: one instance at row 0)
@@ -43,6 +51,7 @@ struct PointsJob {
     int32_t *kmax_out;         // optional: K of instance 0
     MfmaAux mfma;              // used when mfma.tile_max is set (d >= 16)
     int32_t no_matrix;         // 1: maximum and thresholds only (costs computed on the fly)
+    PruneAux prune;            // used when prune.cx is set (one instance, d = 2, 3)
 
     __device__ Instance instance(int i) const
     {

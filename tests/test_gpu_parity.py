@@ -366,3 +366,71 @@ def test_points_n50000_d3_full_size_on_the_fly(ctx):
         assert torch.equal(getattr(same, x), getattr(full, x))
     for key in ("phases", "rounds", "scanned", "sum_k"):
         assert same.stats[key] == full.stats[key]
+
+
+@pytest.fixture(scope="module")
+def prune_ctx():
+    """A context that prunes the maximum pass at every size (the default
+    starts at n = 16384)."""
+    import os
+    import paper_2203_03732_amd as prot
+    old = os.environ.get("PROT_PRUNE_MIN_N")
+    os.environ["PROT_PRUNE_MIN_N"] = "0"
+    try:
+        c = prot.Context(0)
+    finally:
+        if old is None:
+            del os.environ["PROT_PRUNE_MIN_N"]
+        else:
+            os.environ["PROT_PRUNE_MIN_N"] = old
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _pruning_points(case, d):
+    rng = np.random.default_rng(sum(map(ord, case)) + d)
+    n = 1 if case == "one" else 700
+    if case == "clusters":  # every cross pair is near the maximum: nothing pruned
+        X = (rng.random((n, d)) * 1e-3).astype(np.float32)
+        Y = (5.0 + rng.random((n, d)) * 1e-3).astype(np.float32)
+    elif case == "equal":
+        X = np.full((n, d), -3.5, np.float32)
+        Y = X.copy()
+    elif case == "negative":
+        X = (-rng.random((n, d)) * 7).astype(np.float32)
+        Y = (-rng.random((n, d)) * 3 - 2).astype(np.float32)
+    elif case == "offset":
+        X = (1000.0 + rng.standard_normal((n, d))).astype(np.float32)
+        Y = (1000.0 + rng.standard_normal((n, d))).astype(np.float32)
+    elif case == "line":
+        t = rng.random(n).astype(np.float32)
+        X = np.stack([t, 2 * t] + [t] * (d - 2), 1).astype(np.float32)
+        Y = np.stack([1 - t, 2 - 2 * t] + [t] * (d - 2), 1).astype(np.float32)
+    elif case == "sphere":
+        v = rng.standard_normal((n, d))
+        X = (v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
+        w = rng.standard_normal((n, d))
+        Y = (w / np.linalg.norm(w, axis=1, keepdims=True)).astype(np.float32)
+    else:  # one point each
+        X = rng.random((n, d), dtype=np.float32)
+        Y = rng.random((n, d), dtype=np.float32)
+    return np.ascontiguousarray(X), np.ascontiguousarray(Y)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("case", ["clusters", "equal", "one", "negative", "offset", "line",
+                                  "sphere"])
+def test_points_maximum_pruning_cases(prune_ctx, case, d):
+    """The maximum over all pairs is found by pruning to candidate pairs; it
+    must equal the definition's maximum bit for bit, in the cost build and in
+    the solve with costs on the fly."""
+    ctx = prune_ctx
+    X, Y = _pruning_points(case, d)
+    k, m = ctx.build_costs(dev(X), dev(Y), 0.05)
+    torch.cuda.synchronize()
+    ko, mo = oracle.round_points_f32(X, Y, 0.05)
+    assert float(host(m)[0]) == mo
+    assert np.array_equal(host(k)[:, :X.shape[0]], ko)
+    gpu = ctx.solve_points(dev(X), dev(Y), 0.05, storage="on_the_fly")
+    assert gpu.stats["cost_scale"] == mo
