@@ -422,6 +422,7 @@ struct prot_batch {
     prot::LoopArgs *loops = nullptr;
     unsigned long long *t_key = nullptr, *t_lists = nullptr, *t_words = nullptr;
     uint16_t *t_t = nullptr;
+    uint32_t *t_skip = nullptr;
     Ctl *t_ctl = nullptr;
     int32_t *t_scratch = nullptr;
 };
@@ -479,6 +480,7 @@ int setup_teams(prot_ctx *c, prot_batch *bp, const std::vector<int32_t> &n_arr,
     if (!rc) rc = dev_alloc(c, &bp->t_words, (size_t)(words_per * batch));
     if (!rc) rc = dev_alloc(c, &bp->t_ctl, (size_t)batch);
     if (!rc) rc = dev_alloc(c, &bp->t_scratch, (size_t)ns);
+    if (!rc) rc = dev_alloc(c, &bp->t_skip, (size_t)nk);
     if (rc) return rc;
     // list entries carry tags, so fresh memory must hold none by chance
     HIP_TRY(c, hipMemset(bp->t_lists, 0, sizeof(unsigned long long) * (size_t)nl));
@@ -497,6 +499,7 @@ int setup_teams(prot_ctx *c, prot_batch *bp, const std::vector<int32_t> &n_arr,
         a.origin = origin;
         a.max_phases = bp->opts.max_phases;
         a.key = bp->t_key + ok;
+        a.skip = bp->t_skip + ok;
         a.t = bp->t_t + ot;
         a.y_b = nullptr;  // the launch's y_b base + y_off
         for (int q = 0; q < 2; ++q) {
@@ -1008,6 +1011,7 @@ int prot_batch_destroy(prot_batch *bp)
     (void)hipFree(bp->t_t);
     (void)hipFree(bp->t_ctl);
     (void)hipFree(bp->t_scratch);
+    (void)hipFree(bp->t_skip);
     delete bp;
     return PROT_OK;
 }

@@ -67,6 +67,10 @@ struct LoopArgs {
     int64_t *rtime;           // optional: 3 int64 per round (see kRoundTimeCap)
     // Matrix-free (pd = 2 or 3): k is computed from the points instead of read
     // from k; m, the threshold table and eps are those of the cost build.
+    // Exact fast-forward (null: off): skip[b] > 0 means row b cannot find an
+    // admissible column in its next skip[b] phases (its smallest slack, seen
+    // by a full first-round scan that found none, was skip[b] + 1 or more).
+    uint32_t *skip;
     int32_t pd;               // 0: read k
     int32_t pad3;
     const float *px, *py;     // n x pd rows (supply) and columns (demand)

@@ -98,6 +98,13 @@ __device__ inline uint32_t wave_sum(uint32_t v)
     return v;
 }
 
+__device__ inline int wave_min(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return v;
+}
+
 __device__ inline uint32_t wave_exclusive_scan(uint32_t v, int lane)
 {
     uint32_t x = v;
@@ -281,9 +288,10 @@ __device__ inline PointsSrc<D> points_src(const LoopArgs &A)
 
 // Continue the wave-cooperative scan of a row in segment sg at column base
 // (a multiple of 8), kPrefetch chunks in flight; the duals come from LDS.
-template <class Src>
+template <int AHEAD, class Src>
 __device__ Hit scan_from(const Src &src, const typename Src::Row &row, const uint16_t *t_lds,
-                         int n, int origin, const Segs &S, int sg, int base, int need, int lane)
+                         int n, int origin, const Segs &S, int sg, int base, int need, int lane,
+                         int *mn)
 {
     for (; sg < 2; ++sg) {
         const int slo = S.lo(sg), shi = S.hi(sg);
@@ -293,22 +301,24 @@ __device__ Hit scan_from(const Src &src, const typename Src::Row &row, const uin
         }
         if (base < 0) base = slo & ~7;
         while (base < shi) {
-            uint4 kv[Src::kAhead];
+            uint4 kv[AHEAD];
 #pragma unroll
-            for (int u = 0; u < Src::kAhead; ++u) {
+            for (int u = 0; u < AHEAD; ++u) {
                 const int col0 = base + u * kChunk + lane * 8;
                 kv[u] = make_uint4(0u, 0u, 0u, 0u);
                 if (col0 < shi) kv[u] = src.chunk(row, col0);
             }
 #pragma unroll
-            for (int u = 0; u < Src::kAhead; ++u) {
+            for (int u = 0; u < AHEAD; ++u) {
                 const int col0 = base + u * kChunk + lane * 8;
                 uint4 tv = make_uint4(0u, 0u, 0u, 0u);
                 if (col0 < shi) tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
+                if (mn && col0 < shi)
+                    *mn = min(*mn, min_sum_masked(kv[u], tv, range_mask(col0, slo, shi)));
                 const int a = chunk_hit(col0, kv[u], tv, need, slo, shi);
                 if (a >= 0) return hit_at(a, origin, n);
             }
-            base += Src::kAhead * kChunk;
+            base += AHEAD * kChunk;
         }
         base = -1;
     }
@@ -327,7 +337,7 @@ constexpr int kNoHit = 0x7FFFFFFF;
 template <class Src>
 __device__ int team_scan(const Src &src, const typename Src::Row &row, const uint16_t *t_lds,
                          int n, int origin, const Segs &S, int need, int k, int R, int lane,
-                         const int *best)
+                         const int *best, int *mn)
 {
     const int b0 = S.lo0 & ~7, b1 = S.lo1 & ~7;
     const int nc0 = S.lo0 < S.hi0 ? (S.hi0 - b0 + kChunk - 1) / kChunk : 0;
@@ -356,6 +366,7 @@ __device__ int team_scan(const Src &src, const typename Src::Row &row, const uin
             const int col0 = (s1 ? b1 + (cc - nc0) * kChunk : b0 + cc * kChunk) + lane * 8;
             uint4 tv = make_uint4(0u, 0u, 0u, 0u);
             if (col0 < hi) tv = *reinterpret_cast<const uint4 *>(t_lds + col0);
+            if (mn && col0 < hi) *mn = min(*mn, min_sum_masked(kv[u], tv, range_mask(col0, lo, hi)));
             const int a = chunk_hit(col0, kv[u], tv, need, lo, hi);
             if (a >= 0) return hit_at(a, origin, n).j;
         }
@@ -398,6 +409,7 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
         const int i = base + threadIdx.x;
         bool is_free = false;
         if (i < n) {
+            if (a.skip) a.skip[i] = 0u;
             if (!warm) {
                 a.key[i] = 0ull;
                 a.t[i] = 0;
@@ -459,11 +471,13 @@ struct SrcOf<0> {
 };
 
 // kSrcD: 0 reads the rounded-cost matrix; 2 or 3 computes it from points of
-// that dimension (matrix-free).
-template <bool kMulti, int kSrcD>
+// that dimension (matrix-free). kFF: exact fast-forward through A.skip.
+template <bool kMulti, int kSrcD, bool kFF>
 __global__ void __launch_bounds__(kLoopThreads)
 phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32_t *y_base)
 {
+    // the fast-forward's slack tracking costs registers: shallower prefetch
+    constexpr int kScanAhead = kFF ? 4 : SrcOf<kSrcD>::type::kAhead;
     // the instance's arguments stay where they are (kernel arguments, or the
     // array in global memory), read through the scalar cache when needed
     const LoopArgs &A = kMulti ? arr[blockIdx.x / team] : A0;
@@ -482,6 +496,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         s_lnew[kMaxGroups], s_lpre[kMaxGroups], s_fpre[kMaxGroups];
     // team mode: best hit position of each team's row, by round parity
     __shared__ int s_best[2][kLoopThreads / kWave];
+    __shared__ int s_mn[kLoopThreads / kWave];  // team mode: smallest k + t of a row's scan
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wpg = blockDim.x / kWave;
@@ -555,17 +570,23 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                                        : (team_id < n_i ? 1u : 0u);
         if (threadIdx.x < 2 * (kLoopThreads / kWave))
             (&s_best[0][0])[threadIdx.x] = kNoHit;
+        if (threadIdx.x < kLoopThreads / kWave) s_mn[threadIdx.x] = kNoHit;
         __syncthreads();
         int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0;
+        uint32_t s_skip = 0;
         unsigned long long s_key = 0;
         if ((uint32_t)lane < nslots) {
             const uint32_t e = R == 1 ? gw + (uint32_t)lane * W : team_id;
             const int j = group_of(s_fpre, G, e);
             s_b = take_entry(Fc + j * cap + (e - s_fpre[j]), tag0 + (uint32_t)p, n, &ctl->err);
             s_yb = ld_agent(y_b + s_b);
+            if (kFF && A.skip) s_skip = ld_agent(A.skip + s_b);
         }
-        unsigned long long active = __ballot((uint32_t)lane < nslots);
+        // rows that cannot find a column this phase are exhausted without a scan
+        const unsigned long long pre = __ballot((uint32_t)lane < nslots && s_skip > 0u);
+        unsigned long long active = __ballot((uint32_t)lane < nslots) & ~pre;
         unsigned long long wave_scan = 0;
+        bool first_round = true;
 
         for (;;) {
             r += 1;
@@ -592,15 +613,36 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             bool proposed = false;
             int32_t my_f = -1;             // row this lane's slot puts on the next B'
             uint32_t n_prop = 0;
+            // fast-forward: a full first-round scan that finds nothing records
+            // the row's smallest slack
+            const bool track = kFF && A.skip != nullptr && first_round;
+            if (first_round && pre) {
+                // exhausted as its scan from position 0 would be (extent n), (III b)
+                const bool lead = R == 1 || k_rank == 0;
+                if (lead) {
+                    if ((pre >> lane) & 1ull) {
+                        st_agent(y_b + s_b, s_yb + 1);
+                        st_agent(A.skip + s_b, s_skip - 1u);
+                        my_f = s_b;
+                    }
+                    wave_scan += (unsigned long long)n * (unsigned long long)__popcll(pre);
+                }
+            }
+            first_round = false;
             if (R > 1) {
                 // team mode: every wave of the team scans its share of the row;
                 // the team's first hit is the smallest position found
                 int* best = &s_best[r & 1][team_local];
                 if (active & 1ull) {
                     const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, n);
+                    int mn = kNoHit;
                     const int j = team_scan(src, src.row(v.b), t_lds, n, v.origin, v.S,
-                                            v.yb - 1, k_rank, R, lane, best);
+                                            v.yb - 1, k_rank, R, lane, best, track ? &mn : nullptr);
                     if (lane == 0 && j != kNoHit) atomicMin(best, j);
+                    if (track) {
+                        mn = wave_min(mn);
+                        if (lane == 0) atomicMin(&s_mn[team_local], mn);
+                    }
                 }
                 __syncthreads();
                 if (active & 1ull) {
@@ -633,6 +675,11 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                             if (lane == 0) {
                                 st_agent(y_b + b, yb + 1);
                                 my_f = b;
+                                if (track) {
+                                    const int slack = s_mn[team_local] - (yb - 1);
+                                    if (slack >= 2)
+                                        st_agent(A.skip + b, (uint32_t)min(slack - 1, 1 << 30));
+                                }
                             }
                         }
                         active = 0ull;
@@ -671,11 +718,14 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     const uint4 tv = col0 < shi ? *reinterpret_cast<const uint4 *>(t_lds + col0)
                                                 : make_uint4(0u, 0u, 0u, 0u);
                     Hit h{-1, -1};
+                    int mn = kNoHit;
+                    if (track && col0 < shi)
+                        mn = min_sum_masked(kvq[q], tv, range_mask(col0, slo, shi));
                     const int a = chunk_hit(col0, kvq[q], tv, yb - 1, slo, shi);
                     if (a >= 0) h = hit_at(a, v.origin, n);
                     else if (slo < shi)
-                        h = scan_from(src, src.row(b), t_lds, n, v.origin, v.S, v.sg,
-                                      v.base + kChunk, yb - 1, lane);
+                        h = scan_from<kScanAhead>(src, src.row(b), t_lds, n, v.origin, v.S, v.sg,
+                                      v.base + kChunk, yb - 1, lane, track ? &mn : nullptr);
                     if (h.j >= 0) {
                         wave_scan += (unsigned long long)(h.j - pos + 1);
                         const unsigned long long kn =
@@ -694,9 +744,11 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     } else {
                         // b has no admissible untaken column: free in M', (III b).
                         wave_scan += (unsigned long long)(n - pos);
+                        const int slack = track ? wave_min(mn) - (yb - 1) : 0;
                         if (lane == s) {
                             st_agent(y_b + b, yb + 1);
                             my_f = b;
+                            if (slack >= 2) st_agent(A.skip + b, (uint32_t)min(slack - 1, 1 << 30));
                         }
                         active &= ~(1ull << s);
                     }
@@ -1011,6 +1063,7 @@ __global__ void team_init_kernel(TeamArgs T)
             a.t[i] = 0;
             y_b[i] = 1;
             a.F[0][i] = tagged(tag0, i);
+            if (a.skip) a.skip[i] = 0u;
         } else {
             a.t[i] = 0;
         }
@@ -1162,12 +1215,12 @@ hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max)
     const size_t lds = (size_t)n_pad * sizeof(uint16_t);
     hipError_t e = hipSuccess;
     if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)phase_loop_kernel<false, 0>,
+        e = hipFuncSetAttribute((const void *)phase_loop_kernel<false, 0, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<false, 0>,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<false, 0, false>,
                                                      kLoopThreads, lds);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0;
@@ -1190,9 +1243,9 @@ hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
     int32_t *no_base = nullptr;
     void *args[] = {&copy, &none, &team, &no_base};
     const size_t lds = (size_t)a.n_pad * sizeof(uint16_t);
-    const void *fn = a.pd == 2   ? (const void *)phase_loop_kernel<false, 2>
-                     : a.pd == 3 ? (const void *)phase_loop_kernel<false, 3>
-                                 : (const void *)phase_loop_kernel<false, 0>;
+    const void *fn = a.pd == 2   ? (const void *)phase_loop_kernel<false, 2, false>
+                     : a.pd == 3 ? (const void *)phase_loop_kernel<false, 3, false>
+                                 : (const void *)phase_loop_kernel<false, 0, false>;
     if (a.pd && lds > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);
@@ -1206,12 +1259,12 @@ hipError_t loop_grid_multi(int32_t n_pad_max, int wgs_per_cu, int *grid_max)
     const size_t lds = (size_t)n_pad_max * sizeof(uint16_t);
     hipError_t e = hipSuccess;
     if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void *)phase_loop_kernel<true, 0>,
+        e = hipFuncSetAttribute((const void *)phase_loop_kernel<true, 0, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     int per_cu = 0, dev = 0, cus = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<true, 0>,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, phase_loop_kernel<true, 0, true>,
                                                      kLoopThreads, lds);
     if (e != hipSuccess) return e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
@@ -1236,7 +1289,7 @@ hipError_t launch_loop_multi(const LoopArgs *arr, int count, int team, int32_t n
     LoopArgs none{};
     void *args[] = {&none, &arr, &team, &y_base};
     const size_t lds = (size_t)n_pad_max * sizeof(uint16_t);
-    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel<true, 0>,
+    return hipLaunchCooperativeKernel((const void *)phase_loop_kernel<true, 0, true>,
                                       dim3((unsigned)(count * team)), dim3(kLoopThreads), args,
                                       (unsigned)lds, s);
 }
