@@ -63,10 +63,13 @@ def _load():
     lib.orc_points_cost_f64.argtypes = [p, p, i64, i64, i32, f64, p, p, p]
     lib.orc_solve_rounded.argtypes = [p, i64, i64, i64, i32, i64, i32, i32,
                                       p, p, p, p, p, p, i64]
+    lib.orc_solve_rounded_rect.argtypes = [p, i64, i64, i64, i64, i32, i64, i32, i32,
+                                           p, p, p, p, p, p, i64]
     lib.orc_points_max_f32.argtypes = [p, p, i64, i64, i32, p]
     lib.orc_points_pairs_f32.argtypes = [p, p, i32, f64, ctypes.c_float, p, p, i64, p]
     for fn in (lib.orc_round_cost, lib.orc_round_points_f32,
-               lib.orc_points_cost_f64, lib.orc_solve_rounded, lib.orc_points_max_f32,
+               lib.orc_points_cost_f64, lib.orc_solve_rounded, lib.orc_solve_rounded_rect,
+               lib.orc_points_max_f32,
                lib.orc_points_pairs_f32):
         fn.restype = ctypes.c_int
     _lib = lib
@@ -161,20 +164,21 @@ def solve_rounded(k: np.ndarray, T: int, origin: str = "diag",
                   max_phases: int = 0, state: dict | None = None,
                   complete: bool = True, trace: bool = False,
                   trace_cap: int = 1 << 20) -> dict:
-    """Run the phase loop of Section 2.2 on rounded costs k (rows B).
+    """Run the phase loop of Section 2.2 on rounded costs k (rows B, columns
+    A, |B| <= |A|: the unbalanced case of Section 3.3 when k is not square).
 
     state, if given, is a dict with int32 arrays mate_a, mate_b, y_a, y_b to
     resume from (copied, not modified). Returns a dict with the final arrays,
     the status ('ok' or 'partial'), the stats and, if asked, the per-phase
     trace as an (phases, 4) array of (|B'|, rounds, scanned, |M'|)."""
     k = np.ascontiguousarray(k, dtype=np.int16)
-    n = k.shape[0]
-    assert k.shape == (n, n)
+    n_b, n_a = k.shape
+    assert n_b <= n_a, "the unbalanced case needs |B| <= |A| (transpose k)"
     if state is None:
-        mate_a = np.full(n, -1, np.int32)
-        mate_b = np.full(n, -1, np.int32)
-        y_a = np.zeros(n, np.int32)
-        y_b = np.ones(n, np.int32)
+        mate_a = np.full(n_a, -1, np.int32)
+        mate_b = np.full(n_b, -1, np.int32)
+        y_a = np.zeros(n_a, np.int32)
+        y_b = np.ones(n_b, np.int32)
         warm = 0
     else:
         mate_a = np.array(state["mate_a"], dtype=np.int32, copy=True)
@@ -184,8 +188,8 @@ def solve_rounded(k: np.ndarray, T: int, origin: str = "diag",
         warm = 1
     st = _Stats()
     tr = np.zeros((trace_cap, 4), np.int64) if trace else None
-    rc = _check(_load().orc_solve_rounded(
-        _ptr(k), n, n, int(T), ORIGIN[origin], int(max_phases), warm,
+    rc = _check(_load().orc_solve_rounded_rect(
+        _ptr(k), n_b, n_a, n_a, int(T), ORIGIN[origin], int(max_phases), warm,
         1 if complete else 0, _ptr(mate_a), _ptr(mate_b), _ptr(y_a), _ptr(y_b),
         ctypes.byref(st), _ptr(tr) if tr is not None else None,
         trace_cap if tr is not None else 0), "solve_rounded")

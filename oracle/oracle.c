@@ -179,14 +179,14 @@ static int admissible(const int16_t *k, int64_t ldk, const int32_t *y_a,
     return (int64_t)k[b * ldk + a] + 1 == (int64_t)y_a[a] + (int64_t)y_b[b];
 }
 
-int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
-                      int32_t origin_mode, int64_t max_phases, int32_t warm,
-                      int32_t complete, int32_t *mate_a, int32_t *mate_b,
-                      int32_t *y_a, int32_t *y_b, orc_stats *st,
-                      int64_t *trace, int64_t trace_cap)
+int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t ldk,
+                           int64_t T, int32_t origin_mode, int64_t max_phases, int32_t warm,
+                           int32_t complete, int32_t *mate_a, int32_t *mate_b,
+                           int32_t *y_a, int32_t *y_b, orc_stats *st,
+                           int64_t *trace, int64_t trace_cap)
 {
-    if (n < 0 || (n > 0 && (!k || ldk < n)) || !mate_a || !mate_b || !y_a ||
-        !y_b || !st)
+    if (n_b < 0 || n_a < n_b || (n_b > 0 && (!k || ldk < n_a)) || !mate_a || !mate_b ||
+        !y_a || !y_b || !st)
         return ORC_E_ARG;
     if (origin_mode != ORC_ORIGIN_DIAG && origin_mode != ORC_ORIGIN_ZERO)
         return ORC_E_ARG;
@@ -194,15 +194,17 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
 
     /* Initialisation: y(b) = eps, y(a) = 0, M empty. */
     if (!warm) {
-        for (int64_t v = 0; v < n; ++v) {
-            y_b[v] = 1;
-            y_a[v] = 0;
-            mate_a[v] = -1;
-            mate_b[v] = -1;
+        for (int64_t b = 0; b < n_b; ++b) {
+            y_b[b] = 1;
+            mate_b[b] = -1;
+        }
+        for (int64_t a = 0; a < n_a; ++a) {
+            y_a[a] = 0;
+            mate_a[a] = -1;
         }
     }
 
-    size_t sz = (size_t)(n > 0 ? n : 1);
+    size_t sz = (size_t)(n_a > 0 ? n_a : 1);  /* n_b <= n_a */
     int64_t *B_prime = (int64_t *)malloc(sizeof(int64_t) * sz);
     int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * sz);
     int64_t *target = (int64_t *)malloc(sizeof(int64_t) * sz);
@@ -221,10 +223,10 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
     for (;;) {
         /* B' = the free vertices of B, in ascending order. */
         int64_t n_i = 0;
-        for (int64_t b = 0; b < n; ++b)
+        for (int64_t b = 0; b < n_b; ++b)
             if (mate_b[b] < 0) B_prime[n_i++] = b;
 
-        /* Stop once |B'| <= eps n (integer threshold T). */
+        /* Stop once |B'| <= eps |B| (integer threshold T). */
         if (n_i <= T) break;
         if (max_phases > 0 && st->phases == max_phases) {
             status = ORC_PARTIAL;
@@ -242,7 +244,7 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
          * column proposed to goes to its lowest-index proposer; losers go on
          * scanning after the column they lost. A b that finds nothing stays
          * free in M'. */
-        for (int64_t a = 0; a < n; ++a) taken_by[a] = -1;
+        for (int64_t a = 0; a < n_a; ++a) taken_by[a] = -1;
         for (int64_t i = 0; i < n_i; ++i) {
             pos[i] = 0;
             active[i] = 1;
@@ -256,15 +258,15 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
                 int64_t b = B_prime[i];
                 target[i] = -1;
                 int64_t j;
-                for (j = pos[i]; j < n; ++j) {
-                    int64_t a = scan_col(origin_mode, b, j, n);
+                for (j = pos[i]; j < n_a; ++j) {
+                    int64_t a = scan_col(origin_mode, b, j, n_a);
                     if (taken_by[a] < 0 && admissible(k, ldk, y_a, y_b, a, b)) {
                         target[i] = a;
                         break;
                     }
                 }
                 if (target[i] < 0) {
-                    phase_scanned += n - pos[i];
+                    phase_scanned += n_a - pos[i];
                     active[i] = 0; /* no admissible free column is left */
                 } else {
                     phase_scanned += j - pos[i] + 1;
@@ -299,7 +301,7 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
 
         /* Step (II): add M' to M and delete the M-edges of the columns that
          * M' re-matches (the set A'' and its edges M''). */
-        for (int64_t a = 0; a < n; ++a) {
+        for (int64_t a = 0; a < n_a; ++a) {
             int64_t b = taken_by[a];
             if (b < 0) continue;
             if (mate_a[a] >= 0) mate_b[mate_a[a]] = -1;
@@ -307,7 +309,7 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
             mate_b[b] = (int32_t)a;
         }
         /* Step (III a): y(a) -= eps for every edge (a, b) of M'. */
-        for (int64_t a = 0; a < n; ++a)
+        for (int64_t a = 0; a < n_a; ++a)
             if (taken_by[a] >= 0) y_a[a] -= 1;
         /* Step (III b): y(b) += eps for every b of B' left free by M'. */
         for (int64_t i = 0; i < n_i; ++i)
@@ -326,7 +328,7 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
     }
 
     int64_t matched = 0;
-    for (int64_t b = 0; b < n; ++b)
+    for (int64_t b = 0; b < n_b; ++b)
         if (mate_b[b] >= 0) matched += 1;
     st->matched_in_phases = matched;
 
@@ -335,10 +337,10 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
      * i-th free a (ascending). */
     if (complete && status == ORC_OK) {
         int64_t ia = 0;
-        for (int64_t b = 0; b < n; ++b) {
+        for (int64_t b = 0; b < n_b; ++b) {
             if (mate_b[b] >= 0) continue;
-            while (ia < n && mate_a[ia] >= 0) ++ia;
-            if (ia >= n) break;
+            while (ia < n_a && mate_a[ia] >= 0) ++ia;
+            if (ia >= n_a) break;
             mate_b[b] = (int32_t)ia;
             mate_a[ia] = (int32_t)b;
             st->completed_pairs += 1;
@@ -346,11 +348,21 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
     }
 
     int64_t sum_k = 0;
-    for (int64_t b = 0; b < n; ++b)
+    for (int64_t b = 0; b < n_b; ++b)
         if (mate_b[b] >= 0) sum_k += k[b * ldk + mate_b[b]];
     st->sum_k = sum_k;
 
     free(B_prime); free(pos); free(target); free(active); free(won);
     free(taken_by); free(proposer);
     return status;
+}
+
+int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
+                      int32_t origin_mode, int64_t max_phases, int32_t warm,
+                      int32_t complete, int32_t *mate_a, int32_t *mate_b,
+                      int32_t *y_a, int32_t *y_b, orc_stats *st,
+                      int64_t *trace, int64_t trace_cap)
+{
+    return orc_solve_rounded_rect(k, n, n, ldk, T, origin_mode, max_phases, warm, complete,
+                                  mate_a, mate_b, y_a, y_b, st, trace, trace_cap);
 }

@@ -83,6 +83,17 @@ int orc_points_cost_f64(const float *X, const float *Y, int64_t n_b,
  *   y_a, y_b    : dual weights in units of eps
  *   trace       : optional, 4 int64 per phase (|B'|, rounds, scanned, |M'|)
  * Returns ORC_OK, ORC_PARTIAL (max_phases reached) or an error. */
+/* The unbalanced case (Section 3.3): |B| = n_b rows <= |A| = n_a columns,
+ * k is n_b x ldk (ldk >= n_a), y_b/mate_b have n_b entries, y_a/mate_a n_a.
+ * The loop is unchanged; it stops at |B'| <= T with T = floor(eps n_b), and
+ * the completion pairs the i-th free b with the i-th free a. DIAG starts row
+ * b at column b (b < n_b <= n_a). */
+int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t ldk,
+                           int64_t T, int32_t origin_mode, int64_t max_phases, int32_t warm,
+                           int32_t complete, int32_t *mate_a, int32_t *mate_b,
+                           int32_t *y_a, int32_t *y_b, orc_stats *st,
+                           int64_t *trace, int64_t trace_cap);
+
 int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
                       int32_t origin_mode, int64_t max_phases, int32_t warm,
                       int32_t complete, int32_t *mate_a, int32_t *mate_b,

@@ -99,10 +99,12 @@ def check_phase(k, before, after):
     return len(F)
 
 
-def safe_phase_bounds(n, K, T):
+def safe_phase_bounds(n, K, T, n_a=None):
     """Bounds on sum |B'| and on the phase count from Lemma 3.2 applied to all
-    2n vertices: Phi <= 2n(K+2), Phi starts at n, each phase adds n_i > T."""
-    sum_free = 2 * n * (K + 2) - n
+    n_b + n_a vertices: Phi <= (n_b + n_a)(K+2), Phi starts at n_b, each phase
+    adds n_i > T. (n_b = n; n_a = n unless given.)"""
+    n_a = n if n_a is None else n_a
+    sum_free = (n + n_a) * (K + 2) - n
     return sum_free, sum_free // (T + 1)
 
 

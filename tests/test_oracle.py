@@ -387,3 +387,89 @@ def test_points_max_and_pairs_equal_full_matrix():
     X = np.full((5, 2), 0.5, np.float32)
     assert oracle.points_max_f32(X, X) == 0.0
     assert (oracle.points_pairs_f32(X, X, 0.1, 0.0, [0, 4], [3, 1]) == 0).all()
+
+
+# ---------------------------------------------------------------- unbalanced
+
+def _rect_case(n_b, n_a, K, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, K + 1, (n_b, n_a)).astype(np.int16)
+
+
+@pytest.mark.parametrize("origin", ["diag", "zero"])
+@pytest.mark.parametrize("n_b,n_a,K,T", [(5, 9, 6, 0), (20, 31, 8, 1), (40, 41, 10, 2),
+                                         (1, 7, 5, 0), (33, 100, 12, 3)])
+def test_unbalanced_phase_invariants(n_b, n_a, K, T, origin):
+    """|B| < |A| (Section 3.3): every phase keeps (I1), (I2), Lemma 2.1,
+    a maximal admissible M', the step (III) updates and Lemma 3.3 exactly; the
+    loop ends with |B'| <= T, within the phase bound of Lemma 3.2 over all
+    n_b + n_a vertices."""
+    k = _rect_case(n_b, n_a, K, seed=n_b * 7 + n_a)
+    state = None
+    phases = sum_free = 0
+    while True:
+        r = oracle.solve_rounded(k, T, origin=origin, max_phases=1, state=state, complete=False)
+        before = state if state is not None else dict(
+            mate_a=np.full(n_a, -1), mate_b=np.full(n_b, -1), y_a=np.zeros(n_a, np.int64),
+            y_b=np.ones(n_b, np.int64))
+        if r["stats"]["phases"] == 0:
+            break
+        check_matching(r["mate_a"], r["mate_b"])
+        check_I1(r["mate_a"], r["y_a"], r["y_b"])
+        check_I2(k, r["mate_b"], r["y_a"], r["y_b"])
+        sum_free += check_phase(k, before, r)
+        phases += 1
+        state = r
+    final = state if state is not None else oracle.solve_rounded(k, T, origin=origin, complete=False)
+    assert (np.asarray(final["mate_b"]) < 0).sum() <= T
+    full = oracle.solve_rounded(k, T, origin=origin, complete=False)
+    assert full["stats"]["phases"] == phases and full["stats"]["sum_free"] == sum_free
+    for key in ("mate_a", "mate_b", "y_a", "y_b"):
+        assert np.array_equal(full[key], final[key])
+    bound_free, bound_phases = safe_phase_bounds(n_b, K, T, n_a)
+    assert sum_free <= bound_free and phases <= bound_phases
+
+
+@pytest.mark.parametrize("n_b,n_a,eps", [(30, 45, 0.1), (60, 61, 0.05), (25, 200, 0.02),
+                                         (100, 150, 0.05)])
+def test_unbalanced_lemma_3_5_and_total_error(n_b, n_a, eps):
+    """Lemma 3.5: the loop's matching (size >= (1 - eps)|B|) costs at most
+    eps |B| more than an optimal |B|-matching under the rounded costs, i.e.
+    sum_M k <= OPT_k + |B|; after the completion the true cost is within
+    3 eps |B| of the optimal |B|-matching."""
+    rng = np.random.default_rng(n_b + n_a)
+    C = rng.random((n_b, n_a), dtype=np.float32)
+    C[0, 0] = 1.0
+    k = oracle.round_cost(C, eps)
+    T = oracle.threshold(eps, n_b)
+    r = oracle.solve_rounded(k, T, complete=False)
+    mb = np.asarray(r["mate_b"])
+    matched = np.nonzero(mb >= 0)[0]
+    assert len(matched) >= n_b - T
+    rows, cols = linear_sum_assignment(k.astype(np.int64))
+    opt_k = int(k.astype(np.int64)[rows, cols].sum())
+    assert int(k.astype(np.int64)[matched, mb[matched]].sum()) <= opt_k + n_b
+    done = oracle.solve_rounded(k, T)
+    mb = np.asarray(done["mate_b"])
+    assert (mb >= 0).all()
+    check_matching(done["mate_a"], mb)
+    c64 = C.astype(np.float64)
+    rows, cols = linear_sum_assignment(c64)
+    opt = c64[rows, cols].sum()
+    assert c64[np.arange(n_b), mb].sum() <= opt + 3 * eps * n_b + 1e-9
+
+
+def test_unbalanced_closed_forms():
+    """One row: its dual rises one step per phase until its smallest cost is
+    admissible, so there are min k + 1 phases and it takes the first column
+    of smallest cost in its scan order; T >= |B| runs no phase and the
+    completion pairs rows with the lowest free columns."""
+    k = np.array([[5, 3, 7, 3, 9]], np.int16)
+    for origin, want in (("diag", 1), ("zero", 1)):
+        r = oracle.solve_rounded(k, 0, origin=origin)
+        assert r["stats"]["phases"] == 4 and r["mate_b"][0] == want
+        assert r["y_b"][0] == 4 and r["y_a"][want] == -1
+    k = _rect_case(4, 6, 3, seed=1)
+    r = oracle.solve_rounded(k, 4)
+    assert r["stats"]["phases"] == 0
+    assert list(r["mate_b"]) == [0, 1, 2, 3] and list(r["mate_a"]) == [0, 1, 2, 3, -1, -1]
