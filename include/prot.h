@@ -171,6 +171,35 @@ int prot_solve_points(prot_ctx *ctx, const float *X, const float *Y,
                       int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
                       int32_t *y_b, prot_stats *stats);
 
+/* The unbalanced case (Section 3.3, Lemma 3.5): |B| = n_b rows (supply)
+ * and |A| = n_a >= n_b columns (demand). The algorithm is unchanged; the
+ * loop stops when |B'| <= T = floor(eps_internal n_b), giving a matching of at
+ * least (1 - eps)|B| rows whose rounded cost is within eps |B| of an optimal
+ * |B|-matching; the completion then gives every row a column (the i-th free
+ * b takes the i-th free a). Layouts as for the square calls, with n_b rows of
+ * n_a columns: k and C are n_b x ld (ld >= n_a), X is n_b x d, Y is n_a x d;
+ * mate_b and y_b have n_b entries, mate_a and y_a n_a (mate_a = -1 for the
+ * n_a - n_b columns left unmatched). n_a < n_b returns PROT_E_ARG (transpose
+ * the input). n_b = 0 with n_a > 0 writes the cold-start column state
+ * (mate_a = -1, y_a = 0; untouched when warm). The square calls are these
+ * with n_b = n_a = n. */
+int prot_round_costs_rect(prot_ctx *ctx, const float *C, int64_t n_b, int64_t n_a,
+                          int64_t ldc, double eps, int16_t *k, int64_t ldk);
+int prot_build_costs_rect(prot_ctx *ctx, const float *X, int64_t n_b, const float *Y,
+                          int64_t n_a, int32_t d, double eps, int16_t *k, int64_t ldk,
+                          float *m_out);
+int prot_solve_rounded_rect(prot_ctx *ctx, const int16_t *k, int64_t n_b, int64_t n_a,
+                            int64_t ldk, int64_t T, const prot_opts *opts, int32_t warm,
+                            int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
+                            int32_t *y_b, prot_stats *stats);
+int prot_solve_cost_rect(prot_ctx *ctx, const float *C, int64_t n_b, int64_t n_a,
+                         int64_t ldc, double eps, const prot_opts *opts, int32_t *mate_a,
+                         int32_t *mate_b, int32_t *y_a, int32_t *y_b, prot_stats *stats);
+int prot_solve_points_rect(prot_ctx *ctx, const float *X, int64_t n_b, const float *Y,
+                           int64_t n_a, int32_t d, double eps, const prot_opts *opts,
+                           int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
+                           int32_t *y_b, prot_stats *stats);
+
 /* ---- Batches of independent instances (minibatch optimal transport) ---- */
 
 /* Per-instance results of a batched solve. */

@@ -73,7 +73,9 @@ EXPORTS = [
     "prot_ctx_create", "prot_ctx_destroy", "prot_set_stream", "prot_set_cost_path",
     "prot_reserve", "prot_pitch",
     "prot_threshold", "prot_max_n", "prot_round_costs", "prot_build_costs",
-    "prot_solve_rounded", "prot_solve_cost", "prot_solve_points", "prot_get_trace",
+    "prot_solve_rounded", "prot_solve_cost", "prot_solve_points",
+    "prot_round_costs_rect", "prot_build_costs_rect", "prot_solve_rounded_rect",
+    "prot_solve_cost_rect", "prot_solve_points_rect", "prot_get_trace",
     "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
     "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
     "prot_batch_loss_fwd", "prot_batch_loss_bwd",
@@ -109,6 +111,16 @@ def load():
                                            p, p, p, p, ctypes.POINTER(Stats)]),
         "prot_solve_points": (ctypes.c_int, [p, p, p, i64, i32, f64, ctypes.POINTER(Opts),
                                              p, p, p, p, ctypes.POINTER(Stats)]),
+        "prot_round_costs_rect": (ctypes.c_int, [p, p, i64, i64, i64, f64, p, i64]),
+        "prot_build_costs_rect": (ctypes.c_int, [p, p, i64, p, i64, i32, f64, p, i64, p]),
+        "prot_solve_rounded_rect": (ctypes.c_int, [p, p, i64, i64, i64, i64,
+                                                   ctypes.POINTER(Opts), i32, p, p, p, p,
+                                                   ctypes.POINTER(Stats)]),
+        "prot_solve_cost_rect": (ctypes.c_int, [p, p, i64, i64, i64, f64, ctypes.POINTER(Opts),
+                                                p, p, p, p, ctypes.POINTER(Stats)]),
+        "prot_solve_points_rect": (ctypes.c_int, [p, p, i64, p, i64, i32, f64,
+                                                  ctypes.POINTER(Opts), p, p, p, p,
+                                                  ctypes.POINTER(Stats)]),
         "prot_get_trace": (i64, [p, p, i64]),
         "prot_get_round_times": (i64, [p, p, i64]),
         "prot_batch_max_n": (i32, []),
@@ -219,10 +231,12 @@ class Context:
         o.max_phases = int(max_phases)
         return o
 
-    def _outputs(self, n):
+    def _outputs(self, n, n_a=None):
+        """mate_a, mate_b, y_a, y_b for n rows and n_a (default n) columns."""
         torch = _torch()
+        n_a = n if n_a is None else n_a
         kw = dict(dtype=torch.int32, device=f"cuda:{self.device}")
-        return (torch.empty(n, **kw), torch.empty(n, **kw), torch.empty(n, **kw),
+        return (torch.empty(n_a, **kw), torch.empty(n, **kw), torch.empty(n_a, **kw),
                 torch.empty(n, **kw))
 
     # -- API
@@ -232,20 +246,22 @@ class Context:
     def max_n(self) -> int:
         return int(self._lib.prot_max_n(self._h))
 
-    def alloc_k(self, n: int):
+    def alloc_k(self, n: int, n_a: int | None = None):
         torch = _torch()
-        return torch.empty((n, pitch(n)), dtype=torch.int16, device=f"cuda:{self.device}")
+        n_a = n if n_a is None else n_a
+        return torch.empty((n, pitch(n_a)), dtype=torch.int16, device=f"cuda:{self.device}")
 
     def round_costs(self, C, eps: float, k=None):
+        """C: n_b x n_a row-major float32 (n_b rows of supply)."""
         torch = _torch()
-        n = C.shape[0]
-        if C.dim() != 2 or C.shape[1] < n or C.stride(1) != 1:
-            raise ValueError("C must be an n x n (row-major) float32 matrix")
+        if C.dim() != 2 or C.stride(1) != 1:
+            raise ValueError("C must be a row-major n_b x n_a float32 matrix")
+        n_b, n_a = C.shape
         if k is None:
-            k = self.alloc_k(n)
+            k = self.alloc_k(n_b, n_a)
         self._bind_stream()
-        self._check(self._lib.prot_round_costs(
-            self._h, _dev_ptr(C, torch.float32, "C", 2), n, C.stride(0), float(eps),
+        self._check(self._lib.prot_round_costs_rect(
+            self._h, _dev_ptr(C, torch.float32, "C", 2), n_b, n_a, C.stride(0), float(eps),
             _dev_ptr(k, torch.int16, "k", 2), k.stride(0)))
         return k
 
@@ -257,28 +273,33 @@ class Context:
         self._check(self._lib.prot_set_cost_path(self._h, self.COST_PATHS[path]))
 
     def build_costs(self, X, Y, eps: float, k=None):
+        """X: n_b x d rows, Y: n_a x d columns (contiguous float32)."""
         torch = _torch()
-        n, d = X.shape
-        if Y.shape != (n, d) or not X.is_contiguous() or not Y.is_contiguous():
-            raise ValueError("X and Y must be contiguous n x d float32")
+        n_b, d = X.shape
+        n_a = Y.shape[0]
+        if Y.shape != (n_a, d) or not X.is_contiguous() or not Y.is_contiguous():
+            raise ValueError("X and Y must be contiguous n_b x d and n_a x d float32")
         if k is None:
-            k = self.alloc_k(n)
+            k = self.alloc_k(n_b, n_a)
         m = torch.empty(1, dtype=torch.float32, device=f"cuda:{self.device}")
         self._bind_stream()
-        self._check(self._lib.prot_build_costs(
-            self._h, _dev_ptr(X, torch.float32, "X", 2), _dev_ptr(Y, torch.float32, "Y", 2),
-            n, d, float(eps), _dev_ptr(k, torch.int16, "k", 2), k.stride(0),
+        self._check(self._lib.prot_build_costs_rect(
+            self._h, _dev_ptr(X, torch.float32, "X", 2), n_b, _dev_ptr(Y, torch.float32, "Y", 2),
+            n_a, d, float(eps), _dev_ptr(k, torch.int16, "k", 2), k.stride(0),
             _dev_ptr(m, torch.float32, "m")))
         return k, m
 
-    def solve_rounded(self, k, T: int, n: int | None = None, *, state=None, origin="diag",
-                      complete=True, max_phases=0) -> Result:
+    def solve_rounded(self, k, T: int, n: int | None = None, *, n_a: int | None = None,
+                      state=None, origin="diag", complete=True, max_phases=0) -> Result:
+        """k: n rows x ldk (ldk >= n_a) int16; n_a columns, default n (the
+        unbalanced case of Section 3.3 when n_a > n)."""
         torch = _torch()
         n = k.shape[0] if n is None else int(n)
-        if k.dim() != 2 or k.stride(1) != 1 or k.shape[1] < n:
-            raise ValueError("k must be a row-major n x ldk int16 matrix")
+        n_a = n if n_a is None else int(n_a)
+        if k.dim() != 2 or k.stride(1) != 1 or k.shape[1] < n_a or k.shape[0] < n:
+            raise ValueError("k must be a row-major n x ldk int16 matrix, ldk >= n_a")
         if state is None:
-            mate_a, mate_b, y_a, y_b = self._outputs(n)
+            mate_a, mate_b, y_a, y_b = self._outputs(n, n_a)
             warm = 0
         else:
             mate_a, mate_b, y_a, y_b = (state[x].clone() for x in ("mate_a", "mate_b", "y_a", "y_b"))
@@ -286,8 +307,8 @@ class Context:
         st = Stats()
         o = self._opts(origin=origin, complete=complete, max_phases=max_phases)
         self._bind_stream()
-        rc = self._check(self._lib.prot_solve_rounded(
-            self._h, _dev_ptr(k, torch.int16, "k", 2), n, k.stride(0), int(T), ctypes.byref(o),
+        rc = self._check(self._lib.prot_solve_rounded_rect(
+            self._h, _dev_ptr(k, torch.int16, "k", 2), n, n_a, k.stride(0), int(T), ctypes.byref(o),
             warm, _dev_ptr(mate_a, torch.int32, "mate_a"), _dev_ptr(mate_b, torch.int32, "mate_b"),
             _dev_ptr(y_a, torch.int32, "y_a"), _dev_ptr(y_b, torch.int32, "y_b"),
             ctypes.byref(st)))
@@ -295,16 +316,17 @@ class Context:
 
     def solve_cost(self, C, eps: float, *, eps_mode="algorithmic", origin="diag",
                    complete=True, max_phases=0) -> Result:
+        """C: n_b x n_a row-major float32 in [0, 1], n_b <= n_a."""
         torch = _torch()
-        n = C.shape[0]
-        if C.dim() != 2 or C.shape[1] < n or C.stride(1) != 1:
-            raise ValueError("C must be an n x n (row-major) float32 matrix")
-        mate_a, mate_b, y_a, y_b = self._outputs(n)
+        if C.dim() != 2 or C.stride(1) != 1:
+            raise ValueError("C must be a row-major n_b x n_a float32 matrix")
+        n, n_a = C.shape
+        mate_a, mate_b, y_a, y_b = self._outputs(n, n_a)
         st = Stats()
         o = self._opts(eps_mode, origin, complete, max_phases)
         self._bind_stream()
-        rc = self._check(self._lib.prot_solve_cost(
-            self._h, _dev_ptr(C, torch.float32, "C", 2), n, C.stride(0), float(eps),
+        rc = self._check(self._lib.prot_solve_cost_rect(
+            self._h, _dev_ptr(C, torch.float32, "C", 2), n, n_a, C.stride(0), float(eps),
             ctypes.byref(o), _dev_ptr(mate_a, torch.int32, "mate_a"),
             _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
             _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)))
@@ -317,15 +339,16 @@ class Context:
         the points); all give the same result."""
         torch = _torch()
         n, d = X.shape
-        if Y.shape != (n, d) or not X.is_contiguous() or not Y.is_contiguous():
-            raise ValueError("X and Y must be contiguous n x d float32")
-        mate_a, mate_b, y_a, y_b = self._outputs(n)
+        n_a = Y.shape[0]
+        if Y.shape != (n_a, d) or not X.is_contiguous() or not Y.is_contiguous():
+            raise ValueError("X and Y must be contiguous n_b x d and n_a x d float32")
+        mate_a, mate_b, y_a, y_b = self._outputs(n, n_a)
         st = Stats()
         o = self._opts(eps_mode, origin, complete, max_phases, storage)
         self._bind_stream()
-        rc = self._check(self._lib.prot_solve_points(
-            self._h, _dev_ptr(X, torch.float32, "X", 2), _dev_ptr(Y, torch.float32, "Y", 2),
-            n, d, float(eps), ctypes.byref(o), _dev_ptr(mate_a, torch.int32, "mate_a"),
+        rc = self._check(self._lib.prot_solve_points_rect(
+            self._h, _dev_ptr(X, torch.float32, "X", 2), n, _dev_ptr(Y, torch.float32, "Y", 2),
+            n_a, d, float(eps), ctypes.byref(o), _dev_ptr(mate_a, torch.int32, "mate_a"),
             _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
             _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)))
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())

@@ -135,9 +135,9 @@ int ensure_loop(prot_ctx *c, int64_t n)
     return PROT_OK;
 }
 
-int ensure_matrix(prot_ctx *c, int64_t n)
+int ensure_matrix(prot_ctx *c, int64_t n_b, int64_t n_a)
 {
-    const int64_t need = n * prot_pitch(n);
+    const int64_t need = n_b * prot_pitch(n_a);
     if (need <= c->cap_mat && c->kmat) return PROT_OK;
     int rc = dev_alloc(c, &c->kmat, (size_t)need);
     if (rc) return rc;
@@ -159,14 +159,15 @@ int ensure_thresholds(prot_ctx *c, double eps)
 // fits the 256 MiB Infinity Cache is built and scanned (its reads are cheaper
 // than recomputing); a larger one costs more to write than the recomputation
 // in the greedy step, so d = 2, 3 computes costs on the fly.
-bool auto_on_the_fly(int32_t d, int64_t n)
+bool auto_on_the_fly(int32_t d, int64_t n_b, int64_t n_a)
 {
-    return (d == 2 || d == 3) && 2 * n * prot_pitch(n) > ((int64_t)256 << 20);
+    return (d == 2 || d == 3) && 2 * n_b * prot_pitch(n_a) > ((int64_t)256 << 20);
 }
 
-int grid_for(prot_ctx *c, int64_t n, int *grid)
+// rows n (slots), columns n_a (LDS duals)
+int grid_for(prot_ctx *c, int64_t n, int64_t n_a, int *grid)
 {
-    const int n_pad = (int)round_up(n, 8);
+    const int n_pad = (int)round_up(n_a, 8);
     if (c->grid_npad != n_pad) {
         int lds_max = 0;
         HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
@@ -174,14 +175,14 @@ int grid_for(prot_ctx *c, int64_t n, int *grid)
         // the column duals live in LDS, 2 bytes per column (plus ~1 KB of state)
         if ((int64_t)n_pad * 2 + 2048 > lds_max)
             return fail(c, PROT_E_UNSUPPORTED,
-                        "n=%lld: the column duals (2 bytes each) exceed the %d bytes of LDS",
-                        (long long)n, lds_max);
+                        "%lld columns: the column duals (2 bytes each) exceed the %d bytes of LDS",
+                        (long long)n_a, lds_max);
         int gm = 0;
         hipError_t e = prot::loop_grid(n_pad, c->wgs_per_cu, &gm);
         if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
         if (gm <= 0)
-            return fail(c, PROT_E_UNSUPPORTED, "n=%lld: the column duals do not fit in LDS",
-                        (long long)n);
+            return fail(c, PROT_E_UNSUPPORTED, "%lld columns: the column duals do not fit in LDS",
+                        (long long)n_a);
         c->grid_npad = n_pad;
         c->grid_max = gm;
     }
@@ -203,7 +204,8 @@ int grid_for(prot_ctx *c, int64_t n, int *grid)
 int setup_mfma(prot_ctx *c, prot::PointsJob &j, int64_t n_max, float **buf, int64_t *cap)
 {
     j.mfma = prot::MfmaAux{};
-    if (j.d < prot::kMfmaMinD || c->cost_path != PROT_COST_MATRIX_CORES) return PROT_OK;
+    if (j.d < prot::kMfmaMinD || c->cost_path != PROT_COST_MATRIX_CORES || j.na_single)
+        return PROT_OK;  // (unbalanced instances take the direct path)
     const int64_t tx = (n_max + prot::kMfmaTile - 1) / prot::kMfmaTile;
     const int64_t need = 2 * (int64_t)j.batch + (int64_t)j.batch * tx * tx;
     if (need > *cap || !*buf) {
@@ -223,7 +225,7 @@ int setup_mfma(prot_ctx *c, prot::PointsJob &j, int64_t n_max, float **buf, int6
 // Single-instance point build into k (thresholds in the context workspace).
 // Workspace of the pruned exact maximum: 16 extreme keys, 12 box bounds, 2
 // counts, then two candidate lists of n indices.
-int setup_prune(prot_ctx *c, prot::PointsJob &j, int64_t n)
+int setup_prune(prot_ctx *c, prot::PointsJob &j, int64_t n)  // n: max(rows, columns)
 {
     j.prune = prot::PruneAux{};
     // below this size the plain n^2 pass is cheaper than the four pruning
@@ -243,12 +245,13 @@ int setup_prune(prot_ctx *c, prot::PointsJob &j, int64_t n)
 }
 
 prot::PointsJob points_job(prot_ctx *c, const float *X, const float *Y, int64_t n, int32_t d,
-                           double eps, int16_t *k, int64_t ldk)
+                           double eps, int16_t *k, int64_t ldk, int64_t n_a = 0)
 {
     prot::PointsJob j{};
     j.X = X;
     j.Y = Y;
     j.n_single = n;
+    j.na_single = (n_a && n_a != n) ? n_a : 0;
     j.ldk_single = ldk;
     j.d = d;
     j.batch = 1;
@@ -262,14 +265,15 @@ prot::PointsJob points_job(prot_ctx *c, const float *X, const float *Y, int64_t 
     return j;
 }
 
-prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
-                         const prot_opts *o, int32_t *y_b)
+prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
+                         int64_t T, const prot_opts *o, int32_t *y_b)
 {
     prot::LoopArgs a{};
     a.k = k;
     a.ldk = ldk;
     a.n = (int32_t)n;
-    a.n_pad = (int32_t)round_up(n, 8);
+    a.n_a = (int32_t)n_a;
+    a.n_pad = (int32_t)round_up(n_a, 8);
     a.T = T;
     a.origin = (o && o->origin_mode == PROT_ORIGIN_ZERO) ? 1 : 0;
     a.max_phases = o ? o->max_phases : 0;
@@ -297,15 +301,16 @@ struct OnTheFly {
     double eps = 0.0;
 };
 
-int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
+// n rows (B), n_a >= n columns (A).
+int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk, int64_t T,
              const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
              int32_t *y_b, const OnTheFly &otf = OnTheFly())
 {
-    int rc = ensure_loop(c, n);
+    int rc = ensure_loop(c, n_a);
     if (rc) return rc;
     int grid = 0;
-    if ((rc = grid_for(c, n, &grid))) return rc;
-    prot::LoopArgs a = loop_args(c, k, n, ldk, T, o, y_b);
+    if ((rc = grid_for(c, n, n_a, &grid))) return rc;
+    prot::LoopArgs a = loop_args(c, k, n, n_a, ldk, T, o, y_b);
     a.groups = std::min(c->loop_groups, grid);
     if (otf.d) {
         a.pd = otf.d;
@@ -318,7 +323,8 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
     if (warm) {
         // (I1) and the matching structure of the given state, O(n).
         HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
-        HIP_TRY(c, prot::launch_check_state(n, mate_a, mate_b, y_a, y_b, c->ctl, c->stream));
+        HIP_TRY(c, prot::launch_check_state(n, n_a, mate_a, mate_b, y_a, y_b, c->ctl,
+                                            c->stream));
         HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl.err, &c->ctl->err, sizeof(int32_t),
                                   hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -389,6 +395,19 @@ void fill_match_counts(prot_ctx *c, int64_t n, prot_stats *st, const prot_opts *
     const int64_t free_after = c->stage->ctl.free_after;
     st->matched_in_phases = n - free_after;
     st->completed_pairs = (o && o->no_completion) ? 0 : free_after;
+}
+
+// |B| = 0 with |A| > 0: nothing to match; a cold start still hands back the
+// initial column state (every a free, y(a) = 0).
+int no_rows(prot_ctx *c, int64_t n_a, int32_t warm, int32_t *mate_a, int32_t *y_a)
+{
+    if (warm || n_a <= 0) return PROT_OK;
+    if (!mate_a || !y_a) return fail(c, PROT_E_ARG, "null column output");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemsetAsync(mate_a, 0xFF, sizeof(int32_t) * n_a, c->stream));
+    HIP_TRY(c, hipMemsetAsync(y_a, 0, sizeof(int32_t) * n_a, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return PROT_OK;
 }
 
 }  // namespace
@@ -494,6 +513,7 @@ int setup_teams(prot_ctx *c, prot_batch *bp, const std::vector<int32_t> &n_arr,
         a.k = bp->k + k_off[i];
         a.ldk = ldk[i];
         a.n = (int32_t)n;
+        a.n_a = (int32_t)n;
         a.n_pad = (int32_t)round_up(n, 8);
         a.T = prot_threshold(bp->eps, n);
         a.origin = origin;
@@ -725,10 +745,10 @@ int prot_reserve(prot_ctx *c, int64_t n_max, int32_t with_matrix)
     if (!c || n_max < 0) return fail(c, PROT_E_ARG, "prot_reserve: bad arguments");
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = ensure_loop(c, n_max);
-    if (!rc && with_matrix) rc = ensure_matrix(c, n_max);
+    if (!rc && with_matrix) rc = ensure_matrix(c, n_max, n_max);
     if (!rc) {
         int grid = 0;
-        rc = grid_for(c, n_max, &grid);
+        rc = grid_for(c, n_max, n_max, &grid);
     }
     return rc;
 }
@@ -748,15 +768,16 @@ int64_t prot_max_n(prot_ctx *c)
     return best;
 }
 
-int prot_round_costs(prot_ctx *c, const float *C, int64_t n, int64_t ldc, double eps,
-                     int16_t *k, int64_t ldk)
+int prot_round_costs_rect(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                          double eps, int16_t *k, int64_t ldk)
 {
     if (!c) return PROT_E_ARG;
-    if (!C || !k || n < 0 || ldc < n || ldk < n || ldk % 8 || ((uintptr_t)k & 15))
+    if (!C || !k || n_b < 0 || n_a < 0 || ldc < n_a || ldk < n_a || ldk % 8 ||
+        ((uintptr_t)k & 15))
         return fail(c, PROT_E_ARG, "prot_round_costs: bad pointer, size or alignment");
     if (!eps_valid(eps)) return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, prot::launch_round_costs(C, n, ldc, eps, k, ldk, c->ctl, c->stream));
+    HIP_TRY(c, prot::launch_round_costs(C, n_b, n_a, ldc, eps, k, ldk, c->ctl, c->stream));
     HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl.err, &c->ctl->err, sizeof(int32_t),
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -764,20 +785,28 @@ int prot_round_costs(prot_ctx *c, const float *C, int64_t n, int64_t ldc, double
     return PROT_OK;
 }
 
-int prot_build_costs(prot_ctx *c, const float *X, const float *Y, int64_t n, int32_t d,
-                     double eps, int16_t *k, int64_t ldk, float *m_out)
+int prot_round_costs(prot_ctx *c, const float *C, int64_t n, int64_t ldc, double eps,
+                     int16_t *k, int64_t ldk)
+{
+    return prot_round_costs_rect(c, C, n, n, ldc, eps, k, ldk);
+}
+
+int prot_build_costs_rect(prot_ctx *c, const float *X, int64_t n_b, const float *Y, int64_t n_a,
+                          int32_t d, double eps, int16_t *k, int64_t ldk, float *m_out)
 {
     if (!c) return PROT_E_ARG;
-    if (!X || !Y || !k || n < 0 || d < 1 || ldk < n || ldk % 8 || ((uintptr_t)k & 15))
+    if (!X || !Y || !k || n_b < 0 || n_a < 0 || d < 1 || ldk < n_a || ldk % 8 ||
+        ((uintptr_t)k & 15))
         return fail(c, PROT_E_ARG, "prot_build_costs: bad pointer, size or alignment");
     if (!eps_valid(eps)) return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = ensure_thresholds(c, eps);
     if (rc) return rc;
-    prot::PointsJob j = points_job(c, X, Y, n, d, eps, k, ldk);
-    if ((rc = setup_mfma(c, j, n, &c->mfma_buf, &c->mfma_cap))) return rc;
-    if ((rc = setup_prune(c, j, n))) return rc;
-    HIP_TRY(c, prot::launch_points(j, n, ldk, c->stream));
+    const int64_t n_max = std::max(n_b, n_a);
+    prot::PointsJob j = points_job(c, X, Y, n_b, d, eps, k, ldk, n_a);
+    if ((rc = setup_mfma(c, j, n_max, &c->mfma_buf, &c->mfma_cap))) return rc;
+    if ((rc = setup_prune(c, j, n_max))) return rc;
+    HIP_TRY(c, prot::launch_points(j, n_max, ldk, c->stream));
     if (m_out)
         HIP_TRY(c, hipMemcpyAsync(m_out, &c->ctl->m, sizeof(float), hipMemcpyDeviceToDevice,
                                   c->stream));
@@ -788,29 +817,80 @@ int prot_build_costs(prot_ctx *c, const float *X, const float *Y, int64_t n, int
     return PROT_OK;
 }
 
-int prot_solve_rounded(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
-                       const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b,
-                       int32_t *y_a, int32_t *y_b, prot_stats *st)
+int prot_build_costs(prot_ctx *c, const float *X, const float *Y, int64_t n, int32_t d,
+                     double eps, int16_t *k, int64_t ldk, float *m_out)
+{
+    return prot_build_costs_rect(c, X, n, Y, n, d, eps, k, ldk, m_out);
+}
+
+int prot_solve_rounded_rect(prot_ctx *c, const int16_t *k, int64_t n_b, int64_t n_a,
+                            int64_t ldk, int64_t T, const prot_opts *o, int32_t warm,
+                            int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,
+                            prot_stats *st)
 {
     if (!c) return PROT_E_ARG;
-    if (n < 0 || T < 0 || (n > 0 && (!k || ldk < n || ldk % 8 || ((uintptr_t)k & 15))) ||
-        (n > 0 && (!mate_a || !mate_b || !y_a || !y_b)))
-        return fail(c, PROT_E_ARG, "prot_solve_rounded: bad pointer, size or alignment");
-    if (n > INT32_MAX / 2) return fail(c, PROT_E_UNSUPPORTED, "n too large");
+    if (n_b < 0 || n_a < n_b || T < 0 ||
+        (n_b > 0 && (!k || ldk < n_a || ldk % 8 || ((uintptr_t)k & 15))) ||
+        (n_b > 0 && (!mate_a || !mate_b || !y_a || !y_b)))
+        return fail(c, PROT_E_ARG,
+                    "prot_solve_rounded: bad pointer, size or alignment (|B| <= |A| required)");
+    if (n_a > INT32_MAX / 2) return fail(c, PROT_E_UNSUPPORTED, "n too large");
     if (st) std::memset(st, 0, sizeof(*st));
-    if (n == 0) return PROT_OK;
+    if (n_b == 0) return no_rows(c, n_a, warm, mate_a, y_a);
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-    int rc = run_loop(c, k, n, ldk, T, o, warm, mate_a, mate_b, y_a, y_b);
+    int rc = run_loop(c, k, n_b, n_a, ldk, T, o, warm, mate_a, mate_b, y_a, y_b);
     if (rc) return rc;
-    HIP_TRY(c, prot::launch_finalize(n, mate_b, k, ldk, 0, nullptr, 0, nullptr, nullptr, 0,
+    HIP_TRY(c, prot::launch_finalize(n_b, mate_b, k, ldk, 0, nullptr, 0, nullptr, nullptr, 0,
                                      c->part_k, c->part_c, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
     if (!st) return PROT_OK;
     rc = collect(c, st, T, 0.0, 0, false);
     if (rc) return rc;
-    fill_match_counts(c, n, st, o);
+    fill_match_counts(c, n_b, st, o);
+    return st->status;
+}
+
+int prot_solve_rounded(prot_ctx *c, const int16_t *k, int64_t n, int64_t ldk, int64_t T,
+                       const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b,
+                       int32_t *y_a, int32_t *y_b, prot_stats *st)
+{
+    return prot_solve_rounded_rect(c, k, n, n, ldk, T, o, warm, mate_a, mate_b, y_a, y_b, st);
+}
+
+int prot_solve_cost_rect(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                         double eps, const prot_opts *o, int32_t *mate_a, int32_t *mate_b,
+                         int32_t *y_a, int32_t *y_b, prot_stats *st)
+{
+    if (!c) return PROT_E_ARG;
+    if (n_b < 0 || n_a < n_b ||
+        (n_b > 0 && (!C || ldc < n_a || !mate_a || !mate_b || !y_a || !y_b)))
+        return fail(c, PROT_E_ARG, "prot_solve_cost: bad pointer or size (|B| <= |A| required)");
+    if (!eps_valid(eps_internal(eps, o)))
+        return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    prot_stats local;
+    if (!st) st = &local;
+    std::memset(st, 0, sizeof(*st));
+    if (n_b == 0) return no_rows(c, n_a, 0, mate_a, y_a);
+    HIP_TRY(c, hipSetDevice(c->device));
+    const double ei = eps_internal(eps, o);
+    const int64_t T = prot_threshold(ei, n_b), ldk = prot_pitch(n_a);
+    int rc = ensure_matrix(c, n_b, n_a);
+    if (rc) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    HIP_TRY(c, prot::launch_round_costs(C, n_b, n_a, ldc, ei, c->kmat, ldk, c->ctl, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    rc = run_loop(c, c->kmat, n_b, n_a, ldk, T, o, 0, mate_a, mate_b, y_a, y_b);
+    if (rc) return rc;
+    HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, 1, C, ldc, nullptr, nullptr, 0,
+                                     c->part_k, c->part_c, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+    rc = collect(c, st, T, ei, 1, true);
+    if (rc) return rc;
+    fill_match_counts(c, n_b, st, o);
+    st->kmax = (int32_t)std::floor(1.0 / ei);
+    if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a cost is NaN or outside [0,1]");
     return st->status;
 }
 
@@ -818,69 +898,45 @@ int prot_solve_cost(prot_ctx *c, const float *C, int64_t n, int64_t ldc, double 
                     const prot_opts *o, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
                     int32_t *y_b, prot_stats *st)
 {
-    if (!c) return PROT_E_ARG;
-    if (n < 0 || (n > 0 && (!C || ldc < n || !mate_a || !mate_b || !y_a || !y_b)))
-        return fail(c, PROT_E_ARG, "prot_solve_cost: bad pointer or size");
-    if (!eps_valid(eps_internal(eps, o)))
-        return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
-    prot_stats local;
-    if (!st) st = &local;
-    std::memset(st, 0, sizeof(*st));
-    if (n == 0) return PROT_OK;
-    HIP_TRY(c, hipSetDevice(c->device));
-    const double ei = eps_internal(eps, o);
-    const int64_t T = prot_threshold(ei, n), ldk = prot_pitch(n);
-    int rc = ensure_matrix(c, n);
-    if (rc) return rc;
-    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(c, prot::launch_round_costs(C, n, ldc, ei, c->kmat, ldk, c->ctl, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-    rc = run_loop(c, c->kmat, n, ldk, T, o, 0, mate_a, mate_b, y_a, y_b);
-    if (rc) return rc;
-    HIP_TRY(c, prot::launch_finalize(n, mate_b, c->kmat, ldk, 1, C, ldc, nullptr, nullptr, 0,
-                                     c->part_k, c->part_c, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
-    rc = collect(c, st, T, ei, 1, true);
-    if (rc) return rc;
-    fill_match_counts(c, n, st, o);
-    st->kmax = (int32_t)std::floor(1.0 / ei);
-    if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a cost is NaN or outside [0,1]");
-    return st->status;
+    return prot_solve_cost_rect(c, C, n, n, ldc, eps, o, mate_a, mate_b, y_a, y_b, st);
 }
 
-int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, int32_t d,
-                      double eps, const prot_opts *o, int32_t *mate_a, int32_t *mate_b,
-                      int32_t *y_a, int32_t *y_b, prot_stats *st)
+int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float *Y,
+                           int64_t n_a, int32_t d, double eps, const prot_opts *o,
+                           int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,
+                           prot_stats *st)
 {
     if (!c) return PROT_E_ARG;
-    if (n < 0 || d < 1 || (n > 0 && (!X || !Y || !mate_a || !mate_b || !y_a || !y_b)))
-        return fail(c, PROT_E_ARG, "prot_solve_points: bad pointer or size");
+    if (n_b < 0 || n_a < n_b || d < 1 ||
+        (n_b > 0 && (!X || !Y || !mate_a || !mate_b || !y_a || !y_b)))
+        return fail(c, PROT_E_ARG, "prot_solve_points: bad pointer or size (|B| <= |A| required)");
     if (!eps_valid(eps_internal(eps, o)))
         return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
     prot_stats local;
     if (!st) st = &local;
     std::memset(st, 0, sizeof(*st));
-    if (n == 0) return PROT_OK;
+    if (n_b == 0) return no_rows(c, n_a, 0, mate_a, y_a);
     HIP_TRY(c, hipSetDevice(c->device));
     const double ei = eps_internal(eps, o);
-    const int64_t T = prot_threshold(ei, n), ldk = prot_pitch(n);
+    const int64_t T = prot_threshold(ei, n_b), ldk = prot_pitch(n_a);
+    const int64_t n_max = std::max(n_b, n_a);
     const int32_t storage = o ? o->cost_storage : PROT_COSTS_AUTO;
     if (storage < PROT_COSTS_AUTO || storage > PROT_COSTS_ON_THE_FLY)
         return fail(c, PROT_E_ARG, "unknown cost_storage %d", (int)storage);
     if (storage == PROT_COSTS_ON_THE_FLY && d != 2 && d != 3)
         return fail(c, PROT_E_UNSUPPORTED, "costs on the fly need d = 2 or 3 (d = %d)", (int)d);
-    const bool on_the_fly =
-        storage == PROT_COSTS_ON_THE_FLY || (storage == PROT_COSTS_AUTO && auto_on_the_fly(d, n));
-    int rc = on_the_fly ? PROT_OK : ensure_matrix(c, n);
+    const bool on_the_fly = storage == PROT_COSTS_ON_THE_FLY ||
+                            (storage == PROT_COSTS_AUTO && auto_on_the_fly(d, n_b, n_a));
+    int rc = on_the_fly ? PROT_OK : ensure_matrix(c, n_b, n_a);
     if (!rc) rc = ensure_thresholds(c, ei);
     if (rc) return rc;
     int16_t *kmat = on_the_fly ? nullptr : c->kmat;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    prot::PointsJob j = points_job(c, X, Y, n, d, ei, kmat, ldk);
+    prot::PointsJob j = points_job(c, X, Y, n_b, d, ei, kmat, ldk, n_a);
     j.no_matrix = on_the_fly ? 1 : 0;
-    if (!on_the_fly && (rc = setup_mfma(c, j, n, &c->mfma_buf, &c->mfma_cap))) return rc;
-    if ((rc = setup_prune(c, j, n))) return rc;
-    HIP_TRY(c, prot::launch_points(j, n, ldk, c->stream));
+    if (!on_the_fly && (rc = setup_mfma(c, j, n_max, &c->mfma_buf, &c->mfma_cap))) return rc;
+    if ((rc = setup_prune(c, j, n_max))) return rc;
+    HIP_TRY(c, prot::launch_points(j, n_max, ldk, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     OnTheFly otf;
     if (on_the_fly) {
@@ -889,21 +945,28 @@ int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, in
         otf.Y = Y;
         otf.eps = ei;
     }
-    rc = run_loop(c, kmat, n, on_the_fly ? round_up(n, 8) : ldk, T, o, 0, mate_a, mate_b, y_a,
-                  y_b, otf);
+    rc = run_loop(c, kmat, n_b, n_a, on_the_fly ? round_up(n_a, 8) : ldk, T, o, 0, mate_a,
+                  mate_b, y_a, y_b, otf);
     if (rc) return rc;
     if (on_the_fly)
-        HIP_TRY(c, prot::launch_finalize(n, mate_b, nullptr, 0, 2, nullptr, 0, X, Y, d,
+        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, nullptr, 0, 2, nullptr, 0, X, Y, d,
                                          c->part_k, c->part_c, c->stream, &c->ctl->m, ei, c->th));
     else
-        HIP_TRY(c, prot::launch_finalize(n, mate_b, c->kmat, ldk, 2, nullptr, 0, X, Y, d,
+        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, 2, nullptr, 0, X, Y, d,
                                          c->part_k, c->part_c, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
     rc = collect(c, st, T, ei, 2, true);
     if (rc) return rc;
-    fill_match_counts(c, n, st, o);
+    fill_match_counts(c, n_b, st, o);
     if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");
     return st->status;
+}
+
+int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, int32_t d,
+                      double eps, const prot_opts *o, int32_t *mate_a, int32_t *mate_b,
+                      int32_t *y_a, int32_t *y_b, prot_stats *st)
+{
+    return prot_solve_points_rect(c, X, n, Y, n, d, eps, o, mate_a, mate_b, y_a, y_b, st);
 }
 
 

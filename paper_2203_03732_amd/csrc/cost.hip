@@ -31,7 +31,7 @@ constexpr int kMaxRows = 256;   // rows per block of the max pass
 constexpr int kMaxD = 3;        // largest d of the low-dimensional kernels
 
 __global__ void __launch_bounds__(kBuildThreads)
-round_costs_kernel(const float *__restrict__ C, int64_t n, int64_t ldc, double eps,
+round_costs_kernel(const float *__restrict__ C, int64_t n, int64_t na, int64_t ldc, double eps,
                    int16_t *__restrict__ k, int64_t ldk, Ctl *ctl)
 {
     const int64_t col0 = ((int64_t)blockIdx.x * kBuildThreads + threadIdx.x) * kColsPerThread;
@@ -43,7 +43,7 @@ round_costs_kernel(const float *__restrict__ C, int64_t n, int64_t ldc, double e
 #pragma unroll
         for (int e = 0; e < kColsPerThread; ++e) {
             const int64_t col = col0 + e;
-            if (col < n) {
+            if (col < na) {
                 const float c = crow[col];
                 bad |= !(c >= 0.0f && c <= 1.0f);
                 v[e] = (int16_t)floor((double)c / eps);
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
     const Instance in = j.instance(blockIdx.z);
     const int64_t a = (int64_t)blockIdx.x * kBuildThreads + threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.y * kMaxRows;
-    if (b0 >= in.n || (int64_t)blockIdx.x * kBuildThreads >= in.n) return;
+    if (b0 >= in.n || (int64_t)blockIdx.x * kBuildThreads >= in.na) return;
     const int rows = (int)min<int64_t>(kMaxRows, in.n - b0);
     // A non-finite coordinate is caught where it is loaded; with finite
     // coordinates a distance can only overflow to +inf, which the maximum
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
     }
     __syncthreads();
     float mx = 0.0f;
-    if (a < in.n) {
+    if (a < in.na) {
         float y[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) {
@@ -156,7 +156,8 @@ __global__ void __launch_bounds__(256) extent_kernel(PointsJob j)
 {
     constexpr int U = 1 << D;
     const PruneAux &P = j.prune;
-    const int64_t n = j.n_single;
+    const int64_t n = j.n_single, na = j.na_single ? j.na_single : j.n_single;
+    const int64_t top = n > na ? n : na;
     unsigned long long ex[U], ey[U];
     float lo[2][D], hi[2][D];
 #pragma unroll
@@ -167,18 +168,23 @@ __global__ void __launch_bounds__(256) extent_kernel(PointsJob j)
         hi[0][q] = hi[1][q] = -FLT_MAX;
     }
     bool bad = false;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < top;
          i += (int64_t)gridDim.x * blockDim.x) {
+        const bool hx = i < n, hy = i < na;
         float x[D], y[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) {
-            x[q] = j.X[i * D + q];
-            y[q] = j.Y[i * D + q];
+            x[q] = hx ? j.X[i * D + q] : 0.0f;
+            y[q] = hy ? j.Y[i * D + q] : 0.0f;
             bad |= !(fabsf(x[q]) <= FLT_MAX) || !(fabsf(y[q]) <= FLT_MAX);
-            lo[0][q] = fminf(lo[0][q], x[q]);
-            hi[0][q] = fmaxf(hi[0][q], x[q]);
-            lo[1][q] = fminf(lo[1][q], y[q]);
-            hi[1][q] = fmaxf(hi[1][q], y[q]);
+            if (hx) {
+                lo[0][q] = fminf(lo[0][q], x[q]);
+                hi[0][q] = fmaxf(hi[0][q], x[q]);
+            }
+            if (hy) {
+                lo[1][q] = fminf(lo[1][q], y[q]);
+                hi[1][q] = fmaxf(hi[1][q], y[q]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -190,8 +196,8 @@ __global__ void __launch_bounds__(256) extent_kernel(PointsJob j)
             }
             const unsigned long long kx = ((unsigned long long)order_of(px) << 32) | (uint32_t)i;
             const unsigned long long ky = ((unsigned long long)order_of(py) << 32) | (uint32_t)i;
-            ex[u] = kx > ex[u] ? kx : ex[u];
-            ey[u] = ky > ey[u] ? ky : ey[u];
+            if (hx) ex[u] = kx > ex[u] ? kx : ex[u];
+            if (hy) ey[u] = ky > ey[u] ? ky : ey[u];
         }
     }
     // wave reductions, then one atomic per wave
@@ -250,7 +256,8 @@ template <int D>
 __global__ void __launch_bounds__(256) prune_kernel(PointsJob j)
 {
     const PruneAux &P = j.prune;
-    const int64_t n = j.n_single;
+    const int64_t n = j.n_single, na = j.na_single ? j.na_single : j.n_single;
+    const int64_t top = n > na ? n : na;
     const double L = (double)prune_lower_bound<D>(j) * (1.0 - 1e-5);
     double blo[2][D], bhi[2][D];
 #pragma unroll
@@ -261,23 +268,24 @@ __global__ void __launch_bounds__(256) prune_kernel(PointsJob j)
             bhi[w][q] = (double)float_of(P.bb[6 * w + 3 + q]);
         }
     const int lane = threadIdx.x & 63;
-    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < top;
          base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = base + threadIdx.x;
         bool cx = false, cy = false;
-        if (i < n) {
+        if (i < top) {
             // furthest corner of the other set's box, per coordinate
             double ux = 0.0, uy = 0.0;
 #pragma unroll
             for (int q = 0; q < D; ++q) {
-                const double x = (double)j.X[i * D + q], y = (double)j.Y[i * D + q];
+                const double x = i < n ? (double)j.X[i * D + q] : 0.0;
+                const double y = i < na ? (double)j.Y[i * D + q] : 0.0;
                 const double a0 = x - blo[1][q], a1 = x - bhi[1][q];
                 const double b0 = y - blo[0][q], b1 = y - bhi[0][q];
                 ux += fmax(a0 * a0, a1 * a1);
                 uy += fmax(b0 * b0, b1 * b1);
             }
-            cx = ux >= L;
-            cy = uy >= L;
+            cx = i < n && ux >= L;
+            cy = i < na && uy >= L;
         }
         const unsigned long long bx = __ballot(cx), by = __ballot(cy);
         uint32_t ox = 0, oy = 0;
@@ -358,7 +366,7 @@ __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
     for (int i = threadIdx.x; i < rows * D; i += kBuildThreads) xs[i] = in.X[b0 * D + i];
     __syncthreads();
     if (col0 >= in.ldk) return;
-    const int64_t n = in.n;
+    const int64_t n = in.na;  // columns
     const float mf = j.m[blockIdx.z];
     const int32_t K = (mf > 0.0f) ? (int32_t)floor(1.0 / j.eps) : 0;
     const float inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * j.eps)) : 0.0f;
@@ -424,9 +432,9 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
     __shared__ __align__(16) float ys[kTj][kTile + 4];
     __shared__ float red[4];
     const Instance in = j.instance(blockIdx.z);
-    const int64_t n = in.n;
+    const int64_t n = in.n, na = in.na;  // rows, columns
     const int64_t b0 = (int64_t)blockIdx.y * kTile, a0 = (int64_t)blockIdx.x * kTile;
-    if (b0 >= n || a0 >= (PASS ? in.ldk : n)) return;
+    if (b0 >= n || a0 >= (PASS ? in.ldk : na)) return;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int d = j.d;
     float acc[4][4];
@@ -439,7 +447,7 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
             const int r = q / kTj, jj = q - r * kTj;
             const bool cj = j0 + jj < d;
             xs[jj][r] = (cj && b0 + r < n) ? in.X[(b0 + r) * d + j0 + jj] : 0.0f;
-            ys[jj][r] = (cj && a0 + r < n) ? in.Y[(a0 + r) * d + j0 + jj] : 0.0f;
+            ys[jj][r] = (cj && a0 + r < na) ? in.Y[(a0 + r) * d + j0 + jj] : 0.0f;
         }
         __syncthreads();
 #pragma unroll
@@ -465,7 +473,7 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if (b0 + ty * 4 + i < n && a0 + tx * 4 + c < n) {
+                if (b0 + ty * 4 + i < n && a0 + tx * 4 + c < na) {
                     bad |= !(acc[i][c] <= FLT_MAX);
                     mx = fmaxf(mx, acc[i][c]);
                 }
@@ -493,7 +501,7 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int64_t col = a0 + tx * 4 + c;
-                if (col >= n) {
+                if (col >= na) {
                     g[c] = 0x7FFF;
                     continue;
                 }
@@ -545,7 +553,7 @@ void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStre
 
 }  // namespace
 
-hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps,
+hipError_t launch_round_costs(const float *C, int64_t n, int64_t na, int64_t ldc, double eps,
                               int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s)
 {
     PointsJob j{};
@@ -557,7 +565,7 @@ hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps
     const int64_t per_block = (int64_t)kBuildThreads * kColsPerThread;
     dim3 grid((unsigned)((ldk + per_block - 1) / per_block), (unsigned)(n < 65535 ? n : 65535));
     if (n > 0)
-        hipLaunchKernelGGL(round_costs_kernel, grid, dim3(kBuildThreads), 0, s, C, n, ldc,
+        hipLaunchKernelGGL(round_costs_kernel, grid, dim3(kBuildThreads), 0, s, C, n, na, ldc,
                            eps, k, ldk, ctl);
     return hipGetLastError();
 }

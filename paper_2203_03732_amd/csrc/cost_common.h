@@ -9,8 +9,9 @@ namespace prot {
 // One instance of a (possibly batched) point-set cost build.
 struct Instance {
     const float *X;   // n x d rows (supply B)
-    const float *Y;   // n x d columns (demand A)
-    int64_t n;
+    const float *Y;   // na x d columns (demand A)
+    int64_t n;        // rows
+    int64_t na;       // columns (na >= n; = n except for unbalanced single instances)
     int64_t ldk;      // row pitch of its rounded-cost matrix
     int16_t *k;
 };
@@ -40,6 +41,7 @@ struct PointsJob {
     const int64_t *k_off;      // device, element offset of each instance's matrix
     const int32_t *ldk_arr;    // device, row pitch per instance (null: ldk_single)
     int64_t n_single, ldk_single;
+    int64_t na_single;         // columns of a single instance (0: n_single)
     int32_t d;
     int32_t batch;
     double eps;
@@ -60,6 +62,7 @@ struct PointsJob {
         in.X = X + off * d;
         in.Y = Y + off * d;
         in.n = n_arr ? n_arr[i] : n_single;
+        in.na = (n_arr || na_single == 0) ? in.n : na_single;
         in.ldk = ldk_arr ? ldk_arr[i] : ldk_single;
         in.k = k + (k_off ? k_off[i] : 0);
         return in;

@@ -46,8 +46,10 @@ constexpr int kRoundTimeCap = 65536;    // rounds recorded by the round timer
 struct LoopArgs {
     const int16_t *k;
     int64_t ldk;
-    int32_t n;
-    int32_t n_pad;          // n rounded up to 8 (LDS dual array length)
+    int32_t n;              // rows |B|
+    int32_t n_pad;          // n_a rounded up to 8 (LDS dual array length)
+    int32_t n_a;            // columns |A| >= |B| (Section 3.3; = n when balanced)
+    int32_t pad4;
     int64_t T;
     int32_t origin;         // 0: diagonal, 1: zero
     int32_t pad;
@@ -134,7 +136,7 @@ struct LossArgs {
 };
 
 // cost.hip
-hipError_t launch_round_costs(const float *C, int64_t n, int64_t ldc, double eps,
+hipError_t launch_round_costs(const float *C, int64_t n, int64_t na, int64_t ldc, double eps,
                               int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s);
 hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s);
 
@@ -159,9 +161,9 @@ hipError_t launch_loss_bwd(const LossArgs &a, int64_t n_max, const float *grad_l
 hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
                        const int32_t *mate_b, const int32_t *y_a, hipStream_t s);
 hipError_t launch_clear_err(Ctl *ctl, hipStream_t s);
-hipError_t launch_check_state(int64_t n, const int32_t *mate_a, const int32_t *mate_b,
-                              const int32_t *y_a, const int32_t *y_b, Ctl *ctl,
-                              hipStream_t s);
+hipError_t launch_check_state(int64_t n, int64_t na, const int32_t *mate_a,
+                              const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
+                              Ctl *ctl, hipStream_t s);
 hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max);
 hipError_t launch_clear_times(int64_t *rtime, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);

@@ -282,7 +282,7 @@ __device__ inline PointsSrc<D> points_src(const LoopArgs &A)
     s.K = (mf > 0.0f) ? (int32_t)floor(1.0 / A.peps) : 0;
     s.inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * A.peps)) : 0.0f;
     s.delta = classify_margin(s.K);
-    s.n = A.n;
+    s.n = A.n_a;
     return s;
 }
 
@@ -402,27 +402,33 @@ __global__ void loop_reset_kernel(LoopArgs a)
 __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
                             const int32_t *mate_b, const int32_t *y_a)
 {
-    const int n = a.n;
+    const int n = a.n, na = a.n_a;  // rows, columns
     const int lane = threadIdx.x & 63;
     const uint32_t tag0 = a.ctl->tag_last + 1u;
-    for (int base = blockIdx.x * blockDim.x; base < a.n_pad; base += gridDim.x * blockDim.x) {
+    const int top = a.n_pad > n ? a.n_pad : n;
+    for (int base = blockIdx.x * blockDim.x; base < top; base += gridDim.x * blockDim.x) {
         const int i = base + threadIdx.x;
         bool is_free = false;
-        if (i < n) {
-            if (a.skip) a.skip[i] = 0u;
+        if (i < na) {
             if (!warm) {
                 a.key[i] = 0ull;
                 a.t[i] = 0;
-                a.y_b[i] = 1;
-                a.F[0][i] = tagged(tag0, i);
             } else {
                 const int32_t m = mate_a[i];
                 a.key[i] = m >= 0 ? (unsigned long long)(uint32_t)~(uint32_t)m : 0ull;
                 a.t[i] = (uint16_t)(-y_a[i]);
-                is_free = mate_b[i] < 0;
             }
         } else if (i < a.n_pad) {
             a.t[i] = 0;
+        }
+        if (i < n) {
+            if (a.skip) a.skip[i] = 0u;
+            if (!warm) {
+                a.y_b[i] = 1;
+                a.F[0][i] = tagged(tag0, i);
+            } else {
+                is_free = mate_b[i] < 0;
+            }
         }
         if (warm) {
             const unsigned long long bal = __ballot(is_free);
@@ -438,20 +444,24 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
 }
 
 // Warm-start check, O(n): the mate arrays form one matching and (I1) holds.
-__global__ void check_state_kernel(int64_t n, const int32_t *mate_a, const int32_t *mate_b,
-                                   const int32_t *y_a, const int32_t *y_b, Ctl *ctl)
+__global__ void check_state_kernel(int64_t n, int64_t na, const int32_t *mate_a,
+                                   const int32_t *mate_b, const int32_t *y_a,
+                                   const int32_t *y_b, Ctl *ctl)
 {
     bool bad = false;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t ma = mate_a[i], mb = mate_b[i];
-        if (ma >= n || mb >= n || ma < -1 || mb < -1) bad = true;
-        else {
-            if (ma >= 0 && mate_b[ma] != i) bad = true;
-            if (mb >= 0 && mate_a[mb] != i) bad = true;
-        }
-        if (y_a[i] > 0 || y_a[i] < -32000 || y_b[i] < 0 || y_b[i] > 32000) bad = true;
+        const int32_t ma = mate_a[i];
+        if (ma >= n || ma < -1) bad = true;
+        else if (ma >= 0 && mate_b[ma] != i) bad = true;
+        if (y_a[i] > 0 || y_a[i] < -32000) bad = true;
         if (ma < 0 && y_a[i] != 0) bad = true;
+        if (i < n) {
+            const int32_t mb = mate_b[i];
+            if (mb >= na || mb < -1) bad = true;
+            else if (mb >= 0 && mate_a[mb] != i) bad = true;
+            if (y_b[i] < 0 || y_b[i] > 32000) bad = true;
+        }
     }
     if (bad) __hip_atomic_fetch_or(&ctl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -504,7 +514,8 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     const uint32_t gw = wg * wpg + threadIdx.x / kWave;
     const bool leader = wg == 0 && threadIdx.x == 0;
     Ctl *ctl = A.ctl;
-    const int n = A.n;
+    const int n = A.n;     // rows, |B|
+    const int na = A.n_a;  // columns, |A| >= |B| (Section 3.3)
 
     const int G = A.groups;
     const int grp = (int)(wg % (uint32_t)G);
@@ -596,7 +607,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
                     const int j = group_of(s_lpre, G, i);
                     const int32_t a =
-                        take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, n, &ctl->err);
+                        take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, na, &ctl->err);
                     t_lds[a] = (uint16_t)((t_lds[a] + 1) | kTaken);
                 }
                 // the rows of this wave that proposed: won (matched in M') or
@@ -617,7 +628,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             // the row's smallest slack
             const bool track = kFF && A.skip != nullptr && first_round;
             if (first_round && pre) {
-                // exhausted as its scan from position 0 would be (extent n), (III b)
+                // exhausted as its scan from position 0 would be (extent na), (III b)
                 const bool lead = R == 1 || k_rank == 0;
                 if (lead) {
                     if ((pre >> lane) & 1ull) {
@@ -625,7 +636,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         st_agent(A.skip + s_b, s_skip - 1u);
                         my_f = s_b;
                     }
-                    wave_scan += (unsigned long long)n * (unsigned long long)__popcll(pre);
+                    wave_scan += (unsigned long long)na * (unsigned long long)__popcll(pre);
                 }
             }
             first_round = false;
@@ -634,9 +645,9 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 // the team's first hit is the smallest position found
                 int* best = &s_best[r & 1][team_local];
                 if (active & 1ull) {
-                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, n);
+                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, na);
                     int mn = kNoHit;
-                    const int j = team_scan(src, src.row(v.b), t_lds, n, v.origin, v.S,
+                    const int j = team_scan(src, src.row(v.b), t_lds, na, v.origin, v.S,
                                             v.yb - 1, k_rank, R, lane, best, track ? &mn : nullptr);
                     if (lane == 0 && j != kNoHit) atomicMin(best, j);
                     if (track) {
@@ -646,12 +657,12 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 }
                 __syncthreads();
                 if (active & 1ull) {
-                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, n);
+                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, na);
                     const int j = *best;
                     const int b = v.b, pos = v.pos, yb = v.yb;
                     const bool lead = k_rank == 0;
                     if (j != kNoHit) {
-                        const int a = v.origin + j < n ? v.origin + j : v.origin + j - n;
+                        const int a = v.origin + j < na ? v.origin + j : v.origin + j - na;
                         const unsigned long long kn =
                             ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
                         if (lead) {
@@ -671,7 +682,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     } else {
                         // b has no admissible untaken column: free in M', (III b).
                         if (lead) {
-                            wave_scan += (unsigned long long)(n - pos);
+                            wave_scan += (unsigned long long)(na - pos);
                             if (lane == 0) {
                                 st_agent(y_b + b, yb + 1);
                                 my_f = b;
@@ -702,7 +713,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     if (!rem) continue;
                     sl[q] = __builtin_ctzll(rem);
                     rem &= rem - 1;
-                    const SlotView v = slot_view(sl[q], s_b, s_pos, s_yb, A.origin, n);
+                    const SlotView v = slot_view(sl[q], s_b, s_pos, s_yb, A.origin, na);
                     const int col0 = v.base + lane * 8;
                     if (col0 < v.S.hi(v.sg))
                         kvq[q] = src.chunk(src.row(v.b), col0);
@@ -711,7 +722,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 for (int q = 0; q < SrcOf<kSrcD>::type::kBatch; ++q) {
                     if (sl[q] < 0) continue;
                     const int s = sl[q];
-                    const SlotView v = slot_view(s, s_b, s_pos, s_yb, A.origin, n);
+                    const SlotView v = slot_view(s, s_b, s_pos, s_yb, A.origin, na);
                     const int b = v.b, pos = v.pos, yb = v.yb;
                     const int slo = v.S.lo(v.sg), shi = v.S.hi(v.sg);
                     const int col0 = v.base + lane * 8;
@@ -722,9 +733,9 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     if (track && col0 < shi)
                         mn = min_sum_masked(kvq[q], tv, range_mask(col0, slo, shi));
                     const int a = chunk_hit(col0, kvq[q], tv, yb - 1, slo, shi);
-                    if (a >= 0) h = hit_at(a, v.origin, n);
+                    if (a >= 0) h = hit_at(a, v.origin, na);
                     else if (slo < shi)
-                        h = scan_from<kScanAhead>(src, src.row(b), t_lds, n, v.origin, v.S, v.sg,
+                        h = scan_from<kScanAhead>(src, src.row(b), t_lds, na, v.origin, v.S, v.sg,
                                       v.base + kChunk, yb - 1, lane, track ? &mn : nullptr);
                     if (h.j >= 0) {
                         wave_scan += (unsigned long long)(h.j - pos + 1);
@@ -743,7 +754,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         n_prop += 1;
                     } else {
                         // b has no admissible untaken column: free in M', (III b).
-                        wave_scan += (unsigned long long)(n - pos);
+                        wave_scan += (unsigned long long)(na - pos);
                         const int slack = track ? wave_min(mn) - (yb - 1) : 0;
                         if (lane == s) {
                             st_agent(y_b + b, yb + 1);
@@ -853,7 +864,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
             const int j = group_of(s_lpre, G, i);
             const int32_t a =
-                take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, n, &ctl->err);
+                take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, na, &ctl->err);
             t_lds[a] = (uint16_t)(t_lds[a] + 1);
         }
         __syncthreads();
@@ -912,7 +923,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         ctl->free_after = n_i;
     }
     if (wg == 0)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) A.t[i] = t_lds[i];
+        for (int i = threadIdx.x; i < na; i += blockDim.x) A.t[i] = t_lds[i];
 }
 
 __global__ void clear_err_kernel(Ctl *ctl) { ctl->err = 0; }
@@ -934,7 +945,7 @@ __global__ void fill_kernel(int32_t *p, int64_t n, int32_t v)
 // Matching and duals from the per-column keys and t.
 __global__ void decode_kernel(LoopArgs a, int32_t *mate_a, int32_t *mate_b, int32_t *y_a)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_a; i += gridDim.x * blockDim.x) {
         const unsigned long long kk = a.key[i];
         const int32_t m = kk ? (int32_t)~(uint32_t)kk : -1;
         mate_a[i] = m;
@@ -972,11 +983,12 @@ __device__ int list_flags(const int32_t *mate, int n, int32_t *out, int *cnt)
 
 // Completion (Section 2.1): the i-th free b (ascending) takes the i-th free a.
 __global__ void __launch_bounds__(kCompleteThreads)
-complete_kernel(int n, int32_t *mate_a, int32_t *mate_b, int32_t *scratch, int32_t complete)
+complete_kernel(int n, int n_a, int32_t *mate_a, int32_t *mate_b, int32_t *scratch,
+                int32_t complete)
 {
     __shared__ int cnt[kCompleteThreads];
     const int nb = list_flags(mate_b, n, scratch, cnt);
-    const int na = list_flags(mate_a, n, scratch + n, cnt);
+    const int na = list_flags(mate_a, n_a, scratch + n, cnt);
     if (!complete) return;
     const int m = min(nb, na);
     for (int i = threadIdx.x; i < m; i += kCompleteThreads) {
@@ -1177,7 +1189,8 @@ hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
                        const int32_t *mate_b, const int32_t *y_a, hipStream_t s)
 {
     hipLaunchKernelGGL(loop_reset_kernel, dim3(1), dim3(1), 0, s, a);
-    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(a.n_pad, 256)), dim3(256), 0, s, a, warm,
+    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(a.n_pad > a.n ? a.n_pad : a.n, 256)), dim3(256),
+                       0, s, a, warm,
                        mate_a, mate_b, y_a);
     return hipGetLastError();
 }
@@ -1188,11 +1201,12 @@ hipError_t launch_clear_err(Ctl *ctl, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_check_state(int64_t n, const int32_t *mate_a, const int32_t *mate_b,
-                              const int32_t *y_a, const int32_t *y_b, Ctl *ctl, hipStream_t s)
+hipError_t launch_check_state(int64_t n, int64_t na, const int32_t *mate_a,
+                              const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
+                              Ctl *ctl, hipStream_t s)
 {
-    hipLaunchKernelGGL(check_state_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, mate_a,
-                       mate_b, y_a, y_b, ctl);
+    hipLaunchKernelGGL(check_state_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, n, na,
+                       mate_a, mate_b, y_a, y_b, ctl);
     return hipGetLastError();
 }
 
@@ -1307,10 +1321,10 @@ hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a, i
 {
     hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, mate_b,
                        (int64_t)a.n, -1);
-    hipLaunchKernelGGL(decode_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a, mate_a,
+    hipLaunchKernelGGL(decode_kernel, dim3(blocks_for(a.n_a, 256)), dim3(256), 0, s, a, mate_a,
                        mate_b, y_a);
-    hipLaunchKernelGGL(complete_kernel, dim3(1), dim3(kCompleteThreads), 0, s, a.n, mate_a,
-                       mate_b, scratch, complete);
+    hipLaunchKernelGGL(complete_kernel, dim3(1), dim3(kCompleteThreads), 0, s, a.n, a.n_a,
+                       mate_a, mate_b, scratch, complete);
     return hipGetLastError();
 }
 
