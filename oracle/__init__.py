@@ -66,10 +66,13 @@ def _load():
     lib.orc_solve_rounded_rect.argtypes = [p, i64, i64, i64, i64, i32, i64, i32, i32,
                                            p, p, p, p, p, p, i64]
     lib.orc_points_max_f32.argtypes = [p, p, i64, i64, i32, p]
+    lib.orc_ot_scale.argtypes = [p, i64, p, i64, f64, p, p, p, p, p]
+    lib.orc_ot_solve.argtypes = [p, i64, i64, i64, p, p, f64, i32, i64, i32, p, p, p, p, p,
+                                 p, p, p, i64]
     lib.orc_points_pairs_f32.argtypes = [p, p, i32, f64, ctypes.c_float, p, p, i64, p]
     for fn in (lib.orc_round_cost, lib.orc_round_points_f32,
                lib.orc_points_cost_f64, lib.orc_solve_rounded, lib.orc_solve_rounded_rect,
-               lib.orc_points_max_f32,
+               lib.orc_points_max_f32, lib.orc_ot_scale, lib.orc_ot_solve,
                lib.orc_points_pairs_f32):
         fn.restype = ctypes.c_int
     _lib = lib
@@ -196,6 +199,62 @@ def solve_rounded(k: np.ndarray, T: int, origin: str = "diag",
     stats = {name: int(getattr(st, name)) for name, _ in _Stats._fields_}
     out = dict(mate_a=mate_a, mate_b=mate_b, y_a=y_a, y_b=y_b,
                status=STATUS[rc], stats=stats)
+    if tr is not None:
+        out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
+    return out
+
+
+def ot_scale(nu, mu, eps: float):
+    """Section 4 scaling: (s, d, theta) with s_b = floor(theta nu_b) supply
+    copies and d_a = ceil(theta mu_a) demand copies, theta = 4 max(n_b, n_a)/eps."""
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    s = np.zeros(len(nu), np.int64)
+    d = np.zeros(len(mu), np.int64)
+    th = ctypes.c_double()
+    cb, ca = ctypes.c_int64(), ctypes.c_int64()
+    _check(_load().orc_ot_scale(_ptr(nu), len(nu), _ptr(mu), len(mu), float(eps), _ptr(s),
+                                _ptr(d), ctypes.byref(th), ctypes.byref(cb), ctypes.byref(ca)),
+           "ot_scale")
+    return s, d, th.value
+
+
+def ot_solve(C: np.ndarray, nu, mu, eps: float, origin: str = "diag", max_phases: int = 0,
+             state: dict | None = None, trace: bool = False, trace_cap: int = 1 << 20) -> dict:
+    """Section 4: approximate transport plan from supplies nu (rows of C) to
+    demands mu (columns) through unit copies, with the free-copy dual raise.
+    Returns the plan (n_b x n_a float64; None unless the loop finished), the
+    copy-level mates and duals, the copy counts s and d, theta, the plan's
+    cost, the mass moved by the feasibility repair, T, status and stats."""
+    C = np.ascontiguousarray(C, dtype=np.float32)
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    n_b, n_a = C.shape
+    s, d, theta = ot_scale(nu, mu, eps)
+    NB, NA = int(s.sum()), int(d.sum())
+    if state is None:
+        mate_a = np.full(NA, -1, np.int32)
+        mate_b = np.full(NB, -1, np.int32)
+        y_a = np.zeros(NA, np.int32)
+        y_b = np.ones(NB, np.int32)
+        warm = 0
+    else:
+        mate_a, mate_b, y_a, y_b = (np.array(state[x], dtype=np.int32, copy=True)
+                                    for x in ("mate_a", "mate_b", "y_a", "y_b"))
+        warm = 1
+    plan = np.zeros((n_b, n_a), np.float64)
+    info = np.zeros(4, np.float64)
+    st = _Stats()
+    tr = np.zeros((trace_cap, 4), np.int64) if trace else None
+    rc = _check(_load().orc_ot_solve(
+        _ptr(C), n_b, n_a, n_a, _ptr(nu), _ptr(mu), float(eps), ORIGIN[origin],
+        int(max_phases), warm, _ptr(mate_a), _ptr(mate_b), _ptr(y_a), _ptr(y_b), _ptr(plan),
+        ctypes.byref(st), _ptr(info), _ptr(tr) if tr is not None else None,
+        trace_cap if tr is not None else 0), "ot_solve")
+    stats = {name: int(getattr(st, name)) for name, _ in _Stats._fields_}
+    out = dict(plan=plan if rc == 0 else None, mate_a=mate_a, mate_b=mate_b, y_a=y_a, y_b=y_b,
+               s=s, d=d, theta=float(info[0]), cost=float(info[1]), repaired=float(info[2]),
+               T=int(info[3]), status=STATUS[rc], stats=stats)
     if tr is not None:
         out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
     return out

@@ -169,25 +169,42 @@ static int64_t scan_col(int32_t origin_mode, int64_t b, int64_t j, int64_t n)
     return a >= n ? a - n : a;
 }
 
+/* The rounded cost of edge (a, b). Plain instances read k[b][a]. The copies
+ * of the transport reduction (Section 4) read the cost of the points they
+ * copy: row_pt[b] and col_pt[a] name those points. */
+typedef struct {
+    const int16_t *k;
+    int64_t ldk;
+    const int32_t *row_pt, *col_pt;  /* NULL: the identity */
+} costs_t;
+
+static int16_t cost_of(const costs_t *c, int64_t b, int64_t a)
+{
+    int64_t r = c->row_pt ? c->row_pt[b] : b;
+    int64_t q = c->col_pt ? c->col_pt[a] : a;
+    return c->k[r * c->ldk + q];
+}
+
 /* An edge (a, b) outside M is admissible when its slack is zero. With the
  * duals and costs in units of eps, the reading that makes the proof of (I2)
  * go through (a new M' edge must end with y(a) + y(b) = cbar after y(a)
  * drops by one step) is y(a) + y(b) = cbar(a, b) + eps. */
-static int admissible(const int16_t *k, int64_t ldk, const int32_t *y_a,
-                      const int32_t *y_b, int64_t a, int64_t b)
+static int admissible_c(const costs_t *c, const int32_t *y_a, const int32_t *y_b, int64_t a,
+                        int64_t b)
 {
-    return (int64_t)k[b * ldk + a] + 1 == (int64_t)y_a[a] + (int64_t)y_b[b];
+    return (int64_t)cost_of(c, b, a) + 1 == (int64_t)y_a[a] + (int64_t)y_b[b];
 }
 
-int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t ldk,
-                           int64_t T, int32_t origin_mode, int64_t max_phases, int32_t warm,
-                           int32_t complete, int32_t *mate_a, int32_t *mate_b,
-                           int32_t *y_a, int32_t *y_b, orc_stats *st,
-                           int64_t *trace, int64_t trace_cap)
+/* The phase loop on n_b rows and n_a >= n_b columns. With raise_groups > 0
+ * (the copies of Section 4) row b is a copy of supply point cs->row_pt[b]
+ * and, after step (III) of every phase, each free copy's dual is raised to
+ * the largest dual among the copies of its point. */
+static int phase_loop(const costs_t *cs, int64_t n_b, int64_t n_a, int64_t raise_groups,
+                      int64_t T, int32_t origin_mode, int64_t max_phases, int32_t warm,
+                      int32_t complete, int32_t *mate_a, int32_t *mate_b,
+                      int32_t *y_a, int32_t *y_b, orc_stats *st,
+                      int64_t *trace, int64_t trace_cap)
 {
-    if (n_b < 0 || n_a < n_b || (n_b > 0 && (!k || ldk < n_a)) || !mate_a || !mate_b ||
-        !y_a || !y_b || !st)
-        return ORC_E_ARG;
     if (origin_mode != ORC_ORIGIN_DIAG && origin_mode != ORC_ORIGIN_ZERO)
         return ORC_E_ARG;
     memset(st, 0, sizeof(*st));
@@ -205,6 +222,11 @@ int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t l
     }
 
     size_t sz = (size_t)(n_a > 0 ? n_a : 1);  /* n_b <= n_a */
+    int32_t *group_max = NULL;
+    if (raise_groups > 0) {
+        group_max = (int32_t *)malloc(sizeof(int32_t) * (size_t)raise_groups);
+        if (!group_max) return ORC_E_NOMEM;
+    }
     int64_t *B_prime = (int64_t *)malloc(sizeof(int64_t) * sz);
     int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * sz);
     int64_t *target = (int64_t *)malloc(sizeof(int64_t) * sz);
@@ -215,7 +237,7 @@ int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t l
     if (!B_prime || !pos || !target || !active || !won || !taken_by ||
         !proposer) {
         free(B_prime); free(pos); free(target); free(active); free(won);
-        free(taken_by); free(proposer);
+        free(taken_by); free(proposer); free(group_max);
         return ORC_E_NOMEM;
     }
 
@@ -260,7 +282,7 @@ int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t l
                 int64_t j;
                 for (j = pos[i]; j < n_a; ++j) {
                     int64_t a = scan_col(origin_mode, b, j, n_a);
-                    if (taken_by[a] < 0 && admissible(k, ldk, y_a, y_b, a, b)) {
+                    if (taken_by[a] < 0 && admissible_c(cs, y_a, y_b, a, b)) {
                         target[i] = a;
                         break;
                     }
@@ -315,6 +337,21 @@ int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t l
         for (int64_t i = 0; i < n_i; ++i)
             if (!won[i]) y_b[B_prime[i]] += 1;
 
+        /* Section 4: every free copy takes the largest dual among the copies
+         * of its point (the duals of the copies only grow, and a free copy
+         * raised to a sibling's dual keeps eq. (2): the copies share one
+         * row of costs). */
+        if (raise_groups > 0) {
+            for (int64_t g = 0; g < raise_groups; ++g) group_max[g] = INT32_MIN;
+            for (int64_t b = 0; b < n_b; ++b) {
+                int32_t g = cs->row_pt[b];
+                if (y_b[b] > group_max[g]) group_max[g] = y_b[b];
+            }
+            for (int64_t b = 0; b < n_b; ++b)
+                if (mate_b[b] < 0 && y_b[b] < group_max[cs->row_pt[b]])
+                    y_b[b] = group_max[cs->row_pt[b]];
+        }
+
         st->rounds += phase_rounds;
         if (phase_rounds > st->max_rounds) st->max_rounds = phase_rounds;
         st->scanned += phase_scanned;
@@ -349,12 +386,26 @@ int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t l
 
     int64_t sum_k = 0;
     for (int64_t b = 0; b < n_b; ++b)
-        if (mate_b[b] >= 0) sum_k += k[b * ldk + mate_b[b]];
+        if (mate_b[b] >= 0) sum_k += cost_of(cs, b, mate_b[b]);
     st->sum_k = sum_k;
 
     free(B_prime); free(pos); free(target); free(active); free(won);
-    free(taken_by); free(proposer);
+    free(taken_by); free(proposer); free(group_max);
     return status;
+}
+
+int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t ldk,
+                           int64_t T, int32_t origin_mode, int64_t max_phases, int32_t warm,
+                           int32_t complete, int32_t *mate_a, int32_t *mate_b,
+                           int32_t *y_a, int32_t *y_b, orc_stats *st,
+                           int64_t *trace, int64_t trace_cap)
+{
+    if (n_b < 0 || n_a < n_b || (n_b > 0 && (!k || ldk < n_a)) || !mate_a || !mate_b ||
+        !y_a || !y_b || !st)
+        return ORC_E_ARG;
+    costs_t cs = {k, ldk, NULL, NULL};
+    return phase_loop(&cs, n_b, n_a, 0, T, origin_mode, max_phases, warm, complete, mate_a,
+                      mate_b, y_a, y_b, st, trace, trace_cap);
 }
 
 int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
@@ -365,4 +416,154 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
 {
     return orc_solve_rounded_rect(k, n, n, ldk, T, origin_mode, max_phases, warm, complete,
                                   mate_a, mate_b, y_a, y_b, st, trace, trace_cap);
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 4: optimal transport through copies.                        */
+/* ------------------------------------------------------------------ */
+
+int orc_ot_scale(const double *nu, int64_t n_b, const double *mu, int64_t n_a, double eps,
+                 int64_t *s, int64_t *d, double *theta, int64_t *copies_b, int64_t *copies_a)
+{
+    if (!nu || !mu || n_b < 1 || n_a < 1 || !theta || !copies_b || !copies_a)
+        return ORC_E_ARG;
+    if (!eps_ok(eps)) return ORC_E_EPS;
+    /* the masses are probability vectors */
+    double sb = 0.0, sa = 0.0;
+    for (int64_t b = 0; b < n_b; ++b) {
+        if (!(nu[b] >= 0.0 && nu[b] <= 1.0)) return ORC_E_RANGE;
+        sb += nu[b];
+    }
+    for (int64_t a = 0; a < n_a; ++a) {
+        if (!(mu[a] >= 0.0 && mu[a] <= 1.0)) return ORC_E_RANGE;
+        sa += mu[a];
+    }
+    if (fabs(sb - 1.0) > 1e-9 || fabs(sa - 1.0) > 1e-9) return ORC_E_RANGE;
+    /* theta = 4n / eps; supplies rounded down, demands rounded up */
+    const int64_t n = n_b > n_a ? n_b : n_a;
+    const double th = 4.0 * (double)n / eps;
+    int64_t cb = 0, ca = 0;
+    for (int64_t b = 0; b < n_b; ++b) {
+        int64_t v = (int64_t)floor(th * nu[b]);
+        if (s) s[b] = v;
+        cb += v;
+    }
+    for (int64_t a = 0; a < n_a; ++a) {
+        int64_t v = (int64_t)ceil(th * mu[a]);
+        if (d) d[a] = v;
+        ca += v;
+    }
+    if (cb > ca || ca > INT32_MAX) return ORC_E_ARG;
+    *theta = th;
+    *copies_b = cb;
+    *copies_a = ca;
+    return ORC_OK;
+}
+
+int orc_ot_solve(const float *C, int64_t n_b, int64_t n_a, int64_t ldc, const double *nu,
+                 const double *mu, double eps, int32_t origin_mode, int64_t max_phases,
+                 int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,
+                 double *plan, orc_stats *st, double *info, int64_t *trace, int64_t trace_cap)
+{
+    if (!C || ldc < n_a || !mate_a || !mate_b || !y_a || !y_b || !plan || !st || !info)
+        return ORC_E_ARG;
+    double theta = 0.0;
+    int64_t NB = 0, NA = 0;
+    int64_t *s = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_b > 0 ? n_b : 1));
+    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_a > 0 ? n_a : 1));
+    if (!s || !d) {
+        free(s); free(d);
+        return ORC_E_NOMEM;
+    }
+    int rc = orc_ot_scale(nu, n_b, mu, n_a, eps, s, d, &theta, &NB, &NA);
+    if (rc) {
+        free(s); free(d);
+        return rc;
+    }
+    /* the copies: supply point b owns rows [sum_{b'<b} s_b', ...), demand
+     * point a owns columns [sum_{a'<a} d_a', ...) */
+    int32_t *row_pt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(NB > 0 ? NB : 1));
+    int32_t *col_pt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(NA > 0 ? NA : 1));
+    int16_t *k = (int16_t *)malloc(sizeof(int16_t) * (size_t)(n_b * n_a));
+    int64_t *cnt = (int64_t *)calloc((size_t)(n_b * n_a), sizeof(int64_t));
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n_b + 1));
+    double *q = (double *)malloc(sizeof(double) * (size_t)(n_a + 1));
+    if (!row_pt || !col_pt || !k || !cnt || !r || !q) {
+        rc = ORC_E_NOMEM;
+        goto out;
+    }
+    for (int64_t b = 0, i = 0; b < n_b; ++b)
+        for (int64_t c = 0; c < s[b]; ++c) row_pt[i++] = (int32_t)b;
+    for (int64_t a = 0, i = 0; a < n_a; ++a)
+        for (int64_t c = 0; c < d[a]; ++c) col_pt[i++] = (int32_t)a;
+
+    /* eq. (1) on the points' costs; every copy inherits its point's row */
+    rc = orc_round_cost(C, n_b, n_a, ldc, eps, k, n_a);
+    if (rc) goto out;
+
+    /* the unbalanced matching of the copies (Section 3.3) with the free-copy
+     * raise of Section 4; stop at |B'| <= eps |B copies| */
+    const int64_t T = (int64_t)floor(eps * (double)NB + 1e-9);
+    costs_t cs = {k, n_a, row_pt, col_pt};
+    rc = phase_loop(&cs, NB, NA, n_b, T, origin_mode, max_phases, warm, 1, mate_a, mate_b,
+                    y_a, y_b, st, trace, trace_cap);
+    info[0] = theta;
+    info[1] = 0.0;
+    info[2] = 0.0;
+    info[3] = (double)T;
+    if (rc != ORC_OK) goto out;
+
+    /* The plan: every matched pair of copies carries 1/theta. */
+    for (int64_t b = 0; b < NB; ++b)
+        if (mate_b[b] >= 0) cnt[row_pt[b] * n_a + col_pt[mate_b[b]]] += 1;
+    for (int64_t i = 0; i < n_b * n_a; ++i) plan[i] = (double)cnt[i] / theta;
+
+    /* Feasibility repair (the paper leaves it implicit). A demand point that
+     * received more than mu_a (its copies were rounded up) gives the excess
+     * back, taken from its edges in ascending b. */
+    for (int64_t a = 0; a < n_a; ++a) {
+        int64_t c_a = 0;
+        for (int64_t b = 0; b < n_b; ++b) c_a += cnt[b * n_a + a];
+        double ex = (double)c_a / theta - mu[a];
+        for (int64_t b = 0; b < n_b && ex > 0.0; ++b) {
+            double v = plan[b * n_a + a];
+            if (v <= 0.0) continue;
+            double take = v < ex ? v : ex;
+            plan[b * n_a + a] = v - take;
+            ex = ex - take;
+        }
+    }
+    /* What each supply point still has to send, and the room each demand
+     * point has left ... */
+    r[0] = 0.0;
+    for (int64_t b = 0; b < n_b; ++b) {
+        double sent = 0.0;
+        for (int64_t a = 0; a < n_a; ++a) sent += plan[b * n_a + a];
+        double left = nu[b] - sent;
+        r[b + 1] = r[b] + (left > 0.0 ? left : 0.0);
+    }
+    q[0] = 0.0;
+    for (int64_t a = 0; a < n_a; ++a) {
+        double got = 0.0;
+        for (int64_t b = 0; b < n_b; ++b) got += plan[b * n_a + a];
+        double room = mu[a] - got;
+        q[a + 1] = q[a] + (room > 0.0 ? room : 0.0);
+    }
+    /* ... are paired in order (north-west corner rule): supply b's share
+     * [r_b, r_{b+1}) of the running total meets demand a's [q_a, q_{a+1}). */
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) {
+            double lo = r[b] > q[a] ? r[b] : q[a];
+            double hi = r[b + 1] < q[a + 1] ? r[b + 1] : q[a + 1];
+            if (hi > lo) plan[b * n_a + a] += hi - lo;
+        }
+    double cost = 0.0;
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) cost += plan[b * n_a + a] * (double)C[b * ldc + a];
+    info[1] = cost;
+    info[2] = r[n_b];
+
+out:
+    free(s); free(d); free(row_pt); free(col_pt); free(k); free(cnt); free(r); free(q);
+    return rc;
 }

@@ -100,6 +100,37 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
                       int32_t *y_a, int32_t *y_b, orc_stats *st,
                       int64_t *trace, int64_t trace_cap);
 
+/* Section 4, scaling: theta = 4 max(n_b, n_a) / eps; supply point b becomes
+ * s_b = floor(theta nu_b) unit copies, demand point a d_a = ceil(theta mu_a)
+ * (binary64 products). nu and mu are probability vectors (entries in [0, 1],
+ * sums within 1e-9 of 1). s and d are optional outputs. */
+int orc_ot_scale(const double *nu, int64_t n_b, const double *mu, int64_t n_a, double eps,
+                 int64_t *s, int64_t *d, double *theta, int64_t *copies_b, int64_t *copies_a);
+
+/* Section 4: an approximate transport plan from supplies nu (rows of C,
+ * n_b points) to demands mu (columns, n_a points), costs C in [0, 1].
+ * The copies (rows: supply copies, point b's copies contiguous and in order
+ * of b; columns likewise) form an unbalanced matching instance whose
+ * rounded cost is eq. (1) of the points' cost. The phase loop runs on it
+ * with T = floor(eps |B copies|) and, after step (III) of every phase, each
+ * free supply copy's dual is raised to the largest dual among the copies of
+ * its point. After the completion every matched pair of copies carries
+ * 1/theta from its supply point to its demand point; then (feasibility
+ * repair) a demand point holding more than mu_a gives the excess back, taken
+ * from its edges in ascending b, and the mass still to be sent (what the
+ * rounding down of the supplies kept back, plus the excess) is paired with
+ * the room left at the demand points in order of index (north-west corner
+ * rule on the running totals).
+ *   mate_a, y_a : copies_a entries; mate_b, y_b: copies_b entries (copy level)
+ *   plan        : n_b x n_a, row-major (written when the loop finished)
+ *   info        : theta, plan cost sum plan * C, mass moved by the repair, T
+ * max_phases and warm as for the phase loop (warm resumes from the copy-level
+ * arrays); the plan is written only when the loop finished (ORC_OK). */
+int orc_ot_solve(const float *C, int64_t n_b, int64_t n_a, int64_t ldc, const double *nu,
+                 const double *mu, double eps, int32_t origin_mode, int64_t max_phases,
+                 int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,
+                 double *plan, orc_stats *st, double *info, int64_t *trace, int64_t trace_cap);
+
 #ifdef __cplusplus
 }
 #endif

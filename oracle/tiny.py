@@ -81,3 +81,84 @@ def solve(k, T: int, origin: str = "diag"):
         mate_of_a[a] = b
     mate_b = [mate_of_b.get(b, -1) for b in range(n)]
     return mate_b, y_a, y_b, phases, rounds
+
+
+def solve_copies(kp, s, d, T: int, origin: str = "diag"):
+    """Section 4 on small inputs: supply point p becomes s[p] unit copies and
+    demand point q d[q] copies (in point order); a copy's rounded cost is its
+    points' kp[p][q]. Phases as in `solve` on the copies, and after each
+    phase every free supply copy takes the largest dual among its point's
+    copies. Returns (mate_b, y_a, y_b, phases, rounds) at copy level, with the
+    completion applied and the duals from before it."""
+    owner_b = [p for p, c in enumerate(s) for _ in range(c)]
+    owner_a = [q for q, c in enumerate(d) for _ in range(c)]
+    nb, na = len(owner_b), len(owner_a)
+    y_a = [0] * na
+    y_b = [1] * nb
+    mate_of_b: dict[int, int] = {}
+    mate_of_a: dict[int, int] = {}
+    phases = rounds = 0
+
+    def cost(b, a):
+        return kp[owner_b[b]][owner_a[a]]
+
+    def column(b, j):
+        return (b + j) % na if origin == "diag" else j
+
+    while True:
+        free_b = [b for b in range(nb) if b not in mate_of_b]
+        if len(free_b) <= T:
+            break
+        phases += 1
+        taken: dict[int, int] = {}
+        cursor = {b: 0 for b in free_b}
+        looking = set(free_b)
+        while True:
+            offers: dict[int, list[int]] = {}
+            for b in sorted(looking):
+                hit = None
+                for j in range(cursor[b], na):
+                    a = column(b, j)
+                    if a not in taken and cost(b, a) + 1 == y_a[a] + y_b[b]:
+                        hit = j
+                        break
+                if hit is None:
+                    looking.discard(b)
+                else:
+                    cursor[b] = hit
+                    offers.setdefault(column(b, hit), []).append(b)
+            if not offers:
+                break
+            rounds += 1
+            for a, bs in offers.items():
+                w = min(bs)
+                taken[a] = w
+                looking.discard(w)
+                for b in bs:
+                    if b != w:
+                        cursor[b] += 1
+        for a, b in taken.items():
+            old = mate_of_a.get(a)
+            if old is not None:
+                del mate_of_b[old]
+            mate_of_a[a] = b
+            mate_of_b[b] = a
+            y_a[a] -= 1
+        winners = set(taken.values())
+        for b in free_b:
+            if b not in winners:
+                y_b[b] += 1
+        top: dict[int, int] = {}
+        for b in range(nb):
+            top[owner_b[b]] = max(top.get(owner_b[b], y_b[b]), y_b[b])
+        for b in range(nb):
+            if b not in mate_of_b:
+                y_b[b] = top[owner_b[b]]
+
+    free_b = [b for b in range(nb) if b not in mate_of_b]
+    free_a = [a for a in range(na) if a not in mate_of_a]
+    for b, a in zip(free_b, free_a):
+        mate_of_b[b] = a
+        mate_of_a[a] = b
+    mate_b = [mate_of_b.get(b, -1) for b in range(nb)]
+    return mate_b, y_a, y_b, phases, rounds
