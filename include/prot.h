@@ -212,6 +212,50 @@ typedef struct {
     double cost_scale;         /* m, the instance's max squared distance */
 } prot_instance_stats;
 
+/* Optimal transport (Section 4). The supplies nu (n_b points, the rows of
+ * C) and demands mu (n_a points, the columns) are probability vectors;
+ * C (row-major, ldc >= n_a) holds costs in [0, 1].
+ *   1. Scaling: theta = 4 max(n_b, n_a) / eps_internal; supply point b
+ *      becomes floor(theta nu_b) unit copies, demand point a
+ *      ceil(theta mu_a) (binary64 products); copies of a point are
+ *      contiguous, in point order.
+ *   2. The phase loop of Section 2.2 on the unbalanced instance of copies
+ *      (rows: supply copies, columns: demand copies; a copy's rounded cost is
+ *      eq. (1) of its points' cost), stopping at |B'| <= floor(eps_internal x
+ *      supply copies), with the invariant of Section 4: after every phase
+ *      each free supply copy's dual is raised to the largest dual among the
+ *      copies of its point. The completion then matches every supply copy.
+ *   3. The plan: 1/theta per matched pair of copies, made feasible by a
+ *      repair the paper leaves implicit: a demand point holding more than
+ *      mu_a (its copies were rounded up) returns the excess, taken from its
+ *      edges in ascending b; the mass still to be sent is then paired with
+ *      the room left at the demand points in index order (north-west corner
+ *      rule on the running totals). The result sends exactly nu_b from each
+ *      b (to rounding) and at most mu_a into each a; its cost is within
+ *      3 eps + eps/2 of the optimal transport cost (ALGORITHMIC eps).
+ * Outputs (device memory owned by the caller): plan, n_b x ldp binary64
+ * (written only when the call returns PROT_OK); the duals in the
+ * two-cluster form of Lemma 4.1: for each point the smaller dual of its
+ * copies (units of eps_internal) and how many copies hold it, the others
+ * holding that value + 1 (points without copies: 0 and 0). Errors:
+ * PROT_E_RANGE for masses that are not probability vectors or costs outside
+ * [0, 1]; PROT_E_UNSUPPORTED when the demand copies exceed the column-dual
+ * capacity of one workgroup's LDS (about 81,000: theta + n_a must fit).
+ * opts: eps_mode, origin_mode and max_phases apply (no_completion is
+ * ignored); with PROT_PARTIAL the plan is not valid. */
+typedef struct {
+    double theta;              /* 4 max(n_b, n_a) / eps_internal */
+    int64_t copies_b;          /* sum floor(theta nu_b) */
+    int64_t copies_a;          /* sum ceil(theta mu_a) */
+    double repaired_mass;      /* mass moved by the feasibility repair (<= eps/2) */
+    prot_stats loop;           /* the phase loop on the copies; loop.cost is the plan's cost */
+} prot_ot_stats;
+
+int prot_ot_solve(prot_ctx *ctx, const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                  const double *nu, const double *mu, double eps, const prot_opts *opts,
+                  double *plan, int64_t ldp, int32_t *y_b_lo, int32_t *y_b_nlo,
+                  int32_t *y_a_lo, int32_t *y_a_nlo, prot_ot_stats *stats);
+
 typedef struct prot_batch prot_batch;
 
 /* Largest n of one instance in a batch. */

@@ -14,7 +14,7 @@ GPU works; any solver call then needs the built library and a GPU.
 """
 from __future__ import annotations
 
-from ._lib import (Context, ProtError, Result, context, load, pitch,  # noqa: F401
+from ._lib import (Context, OTResult, ProtError, Result, context, load, pitch,  # noqa: F401
                    threshold, EXPORTS)
 
 

@@ -48,6 +48,17 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class OTStats(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("copies_b", ctypes.c_int64),
+                ("copies_a", ctypes.c_int64), ("repaired_mass", ctypes.c_double),
+                ("loop", Stats)]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_[:4]}
+        d.update(self.loop.as_dict())
+        return d
+
+
 class InstanceStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "phases", "sum_free", "rounds", "max_rounds", "scanned", "matched_in_phases",
@@ -75,7 +86,7 @@ EXPORTS = [
     "prot_threshold", "prot_max_n", "prot_round_costs", "prot_build_costs",
     "prot_solve_rounded", "prot_solve_cost", "prot_solve_points",
     "prot_round_costs_rect", "prot_build_costs_rect", "prot_solve_rounded_rect",
-    "prot_solve_cost_rect", "prot_solve_points_rect", "prot_get_trace",
+    "prot_solve_cost_rect", "prot_solve_points_rect", "prot_ot_solve", "prot_get_trace",
     "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
     "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
     "prot_batch_loss_fwd", "prot_batch_loss_bwd",
@@ -121,6 +132,8 @@ def load():
         "prot_solve_points_rect": (ctypes.c_int, [p, p, i64, p, i64, i32, f64,
                                                   ctypes.POINTER(Opts), p, p, p, p,
                                                   ctypes.POINTER(Stats)]),
+        "prot_ot_solve": (ctypes.c_int, [p, p, i64, i64, i64, p, p, f64, ctypes.POINTER(Opts),
+                                         p, i64, p, p, p, p, ctypes.POINTER(OTStats)]),
         "prot_get_trace": (i64, [p, p, i64]),
         "prot_get_round_times": (i64, [p, p, i64]),
         "prot_batch_max_n": (i32, []),
@@ -159,6 +172,19 @@ class Result:
     mate_b: object
     y_a: object
     y_b: object
+    status: str
+    stats: dict = field(default_factory=dict)
+
+
+@dataclass
+class OTResult:
+    """plan: n_b x n_a float64; duals in the two-cluster form of Lemma 4.1:
+    per point the smaller dual of its copies and how many copies hold it."""
+    plan: object
+    y_b_lo: object
+    y_b_nlo: object
+    y_a_lo: object
+    y_a_nlo: object
     status: str
     stats: dict = field(default_factory=dict)
 
@@ -352,6 +378,39 @@ class Context:
             _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
             _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)))
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
+
+    def ot_solve(self, C, nu, mu, eps: float, *, eps_mode="algorithmic", origin="diag",
+                 max_phases=0, plan=None) -> OTResult:
+        """Optimal transport (Section 4) from supplies nu (rows of C) to
+        demands mu (columns): C n_b x n_a float32 in [0, 1], nu and mu float64
+        probability vectors, all on the device."""
+        torch = _torch()
+        if C.dim() != 2 or C.stride(1) != 1:
+            raise ValueError("C must be a row-major n_b x n_a float32 matrix")
+        n_b, n_a = C.shape
+        if nu.shape != (n_b,) or mu.shape != (n_a,):
+            raise ValueError("nu must have n_b entries and mu n_a")
+        nu, mu = nu.contiguous(), mu.contiguous()  # kept alive across the call
+        dev = f"cuda:{self.device}"
+        if plan is None:
+            plan = torch.empty((n_b, n_a), dtype=torch.float64, device=dev)
+        if plan.shape != (n_b, n_a) or plan.stride(1) != 1:
+            raise ValueError("plan must be a row-major n_b x n_a float64 matrix")
+        kw = dict(dtype=torch.int32, device=dev)
+        yb, nb_, ya, na_ = (torch.empty(n_b, **kw), torch.empty(n_b, **kw),
+                            torch.empty(n_a, **kw), torch.empty(n_a, **kw))
+        st = OTStats()
+        o = self._opts(eps_mode, origin, True, max_phases)
+        self._bind_stream()
+        rc = self._check(self._lib.prot_ot_solve(
+            self._h, _dev_ptr(C, torch.float32, "C", 2), n_b, n_a, C.stride(0),
+            _dev_ptr(nu, torch.float64, "nu", 1), _dev_ptr(mu, torch.float64, "mu", 1),
+            float(eps), ctypes.byref(o),
+            _dev_ptr(plan, torch.float64, "plan", 2), plan.stride(0),
+            _dev_ptr(yb, torch.int32, "y_b_lo"), _dev_ptr(nb_, torch.int32, "y_b_nlo"),
+            _dev_ptr(ya, torch.int32, "y_a_lo"), _dev_ptr(na_, torch.int32, "y_a_nlo"),
+            ctypes.byref(st)))
+        return OTResult(plan, yb, nb_, ya, na_, STATUS_NAMES[rc], st.as_dict())
 
     def round_times(self, cap: int = 65536):
         """(rounds, 3) int64: barrier arrival of the last workgroup, barrier

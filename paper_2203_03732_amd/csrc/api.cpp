@@ -50,6 +50,7 @@ struct prot_ctx {
         Ctl ctl;
         long long part_k[prot::kFinalizeBlocks];
         double part_c[prot::kFinalizeBlocks];
+        prot::OtInfo ot;
     } *stage = nullptr;              // pinned host memory
 
     int64_t *rtime = nullptr;        // round timer (PROT_DEBUG_ROUND_TIMES=1)
@@ -61,6 +62,16 @@ struct prot_ctx {
     int wgs_per_cu = 1;              // PROT_LOOP_WGS_PER_CU (diagnostics)
     int grid_npad = -1;
     int grid_max = 0;
+    // optimal transport through copies (prot_ot_solve)
+    struct Ot {
+        int64_t cap_b = 0, cap_a = 0, cap_cb = 0, cap_ca = 0, cap_cells = 0;
+        int64_t *s_off = nullptr, *d_off = nullptr;
+        int32_t *row_pt = nullptr, *col_pt = nullptr, *cnt = nullptr;
+        unsigned long long *ymax = nullptr;
+        int32_t *mate_a = nullptr, *mate_b = nullptr, *y_a = nullptr, *y_b = nullptr;
+        double *rv = nullptr, *qv = nullptr, *R = nullptr, *Q = nullptr;
+        prot::OtInfo *info = nullptr;
+    } ot;
     // 0 build start, 1 build end, 2 loop start, 3 loop end, 4 all done
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
@@ -302,9 +313,16 @@ struct OnTheFly {
 };
 
 // n rows (B), n_a >= n columns (A).
+// Copies of the transport reduction: row b reads cost row rmap[b]; ymax holds
+// the largest dual of each point's copies.
+struct Copies {
+    const int32_t *rmap = nullptr;
+    unsigned long long *ymax = nullptr;
+};
+
 int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk, int64_t T,
              const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
-             int32_t *y_b, const OnTheFly &otf = OnTheFly())
+             int32_t *y_b, const OnTheFly &otf = OnTheFly(), const Copies &cp = Copies())
 {
     int rc = ensure_loop(c, n_a);
     if (rc) return rc;
@@ -312,6 +330,8 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
     if ((rc = grid_for(c, n, n_a, &grid))) return rc;
     prot::LoopArgs a = loop_args(c, k, n, n_a, ldk, T, o, y_b);
     a.groups = std::min(c->loop_groups, grid);
+    a.rmap = cp.rmap;
+    a.ymax = cp.ymax;
     if (otf.d) {
         a.pd = otf.d;
         a.px = otf.X;
@@ -394,7 +414,8 @@ void fill_match_counts(prot_ctx *c, int64_t n, prot_stats *st, const prot_opts *
     if (!st) return;
     const int64_t free_after = c->stage->ctl.free_after;
     st->matched_in_phases = n - free_after;
-    st->completed_pairs = (o && o->no_completion) ? 0 : free_after;
+    st->completed_pairs =
+        ((o && o->no_completion) || st->status == PROT_PARTIAL) ? 0 : free_after;
 }
 
 // |B| = 0 with |A| > 0: nothing to match; a cold start still hands back the
@@ -717,6 +738,12 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->th);
     (void)hipFree(c->rtime);
     (void)hipFree(c->mfma_buf);
+    for (void *p : {(void *)c->ot.s_off, (void *)c->ot.d_off, (void *)c->ot.row_pt,
+                    (void *)c->ot.col_pt, (void *)c->ot.ymax, (void *)c->ot.cnt,
+                    (void *)c->ot.mate_a, (void *)c->ot.mate_b, (void *)c->ot.y_a,
+                    (void *)c->ot.y_b, (void *)c->ot.rv, (void *)c->ot.qv, (void *)c->ot.R,
+                    (void *)c->ot.Q, (void *)c->ot.info})
+        (void)hipFree(p);
     if (c->stage) (void)hipHostFree(c->stage);
     for (int i = 0; i < 5; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -969,6 +996,143 @@ int prot_solve_points(prot_ctx *c, const float *X, const float *Y, int64_t n, in
     return prot_solve_points_rect(c, X, n, Y, n, d, eps, o, mate_a, mate_b, y_a, y_b, st);
 }
 
+
+namespace {
+
+int ensure_ot(prot_ctx *c, int64_t n_b, int64_t n_a, int64_t cb, int64_t ca)
+{
+    prot_ctx::Ot &w = c->ot;
+    int rc = PROT_OK;
+    if (!w.info && (rc = dev_alloc(c, &w.info, 1))) return rc;
+    if (n_b > w.cap_b) {
+        if ((rc = dev_alloc(c, &w.s_off, (size_t)n_b + 1)) ||
+            (rc = dev_alloc(c, &w.ymax, (size_t)n_b)) || (rc = dev_alloc(c, &w.rv, (size_t)n_b)) ||
+            (rc = dev_alloc(c, &w.R, (size_t)n_b + 1)))
+            return rc;
+        w.cap_b = n_b;
+    }
+    if (n_a > w.cap_a) {
+        if ((rc = dev_alloc(c, &w.d_off, (size_t)n_a + 1)) ||
+            (rc = dev_alloc(c, &w.qv, (size_t)n_a)) || (rc = dev_alloc(c, &w.Q, (size_t)n_a + 1)))
+            return rc;
+        w.cap_a = n_a;
+    }
+    if (n_b * n_a > w.cap_cells) {
+        if ((rc = dev_alloc(c, &w.cnt, (size_t)(n_b * n_a)))) return rc;
+        w.cap_cells = n_b * n_a;
+    }
+    if (cb > w.cap_cb) {
+        if ((rc = dev_alloc(c, &w.row_pt, (size_t)cb)) || (rc = dev_alloc(c, &w.mate_b, (size_t)cb)) ||
+            (rc = dev_alloc(c, &w.y_b, (size_t)cb)))
+            return rc;
+        w.cap_cb = cb;
+    }
+    if (ca > w.cap_ca) {
+        if ((rc = dev_alloc(c, &w.col_pt, (size_t)ca)) || (rc = dev_alloc(c, &w.mate_a, (size_t)ca)) ||
+            (rc = dev_alloc(c, &w.y_a, (size_t)ca)))
+            return rc;
+        w.cap_ca = ca;
+    }
+    return PROT_OK;
+}
+
+}  // namespace
+
+int prot_ot_solve(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                  const double *nu, const double *mu, double eps, const prot_opts *o,
+                  double *plan, int64_t ldp, int32_t *y_b_lo, int32_t *y_b_nlo, int32_t *y_a_lo,
+                  int32_t *y_a_nlo, prot_ot_stats *st)
+{
+    if (!c) return PROT_E_ARG;
+    if (n_b < 1 || n_a < 1 || !C || ldc < n_a || !nu || !mu || !plan || ldp < n_a || !y_b_lo ||
+        !y_b_nlo || !y_a_lo || !y_a_nlo)
+        return fail(c, PROT_E_ARG, "prot_ot_solve: bad pointer or size");
+    if (n_b > INT32_MAX / 4 || n_a > INT32_MAX / 4)
+        return fail(c, PROT_E_UNSUPPORTED, "too many points");
+    const double ei = eps_internal(eps, o);
+    if (!eps_valid(ei)) return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    prot_ot_stats local;
+    if (!st) st = &local;
+    std::memset(st, 0, sizeof(*st));
+    HIP_TRY(c, hipSetDevice(c->device));
+    // Section 4: theta = 4n / eps, supplies down, demands up, unit copies
+    const double theta = 4.0 * (double)std::max(n_b, n_a) / ei;
+    int rc = ensure_ot(c, n_b, n_a, 0, 0);
+    if (rc) return rc;
+    prot_ctx::Ot &w = c->ot;
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    HIP_TRY(c, prot::launch_ot_scale(nu, n_b, mu, n_a, theta, w.s_off, w.d_off, w.info,
+                                     c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ot, w.info, sizeof(prot::OtInfo),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const prot::OtInfo info = c->stage->ot;
+    if (info.err & 1)
+        return fail(c, PROT_E_RANGE, "nu and mu must be probability vectors (entries in [0,1], "
+                                     "sums within 1e-9 of 1)");
+    if (info.err & 2) return fail(c, PROT_E_UNSUPPORTED, "too many copies");
+    const int64_t NB = info.copies_b, NA = info.copies_a;
+    st->theta = theta;
+    st->copies_b = NB;
+    st->copies_a = NA;
+    int grid = 0;
+    if ((rc = grid_for(c, NB, NA, &grid))) return rc;
+    if ((rc = ensure_ot(c, n_b, n_a, NB, NA))) return rc;
+    if ((rc = ensure_matrix(c, n_b, NA))) return rc;
+    const int64_t ldk = prot_pitch(NA);
+    HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
+    HIP_TRY(c, prot::launch_ot_prepare(C, n_b, n_a, ldc, ei, w.s_off, NB, w.d_off, NA, w.row_pt,
+                                       w.col_pt, c->kmat, ldk, w.ymax, c->ctl, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    const int64_t T = prot_threshold(ei, NB);
+    prot_opts lo{};
+    if (o) lo = *o;
+    lo.no_completion = 0;
+    Copies cp;
+    cp.rmap = w.row_pt;
+    cp.ymax = w.ymax;
+    rc = run_loop(c, c->kmat, NB, NA, ldk, T, &lo, 0, w.mate_a, w.mate_b, w.y_a, w.y_b,
+                  OnTheFly(), cp);
+    if (rc) return rc;
+    prot::OtPlanArgs pa{};
+    pa.mate_b = w.mate_b;
+    pa.row_pt = w.row_pt;
+    pa.col_pt = w.col_pt;
+    pa.NB = NB;
+    pa.k = c->kmat;
+    pa.ldk = ldk;
+    pa.cnt = w.cnt;
+    pa.n_b = n_b;
+    pa.n_a = n_a;
+    pa.theta = theta;
+    pa.nu = nu;
+    pa.mu = mu;
+    pa.C = C;
+    pa.ldc = ldc;
+    pa.plan = plan;
+    pa.ldp = ldp;
+    pa.rv = w.rv;
+    pa.qv = w.qv;
+    pa.R = w.R;
+    pa.Q = w.Q;
+    pa.part_k = c->part_k;
+    pa.part_c = c->part_c;
+    pa.info = w.info;
+    HIP_TRY(c, prot::launch_ot_plan(pa, c->stream));
+    HIP_TRY(c, prot::launch_ot_duals(w.y_b, w.s_off, n_b, y_b_lo, y_b_nlo, c->ctl, c->stream));
+    HIP_TRY(c, prot::launch_ot_duals(w.y_a, w.d_off, n_a, y_a_lo, y_a_nlo, c->ctl, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ot, w.info, sizeof(prot::OtInfo),
+                              hipMemcpyDeviceToHost, c->stream));
+    rc = collect(c, &st->loop, T, ei, 1, true);  // synchronises the stream
+    if (rc) return rc;
+    fill_match_counts(c, NB, &st->loop, &lo);
+    st->repaired_mass = c->stage->ot.repaired;
+    if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a cost is NaN or outside [0,1]");
+    if (c->stage->ctl.err & 16)
+        return fail(c, PROT_E_HIP, "internal: the copies of a point hold more than two duals");
+    return st->loop.status;
+}
 
 int32_t prot_batch_max_n(void) { return prot::batch_max_n(); }
 

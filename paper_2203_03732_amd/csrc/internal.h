@@ -79,6 +79,16 @@ struct LoopArgs {
     const float *pm;          // device: max squared distance
     const float *pth;         // device: threshold table th[0..K+1]
     double peps;
+    // Copies of the transport reduction (null: off). Row b reads the cost row
+    // rmap[b] (the supply point it copies). A free row's dual is raised to the
+    // largest dual of its point's copies when the row enters a phase and when
+    // the loop ends; ymax[p] = ((q + 1) << 32) | m holds that largest dual m
+    // as it was after phase q, the last phase in which one of p's copies
+    // found no column (initially (0 << 32) | 1). Every copy in B' was raised,
+    // so all that phase's copies of p end at the same m; a reader in phase q
+    // itself takes m - 1.
+    const int32_t *rmap;
+    unsigned long long *ymax;
 };
 
 // Per-instance results of the batched solver (layout of prot_instance_stats).
@@ -186,5 +196,45 @@ hipError_t launch_finalize(int64_t n, const int32_t *mate_b, const int16_t *k,
                            long long *part_k, double *part_c, hipStream_t s,
                            const float *m_dev = nullptr, double eps = 0.0,
                            const float *th = nullptr);
+
+// Optimal transport through copies (Section 4).
+struct OtInfo {
+    long long copies_b, copies_a;  // sum floor(theta nu_b), sum ceil(theta mu_a)
+    int32_t err;                   // 1: masses not probability vectors; 2: too many copies
+    int32_t pad;
+    double repaired;               // mass moved by the feasibility repair
+};
+
+struct OtPlanArgs {
+    const int32_t *mate_b;         // copy level, NB entries
+    const int32_t *row_pt, *col_pt;
+    int64_t NB;
+    const int16_t *k;              // expanded rounded costs, n_b x ldk
+    int64_t ldk;
+    int32_t *cnt;                  // n_b x n_a pair counts
+    int64_t n_b, n_a;
+    double theta;
+    const double *nu, *mu;
+    const float *C;
+    int64_t ldc;
+    double *plan;
+    int64_t ldp;
+    double *rv, *qv;               // left to send (n_b), room left (n_a)
+    double *R, *Q;                 // their running totals (n_b + 1, n_a + 1)
+    long long *part_k;
+    double *part_c;
+    OtInfo *info;
+};
+
+hipError_t launch_ot_scale(const double *nu, int64_t n_b, const double *mu, int64_t n_a,
+                           double theta, int64_t *s_off, int64_t *d_off, OtInfo *info,
+                           hipStream_t s);
+hipError_t launch_ot_prepare(const float *C, int64_t n_b, int64_t n_a, int64_t ldc, double eps,
+                             const int64_t *s_off, int64_t NB, const int64_t *d_off, int64_t NA,
+                             int32_t *row_pt, int32_t *col_pt, int16_t *k, int64_t ldk,
+                             unsigned long long *ymax, Ctl *ctl, hipStream_t s);
+hipError_t launch_ot_plan(const OtPlanArgs &a, hipStream_t s);
+hipError_t launch_ot_duals(const int32_t *y, const int64_t *off, int64_t n_pts, int32_t *lo,
+                           int32_t *nlo, Ctl *ctl, hipStream_t s);
 
 }  // namespace prot

@@ -116,6 +116,24 @@ __device__ inline uint32_t wave_exclusive_scan(uint32_t v, int lane)
     return x - v;
 }
 
+// The largest dual among a point's copies (the transport reduction), tagged
+// with the phase that set it: a device-scope atomic max, complete before the
+// workgroup's arrival like the y(b) store it follows.
+__device__ inline void raise_top(unsigned long long *p, int64_t phase, int32_t v)
+{
+    const unsigned long long w = ((unsigned long long)(phase + 1) << 32) | (uint32_t)v;
+    __hip_atomic_fetch_max(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The largest dual of a point's copies after the previous phase, read in
+// phase `phase` (a copy that found nothing in this phase already moved the
+// word to this phase's value, one more).
+__device__ inline int32_t top_before(unsigned long long w, int64_t phase)
+{
+    const int32_t m = (int32_t)(uint32_t)w;
+    return (int64_t)(w >> 32) == phase + 1 ? m - 1 : m;
+}
+
 __device__ inline unsigned long long tagged(uint32_t tag, int32_t v)
 {
     return ((unsigned long long)tag << 32) | (uint32_t)v;
@@ -158,14 +176,17 @@ __device__ inline Segs segments(int n, int origin, int pos)
 // Where the scan of slot s (held by lane s of the wave) starts this round.
 struct SlotView {
     int b, pos, yb, origin;
+    int rb;         // the row of costs b reads (b, or the point a copy copies)
     Segs S;
     int sg, base;   // first nonempty segment (1 if none) and its first chunk
 };
 
-__device__ inline SlotView slot_view(int s, int s_b, int s_pos, int s_yb, int origin_mode, int n)
+__device__ inline SlotView slot_view(int s, int s_b, int s_pos, int s_yb, int origin_mode, int n,
+                                     int s_rb)
 {
     SlotView v;
     v.b = __builtin_amdgcn_readlane(s_b, s);
+    v.rb = __builtin_amdgcn_readlane(s_rb, s);
     v.pos = __builtin_amdgcn_readlane(s_pos, s);
     v.yb = __builtin_amdgcn_readlane(s_yb, s);
     v.origin = origin_mode == 0 ? v.b : 0;
@@ -482,7 +503,8 @@ struct SrcOf<0> {
 
 // kSrcD: 0 reads the rounded-cost matrix; 2 or 3 computes it from points of
 // that dimension (matrix-free). kFF: exact fast-forward through A.skip.
-template <bool kMulti, int kSrcD, bool kFF>
+// kCopies: the rows are copies of the transport reduction (A.rmap, A.ymax).
+template <bool kMulti, int kSrcD, bool kFF, bool kCopies = false>
 __global__ void __launch_bounds__(kLoopThreads)
 phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32_t *y_base)
 {
@@ -583,7 +605,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             (&s_best[0][0])[threadIdx.x] = kNoHit;
         if (threadIdx.x < kLoopThreads / kWave) s_mn[threadIdx.x] = kNoHit;
         __syncthreads();
-        int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0;
+        int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0, s_rb = 0;
         uint32_t s_skip = 0;
         unsigned long long s_key = 0;
         if ((uint32_t)lane < nslots) {
@@ -591,6 +613,16 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             const int j = group_of(s_fpre, G, e);
             s_b = take_entry(Fc + j * cap + (e - s_fpre[j]), tag0 + (uint32_t)p, n, &ctl->err);
             s_yb = ld_agent(y_b + s_b);
+            if constexpr (kCopies) {
+                // a free copy takes the largest dual of its point's copies
+                // (every y(b) update of the last phase is in ymax by now)
+                s_rb = A.rmap[s_b];
+                const int32_t top = top_before(ld_agent(A.ymax + s_rb), p);
+                if (top > s_yb) {
+                    s_yb = top;
+                    st_agent(y_b + s_b, top);
+                }
+            }
             if (kFF && A.skip) s_skip = ld_agent(A.skip + s_b);
         }
         // rows that cannot find a column this phase are exhausted without a scan
@@ -645,9 +677,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 // the team's first hit is the smallest position found
                 int* best = &s_best[r & 1][team_local];
                 if (active & 1ull) {
-                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, na);
+                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, na,
+                                                 kCopies ? s_rb : s_b);
                     int mn = kNoHit;
-                    const int j = team_scan(src, src.row(v.b), t_lds, na, v.origin, v.S,
+                    const int j = team_scan(src, src.row(v.rb), t_lds, na, v.origin, v.S,
                                             v.yb - 1, k_rank, R, lane, best, track ? &mn : nullptr);
                     if (lane == 0 && j != kNoHit) atomicMin(best, j);
                     if (track) {
@@ -657,7 +690,8 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 }
                 __syncthreads();
                 if (active & 1ull) {
-                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, na);
+                    const SlotView v = slot_view(0, s_b, s_pos, s_yb, A.origin, na,
+                                                 kCopies ? s_rb : s_b);
                     const int j = *best;
                     const int b = v.b, pos = v.pos, yb = v.yb;
                     const bool lead = k_rank == 0;
@@ -685,6 +719,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                             wave_scan += (unsigned long long)(na - pos);
                             if (lane == 0) {
                                 st_agent(y_b + b, yb + 1);
+                                if constexpr (kCopies) raise_top(A.ymax + v.rb, p, yb + 1);
                                 my_f = b;
                                 if (track) {
                                     const int slack = s_mn[team_local] - (yb - 1);
@@ -713,16 +748,18 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     if (!rem) continue;
                     sl[q] = __builtin_ctzll(rem);
                     rem &= rem - 1;
-                    const SlotView v = slot_view(sl[q], s_b, s_pos, s_yb, A.origin, na);
+                    const SlotView v = slot_view(sl[q], s_b, s_pos, s_yb, A.origin, na,
+                                                 kCopies ? s_rb : s_b);
                     const int col0 = v.base + lane * 8;
                     if (col0 < v.S.hi(v.sg))
-                        kvq[q] = src.chunk(src.row(v.b), col0);
+                        kvq[q] = src.chunk(src.row(v.rb), col0);
                 }
 #pragma unroll
                 for (int q = 0; q < SrcOf<kSrcD>::type::kBatch; ++q) {
                     if (sl[q] < 0) continue;
                     const int s = sl[q];
-                    const SlotView v = slot_view(s, s_b, s_pos, s_yb, A.origin, na);
+                    const SlotView v = slot_view(s, s_b, s_pos, s_yb, A.origin, na,
+                                                 kCopies ? s_rb : s_b);
                     const int b = v.b, pos = v.pos, yb = v.yb;
                     const int slo = v.S.lo(v.sg), shi = v.S.hi(v.sg);
                     const int col0 = v.base + lane * 8;
@@ -735,7 +772,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     const int a = chunk_hit(col0, kvq[q], tv, yb - 1, slo, shi);
                     if (a >= 0) h = hit_at(a, v.origin, na);
                     else if (slo < shi)
-                        h = scan_from<kScanAhead>(src, src.row(b), t_lds, na, v.origin, v.S, v.sg,
+                        h = scan_from<kScanAhead>(src, src.row(v.rb), t_lds, na, v.origin, v.S, v.sg,
                                       v.base + kChunk, yb - 1, lane, track ? &mn : nullptr);
                     if (h.j >= 0) {
                         wave_scan += (unsigned long long)(h.j - pos + 1);
@@ -758,6 +795,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         const int slack = track ? wave_min(mn) - (yb - 1) : 0;
                         if (lane == s) {
                             st_agent(y_b + b, yb + 1);
+                            if constexpr (kCopies) raise_top(A.ymax + v.rb, p, yb + 1);
                             my_f = b;
                             if (slack >= 2) st_agent(A.skip + b, (uint32_t)min(slack - 1, 1 << 30));
                         }
@@ -981,15 +1019,27 @@ __device__ int list_flags(const int32_t *mate, int n, int32_t *out, int *cnt)
     return total;
 }
 
+// Copies of the transport reduction: when the loop ends, every free copy
+// takes the largest dual of its point's copies (as after each phase).
+__global__ void raise_free_kernel(LoopArgs a, const int32_t *mate_b)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < a.n; b += gridDim.x * blockDim.x)
+        if (mate_b[b] < 0) {
+            const int32_t top = (int32_t)(uint32_t)a.ymax[a.rmap[b]];
+            if (top > a.y_b[b]) a.y_b[b] = top;
+        }
+}
+
 // Completion (Section 2.1): the i-th free b (ascending) takes the i-th free a.
+// A loop stopped by max_phases is left as it is (a state to resume from).
 __global__ void __launch_bounds__(kCompleteThreads)
 complete_kernel(int n, int n_a, int32_t *mate_a, int32_t *mate_b, int32_t *scratch,
-                int32_t complete)
+                int32_t complete, const Ctl *ctl)
 {
     __shared__ int cnt[kCompleteThreads];
     const int nb = list_flags(mate_b, n, scratch, cnt);
     const int na = list_flags(mate_a, n_a, scratch + n, cnt);
-    if (!complete) return;
+    if (!complete || ctl->status) return;
     const int m = min(nb, na);
     for (int i = threadIdx.x; i < m; i += kCompleteThreads) {
         const int b = scratch[i], a = scratch[n + i];
@@ -1257,10 +1307,11 @@ hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
     int32_t *no_base = nullptr;
     void *args[] = {&copy, &none, &team, &no_base};
     const size_t lds = (size_t)a.n_pad * sizeof(uint16_t);
-    const void *fn = a.pd == 2   ? (const void *)phase_loop_kernel<false, 2, false>
+    const void *fn = a.rmap      ? (const void *)phase_loop_kernel<false, 0, false, true>
+                     : a.pd == 2 ? (const void *)phase_loop_kernel<false, 2, false>
                      : a.pd == 3 ? (const void *)phase_loop_kernel<false, 3, false>
                                  : (const void *)phase_loop_kernel<false, 0, false>;
-    if (a.pd && lds > 64 * 1024) {
+    if ((a.pd || a.rmap) && lds > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);
         if (e != hipSuccess) return e;
@@ -1323,8 +1374,11 @@ hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a, i
                        (int64_t)a.n, -1);
     hipLaunchKernelGGL(decode_kernel, dim3(blocks_for(a.n_a, 256)), dim3(256), 0, s, a, mate_a,
                        mate_b, y_a);
+    if (a.rmap)
+        hipLaunchKernelGGL(raise_free_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a,
+                           mate_b);
     hipLaunchKernelGGL(complete_kernel, dim3(1), dim3(kCompleteThreads), 0, s, a.n, a.n_a,
-                       mate_a, mate_b, scratch, complete);
+                       mate_a, mate_b, scratch, complete, a.ctl);
     return hipGetLastError();
 }
 

@@ -434,3 +434,15 @@ def test_points_maximum_pruning_cases(prune_ctx, case, d):
     assert np.array_equal(host(k)[:, :X.shape[0]], ko)
     gpu = ctx.solve_points(dev(X), dev(Y), 0.05, storage="on_the_fly")
     assert gpu.stats["cost_scale"] == mo
+
+
+def test_max_phases_partial_leaves_state_uncompleted(ctx):
+    """A loop stopped by max_phases is not completed even when completion is
+    asked for: the state stays resumable, as the oracle leaves it."""
+    n, K, T = 300, 20, 3
+    k = synth.random_k(n, K, seed=13)
+    ref = oracle.solve_rounded(k, T, max_phases=2)
+    gpu = ctx.solve_rounded(padded_k(k), T, n, max_phases=2)
+    assert ref["status"] == "partial" and gpu.status == "partial"
+    assert ref["stats"]["completed_pairs"] == 0
+    assert_same(gpu, ref)
