@@ -12,6 +12,10 @@ Workloads (the shapes of the paper's experiments, Section 5):
                   points, as in minibatch optimal transport
   shifted_gaussian_batch  equal-n instances, X ~ N(0, I), Y ~ N(shift, I)
   random_k        small random integer rounded-cost matrices for tests
+  transport_clouds  a transport instance: supply points uniform in the unit
+                  square, demand points uniform in the square shifted by
+                  (shift, 0), squared distances scaled to max 1, and random
+                  masses (uniform in [0.05, 1.05), normalised)
 """
 from __future__ import annotations
 
@@ -54,3 +58,17 @@ def shifted_gaussian_batch(batch: int = 64, n: int = 2048, d: int = 64,
 def random_k(n: int, kmax: int, seed: int = 0, n_a: int | None = None) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.integers(0, kmax + 1, (n, n if n_a is None else n_a)).astype(np.int16)
+
+
+def transport_clouds(n_b: int, n_a: int, seed: int = 0, shift: float = 1.0):
+    """(C, nu, mu): C float32 n_b x n_a in [0, 1], nu and mu float64
+    probability vectors. The costs are input data here (squared distances
+    in binary64, scaled by their maximum, rounded to binary32)."""
+    rng = np.random.default_rng(seed)
+    X = rng.random((n_b, 2))
+    Y = rng.random((n_a, 2)) + np.array([shift, 0.0])
+    C = ((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+    C = (C / C.max()).astype(np.float32)
+    nu = rng.random(n_b) + 0.05
+    mu = rng.random(n_a) + 0.05
+    return C, nu / nu.sum(), mu / mu.sum()

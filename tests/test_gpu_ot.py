@@ -78,14 +78,11 @@ def _compare(gpu, orc, what, plan=True):
 
 
 def _instance(n_b, n_a, seed, zeros=0, points=False, shift=0.0):
-    rng = np.random.default_rng(seed)
     if points:
-        X = rng.random((n_b, 2))
-        Y = rng.random((n_a, 2)) + np.array([shift, 0.0])
-        C = ((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
-        C = (C / C.max()).astype(np.float32)
-    else:
-        C = rng.random((n_b, n_a)).astype(np.float32)
+        from paper_2203_03732_amd import synth
+        return synth.transport_clouds(n_b, n_a, seed=seed, shift=shift)
+    rng = np.random.default_rng(seed)
+    C = rng.random((n_b, n_a)).astype(np.float32)
     return C, _masses(rng, n_b, zeros), _masses(rng, n_a)
 
 
@@ -103,7 +100,7 @@ def test_ot_bit_exact(ctx, n_b, n_a, eps, seed, zeros, origin):
 
 def test_ot_points_shifted_clouds(ctx):
     """Two 1,000-point clouds in the plane, the demand one shifted by 1,
-    random masses, eps = 0.1 (11 phases over ~40,000 copies a side)."""
+    random masses, eps = 0.1 (the transport workload of the benchmark)."""
     C, nu, mu = _instance(1000, 1000, 11, points=True, shift=1.0)
     orc = oracle.ot_solve(C, nu, mu, 0.1)
     gpu = ctx.ot_solve(dev(C), dev(nu), dev(mu), 0.1)
