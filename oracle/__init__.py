@@ -67,12 +67,15 @@ def _load():
                                            p, p, p, p, p, p, i64]
     lib.orc_points_max_f32.argtypes = [p, p, i64, i64, i32, p]
     lib.orc_ot_scale.argtypes = [p, i64, p, i64, f64, p, p, p, p, p]
+    lib.orc_round_points_euclid_f32.argtypes = [p, p, i64, i64, i32, f64, p, i64, p]
+    lib.orc_round_l1_normalized_f32.argtypes = [p, p, i64, i64, i32, f64, p, i64]
     lib.orc_ot_solve.argtypes = [p, i64, i64, i64, p, p, f64, i32, i64, i32, p, p, p, p, p,
                                  p, p, p, i64]
     lib.orc_points_pairs_f32.argtypes = [p, p, i32, f64, ctypes.c_float, p, p, i64, p]
     for fn in (lib.orc_round_cost, lib.orc_round_points_f32,
                lib.orc_points_cost_f64, lib.orc_solve_rounded, lib.orc_solve_rounded_rect,
                lib.orc_points_max_f32, lib.orc_ot_scale, lib.orc_ot_solve,
+               lib.orc_round_points_euclid_f32, lib.orc_round_l1_normalized_f32,
                lib.orc_points_pairs_f32):
         fn.restype = ctypes.c_int
     _lib = lib
@@ -118,6 +121,34 @@ def round_points_f32(X: np.ndarray, Y: np.ndarray, eps: float):
     _check(_load().orc_round_points_f32(_ptr(X), _ptr(Y), nb, na, d, float(eps),
                                         _ptr(k), na, _ptr(m)), "round_points_f32")
     return k, float(m[0])
+
+
+def round_points_euclid_f32(X: np.ndarray, Y: np.ndarray, eps: float):
+    """Plain Euclidean cost (Section 5's synthetic workload): the binary32
+    squared distance and maximum of round_points_f32, cost sqrt(d2 / m) in
+    binary64, eq. (1). Returns (k, m)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    nb, d = X.shape
+    na = Y.shape[0]
+    k = np.empty((nb, na), dtype=np.int16)
+    m = np.zeros(1, dtype=np.float32)
+    _check(_load().orc_round_points_euclid_f32(_ptr(X), _ptr(Y), nb, na, d, float(eps),
+                                               _ptr(k), na, _ptr(m)), "round_points_euclid_f32")
+    return k, float(m[0])
+
+
+def round_l1_normalized_f32(X: np.ndarray, Y: np.ndarray, eps: float) -> np.ndarray:
+    """Section 5's image cost: vectors normalised to sum 1, half their L1
+    distance (binary32, coordinate order), eq. (1)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    nb, d = X.shape
+    na = Y.shape[0]
+    k = np.empty((nb, na), dtype=np.int16)
+    _check(_load().orc_round_l1_normalized_f32(_ptr(X), _ptr(Y), nb, na, d, float(eps),
+                                               _ptr(k), na), "round_l1_normalized_f32")
+    return k
 
 
 def points_max_f32(X: np.ndarray, Y: np.ndarray) -> float:

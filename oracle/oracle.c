@@ -80,6 +80,94 @@ int orc_round_points_f32(const float *X, const float *Y, int64_t n_b,
     return ORC_OK;
 }
 
+/* Section 5's synthetic cost: the plain Euclidean distance. Same binary32
+ * squared distance d2 and maximum m as orc_round_points_f32; the cost scaled
+ * to max 1 is sqrt(d2 / m) (division and square root in binary64) and
+ * k = floor(c / eps). */
+int orc_round_points_euclid_f32(const float *X, const float *Y, int64_t n_b, int64_t n_a,
+                                int32_t d, double eps, int16_t *k, int64_t ldk, float *m_out)
+{
+    if (!X || !Y || !k || n_b < 0 || n_a < 0 || d <= 0 || ldk < n_a)
+        return ORC_E_ARG;
+    if (!eps_ok(eps)) return ORC_E_EPS;
+    float *d2 = (float *)malloc(sizeof(float) * (size_t)(n_b * n_a + 1));
+    if (!d2) return ORC_E_NOMEM;
+    float m = 0.0f;
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) {
+            float s = 0.0f;
+            for (int32_t j = 0; j < d; ++j) {
+                float t = X[b * d + j] - Y[a * d + j];
+                s = fmaf(t, t, s);
+            }
+            d2[b * n_a + a] = s;
+            if (s > m) m = s;
+        }
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) {
+            if (m == 0.0f) {
+                k[b * ldk + a] = 0;
+            } else {
+                double c = sqrt((double)d2[b * n_a + a] / (double)m);
+                k[b * ldk + a] = (int16_t)floor(c / eps);
+            }
+        }
+    if (m_out) *m_out = m;
+    free(d2);
+    return ORC_OK;
+}
+
+/* Section 5's image cost: each vector is normalised to sum 1 (its sum taken
+ * in binary32 in coordinate order, each coordinate divided by it in
+ * binary32), and the cost is the L1 distance of the normalised vectors
+ * (binary32, coordinate order), at most 2; it is scaled by 1/2 (clamped to 1
+ * against rounding) and rounded by eq. (1) in binary64. Entries must be
+ * finite and nonnegative with a positive sum. */
+int orc_round_l1_normalized_f32(const float *X, const float *Y, int64_t n_b, int64_t n_a,
+                                int32_t d, double eps, int16_t *k, int64_t ldk)
+{
+    if (!X || !Y || !k || n_b < 0 || n_a < 0 || d <= 0 || ldk < n_a)
+        return ORC_E_ARG;
+    if (!eps_ok(eps)) return ORC_E_EPS;
+    float *xh = (float *)malloc(sizeof(float) * (size_t)(n_b * d + 1));
+    float *yh = (float *)malloc(sizeof(float) * (size_t)(n_a * d + 1));
+    if (!xh || !yh) {
+        free(xh); free(yh);
+        return ORC_E_NOMEM;
+    }
+    const float *src[2] = {X, Y};
+    float *dst[2] = {xh, yh};
+    const int64_t cnt[2] = {n_b, n_a};
+    for (int w = 0; w < 2; ++w)
+        for (int64_t i = 0; i < cnt[w]; ++i) {
+            float sum = 0.0f;
+            for (int32_t j = 0; j < d; ++j) {
+                float v = src[w][i * d + j];
+                if (!(v >= 0.0f && v <= 3.4028234663852886e38f)) {
+                    free(xh); free(yh);
+                    return ORC_E_RANGE;
+                }
+                sum = sum + v;
+            }
+            if (!(sum > 0.0f && sum <= 3.4028234663852886e38f)) {
+                free(xh); free(yh);
+                return ORC_E_RANGE;
+            }
+            for (int32_t j = 0; j < d; ++j) dst[w][i * d + j] = src[w][i * d + j] / sum;
+        }
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) {
+            float t = 0.0f;
+            for (int32_t j = 0; j < d; ++j) t = t + fabsf(xh[b * d + j] - yh[a * d + j]);
+            double c = (double)t * 0.5;
+            if (c > 1.0) c = 1.0;
+            k[b * ldk + a] = (int16_t)floor(c / eps);
+        }
+    free(xh);
+    free(yh);
+    return ORC_OK;
+}
+
 /* The same binary32 squared distance as orc_round_points_f32, for large
  * instances whose n^2 matrix is not wanted: the maximum over all pairs, then
  * eq. (1) for chosen pairs (b_i, a_i) only. */

@@ -55,6 +55,17 @@ int orc_round_points_f32(const float *X, const float *Y, int64_t n_b,
                          int64_t n_a, int32_t d, double eps, int16_t *k,
                          int64_t ldk, float *m_out);
 
+/* Cost variants of Section 5. Euclidean: the same d2 and m as above, cost
+ * sqrt(d2 / m) (binary64), k = floor(cost / eps). L1 on normalised vectors:
+ * every vector divided by its binary32 sum (coordinate order), cost = half
+ * the binary32 L1 distance (coordinate order) clamped to 1, k = floor(cost /
+ * eps); entries must be finite, nonnegative, with a positive sum
+ * (ORC_E_RANGE otherwise). */
+int orc_round_points_euclid_f32(const float *X, const float *Y, int64_t n_b, int64_t n_a,
+                                int32_t d, double eps, int16_t *k, int64_t ldk, float *m_out);
+int orc_round_l1_normalized_f32(const float *X, const float *Y, int64_t n_b, int64_t n_a,
+                                int32_t d, double eps, int16_t *k, int64_t ldk);
+
 /* Large instances: the binary32 maximum squared distance over all pairs, and
  * eq. (1) for the chosen pairs (b_idx[i], a_idx[i]) given that maximum. Same
  * arithmetic as orc_round_points_f32. */

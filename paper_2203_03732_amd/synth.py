@@ -12,6 +12,9 @@ Workloads (the shapes of the paper's experiments, Section 5):
                   points, as in minibatch optimal transport
   shifted_gaussian_batch  equal-n instances, X ~ N(0, I), Y ~ N(shift, I)
   random_k        small random integer rounded-cost matrices for tests
+  digit_images    28 x 28 nonnegative stroke images (784-vectors), a
+                  stand-in with the shape and sparsity of handwritten-digit
+                  scans (Section 5's image experiment; no dataset is used)
   transport_clouds  a transport instance: supply points uniform in the unit
                   square, demand points uniform in the square shifted by
                   (shift, 0), squared distances scaled to max 1, and random
@@ -72,3 +75,24 @@ def transport_clouds(n_b: int, n_a: int, seed: int = 0, shift: float = 1.0):
     nu = rng.random(n_b) + 0.05
     mu = rng.random(n_a) + 0.05
     return C, nu / nu.sum(), mu / mu.sum()
+
+
+def digit_images(n: int, seed: int = 0) -> np.ndarray:
+    """n x 784 float32 images: 2 to 4 random strokes (line segments in the
+    central 20 x 20 box, drawn with a 3 x 3 brush), intensities in (0.6, 1],
+    about a fifth of the pixels nonzero."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((n, 28, 28), np.float32)
+    t = np.linspace(0.0, 1.0, 40)
+    for i in range(n):
+        img = out[i]
+        for _ in range(int(rng.integers(2, 5))):
+            p0, p1 = rng.uniform(4, 24, 2), rng.uniform(4, 24, 2)
+            rr = np.rint(p0[0] + (p1[0] - p0[0]) * t).astype(int)
+            cc = np.rint(p0[1] + (p1[1] - p0[1]) * t).astype(int)
+            for dr in (-1, 0, 1):
+                for dc in (-1, 0, 1):
+                    img[np.clip(rr + dr, 0, 27), np.clip(cc + dc, 0, 27)] = 1.0
+        nz = img > 0
+        img[nz] *= rng.uniform(0.6, 1.0, int(nz.sum())).astype(np.float32)
+    return out.reshape(n, 784)
