@@ -50,6 +50,7 @@ enum { PROT_EPS_ALGORITHMIC = 0, PROT_EPS_STRICT = 1 };
 enum { PROT_COST_DIRECT = 0, PROT_COST_MATRIX_CORES = 1 };
 enum { PROT_COSTS_AUTO = 0, PROT_COSTS_MATRIX = 1, PROT_COSTS_ON_THE_FLY = 2 };
 enum { PROT_ORIGIN_DIAG = 0, PROT_ORIGIN_ZERO = 1 };
+enum { PROT_METRIC_SQEUCLIDEAN = 0, PROT_METRIC_EUCLIDEAN = 1, PROT_METRIC_L1_NORMALIZED = 2 };
 
 typedef struct {
     /* PROT_EPS_ALGORITHMIC runs with the given eps (additive error 3 eps n,
@@ -112,6 +113,22 @@ int prot_set_stream(prot_ctx *ctx, void *hip_stream);
  * matrix rate equals the FP32 vector rate, so this path is not faster; it is
  * kept for comparison. Returns PROT_E_ARG for an unknown path. */
 int prot_set_cost_path(prot_ctx *ctx, int32_t path);
+/* The cost of a pair in later single-instance point-set builds and solves on
+ * ctx (prot_build_costs*, prot_solve_points*; batches always use the squared
+ * cost). All are scaled to at most 1 and rounded by eq. (1) in binary64.
+ * PROT_METRIC_SQEUCLIDEAN (default): d2 / m, d2 the fma-accumulated binary32
+ * squared distance, m its maximum over all pairs. PROT_METRIC_EUCLIDEAN
+ * (Section 5's synthetic experiment): sqrt(d2 / m) in binary64; every entry
+ * is placed exactly through a table of the smallest binary32 d2 reaching
+ * each k. PROT_METRIC_L1_NORMALIZED (Section 5's image experiment): every
+ * vector is divided by its sum (binary32, sum in coordinate order), the cost
+ * is half the L1 distance of the normalised vectors (binary32, coordinate
+ * order) clamped to 1; entries must be finite and nonnegative with a
+ * positive sum (PROT_E_RANGE otherwise), d <= 12288; m_out and cost_scale
+ * report 2. The last two store the matrix (PROT_COSTS_ON_THE_FLY returns
+ * PROT_E_UNSUPPORTED; AUTO stores it). Returns PROT_E_ARG for an unknown
+ * metric. */
+int prot_set_cost_metric(prot_ctx *ctx, int32_t metric);
 /* Pre-size the workspace for instances up to n_max (and, if with_matrix,
  * an n_max x prot_pitch(n_max) int16 cost matrix) so that later calls do
  * not allocate. */

@@ -86,7 +86,8 @@ EXPORTS = [
     "prot_threshold", "prot_max_n", "prot_round_costs", "prot_build_costs",
     "prot_solve_rounded", "prot_solve_cost", "prot_solve_points",
     "prot_round_costs_rect", "prot_build_costs_rect", "prot_solve_rounded_rect",
-    "prot_solve_cost_rect", "prot_solve_points_rect", "prot_ot_solve", "prot_get_trace",
+    "prot_solve_cost_rect", "prot_solve_points_rect", "prot_ot_solve", "prot_set_cost_metric",
+    "prot_get_trace",
     "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
     "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
     "prot_batch_loss_fwd", "prot_batch_loss_bwd",
@@ -134,6 +135,7 @@ def load():
                                                   ctypes.POINTER(Stats)]),
         "prot_ot_solve": (ctypes.c_int, [p, p, i64, i64, i64, p, p, f64, ctypes.POINTER(Opts),
                                          p, i64, p, p, p, p, ctypes.POINTER(OTStats)]),
+        "prot_set_cost_metric": (ctypes.c_int, [p, i32]),
         "prot_get_trace": (i64, [p, p, i64]),
         "prot_get_round_times": (i64, [p, p, i64]),
         "prot_batch_max_n": (i32, []),
@@ -297,6 +299,14 @@ class Context:
         """'direct' (default) or 'matrix_cores' for later point-set builds;
         both give the same result (include/prot.h, prot_set_cost_path)."""
         self._check(self._lib.prot_set_cost_path(self._h, self.COST_PATHS[path]))
+
+    COST_METRICS = {"sqeuclidean": 0, "euclidean": 1, "l1_normalized": 2}
+
+    def set_cost_metric(self, metric: str) -> None:
+        """'sqeuclidean' (default), 'euclidean' or 'l1_normalized' for later
+        single-instance point-set builds and solves (include/prot.h,
+        prot_set_cost_metric)."""
+        self._check(self._lib.prot_set_cost_metric(self._h, self.COST_METRICS[metric]))
 
     def build_costs(self, X, Y, eps: float, k=None):
         """X: n_b x d rows, Y: n_a x d columns (contiguous float32)."""

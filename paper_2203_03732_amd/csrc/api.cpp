@@ -55,6 +55,9 @@ struct prot_ctx {
 
     int64_t *rtime = nullptr;        // round timer (PROT_DEBUG_ROUND_TIMES=1)
     int32_t cost_path = PROT_COST_DIRECT;  // prot_set_cost_path
+    int32_t cost_metric = PROT_METRIC_SQEUCLIDEAN;  // prot_set_cost_metric
+    float *l1_buf = nullptr;         // normalised vectors of the L1 image cost
+    int64_t l1_cap = 0;
     int loop_groups = 8;             // barrier groups of the phase loop (PROT_LOOP_GROUPS)
     float *mfma_buf = nullptr;       // amax, emax, tile maxima of the matrix-core build
     int64_t mfma_cap = 0;
@@ -215,8 +218,9 @@ int grid_for(prot_ctx *c, int64_t n, int64_t n_a, int *grid)
 int setup_mfma(prot_ctx *c, prot::PointsJob &j, int64_t n_max, float **buf, int64_t *cap)
 {
     j.mfma = prot::MfmaAux{};
-    if (j.d < prot::kMfmaMinD || c->cost_path != PROT_COST_MATRIX_CORES || j.na_single)
-        return PROT_OK;  // (unbalanced instances take the direct path)
+    if (j.d < prot::kMfmaMinD || c->cost_path != PROT_COST_MATRIX_CORES || j.na_single ||
+        j.metric != PROT_METRIC_SQEUCLIDEAN)
+        return PROT_OK;  // (unbalanced instances and other metrics take the direct path)
     const int64_t tx = (n_max + prot::kMfmaTile - 1) / prot::kMfmaTile;
     const int64_t need = 2 * (int64_t)j.batch + (int64_t)j.batch * tx * tx;
     if (need > *cap || !*buf) {
@@ -241,7 +245,8 @@ int setup_prune(prot_ctx *c, prot::PointsJob &j, int64_t n)  // n: max(rows, col
     j.prune = prot::PruneAux{};
     // below this size the plain n^2 pass is cheaper than the four pruning
     // launches (measured: 28 us for n = 10,000, d = 2)
-    if ((j.d != 2 && j.d != 3) || n < c->prune_min_n) return PROT_OK;
+    if ((j.d != 2 && j.d != 3) || n < c->prune_min_n || j.metric == PROT_METRIC_L1_NORMALIZED)
+        return PROT_OK;
     if (n > c->prune_cap || !c->prune_buf) {
         int rc = dev_alloc(c, &c->prune_buf, (size_t)(256 + 8 * std::max<int64_t>(n, 1024)));
         if (rc) return rc;
@@ -273,7 +278,33 @@ prot::PointsJob points_job(prot_ctx *c, const float *X, const float *Y, int64_t 
     j.kcap = (int32_t)std::floor(1.0 / eps) + 2;
     j.err = &c->ctl->err;
     j.kmax_out = &c->ctl->kmax;
+    j.metric = c->cost_metric;
     return j;
+}
+
+// The L1 image cost normalises X and Y into a workspace first.
+int setup_l1(prot_ctx *c, prot::PointsJob &j, int64_t n_b, int64_t n_a)
+{
+    if (j.metric != PROT_METRIC_L1_NORMALIZED) return PROT_OK;
+    if (j.d > 12288)
+        return fail(c, PROT_E_UNSUPPORTED, "the L1 image cost takes d <= 12288 (d = %d)", j.d);
+    const int64_t need = (n_b + n_a) * (int64_t)j.d;
+    if (need > c->l1_cap || !c->l1_buf) {
+        int rc = dev_alloc(c, &c->l1_buf, (size_t)need);
+        if (rc) return rc;
+        c->l1_cap = need;
+    }
+    j.l1_x = c->l1_buf;
+    j.l1_y = c->l1_buf + n_b * (int64_t)j.d;
+    return PROT_OK;
+}
+
+// finalize/collect cost kind of a point-set solve
+int points_cost_kind(const prot_ctx *c)
+{
+    return c->cost_metric == PROT_METRIC_EUCLIDEAN        ? 3
+           : c->cost_metric == PROT_METRIC_L1_NORMALIZED ? 4
+                                                          : 2;
 }
 
 prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
@@ -398,6 +429,14 @@ int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kin
     if (cost_kind == 2) {
         st->cost_scale = (double)h.m;
         st->cost = h.m > 0.0f ? sc / (double)h.m : 0.0;
+    }
+    if (cost_kind == 3) {  // Euclidean: c = sqrt(d2 / m)
+        st->cost_scale = (double)h.m;
+        st->cost = h.m > 0.0f ? sc / std::sqrt((double)h.m) : 0.0;
+    }
+    if (cost_kind == 4) {  // L1 of normalised vectors, halved
+        st->cost_scale = 2.0;
+        st->cost = sc;
     }
     st->kmax = h.kmax;
     float ms = 0.0f;
@@ -738,6 +777,7 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->th);
     (void)hipFree(c->rtime);
     (void)hipFree(c->mfma_buf);
+    (void)hipFree(c->l1_buf);
     for (void *p : {(void *)c->ot.s_off, (void *)c->ot.d_off, (void *)c->ot.row_pt,
                     (void *)c->ot.col_pt, (void *)c->ot.ymax, (void *)c->ot.cnt,
                     (void *)c->ot.mate_a, (void *)c->ot.mate_b, (void *)c->ot.y_a,
@@ -748,6 +788,16 @@ int prot_ctx_destroy(prot_ctx *c)
     for (int i = 0; i < 5; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     delete c;
+    return PROT_OK;
+}
+
+int prot_set_cost_metric(prot_ctx *c, int32_t metric)
+{
+    if (!c) return PROT_E_ARG;
+    if (metric != PROT_METRIC_SQEUCLIDEAN && metric != PROT_METRIC_EUCLIDEAN &&
+        metric != PROT_METRIC_L1_NORMALIZED)
+        return fail(c, PROT_E_ARG, "unknown cost metric %d", (int)metric);
+    c->cost_metric = metric;
     return PROT_OK;
 }
 
@@ -833,6 +883,7 @@ int prot_build_costs_rect(prot_ctx *c, const float *X, int64_t n_b, const float 
     prot::PointsJob j = points_job(c, X, Y, n_b, d, eps, k, ldk, n_a);
     if ((rc = setup_mfma(c, j, n_max, &c->mfma_buf, &c->mfma_cap))) return rc;
     if ((rc = setup_prune(c, j, n_max))) return rc;
+    if ((rc = setup_l1(c, j, n_b, n_a))) return rc;
     HIP_TRY(c, prot::launch_points(j, n_max, ldk, c->stream));
     if (m_out)
         HIP_TRY(c, hipMemcpyAsync(m_out, &c->ctl->m, sizeof(float), hipMemcpyDeviceToDevice,
@@ -952,8 +1003,11 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
         return fail(c, PROT_E_ARG, "unknown cost_storage %d", (int)storage);
     if (storage == PROT_COSTS_ON_THE_FLY && d != 2 && d != 3)
         return fail(c, PROT_E_UNSUPPORTED, "costs on the fly need d = 2 or 3 (d = %d)", (int)d);
+    if (storage == PROT_COSTS_ON_THE_FLY && c->cost_metric != PROT_METRIC_SQEUCLIDEAN)
+        return fail(c, PROT_E_UNSUPPORTED, "costs on the fly take the squared Euclidean cost");
     const bool on_the_fly = storage == PROT_COSTS_ON_THE_FLY ||
-                            (storage == PROT_COSTS_AUTO && auto_on_the_fly(d, n_b, n_a));
+                            (storage == PROT_COSTS_AUTO && c->cost_metric == PROT_METRIC_SQEUCLIDEAN &&
+                             auto_on_the_fly(d, n_b, n_a));
     int rc = on_the_fly ? PROT_OK : ensure_matrix(c, n_b, n_a);
     if (!rc) rc = ensure_thresholds(c, ei);
     if (rc) return rc;
@@ -963,6 +1017,7 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
     j.no_matrix = on_the_fly ? 1 : 0;
     if (!on_the_fly && (rc = setup_mfma(c, j, n_max, &c->mfma_buf, &c->mfma_cap))) return rc;
     if ((rc = setup_prune(c, j, n_max))) return rc;
+    if ((rc = setup_l1(c, j, n_b, n_a))) return rc;
     HIP_TRY(c, prot::launch_points(j, n_max, ldk, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     OnTheFly otf;
@@ -979,10 +1034,10 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
         HIP_TRY(c, prot::launch_finalize(n_b, mate_b, nullptr, 0, 2, nullptr, 0, X, Y, d,
                                          c->part_k, c->part_c, c->stream, &c->ctl->m, ei, c->th));
     else
-        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, 2, nullptr, 0, X, Y, d,
-                                         c->part_k, c->part_c, c->stream));
+        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, points_cost_kind(c), nullptr,
+                                         0, X, Y, d, c->part_k, c->part_c, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
-    rc = collect(c, st, T, ei, 2, true);
+    rc = collect(c, st, T, ei, on_the_fly ? 2 : points_cost_kind(c), true);
     if (rc) return rc;
     fill_match_counts(c, n_b, st, o);
     if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");

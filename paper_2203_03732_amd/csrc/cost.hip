@@ -347,7 +347,7 @@ __global__ void thresholds_kernel(PointsJob j)
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && j.kmax_out && blockIdx.z == 0) *j.kmax_out = K;
     if (i > K + 1 || i >= j.kcap) return;
-    j.th[(int64_t)blockIdx.z * j.kcap + i] = threshold_of(i, K, mf, j.eps);
+    j.th[(int64_t)blockIdx.z * j.kcap + i] = threshold_of(i, K, mf, j.eps, j.metric);
 }
 
 // Pass 2: k for every pair, 8 consecutive columns per thread (their points
@@ -369,7 +369,11 @@ __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
     const int64_t n = in.na;  // columns
     const float mf = j.m[blockIdx.z];
     const int32_t K = (mf > 0.0f) ? (int32_t)floor(1.0 / j.eps) : 0;
-    const float inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * j.eps)) : 0.0f;
+    // Euclidean: an estimate from sqrt(s), made exact by the threshold table
+    const bool euclid = j.metric == 1;
+    const float inv = (mf > 0.0f) ? (float)(1.0 / ((euclid ? sqrt((double)mf) : (double)mf) *
+                                                     j.eps))
+                                  : 0.0f;
     const float delta = classify_margin(K);
     const float *th = j.th + (int64_t)blockIdx.z * j.kcap;
     float yv[kColsPerThread][D];
@@ -389,16 +393,22 @@ __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
         for (int e = 0; e < kColsPerThread; ++e) {
             const float s = sqdist<D>(x, yv[e], D);
             bool ok;
-            g[e] = fast_k(s, inv, delta, K, ok);
+            if (euclid) {
+                g[e] = (int)__fmul_rn(__fsqrt_rn(s), inv);
+                ok = false;
+            } else {
+                g[e] = fast_k(s, inv, delta, K, ok);
+            }
             sv[e] = s;
             all_ok &= ok;
         }
         if (!all_ok) {
-            // rare: entries within the margin of a rounding boundary
+            // rare (squared cost): entries within the margin of a rounding
+            // boundary; Euclidean: every entry
 #pragma unroll
             for (int e = 0; e < kColsPerThread; ++e) {
-                bool ok;
-                fast_k(sv[e], inv, delta, K, ok);
+                bool ok = false;
+                if (!euclid) fast_k(sv[e], inv, delta, K, ok);
                 if (!ok) g[e] = refine_k(sv[e], g[e], K, th);
             }
         }
@@ -425,7 +435,7 @@ __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
 constexpr int kTile = 64;
 constexpr int kTj = 16;
 
-template <int PASS>
+template <int PASS, bool L1 = false>
 __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
 {
     __shared__ __align__(16) float xs[kTj][kTile + 4];
@@ -461,7 +471,8 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const float t = __fsub_rn(xr[i], yc[c]);
-                    acc[i][c] = __fmaf_rn(t, t, acc[i][c]);
+                    if constexpr (L1) acc[i][c] = __fadd_rn(acc[i][c], fabsf(t));
+                    else acc[i][c] = __fmaf_rn(t, t, acc[i][c]);
                 }
         }
         __syncthreads();
@@ -490,7 +501,10 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
     } else {
         const float mf = j.m[blockIdx.z];
         const int32_t K = (mf > 0.0f) ? (int32_t)floor(1.0 / j.eps) : 0;
-        const float inv = (mf > 0.0f) ? (float)(1.0 / ((double)mf * j.eps)) : 0.0f;
+        const bool euclid = j.metric == 1;
+        const float inv = (mf > 0.0f) ? (float)(1.0 / ((euclid ? sqrt((double)mf) : (double)mf) *
+                                                         j.eps))
+                                      : 0.0f;
         const float delta = classify_margin(K);
         const float *th = j.th + (int64_t)blockIdx.z * j.kcap;
 #pragma unroll
@@ -505,9 +519,17 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
                     g[c] = 0x7FFF;
                     continue;
                 }
-                bool ok;
-                g[c] = fast_k(acc[i][c], inv, delta, K, ok);
-                if (!ok) g[c] = refine_k(acc[i][c], g[c], K, th);
+                if constexpr (L1) {
+                    // half the L1 distance, clamped to 1, eq. (1) in binary64
+                    g[c] = (int)floor(fmin((double)acc[i][c] * 0.5, 1.0) / j.eps);
+                } else if (euclid) {
+                    g[c] = refine_k(acc[i][c], (int)__fmul_rn(__fsqrt_rn(acc[i][c]), inv), K,
+                                    th);
+                } else {
+                    bool ok;
+                    g[c] = fast_k(acc[i][c], inv, delta, K, ok);
+                    if (!ok) g[c] = refine_k(acc[i][c], g[c], K, th);
+                }
             }
             uint2 w;
             w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
@@ -515,6 +537,70 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
             *reinterpret_cast<uint2 *>(in.k + row * in.ldk + a0 + tx * 4) = w;
         }
     }
+}
+
+// Section 5's image cost: each vector divided by its sum (binary32, the sum
+// taken in coordinate order by one lane). kNormFloats coordinates of a block's
+// vectors are staged in LDS. Entries must be finite and nonnegative with a
+// positive finite sum (err bit 1 otherwise). Block 0 also records the cost
+// scale 2 (the L1 distance of two such vectors is at most 2) and K.
+constexpr int kNormFloats = 12288;
+
+__global__ void __launch_bounds__(256) l1_normalize_kernel(PointsJob j, const float *src,
+                                                           int64_t n, float *dst)
+{
+    __shared__ float v[kNormFloats];
+    __shared__ float sums[64];
+    __shared__ int bad;
+    const int d = j.d;
+    const int per = min(64, kNormFloats / d);
+    const int64_t first = (int64_t)blockIdx.x * per;
+    if (first >= n) return;
+    const int cnt = (int)min<int64_t>(per, n - first);
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt * d; i += blockDim.x) {
+        const float x = src[first * d + i];
+        if (!(x >= 0.0f && x <= FLT_MAX)) bad = 1;
+        v[i] = x;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+        float t = 0.0f;
+        for (int q = 0; q < d; ++q) t = __fadd_rn(t, v[threadIdx.x * d + q]);
+        if (!(t > 0.0f && t <= FLT_MAX)) bad = 1;
+        sums[threadIdx.x] = t;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt * d; i += blockDim.x)
+        dst[first * d + i] = __fdiv_rn(v[i], sums[i / d]);
+    if (threadIdx.x == 0) {
+        if (bad) __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (blockIdx.x == 0) {
+            j.m[0] = 2.0f;
+            if (j.kmax_out) *j.kmax_out = (int32_t)floor(1.0 / j.eps);
+        }
+    }
+}
+
+void launch_points_l1(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s)
+{
+    // one instance (the batched solver keeps the squared cost)
+    const int64_t nb = j.n_single, na = j.na_single ? j.na_single : j.n_single;
+    const int per = std::min(64, kNormFloats / j.d);
+    PointsJob jn = j;
+    jn.X = j.l1_x;
+    jn.Y = j.l1_y;
+    if (nb > 0)
+        hipLaunchKernelGGL(l1_normalize_kernel, dim3((unsigned)((nb + per - 1) / per)), dim3(256),
+                           0, s, j, j.X, nb, j.l1_x);
+    if (na > 0)
+        hipLaunchKernelGGL(l1_normalize_kernel, dim3((unsigned)((na + per - 1) / per)), dim3(256),
+                           0, s, j, j.Y, na, j.l1_y);
+    const unsigned rows = (unsigned)((n_max + kTile - 1) / kTile);
+    hipLaunchKernelGGL((points_tile_kernel<1, true>),
+                       dim3((unsigned)((ldk_max + kTile - 1) / kTile), rows, 1), dim3(256), 0, s,
+                       jn);
 }
 
 void launch_points_tiled(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s)
@@ -574,7 +660,8 @@ hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hip
 {
     hipLaunchKernelGGL(build_reset_kernel, dim3((j.batch + 255) / 256), dim3(256), 0, s, j);
     if (n_max == 0 || j.batch == 0) return hipGetLastError();
-    if (j.d == 2) launch_points_d<2>(j, n_max, ldk_max, s);
+    if (j.metric == 2) launch_points_l1(j, n_max, ldk_max, s);
+    else if (j.d == 2) launch_points_d<2>(j, n_max, ldk_max, s);
     else if (j.d == 3) launch_points_d<3>(j, n_max, ldk_max, s);
     else if (j.mfma.tile_max) return launch_points_mfma(j, j.mfma, n_max, ldk_max, s);
     else launch_points_tiled(j, n_max, ldk_max, s);

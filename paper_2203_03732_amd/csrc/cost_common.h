@@ -42,6 +42,12 @@ struct PointsJob {
     const int32_t *ldk_arr;    // device, row pitch per instance (null: ldk_single)
     int64_t n_single, ldk_single;
     int64_t na_single;         // columns of a single instance (0: n_single)
+    // Cost of a pair (Section 5's variants): 0 squared Euclidean d2 / m,
+    // 1 Euclidean sqrt(d2 / m), 2 half the L1 distance of the vectors
+    // normalised to sum 1 (X and Y then point at the normalised copies).
+    int32_t metric;
+    int32_t pad_metric;
+    float *l1_x, *l1_y;        // metric 2: workspace for the normalised X and Y
     int32_t d;
     int32_t batch;
     double eps;
@@ -88,16 +94,18 @@ __device__ inline float sqdist(const float *__restrict__ x, const float *__restr
     return s;
 }
 
-// k(s) = floor((s / m) / eps), both divisions binary64 (the definition).
-__device__ inline double k_of(float s, double m, double eps)
+// k(s) = floor((s / m) / eps), both divisions binary64 (the definition);
+// Euclidean (metric 1): floor(sqrt(s / m) / eps), also binary64.
+__device__ inline double k_of(float s, double m, double eps, int metric = 0)
 {
-    return floor(((double)s / m) / eps);
+    const double c = (double)s / m;
+    return floor((metric == 1 ? sqrt(c) : c) / eps);
 }
 
 // Smallest binary32 s >= 0 with k(s) >= j (0 < j <= K); j = 0 gives 0 and
 // j = K + 1 gives +inf. k(s) is non-decreasing in s, hence in the bit
 // pattern of s >= 0, and k(m) = K.
-__device__ inline float threshold_of(int32_t j, int32_t K, float mf, double eps)
+__device__ inline float threshold_of(int32_t j, int32_t K, float mf, double eps, int metric = 0)
 {
     if (j == 0) return 0.0f;
     if (j > K) return __int_as_float(0x7f800000);
@@ -105,7 +113,8 @@ __device__ inline float threshold_of(int32_t j, int32_t K, float mf, double eps)
     uint32_t lo = 0, hi = __float_as_uint(mf);
     while (lo < hi) {
         const uint32_t mid = lo + (hi - lo) / 2;
-        if (k_of(__uint_as_float(mid), m, eps) >= (double)j) hi = mid; else lo = mid + 1;
+        if (k_of(__uint_as_float(mid), m, eps, metric) >= (double)j) hi = mid;
+        else lo = mid + 1;
     }
     return __uint_as_float(lo);
 }

@@ -1087,13 +1087,25 @@ finalize_kernel(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk,
         }
         if (cost_kind == 1) {
             cs = __dadd_rn(cs, (double)C[b * ldc + a]);
-        } else if (cost_kind == 2) {
+        } else if (cost_kind == 2 || cost_kind == 3) {
+            // squared Euclidean (the host divides by m) or Euclidean (by sqrt m)
             double s = 0.0;
             for (int j = 0; j < d; ++j) {
                 const double t = __dsub_rn((double)X[b * d + j], (double)Y[(int64_t)a * d + j]);
                 s = __dadd_rn(s, __dmul_rn(t, t));
             }
-            cs = __dadd_rn(cs, s);
+            cs = __dadd_rn(cs, cost_kind == 3 ? sqrt(s) : s);
+        } else if (cost_kind == 4) {
+            // half the L1 distance of the vectors normalised to sum 1
+            double sx = 0.0, sy = 0.0, s = 0.0;
+            for (int j = 0; j < d; ++j) {
+                sx = __dadd_rn(sx, (double)X[b * d + j]);
+                sy = __dadd_rn(sy, (double)Y[(int64_t)a * d + j]);
+            }
+            for (int j = 0; j < d; ++j)
+                s = __dadd_rn(s, fabs(__dsub_rn((double)X[b * d + j] / sx,
+                                                (double)Y[(int64_t)a * d + j] / sy)));
+            cs = __dadd_rn(cs, 0.5 * s);
         }
     }
     sk[threadIdx.x] = ks;
