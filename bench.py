@@ -181,6 +181,37 @@ def bench_transport(prot, synth, torch, reps=5):
             "repaired_mass": st["repaired_mass"]}
 
 
+def bench_cost_variants(prot, synth, torch, reps=5):
+    """Section 5's two workloads with their own costs: n = 10,000 uniform
+    points in the unit square with the plain Euclidean cost (eps = 0.01),
+    and n = 10,000 stroke images of 784 pixels with half the L1 distance of
+    the normalised images (eps = 0.1). Whole solves, inputs in HBM."""
+    out = {}
+    cases = [("euclidean", synth.uniform_points(10000, 2, seed=0), 0.01,
+              "n=10000 points U[0,1]^2 Euclidean eps=0.01 seed=0"),
+             ("l1_normalized", (synth.digit_images(10000, seed=31),
+                                synth.digit_images(10000, seed=32)), 0.1,
+              "n=10000 28x28 stroke images, L1 of normalised images / 2, eps=0.1")]
+    for metric, (X, Y), eps, name in cases:
+        Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+        ctx = prot.Context(0)
+        ctx.set_cost_metric(metric)
+        r = ctx.solve_points(Xd, Yd, eps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = ctx.solve_points(Xd, Yd, eps)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        st = r.stats
+        ctx.close()
+        out[metric] = {"workload": name, "ms_per_solve": round(ms, 4),
+                       "ms_build": round(st["ms_build"], 4),
+                       "ms_loop": round(st["ms_loop_kernel"], 4), "phases": st["phases"],
+                       "rounds": st["rounds"], "scanned": st["scanned"], "cost": st["cost"]}
+    return out
+
+
 def bench_ot_loss(prot, synth, torch, reps=5):
     """64 instances, n = 2048, X ~ N(0, I_64), Y ~ N(0.5, I_64), eps = 0.01:
     forward (batched solve + loss) and hand-written backward."""
@@ -299,6 +330,7 @@ def main():
         out["large"] = bench_large(prot, synth, torch)
         out["unbalanced"] = bench_unbalanced(prot, synth, torch)
         out["transport"] = bench_transport(prot, synth, torch)
+        out["cost_variants"] = bench_cost_variants(prot, synth, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, Y, eps, args.cpu_reps)
     print(json.dumps(out), flush=True)

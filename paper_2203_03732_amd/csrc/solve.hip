@@ -68,9 +68,10 @@ __device__ inline void wait_memory()
 // Value of a tagged list entry ((tag << 32) | value) once it carries `tag`.
 // The wait is bounded: on time-out bit 2 of the error word is raised and the
 // value is used as found. The value is clamped to [0, n) either way.
-__device__ inline int32_t take_entry(const unsigned long long *p, uint32_t tag, int n, int32_t *err)
+// take_entry_from starts from a value v already loaded from p.
+__device__ inline int32_t take_entry_from(const unsigned long long *p, unsigned long long v,
+                                         uint32_t tag, int n, int32_t *err)
 {
-    unsigned long long v = ld_agent(p);
     for (int spins = 0; (uint32_t)(v >> 32) != tag; v = ld_agent(p)) {
         if (++spins > kSpinLimit) {
             __hip_atomic_fetch_or(err, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -80,6 +81,11 @@ __device__ inline int32_t take_entry(const unsigned long long *p, uint32_t tag, 
     }
     const int32_t x = (int32_t)(uint32_t)v;
     return x < 0 ? 0 : (x >= n ? n - 1 : x);
+}
+
+__device__ inline int32_t take_entry(const unsigned long long *p, uint32_t tag, int n, int32_t *err)
+{
+    return take_entry_from(p, ld_agent(p), tag, n, err);
 }
 
 // Group j holding position i of a list split into group regions, given the
@@ -563,6 +569,21 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     int64_t p = 0;                         // phase index within this launch
     // statistics, kept by the leader
     int64_t st_rounds = 0, st_max_rounds = 0, st_sum_free = 0;
+    // Columns taken in the last round of the previous phase (list pend_L,
+    // tag pend_tag, group layout still in s_lpre / s_lstart): their t is
+    // raised when the next phase starts, so those reads overlap the reads of
+    // the next free list, or when the loop ends.
+    uint32_t pend = 0, pend_tag = 0;
+    const unsigned long long *pend_L = nullptr;
+    auto apply_pending = [&]() {
+        for (uint32_t i = threadIdx.x; i < pend; i += blockDim.x) {
+            const int j = group_of(s_lpre, G, i);
+            const int32_t a =
+                take_entry(pend_L + j * cap + s_lstart[j] + (i - s_lpre[j]), pend_tag, na, &ctl->err);
+            t_lds[a] = (uint16_t)(t_lds[a] + 1);
+        }
+        pend = 0;
+    };
     for (;;) {
         if ((int64_t)n_i <= A.T) break;
         if (A.max_phases > 0 && p >= A.max_phases) {
@@ -604,14 +625,23 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         if (threadIdx.x < 2 * (kLoopThreads / kWave))
             (&s_best[0][0])[threadIdx.x] = kNoHit;
         if (threadIdx.x < kLoopThreads / kWave) s_mn[threadIdx.x] = kNoHit;
-        __syncthreads();
         int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0, s_rb = 0;
         uint32_t s_skip = 0;
         unsigned long long s_key = 0;
+        // this slot's entry of B' is loaded first, then the previous phase's
+        // last taken columns; the two sets of reads are in flight together
+        const unsigned long long *f_at = nullptr;
+        unsigned long long f_val = 0;
         if ((uint32_t)lane < nslots) {
             const uint32_t e = R == 1 ? gw + (uint32_t)lane * W : team_id;
             const int j = group_of(s_fpre, G, e);
-            s_b = take_entry(Fc + j * cap + (e - s_fpre[j]), tag0 + (uint32_t)p, n, &ctl->err);
+            f_at = Fc + j * cap + (e - s_fpre[j]);
+            f_val = ld_agent(f_at);
+        }
+        apply_pending();
+        __syncthreads();  // t of those columns and the team scratch are set
+        if ((uint32_t)lane < nslots) {
+            s_b = take_entry_from(f_at, f_val, tag0 + (uint32_t)p, n, &ctl->err);
             s_yb = ld_agent(y_b + s_b);
             if constexpr (kCopies) {
                 // a free copy takes the largest dual of its point's copies
@@ -634,6 +664,12 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         for (;;) {
             r += 1;
             if (l_new) {
+                // The rows of this wave that proposed: won (matched in M') or
+                // lost (resume one position after the column). The keys are
+                // final since the barrier; their loads go out first so that
+                // they overlap the taken-list reads below.
+                bool mine = (active >> lane) & 1ull;
+                const unsigned long long k_now = mine ? ld_agent(A.key + s_a) : 0ull;
                 // Columns taken in the previous round: marked for the rest of
                 // the phase, t raised now (step (III a)).
                 for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
@@ -642,11 +678,8 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, na, &ctl->err);
                     t_lds[a] = (uint16_t)((t_lds[a] + 1) | kTaken);
                 }
-                // the rows of this wave that proposed: won (matched in M') or
-                // lost (resume one position after the column)
-                bool mine = (active >> lane) & 1ull;
                 if (mine) {
-                    if (ld_agent(A.key + s_a) == s_key) mine = false;
+                    if (k_now == s_key) mine = false;
                     else s_pos += 1;
                 }
                 active = __ballot(mine);
@@ -897,15 +930,11 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             if (l_new) phase_rounds += 1;  // some proposal was made this round
             if (s_over) break;
         }
-        // Columns taken in the last round get their t raised; then the marks
-        // of the phase are cleared.
-        for (uint32_t i = threadIdx.x; i < l_new; i += blockDim.x) {
-            const int j = group_of(s_lpre, G, i);
-            const int32_t a =
-                take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, na, &ctl->err);
-            t_lds[a] = (uint16_t)(t_lds[a] + 1);
-        }
-        __syncthreads();
+        // The marks of the phase are cleared; the columns taken in its last
+        // round (not marked) get their t raised later, see pend.
+        pend = l_new;
+        pend_tag = tag;
+        pend_L = Lc;
         for (int i = threadIdx.x * 8; i < A.n_pad; i += blockDim.x * 8) {
             uint4 *q = reinterpret_cast<uint4 *>(t_lds + i);
             uint4 v = *q;
@@ -960,8 +989,11 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         ctl->max_rounds = st_max_rounds;
         ctl->free_after = n_i;
     }
-    if (wg == 0)
+    if (wg == 0) {
+        apply_pending();
+        __syncthreads();
         for (int i = threadIdx.x; i < na; i += blockDim.x) A.t[i] = t_lds[i];
+    }
 }
 
 __global__ void clear_err_kernel(Ctl *ctl) { ctl->err = 0; }
