@@ -50,6 +50,7 @@ enum { PROT_EPS_ALGORITHMIC = 0, PROT_EPS_STRICT = 1 };
 enum { PROT_COST_DIRECT = 0, PROT_COST_MATRIX_CORES = 1 };
 enum { PROT_COSTS_AUTO = 0, PROT_COSTS_MATRIX = 1, PROT_COSTS_ON_THE_FLY = 2 };
 enum { PROT_ORIGIN_DIAG = 0, PROT_ORIGIN_ZERO = 1 };
+enum { PROT_KTYPE_AUTO = 0, PROT_KTYPE_INT16 = 1, PROT_KTYPE_UINT8 = 2 };
 enum { PROT_METRIC_SQEUCLIDEAN = 0, PROT_METRIC_EUCLIDEAN = 1, PROT_METRIC_L1_NORMALIZED = 2 };
 
 typedef struct {
@@ -69,7 +70,15 @@ typedef struct {
      * from the points with the build's own operations (identical integers,
      * no n^2 memory). */
     int32_t cost_storage;
-    int32_t reserved[4];
+    /* Element type of the rounded-cost matrix that solve_cost / solve_points
+     * store: PROT_KTYPE_AUTO (= int16), PROT_KTYPE_INT16, PROT_KTYPE_UINT8
+     * (K = floor(1/eps_internal) <= 253, else PROT_E_UNSUPPORTED). Bytes halve
+     * the matrix's memory and the cost build's writes (a larger instance fits
+     * HBM or the Infinity Cache); the scan reads half the bytes but widens
+     * them to int16 lanes and is not faster on MI355X. The costs and every
+     * result are the same. */
+    int32_t k_type;
+    int32_t reserved[3];
     /* Stop after this many phases (0: run to completion); the call then
      * returns PROT_PARTIAL and the outputs hold a valid resumable state. */
     int64_t max_phases;

@@ -27,10 +27,12 @@ class ProtError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("eps_mode", ctypes.c_int32), ("origin_mode", ctypes.c_int32),
                 ("no_completion", ctypes.c_int32), ("cost_storage", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4), ("max_phases", ctypes.c_int64)]
+                ("k_type", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("max_phases", ctypes.c_int64)]
 
 
 COST_STORAGE = {"auto": 0, "matrix": 1, "on_the_fly": 2}
+K_TYPES = {"auto": 0, "int16": 1, "uint8": 2}
 
 
 class Stats(ctypes.Structure):
@@ -250,8 +252,9 @@ class Context:
 
     @staticmethod
     def _opts(eps_mode="algorithmic", origin="diag", complete=True, max_phases=0,
-              storage="auto") -> Opts:
+              storage="auto", k_type="auto") -> Opts:
         o = Opts()
+        o.k_type = K_TYPES[k_type]
         o.eps_mode = EPS_MODES[eps_mode]
         o.origin_mode = ORIGINS[origin]
         o.no_completion = 0 if complete else 1
@@ -351,15 +354,16 @@ class Context:
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
 
     def solve_cost(self, C, eps: float, *, eps_mode="algorithmic", origin="diag",
-                   complete=True, max_phases=0) -> Result:
-        """C: n_b x n_a row-major float32 in [0, 1], n_b <= n_a."""
+                   complete=True, max_phases=0, k_type="auto") -> Result:
+        """C: n_b x n_a row-major float32 in [0, 1], n_b <= n_a. k_type: the
+        stored matrix's element type, 'auto', 'int16' or 'uint8'."""
         torch = _torch()
         if C.dim() != 2 or C.stride(1) != 1:
             raise ValueError("C must be a row-major n_b x n_a float32 matrix")
         n, n_a = C.shape
         mate_a, mate_b, y_a, y_b = self._outputs(n, n_a)
         st = Stats()
-        o = self._opts(eps_mode, origin, complete, max_phases)
+        o = self._opts(eps_mode, origin, complete, max_phases, k_type=k_type)
         self._bind_stream()
         rc = self._check(self._lib.prot_solve_cost_rect(
             self._h, _dev_ptr(C, torch.float32, "C", 2), n, n_a, C.stride(0), float(eps),
@@ -369,10 +373,12 @@ class Context:
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
 
     def solve_points(self, X, Y, eps: float, *, eps_mode="algorithmic", origin="diag",
-                     complete=True, max_phases=0, storage="auto") -> Result:
-        """storage: 'auto', 'matrix' (build and scan the n x n int16 matrix) or
+                     complete=True, max_phases=0, storage="auto", k_type="auto") -> Result:
+        """storage: 'auto', 'matrix' (build and scan the n x n matrix) or
         'on_the_fly' (d = 2, 3: no matrix, each examined cost recomputed from
-        the points); all give the same result."""
+        the points); k_type: the stored matrix's element type ('auto' = 'int16',
+        or 'uint8' for floor(1/eps) <= 253: half the memory). All give the same
+        result."""
         torch = _torch()
         n, d = X.shape
         n_a = Y.shape[0]
@@ -380,7 +386,7 @@ class Context:
             raise ValueError("X and Y must be contiguous n_b x d and n_a x d float32")
         mate_a, mate_b, y_a, y_b = self._outputs(n, n_a)
         st = Stats()
-        o = self._opts(eps_mode, origin, complete, max_phases, storage)
+        o = self._opts(eps_mode, origin, complete, max_phases, storage, k_type)
         self._bind_stream()
         rc = self._check(self._lib.prot_solve_points_rect(
             self._h, _dev_ptr(X, torch.float32, "X", 2), n, _dev_ptr(Y, torch.float32, "Y", 2),

@@ -105,6 +105,22 @@ int hip_fail(prot_ctx *c, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);        \
     } while (0)
 
+// Whether solve_cost / solve_points store the rounded costs as bytes.
+int choose_k8(prot_ctx *c, const prot_opts *o, double ei, int *k8)
+{
+    const int32_t type = o ? o->k_type : PROT_KTYPE_AUTO;
+    if (type < PROT_KTYPE_AUTO || type > PROT_KTYPE_UINT8)
+        return fail(c, PROT_E_ARG, "unknown k_type %d", (int)type);
+    const double K = std::floor(1.0 / ei);
+    if (type == PROT_KTYPE_UINT8 && K > 253.0)
+        return fail(c, PROT_E_UNSUPPORTED, "a byte matrix needs floor(1/eps) <= 253 (it is %g)", K);
+    // AUTO keeps int16: on MI355X the byte matrix halves memory and the cost
+    // build's writes, but the scan (latency-bound, with the widening to
+    // int16 lanes) runs 10-30% slower.
+    *k8 = type == PROT_KTYPE_UINT8;
+    return PROT_OK;
+}
+
 bool eps_valid(double eps)
 {
     return eps > 0.0 && eps < 1.0 && std::floor(1.0 / eps) + 2.0 <= 32767.0;
@@ -219,7 +235,7 @@ int setup_mfma(prot_ctx *c, prot::PointsJob &j, int64_t n_max, float **buf, int6
 {
     j.mfma = prot::MfmaAux{};
     if (j.d < prot::kMfmaMinD || c->cost_path != PROT_COST_MATRIX_CORES || j.na_single ||
-        j.metric != PROT_METRIC_SQEUCLIDEAN)
+        j.metric != PROT_METRIC_SQEUCLIDEAN || j.k8)
         return PROT_OK;  // (unbalanced instances and other metrics take the direct path)
     const int64_t tx = (n_max + prot::kMfmaTile - 1) / prot::kMfmaTile;
     const int64_t need = 2 * (int64_t)j.batch + (int64_t)j.batch * tx * tx;
@@ -353,7 +369,8 @@ struct Copies {
 
 int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk, int64_t T,
              const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
-             int32_t *y_b, const OnTheFly &otf = OnTheFly(), const Copies &cp = Copies())
+             int32_t *y_b, const OnTheFly &otf = OnTheFly(), const Copies &cp = Copies(),
+             int k8 = 0)
 {
     int rc = ensure_loop(c, n_a);
     if (rc) return rc;
@@ -363,6 +380,7 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
     a.groups = std::min(c->loop_groups, grid);
     a.rmap = cp.rmap;
     a.ymax = cp.ymax;
+    a.k8 = k8;
     if (otf.d) {
         a.pd = otf.d;
         a.px = otf.X;
@@ -954,15 +972,19 @@ int prot_solve_cost_rect(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, 
     HIP_TRY(c, hipSetDevice(c->device));
     const double ei = eps_internal(eps, o);
     const int64_t T = prot_threshold(ei, n_b), ldk = prot_pitch(n_a);
-    int rc = ensure_matrix(c, n_b, n_a);
+    int k8 = 0;
+    int rc = choose_k8(c, o, ei, &k8);
+    if (!rc) rc = ensure_matrix(c, n_b, n_a);
     if (rc) return rc;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(c, prot::launch_round_costs(C, n_b, n_a, ldc, ei, c->kmat, ldk, c->ctl, c->stream));
+    HIP_TRY(c, prot::launch_round_costs(C, n_b, n_a, ldc, ei, c->kmat, ldk, c->ctl, c->stream,
+                                        k8));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-    rc = run_loop(c, c->kmat, n_b, n_a, ldk, T, o, 0, mate_a, mate_b, y_a, y_b);
+    rc = run_loop(c, c->kmat, n_b, n_a, ldk, T, o, 0, mate_a, mate_b, y_a, y_b, OnTheFly(),
+                  Copies(), k8);
     if (rc) return rc;
     HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, 1, C, ldc, nullptr, nullptr, 0,
-                                     c->part_k, c->part_c, c->stream));
+                                     c->part_k, c->part_c, c->stream, nullptr, 0.0, nullptr, k8));
     HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
     rc = collect(c, st, T, ei, 1, true);
     if (rc) return rc;
@@ -1008,13 +1030,16 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
     const bool on_the_fly = storage == PROT_COSTS_ON_THE_FLY ||
                             (storage == PROT_COSTS_AUTO && c->cost_metric == PROT_METRIC_SQEUCLIDEAN &&
                              auto_on_the_fly(d, n_b, n_a));
-    int rc = on_the_fly ? PROT_OK : ensure_matrix(c, n_b, n_a);
+    int k8 = 0;
+    int rc = on_the_fly ? PROT_OK : choose_k8(c, o, ei, &k8);
+    if (!rc && !on_the_fly) rc = ensure_matrix(c, n_b, n_a);
     if (!rc) rc = ensure_thresholds(c, ei);
     if (rc) return rc;
     int16_t *kmat = on_the_fly ? nullptr : c->kmat;
     HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
     prot::PointsJob j = points_job(c, X, Y, n_b, d, ei, kmat, ldk, n_a);
     j.no_matrix = on_the_fly ? 1 : 0;
+    j.k8 = k8;
     if (!on_the_fly && (rc = setup_mfma(c, j, n_max, &c->mfma_buf, &c->mfma_cap))) return rc;
     if ((rc = setup_prune(c, j, n_max))) return rc;
     if ((rc = setup_l1(c, j, n_b, n_a))) return rc;
@@ -1028,14 +1053,15 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
         otf.eps = ei;
     }
     rc = run_loop(c, kmat, n_b, n_a, on_the_fly ? round_up(n_a, 8) : ldk, T, o, 0, mate_a,
-                  mate_b, y_a, y_b, otf);
+                  mate_b, y_a, y_b, otf, Copies(), k8);
     if (rc) return rc;
     if (on_the_fly)
         HIP_TRY(c, prot::launch_finalize(n_b, mate_b, nullptr, 0, 2, nullptr, 0, X, Y, d,
                                          c->part_k, c->part_c, c->stream, &c->ctl->m, ei, c->th));
     else
         HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, points_cost_kind(c), nullptr,
-                                         0, X, Y, d, c->part_k, c->part_c, c->stream));
+                                         0, X, Y, d, c->part_k, c->part_c, c->stream, nullptr,
+                                         0.0, nullptr, k8));
     HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
     rc = collect(c, st, T, ei, on_the_fly ? 2 : points_cost_kind(c), true);
     if (rc) return rc;

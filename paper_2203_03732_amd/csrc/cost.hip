@@ -30,9 +30,23 @@ constexpr int kRowsPerBlock = 16;
 constexpr int kMaxRows = 256;   // rows per block of the max pass
 constexpr int kMaxD = 3;        // largest d of the low-dimensional kernels
 
+// Eight rounded costs as bytes (uint8 matrix: every real entry is at most
+// K <= 253; the padding sentinel 0x7FFF becomes 0xFF, still never admissible).
+template <class T>
+__device__ inline void store_k8(uint8_t *dst, const T *v)
+{
+    uint32_t b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[e] = (uint32_t)v[e] > 255u ? 255u : (uint32_t)v[e];
+    uint2 w;
+    w.x = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+    w.y = b[4] | (b[5] << 8) | (b[6] << 16) | (b[7] << 24);
+    *reinterpret_cast<uint2 *>(dst) = w;
+}
+
 __global__ void __launch_bounds__(kBuildThreads)
 round_costs_kernel(const float *__restrict__ C, int64_t n, int64_t na, int64_t ldc, double eps,
-                   int16_t *__restrict__ k, int64_t ldk, Ctl *ctl)
+                   int16_t *__restrict__ k, int64_t ldk, Ctl *ctl, int k8)
 {
     const int64_t col0 = ((int64_t)blockIdx.x * kBuildThreads + threadIdx.x) * kColsPerThread;
     if (col0 >= ldk) return;
@@ -51,12 +65,16 @@ round_costs_kernel(const float *__restrict__ C, int64_t n, int64_t na, int64_t l
                 v[e] = 0x7FFF;
             }
         }
-        uint4 w;
-        w.x = (uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
-        w.y = (uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16);
-        w.z = (uint16_t)v[4] | ((uint32_t)(uint16_t)v[5] << 16);
-        w.w = (uint16_t)v[6] | ((uint32_t)(uint16_t)v[7] << 16);
-        *reinterpret_cast<uint4 *>(k + b * ldk + col0) = w;
+        if (k8) {
+            store_k8(reinterpret_cast<uint8_t *>(k) + b * ldk + col0, v);
+        } else {
+            uint4 w;
+            w.x = (uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
+            w.y = (uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16);
+            w.z = (uint16_t)v[4] | ((uint32_t)(uint16_t)v[5] << 16);
+            w.w = (uint16_t)v[6] | ((uint32_t)(uint16_t)v[7] << 16);
+            *reinterpret_cast<uint4 *>(k + b * ldk + col0) = w;
+        }
     }
     if (bad) __hip_atomic_fetch_or(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -417,12 +435,16 @@ __global__ void __launch_bounds__(kBuildThreads) points_k_kernel(PointsJob j)
             for (int e = 0; e < kColsPerThread; ++e)
                 if ((pad >> e) & 1u) g[e] = 0x7FFF;
         }
-        uint4 w;
-        w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
-        w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);
-        w.z = (uint32_t)(uint16_t)g[4] | ((uint32_t)(uint16_t)g[5] << 16);
-        w.w = (uint32_t)(uint16_t)g[6] | ((uint32_t)(uint16_t)g[7] << 16);
-        *reinterpret_cast<uint4 *>(in.k + (b0 + r) * in.ldk + col0) = w;
+        if (j.k8) {
+            store_k8(reinterpret_cast<uint8_t *>(in.k) + (b0 + r) * in.ldk + col0, g);
+        } else {
+            uint4 w;
+            w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
+            w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);
+            w.z = (uint32_t)(uint16_t)g[4] | ((uint32_t)(uint16_t)g[5] << 16);
+            w.w = (uint32_t)(uint16_t)g[6] | ((uint32_t)(uint16_t)g[7] << 16);
+            *reinterpret_cast<uint4 *>(in.k + (b0 + r) * in.ldk + col0) = w;
+        }
     }
 }
 
@@ -531,10 +553,18 @@ __global__ void __launch_bounds__(256) points_tile_kernel(PointsJob j)
                     if (!ok) g[c] = refine_k(acc[i][c], g[c], K, th);
                 }
             }
-            uint2 w;
-            w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
-            w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);
-            *reinterpret_cast<uint2 *>(in.k + row * in.ldk + a0 + tx * 4) = w;
+            if (j.k8) {
+                uint32_t q[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) q[c] = (uint32_t)g[c] > 255u ? 255u : (uint32_t)g[c];
+                *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(in.k) + row * in.ldk + a0 +
+                                              tx * 4) = q[0] | (q[1] << 8) | (q[2] << 16) | (q[3] << 24);
+            } else {
+                uint2 w;
+                w.x = (uint32_t)(uint16_t)g[0] | ((uint32_t)(uint16_t)g[1] << 16);
+                w.y = (uint32_t)(uint16_t)g[2] | ((uint32_t)(uint16_t)g[3] << 16);
+                *reinterpret_cast<uint2 *>(in.k + row * in.ldk + a0 + tx * 4) = w;
+            }
         }
     }
 }
@@ -640,7 +670,7 @@ void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStre
 }  // namespace
 
 hipError_t launch_round_costs(const float *C, int64_t n, int64_t na, int64_t ldc, double eps,
-                              int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s)
+                              int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s, int k8)
 {
     PointsJob j{};
     j.batch = 1;
@@ -652,7 +682,7 @@ hipError_t launch_round_costs(const float *C, int64_t n, int64_t na, int64_t ldc
     dim3 grid((unsigned)((ldk + per_block - 1) / per_block), (unsigned)(n < 65535 ? n : 65535));
     if (n > 0)
         hipLaunchKernelGGL(round_costs_kernel, grid, dim3(kBuildThreads), 0, s, C, n, na, ldc,
-                           eps, k, ldk, ctl);
+                           eps, k, ldk, ctl, k8);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ struct PointsJob {
     // 1 Euclidean sqrt(d2 / m), 2 half the L1 distance of the vectors
     // normalised to sum 1 (X and Y then point at the normalised copies).
     int32_t metric;
-    int32_t pad_metric;
+    int32_t k8;                // 1: write k as uint8 (K <= 253, padding 0xFF); single instance
     float *l1_x, *l1_y;        // metric 2: workspace for the normalised X and Y
     int32_t d;
     int32_t batch;

@@ -74,7 +74,7 @@ struct LoopArgs {
     // by a full first-round scan that found none, was skip[b] + 1 or more).
     uint32_t *skip;
     int32_t pd;               // 0: read k
-    int32_t pad3;
+    int32_t k8;               // 1: k is a uint8 matrix (K <= 253; padding 0xFF)
     const float *px, *py;     // n x pd rows (supply) and columns (demand)
     const float *pm;          // device: max squared distance
     const float *pth;         // device: threshold table th[0..K+1]
@@ -147,7 +147,7 @@ struct LossArgs {
 
 // cost.hip
 hipError_t launch_round_costs(const float *C, int64_t n, int64_t na, int64_t ldc, double eps,
-                              int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s);
+                              int16_t *k, int64_t ldk, Ctl *ctl, hipStream_t s, int k8 = 0);
 hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s);
 
 // cost_mfma.hip
@@ -195,7 +195,7 @@ hipError_t launch_finalize(int64_t n, const int32_t *mate_b, const int16_t *k,
                            const float *X, const float *Y, int32_t d,
                            long long *part_k, double *part_c, hipStream_t s,
                            const float *m_dev = nullptr, double eps = 0.0,
-                           const float *th = nullptr);
+                           const float *th = nullptr, int k8 = 0);
 
 // Optimal transport through copies (Section 4).
 struct OtInfo {

@@ -227,6 +227,29 @@ struct MatrixSrc {
     }
 };
 
+// The same matrix stored as bytes (every cost at most K <= 253; padding 0xFF,
+// which exceeds every y(b) - 1 and so is never admissible): half the bytes
+// per entry. A chunk is 8 bytes, widened to the int16 layout of MatrixSrc.
+struct MatrixSrc8 {
+    static constexpr int kAhead = kPrefetch;
+    static constexpr int kTeamAhead = kTeamPrefetch;
+    static constexpr int kBatch = kSlotBatch;
+    const uint8_t *k;
+    int64_t ldk;
+    using Row = const uint8_t *;
+    __device__ Row row(int b) const { return k + (int64_t)b * ldk; }
+    __device__ uint4 chunk(const Row &r, int col0) const
+    {
+        const uint2 v = *reinterpret_cast<const uint2 *>(r + col0);
+        // bytes c0 c1 c2 c3 -> halfwords c0, c1 and c2, c3 (byte 0x0C of the
+        // selector gives zero)
+        return uint4{__builtin_amdgcn_perm(0u, v.x, 0x0c010c00u),
+                     __builtin_amdgcn_perm(0u, v.x, 0x0c030c02u),
+                     __builtin_amdgcn_perm(0u, v.y, 0x0c010c00u),
+                     __builtin_amdgcn_perm(0u, v.y, 0x0c030c02u)};
+    }
+};
+
 template <int D>
 struct PointsSrc {
     // computing ahead buys less than loading ahead and costs 8 * D registers
@@ -506,8 +529,16 @@ struct SrcOf<0> {
     using type = MatrixSrc;
     static __device__ type make(const LoopArgs &A) { return MatrixSrc{A.k, A.ldk}; }
 };
+template <>
+struct SrcOf<1> {
+    using type = MatrixSrc8;
+    static __device__ type make(const LoopArgs &A)
+    {
+        return MatrixSrc8{reinterpret_cast<const uint8_t *>(A.k), A.ldk};
+    }
+};
 
-// kSrcD: 0 reads the rounded-cost matrix; 2 or 3 computes it from points of
+// kSrcD: 0 reads the rounded-cost matrix (1: stored as bytes); 2 or 3 computes it from points of
 // that dimension (matrix-free). kFF: exact fast-forward through A.skip.
 // kCopies: the rows are copies of the transport reduction (A.rmap, A.ymax).
 template <bool kMulti, int kSrcD, bool kFF, bool kCopies = false>
@@ -1088,7 +1119,7 @@ __global__ void __launch_bounds__(kFinalizeThreads)
 finalize_kernel(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk, int cost_kind,
                 const float *C, int64_t ldc, const float *X, const float *Y, int32_t d,
                 long long *part_k, double *part_c, const float *m_dev, double eps,
-                const float *th)
+                const float *th, int k8)
 {
     // costs on the fly: the cost build's rounding of each matched pair
     int K = 0;
@@ -1109,7 +1140,7 @@ finalize_kernel(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk,
         const int32_t a = mate_b[b];
         if (a < 0) continue;
         if (k) {
-            ks += k[b * ldk + a];
+            ks += k8 ? reinterpret_cast<const uint8_t *>(k)[b * ldk + a] : k[b * ldk + a];
         } else if (m_dev) {
             const float sq = sqdist<0>(X + b * d, Y + (int64_t)a * d, d);
             bool ok;
@@ -1354,8 +1385,9 @@ hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
     const void *fn = a.rmap      ? (const void *)phase_loop_kernel<false, 0, false, true>
                      : a.pd == 2 ? (const void *)phase_loop_kernel<false, 2, false>
                      : a.pd == 3 ? (const void *)phase_loop_kernel<false, 3, false>
+                     : a.k8      ? (const void *)phase_loop_kernel<false, 1, false>
                                  : (const void *)phase_loop_kernel<false, 0, false>;
-    if ((a.pd || a.rmap) && lds > 64 * 1024) {
+    if ((a.pd || a.rmap || a.k8) && lds > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);
         if (e != hipSuccess) return e;
@@ -1429,11 +1461,12 @@ hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a, i
 hipError_t launch_finalize(int64_t n, const int32_t *mate_b, const int16_t *k, int64_t ldk,
                            int cost_kind, const float *C, int64_t ldc, const float *X,
                            const float *Y, int32_t d, long long *part_k, double *part_c,
-                           hipStream_t s, const float *m_dev, double eps, const float *th)
+                           hipStream_t s, const float *m_dev, double eps, const float *th,
+                           int k8)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3(kFinalizeBlocks), dim3(kFinalizeThreads), 0, s, n,
                        mate_b, k, ldk, cost_kind, C, ldc, X, Y, d, part_k, part_c, m_dev, eps,
-                       th);
+                       th, k8);
     return hipGetLastError();
 }
 

@@ -446,3 +446,42 @@ def test_max_phases_partial_leaves_state_uncompleted(ctx):
     assert ref["status"] == "partial" and gpu.status == "partial"
     assert ref["stats"]["completed_pairs"] == 0
     assert_same(gpu, ref)
+
+
+@pytest.mark.parametrize("k_type", ["int16", "uint8"])
+def test_matrix_element_types(ctx, k_type):
+    """The stored matrix as int16 or as bytes (floor(1/eps) <= 253): the
+    same results, on point sets (square and rectangular, both origins), on a
+    cost matrix, and with the Euclidean cost."""
+    for n, n_a, d, eps, origin in [(2000, 2000, 2, 0.01, "diag"), (1500, 2300, 3, 0.005, "zero"),
+                                   (777, 777, 16, 0.05, "diag")]:
+        X, Y = synth.uniform_points(n, d, seed=n + d, n_a=n_a)
+        gpu = ctx.solve_points(dev(X), dev(Y), eps, origin=origin, storage="matrix",
+                               k_type=k_type)
+        k, _ = oracle.round_points_f32(X, Y, eps)
+        orc = oracle.solve_rounded(k, oracle.threshold(eps, n), origin=origin)
+        assert_same(gpu, orc, f"points {n}x{n_a} {k_type}")
+    C = synth.uniform_costs(1000, seed=4)
+    gpu = ctx.solve_cost(dev(C), 0.1, k_type=k_type)
+    orc = oracle.solve_rounded(oracle.round_cost(C, 0.1), oracle.threshold(0.1, 1000))
+    assert_same(gpu, orc, f"costs {k_type}")
+    X, Y = synth.uniform_points(1200, 2, seed=8)
+    ctx.set_cost_metric("euclidean")
+    try:
+        gpu = ctx.solve_points(dev(X), dev(Y), 0.01, k_type=k_type)
+    finally:
+        ctx.set_cost_metric("sqeuclidean")
+    k, _ = oracle.round_points_euclid_f32(X, Y, 0.01)
+    assert_same(gpu, oracle.solve_rounded(k, oracle.threshold(0.01, 1200)), f"euclid {k_type}")
+
+
+def test_byte_matrix_needs_small_k(ctx):
+    import paper_2203_03732_amd as prot
+    X, Y = synth.uniform_points(300, 2, seed=2)
+    with pytest.raises(prot.ProtError) as e:
+        ctx.solve_points(dev(X), dev(Y), 0.002, k_type="uint8")  # floor(1/eps) = 500
+    assert e.value.name == "unsupported"
+    # the automatic choice keeps int16 there
+    gpu = ctx.solve_points(dev(X), dev(Y), 0.002)
+    k, _ = oracle.round_points_f32(X, Y, 0.002)
+    assert_same(gpu, oracle.solve_rounded(k, oracle.threshold(0.002, 300)), "auto K=500")
