@@ -74,16 +74,25 @@ def bench_batched(prot, synth, torch, reps=10):
     X = torch.from_numpy(np.concatenate(Xs)).cuda()
     Y = torch.from_numpy(np.concatenate(Ys)).cuda()
     ctx = prot.Context(0)
-    plan = ctx.batch(ns, 16, 0.05)
-    plan.run(X, Y)
-    plan.capture(X, Y)
-    plan.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def replay_ms_of(plan):
+        plan.run(X, Y)
+        plan.capture(X, Y)
         plan.replay()
-    torch.cuda.synchronize()
-    replay_ms = 1e3 * (time.perf_counter() - t0) / reps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.replay()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    default_plan = ctx.batch(ns, 16, 0.05)
+    default_ms = replay_ms_of(default_plan)
+    default_plan.close()
+    # the autotuner times every configuration on these inputs (untimed here)
+    cfg, tuned_ms, tried = ctx.autotune_batch(ns, 16, 0.05, X, Y, reps=3)
+    plan = ctx.batch(ns, 16, 0.05, config=cfg)
+    replay_ms = replay_ms_of(plan)
     Xl = [torch.from_numpy(x).cuda() for x in Xs]
     Yl = [torch.from_numpy(y).cuda() for y in Ys]
     ctx.reserve(max(ns), with_matrix=True)
@@ -104,6 +113,8 @@ def bench_batched(prot, synth, torch, reps=10):
             "plain_loop_ms": round(loop_ms, 3),
             "plain_loop_solves_per_s": round(512 / (loop_ms * 1e-3), 1),
             "ratio_vs_plain_loop": round(loop_ms / replay_ms, 2),
+            "autotuned_config": cfg, "configs_timed": tried,
+            "default_config_replay_ms": round(default_ms, 4),
             "mean_phases": round(float(np.mean([s["phases"] for s in st])), 2)}
 
 

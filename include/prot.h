@@ -297,6 +297,41 @@ int32_t prot_batch_max_n(void);
  * device workspace (metadata, one rounded-cost matrix per instance). */
 int prot_batch_create(prot_ctx *ctx, int32_t batch, const int64_t *n_host, int32_t d,
                       double eps, const prot_opts *opts, prot_batch **out);
+
+/* How a batch runs (results are the same for every choice):
+ *   engine   PROT_BATCH_ENGINE_LDS: one workgroup solves a whole instance
+ *            with its state in LDS (n <= 2048); PROT_BATCH_ENGINE_TEAMS:
+ *            `team` workgroups of the persistent phase loop per instance;
+ *            PROT_BATCH_ENGINE_AUTO: LDS up to n_max = 1024, teams above.
+ *   team     TEAMS: workgroups per instance, 1..8 (0: as many as fit);
+ *            PROT_E_UNSUPPORTED if fewer than ceil(n_max / 1024) or more
+ *            than fit next to each other on the GPU.
+ *   cost_path  PROT_COST_DIRECT / PROT_COST_MATRIX_CORES, or -1 for the
+ *            context's setting. */
+enum { PROT_BATCH_ENGINE_AUTO = 0, PROT_BATCH_ENGINE_LDS = 1, PROT_BATCH_ENGINE_TEAMS = 2 };
+typedef struct {
+    int32_t engine;
+    int32_t team;
+    int32_t cost_path;
+    int32_t reserved;
+} prot_batch_config;
+
+/* prot_batch_create with an explicit configuration (NULL = automatic). */
+int prot_batch_create_config(prot_ctx *ctx, int32_t batch, const int64_t *n_host, int32_t d,
+                             double eps, const prot_opts *opts, const prot_batch_config *cfg,
+                             prot_batch **out);
+
+/* Autotuner: times every configuration that applies to this batch (the LDS
+ * engine, teams of each size that fits, both cost paths for d >= 16) on
+ * the caller's inputs X, Y (device, the plan's packed layout), each run
+ * once to warm up and then `reps` times (HIP events on the context
+ * stream), and returns the fastest in *best, its mean time in *best_ms and
+ * the number of configurations timed in *tried. Allocates its own
+ * scratch outputs; synchronises the stream. */
+int prot_batch_autotune(prot_ctx *ctx, int32_t batch, const int64_t *n_host, int32_t d,
+                        double eps, const prot_opts *opts, const float *X, const float *Y,
+                        int32_t reps, prot_batch_config *best, double *best_ms,
+                        int32_t *tried);
 int prot_batch_destroy(prot_batch *plan);
 
 /* Enqueue the whole batched solve on the context stream; no synchronisation.

@@ -61,6 +61,24 @@ class OTStats(ctypes.Structure):
         return d
 
 
+class BatchConfig(ctypes.Structure):
+    """prot_batch_config: engine (0 auto, 1 LDS, 2 teams), team, cost_path
+    (-1: the context's)."""
+    _fields_ = [("engine", ctypes.c_int32), ("team", ctypes.c_int32),
+                ("cost_path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    ENGINES = {"auto": 0, "lds": 1, "teams": 2}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "BatchConfig":
+        return cls(cls.ENGINES[d.get("engine", "auto")], int(d.get("team", 0)),
+                   int(d.get("cost_path", -1)), 0)
+
+    def as_dict(self) -> dict:
+        names = {v: k for k, v in self.ENGINES.items()}
+        return {"engine": names[self.engine], "team": self.team, "cost_path": self.cost_path}
+
+
 class InstanceStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "phases", "sum_free", "rounds", "max_rounds", "scanned", "matched_in_phases",
@@ -91,6 +109,7 @@ EXPORTS = [
     "prot_solve_cost_rect", "prot_solve_points_rect", "prot_ot_solve", "prot_set_cost_metric",
     "prot_get_trace",
     "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
+    "prot_batch_create_config", "prot_batch_autotune",
     "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
     "prot_batch_loss_fwd", "prot_batch_loss_bwd",
     "prot_status_string", "prot_last_error",
@@ -141,6 +160,11 @@ def load():
         "prot_get_trace": (i64, [p, p, i64]),
         "prot_get_round_times": (i64, [p, p, i64]),
         "prot_batch_max_n": (i32, []),
+        "prot_batch_create_config": (ctypes.c_int, [p, i32, p, i32, f64, ctypes.POINTER(Opts),
+                                                     ctypes.POINTER(BatchConfig), ctypes.POINTER(p)]),
+        "prot_batch_autotune": (ctypes.c_int, [p, i32, p, i32, f64, ctypes.POINTER(Opts), p, p,
+                                               i32, ctypes.POINTER(BatchConfig),
+                                               ctypes.POINTER(f64), ctypes.POINTER(i32)]),
         "prot_batch_create": (ctypes.c_int, [p, i32, p, i32, f64, ctypes.POINTER(Opts),
                                              ctypes.POINTER(p)]),
         "prot_batch_destroy": (ctypes.c_int, [p]),
@@ -442,16 +466,35 @@ class Context:
 
     def cached_batch(self, ns, d: int, eps: float, **kw) -> "Batch":
         """A plan reused across calls with the same shapes and options."""
-        key = (tuple(int(x) for x in ns), int(d), float(eps), tuple(sorted(kw.items())))
+        key = (tuple(int(x) for x in ns), int(d), float(eps),
+               tuple(sorted((k, repr(v)) for k, v in kw.items())))
         cache = self.__dict__.setdefault("_plans", {})
         if key not in cache:
             cache[key] = Batch(self, ns, d, eps, **kw)
         return cache[key]
 
     def batch(self, ns, d: int, eps: float, *, eps_mode="algorithmic", origin="diag",
-              complete=True, max_phases=0) -> "Batch":
+              complete=True, max_phases=0, config=None) -> "Batch":
+        """config: None (automatic), a dict {'engine': 'lds'|'teams'|'auto',
+        'team': w, 'cost_path': -1|0|1} or a BatchConfig."""
         return Batch(self, ns, d, eps, eps_mode=eps_mode, origin=origin, complete=complete,
-                     max_phases=max_phases)
+                     max_phases=max_phases, config=config)
+
+    def autotune_batch(self, ns, d: int, eps: float, X, Y, *, reps: int = 3,
+                       eps_mode="algorithmic", origin="diag", max_phases=0):
+        """Time every batch configuration on X, Y (prot_batch_autotune);
+        returns (best config dict, its mean ms, number of configurations)."""
+        import numpy as np
+        torch = _torch()
+        ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int64))
+        o = self._opts(eps_mode, origin, True, max_phases)
+        best, ms, tried = BatchConfig(), ctypes.c_double(), ctypes.c_int32()
+        self._bind_stream()
+        self._check(self._lib.prot_batch_autotune(
+            self._h, len(ns), ns.ctypes.data_as(ctypes.c_void_p), int(d), float(eps),
+            ctypes.byref(o), _dev_ptr(X, torch.float32, "X", 2), _dev_ptr(Y, torch.float32, "Y", 2),
+            int(reps), ctypes.byref(best), ctypes.byref(ms), ctypes.byref(tried)))
+        return best.as_dict(), ms.value, tried.value
 
     def solve_batched_points(self, ns, X, Y, eps: float, *, eps_mode="algorithmic",
                              origin="diag", complete=True, max_phases=0):
@@ -499,9 +542,13 @@ class Batch:
         h = ctypes.c_void_p()
         o = Context._opts(kw.get("eps_mode", "algorithmic"), kw.get("origin", "diag"),
                           kw.get("complete", True), kw.get("max_phases", 0))
-        ctx._check(ctx._lib.prot_batch_create(ctx._h, len(self.ns),
-                                              self.ns.ctypes.data_as(ctypes.c_void_p), self.d,
-                                              float(eps), ctypes.byref(o), ctypes.byref(h)))
+        cfg = kw.get("config")
+        cfg = None if cfg is None else (cfg if isinstance(cfg, BatchConfig)
+                                        else BatchConfig.from_dict(cfg))
+        ctx._check(ctx._lib.prot_batch_create_config(
+            ctx._h, len(self.ns), self.ns.ctypes.data_as(ctypes.c_void_p), self.d, float(eps),
+            ctypes.byref(o), ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(h)))
+        self.config = None if cfg is None else cfg.as_dict()
         self._h = h
         torch = _torch()
         self.mate_a, self.mate_b, self.y_a, self.y_b = ctx._outputs(self.total)

@@ -541,11 +541,14 @@ int upload(prot_ctx *c, T **dst, const std::vector<T> &src)
 // w workgroups per instance (0: never use teams).
 int setup_teams(prot_ctx *c, prot_batch *bp, const std::vector<int32_t> &n_arr,
                 const std::vector<int32_t> &ldk, const std::vector<int64_t> &pt_off,
-                const std::vector<int64_t> &k_off)
+                const std::vector<int64_t> &k_off, const prot_batch_config *cfg)
 {
-    int forced = -1;
-    if (const char *v = std::getenv("PROT_BATCH_TEAM")) forced = std::atoi(v);
-    if (forced == 0 || (forced < 0 && bp->n_max <= 1024)) return PROT_OK;
+    int forced = -1;  // -1 automatic, 0 LDS engine, > 0 that team size
+    if (cfg && cfg->engine == PROT_BATCH_ENGINE_LDS) forced = 0;
+    else if (cfg && cfg->engine == PROT_BATCH_ENGINE_TEAMS) forced = cfg->team > 0 ? cfg->team : -2;
+    else if (const char *v = std::getenv("PROT_BATCH_TEAM")) forced = std::atoi(v);
+    const bool must = cfg && cfg->engine == PROT_BATCH_ENGINE_TEAMS;
+    if (forced == 0 || (forced == -1 && bp->n_max <= 1024)) return PROT_OK;
     const int32_t n_pad_max = (int32_t)round_up(bp->n_max, 8);
     int gm = 0;
     hipError_t e = prot::loop_grid_multi(n_pad_max, c->wgs_per_cu, &gm);
@@ -555,9 +558,15 @@ int setup_teams(prot_ctx *c, prot_batch *bp, const std::vector<int32_t> &n_arr,
     // ceil(n_max / (64 * 16)) workgroups at least
     const int wpg = prot::kLoopThreads / 64;
     const int team_min = (int)((bp->n_max + 64 * wpg - 1) / (64 * wpg));
+    if (must && (forced > 8 || (forced > 0 && forced < team_min)))
+        return fail(c, PROT_E_UNSUPPORTED, "team of %d workgroups for n_max = %d", forced,
+                    (int)bp->n_max);
     int team = forced > 0 ? forced : gm / bp->batch;
     team = std::max(team_min, std::min(team, 8));
-    if (team > gm) return PROT_OK;  // keep the LDS-resident kernel
+    if (team > gm) {
+        if (must) return fail(c, PROT_E_UNSUPPORTED, "a team of %d does not fit", team);
+        return PROT_OK;  // keep the LDS-resident kernel
+    }
     bp->team = team;
     bp->per_launch = gm / team;
     bp->n_pad_max = n_pad_max;
@@ -1220,9 +1229,19 @@ int32_t prot_batch_max_n(void) { return prot::batch_max_n(); }
 int prot_batch_create(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t d, double eps,
                       const prot_opts *o, prot_batch **out)
 {
+    return prot_batch_create_config(c, batch, n_host, d, eps, o, nullptr, out);
+}
+
+int prot_batch_create_config(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t d,
+                             double eps, const prot_opts *o, const prot_batch_config *cfg,
+                             prot_batch **out)
+{
     if (!c) return PROT_E_ARG;
     if (!out || batch < 0 || (batch > 0 && !n_host) || d < 1)
         return fail(c, PROT_E_ARG, "prot_batch_create: bad arguments");
+    if (cfg && (cfg->engine < PROT_BATCH_ENGINE_AUTO || cfg->engine > PROT_BATCH_ENGINE_TEAMS ||
+                cfg->team < 0 || cfg->cost_path < -1 || cfg->cost_path > PROT_COST_MATRIX_CORES))
+        return fail(c, PROT_E_ARG, "prot_batch_create: bad configuration");
     *out = nullptr;
     const double ei = eps_internal(eps, o);
     if (!eps_valid(ei)) return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
@@ -1281,10 +1300,13 @@ int prot_batch_create(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t
         prot::PointsJob j{};
         j.d = d;
         j.batch = batch;
+        const int32_t path = c->cost_path;
+        if (cfg && cfg->cost_path >= 0) c->cost_path = cfg->cost_path;
         rc = setup_mfma(c, j, n_max, &bp->mfma_buf, &bp->mfma_cap);
+        c->cost_path = path;
         bp->mfma = j.mfma;
     }
-    if (!rc && batch > 0) rc = setup_teams(c, bp, n_arr, ldk, pt_off, k_off);
+    if (!rc && batch > 0) rc = setup_teams(c, bp, n_arr, ldk, pt_off, k_off, cfg);
     if (rc) {
         prot_batch_destroy(bp);
         return rc;
@@ -1334,6 +1356,71 @@ int prot_batch_run(prot_batch *bp, const float *X, const float *Y, int32_t *mate
         return fail(c, PROT_E_ARG, "prot_batch_run: null pointer");
     HIP_TRY(c, hipSetDevice(c->device));
     return batch_enqueue(bp, c->stream, X, Y, mate_a, mate_b, y_a, y_b, stats);
+}
+
+int prot_batch_autotune(prot_ctx *c, int32_t batch, const int64_t *n_host, int32_t d,
+                        double eps, const prot_opts *o, const float *X, const float *Y,
+                        int32_t reps, prot_batch_config *best, double *best_ms, int32_t *tried)
+{
+    if (!c) return PROT_E_ARG;
+    if (batch < 1 || !n_host || !X || !Y || !best || reps < 1)
+        return fail(c, PROT_E_ARG, "prot_batch_autotune: bad arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int64_t total = 0, n_max = 0;
+    for (int32_t i = 0; i < batch; ++i) {
+        total += n_host[i];
+        n_max = std::max<int64_t>(n_max, n_host[i]);
+    }
+    // the candidates: the LDS engine, teams of every size, each cost path
+    std::vector<prot_batch_config> cand;
+    const int paths = d >= prot::kMfmaMinD ? 2 : 1;
+    for (int path = 0; path < paths; ++path) {
+        cand.push_back(prot_batch_config{PROT_BATCH_ENGINE_LDS, 0, path, 0});
+        for (int team = 1; team <= 8; ++team)
+            if (team * 1024 >= n_max) cand.push_back(prot_batch_config{PROT_BATCH_ENGINE_TEAMS, team, path, 0});
+    }
+    int32_t *out = nullptr;
+    int rc = dev_alloc(c, &out, (size_t)(4 * total));
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipFree(out);
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(c, PROT_E_HIP, "event creation failed");
+    }
+    double best_t = -1.0;
+    int32_t count = 0;
+    for (const prot_batch_config &cf : cand) {
+        prot_batch *bp = nullptr;
+        if (prot_batch_create_config(c, batch, n_host, d, eps, o, &cf, &bp) != PROT_OK) continue;
+        int r = prot_batch_run(bp, X, Y, out, out + total, out + 2 * total, out + 3 * total,
+                               nullptr);
+        float ms = 0.0f;
+        if (r == PROT_OK && hipEventRecord(e0, c->stream) == hipSuccess) {
+            for (int i = 0; i < reps && r == PROT_OK; ++i)
+                r = prot_batch_run(bp, X, Y, out, out + total, out + 2 * total, out + 3 * total,
+                                   nullptr);
+            if (r == PROT_OK && (hipEventRecord(e1, c->stream) != hipSuccess ||
+                                 hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                r = PROT_E_HIP;
+        }
+        prot_batch_destroy(bp);
+        if (r != PROT_OK) continue;
+        count += 1;
+        const double t = (double)ms / reps;
+        if (best_t < 0.0 || t < best_t) {
+            best_t = t;
+            *best = cf;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (tried) *tried = count;
+    if (best_ms) *best_ms = best_t;
+    if (count == 0) return fail(c, PROT_E_UNSUPPORTED, "no configuration ran");
+    return PROT_OK;
 }
 
 int prot_batch_capture(prot_batch *bp, const float *X, const float *Y, int32_t *mate_a,

@@ -191,3 +191,68 @@ def test_batched_rejects_oversized_instance(ctx):
     with pytest.raises(prot.ProtError) as e:
         ctx.solve_batched_points([n], X, X.clone(), 0.1)
     assert e.value.name == "unsupported"
+
+
+@pytest.mark.parametrize("config", [{"engine": "lds"}, {"engine": "teams", "team": 2},
+                                    {"engine": "teams", "team": 8},
+                                    {"engine": "teams", "team": 0},
+                                    {"engine": "lds", "cost_path": 1},
+                                    {"engine": "teams", "team": 4, "cost_path": 1}])
+def test_every_batch_configuration_gives_the_same_instances(ctx, config):
+    """The configurations the autotuner chooses among (engine, team size,
+    cost path) all give every instance exactly as the oracle."""
+    rng = np.random.default_rng(5)
+    d, eps = 16, 0.05
+    ns = [1, 64, 300, 1024, 1025, 1500]
+    Xs = [rng.standard_normal((n, d)).astype(np.float32) for n in ns]
+    Ys = [rng.standard_normal((n, d)).astype(np.float32) for n in ns]
+    plan = ctx.batch(ns, d, eps, config=config)
+    X, Y = pack(Xs), pack(Ys)
+    plan.run(X, Y)
+    torch.cuda.synchronize()
+    check_instances(ns, Xs, Ys, eps, (plan.mate_a, plan.mate_b, plan.y_a, plan.y_b),
+                    plan.stats())
+    plan.close()
+
+
+def test_batch_configuration_rejections(ctx):
+    import paper_2203_03732_amd as prot
+    with pytest.raises(prot.ProtError) as e:
+        ctx.batch([1500, 20], 4, 0.1, config={"engine": "teams", "team": 1})  # needs 2
+    assert e.value.name == "unsupported"
+    with pytest.raises(prot.ProtError) as e:
+        ctx.batch([10], 4, 0.1, config={"engine": "teams", "team": 9})
+    assert e.value.name == "unsupported"
+    with pytest.raises(prot.ProtError) as e:
+        ctx.batch([10], 4, 0.1, config={"engine": "lds", "cost_path": 5})
+    assert e.value.name == "arg"
+
+
+def test_autotuner_picks_a_configuration_and_caches_it(ctx, tmp_path):
+    from paper_2203_03732_amd import autotune
+    rng = np.random.default_rng(9)
+    d, eps = 16, 0.05
+    ns = [int(x) for x in rng.integers(64, 700, 40)]
+    Xs = [rng.standard_normal((n, d)).astype(np.float32) for n in ns]
+    Ys = [rng.standard_normal((n, d)).astype(np.float32) for n in ns]
+    X, Y = pack(Xs), pack(Ys)
+    cfg, ms, tried = ctx.autotune_batch(ns, d, eps, X, Y, reps=2)
+    assert tried >= 10 and ms > 0  # LDS + 8 team sizes, two cost paths
+    assert cfg["engine"] in ("lds", "teams") and cfg["cost_path"] in (0, 1)
+    path = str(tmp_path / "tune.json")
+    plan = autotune.tuned_batch(ctx, ns, d, eps, X, Y, reps=1, path=path)
+    entry = autotune.load(path)
+    assert len(entry) == 1
+    key = next(iter(entry))
+    assert plan.config == {k: entry[key][k] for k in ("engine", "team", "cost_path")}
+    plan.run(X, Y)
+    torch.cuda.synchronize()
+    check_instances(ns, Xs, Ys, eps, (plan.mate_a, plan.mate_b, plan.y_a, plan.y_b),
+                    plan.stats(), which=[0, 7, 39])
+    plan.close()
+    # a second plan of the same class reads the cache and times nothing
+    mtime = (tmp_path / "tune.json").stat().st_mtime_ns
+    plan2 = autotune.tuned_batch(ctx, ns, d, eps, X, Y, reps=1, path=path)
+    assert (tmp_path / "tune.json").stat().st_mtime_ns == mtime
+    assert plan2.config == plan.config
+    plan2.close()
