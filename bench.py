@@ -261,7 +261,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for {args.gpus}); "
               "the solver has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 

@@ -43,7 +43,7 @@ enum {
     PROT_E_STATE = -5,         /* warm-start state violates (I1) or is not a matching */
     PROT_E_HIP = -6,           /* a HIP runtime call failed */
     PROT_E_NOMEM = -7,         /* device allocation failed */
-    PROT_E_UNSUPPORTED = -8    /* size beyond this build's limits */
+    PROT_E_UNSUPPORTED = -8    /* size beyond the library's limits */
 };
 
 enum { PROT_EPS_ALGORITHMIC = 0, PROT_EPS_STRICT = 1 };

@@ -247,8 +247,8 @@ int orc_points_cost_f64(const float *X, const float *Y, int64_t n_b,
 /* ------------------------------------------------------------------ */
 
 /* Column visited at step j of the scan of row b. The paper lets a free b
- * take "the first" admissible edge (proof of Lemma 3.4) without fixing an
- * order. Reading used here: DIAG starts row b at column b and wraps around,
+ * take the first admissible edge it meets (proof of Lemma 3.4) without
+ * fixing the order in which it looks. Reading used here: DIAG starts row b at column b and wraps around,
  * ZERO starts every row at column 0. */
 static int64_t scan_col(int32_t origin_mode, int64_t b, int64_t j, int64_t n)
 {
