@@ -242,6 +242,46 @@ def bench_ot_loss(prot, synth, torch, reps=5):
             "fwd_bwd_ms": round(ms, 3)}
 
 
+def phase_report(prot, synth, torch, n, d, eps, seed):
+    """Per-phase evidence for the phase loop: |B'|, proposal rounds, entries
+    examined, |M'|, the phase's device time from the per-round timestamps
+    (PROT_DEBUG_ROUND_TIMES; the timestamps add a little time of their own)
+    and the useful scan rate (2 B per entry examined / time)."""
+    import numpy as np
+    os.environ["PROT_DEBUG_ROUND_TIMES"] = "1"
+    X, Y = synth.uniform_points(n, d, seed=seed)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    ctx = prot.Context(0)
+    for _ in range(3):
+        res = ctx.solve_points(Xd, Yd, eps)
+    torch.cuda.synchronize()
+    tr = ctx.trace()
+    rt = ctx.round_times()
+    ctx.close()
+    loop_us = 1e3 * res.stats["ms_loop_kernel"]
+    # last exit (100 MHz ticks) of every phase's rounds
+    ends = {}
+    for arr, ex, ph in rt:
+        ends[int(ph)] = max(ends.get(int(ph), 0), int(ex))
+    phases = len(tr)
+    dur = np.zeros(phases)
+    for p in range(1, phases):
+        if p in ends and p - 1 in ends:
+            dur[p] = (ends[p] - ends[p - 1]) / 100.0
+    dur[0] = max(loop_us - dur[1:].sum(), 0.0)  # phase 0 also holds the launch
+    print(f"# per-phase report: n={n} d={d} eps={eps} seed={seed}; loop {loop_us:.1f} us "
+          f"with round timestamps on", flush=True)
+    print(f"{'phase':>5s} {'|B_i|':>7s} {'rounds':>6s} {'entries':>11s} {'|M_i|':>6s} "
+          f"{'us':>8s} {'GB/s':>8s}")
+    for p in range(phases):
+        gbs = 2.0 * tr[p, 2] / (dur[p] * 1e-6) / 1e9 if dur[p] > 0 else 0.0
+        print(f"{p:5d} {tr[p, 0]:7d} {tr[p, 1]:6d} {tr[p, 2]:11d} {tr[p, 3]:6d} {dur[p]:8.1f} "
+              f"{gbs:8.1f}")
+    tot = 2.0 * tr[:, 2].sum()
+    print(f"total: {tr[:, 2].sum()} entries, {tot / 1e6:.1f} MB useful in {loop_us:.1f} us = "
+          f"{tot / (loop_us * 1e-6) / 1e9:.1f} GB/s (bytes-weighted over the phases)", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +295,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and OT-loss measurements")
+    ap.add_argument("--phase-report", action="store_true",
+                    help="print a per-phase table of the phase loop instead of the bench line")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the bench, run 5 plain device copies of this many MiB "
                          "(reference kernel for scaling memory counters)")
@@ -273,6 +315,9 @@ def main():
 
     torch.cuda.set_device(0)
     n, d, eps = args.n, args.d, args.eps
+    if args.phase_report:
+        phase_report(prot, synth, torch, n, d, eps, args.seed)
+        return
     X, Y = synth.uniform_points(n, d, seed=args.seed)
     Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
     ctx = prot.Context(0)
