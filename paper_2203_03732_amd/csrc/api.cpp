@@ -63,6 +63,7 @@ struct prot_ctx {
     int64_t mfma_cap = 0;
     int64_t rtime_start = 0;
     int wgs_per_cu = 1;              // PROT_LOOP_WGS_PER_CU (diagnostics)
+    int max_grid = 0;                // PROT_LOOP_MAX_GRID: cap on the loop's workgroups (0: none)
     int grid_npad = -1;
     int grid_max = 0;
     // optimal transport through copies (prot_ot_solve)
@@ -224,6 +225,7 @@ int grid_for(prot_ctx *c, int64_t n, int64_t n_a, int *grid)
                     (long long)n, (long long)min_grid, c->grid_max);
     int64_t g = (n + wpg - 1) / wpg;  // one row per wave when n is small
     if (g > c->grid_max) g = c->grid_max;
+    if (c->max_grid > 0 && g > c->max_grid) g = std::max<int64_t>(c->max_grid, min_grid);
     if (g < 1) g = 1;
     *grid = (int)g;
     return PROT_OK;
@@ -772,6 +774,7 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
         const int w = std::atoi(v);
         if (w >= 1 && w <= 8) c->wgs_per_cu = w;
     }
+    if (const char *v = std::getenv("PROT_LOOP_MAX_GRID")) c->max_grid = std::atoi(v);
     if (!rc) {
         const char *v = std::getenv("PROT_DEBUG_ROUND_TIMES");
         if (v && v[0] == '1') rc = dev_alloc(c, &c->rtime, (size_t)3 * prot::kRoundTimeCap);

@@ -277,3 +277,22 @@ def test_points_rect_large_auto(ctx):
     assert orc["stats"]["phases"] > 100
     assert gpu.stats["cost_scale"] == m
     assert_same(gpu, orc, "20000x30000")
+
+
+def test_rect_at_the_column_limit(ctx):
+    """The column duals live in one workgroup's LDS (2 bytes each): 80,000
+    columns is close to the limit and runs; 90,000 are refused."""
+    import paper_2203_03732_amd as prot
+    n_b, n_a, K, T = 200, 80000, 10, 2
+    k = (20 + synth.random_k(n_b, K, seed=41, n_a=n_a)).astype(np.int16)  # ~20 empty phases
+    orc = oracle.solve_rounded(k, T)
+    gpu = ctx.solve_rounded(padded_k(k), T, n_b, n_a=n_a)
+    assert_same(gpu, orc, "80000 columns")
+    X, Y = synth.uniform_points(300, 2, seed=42, n_a=80000)
+    gpu = ctx.solve_points(dev(X), dev(Y), 0.01, storage="on_the_fly")
+    kk, m = oracle.round_points_f32(X, Y, 0.01)
+    assert_same(gpu, oracle.solve_rounded(kk, oracle.threshold(0.01, 300)), "80000 on the fly")
+    X, Y = synth.uniform_points(10, 2, seed=43, n_a=90000)
+    with pytest.raises(prot.ProtError) as e:
+        ctx.solve_points(dev(X), dev(Y), 0.1)
+    assert e.value.name == "unsupported"
