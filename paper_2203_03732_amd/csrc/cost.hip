@@ -235,7 +235,41 @@ __global__ void __launch_bounds__(256) extent_kernel(PointsJob j)
                 hi[w][q] = fmaxf(hi[w][q], __shfl_xor(hi[w][q], off));
             }
     }
+    // then over the block's four waves in LDS, and one set of atomics per
+    // block (all waves updating the same few words would serialise on them)
+    __shared__ unsigned long long s_ex[4][U], s_ey[4][U];
+    __shared__ float s_lo[4][2][D], s_hi[4][2][D];
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s_ex[wv][u] = ex[u];
+            s_ey[wv][u] = ey[u];
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                s_lo[wv][w][q] = lo[w][q];
+                s_hi[wv][w][q] = hi[w][q];
+            }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)(blockDim.x >> 6); ++v) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ex[u] = s_ex[v][u] > ex[u] ? s_ex[v][u] : ex[u];
+                ey[u] = s_ey[v][u] > ey[u] ? s_ey[v][u] : ey[u];
+            }
+#pragma unroll
+            for (int q = 0; q < D; ++q)
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    lo[w][q] = fminf(lo[w][q], s_lo[v][w][q]);
+                    hi[w][q] = fmaxf(hi[w][q], s_hi[v][w][q]);
+                }
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             __hip_atomic_fetch_max(&P.ext[u], ex[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -650,7 +684,8 @@ void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStre
     if (j.prune.cx && j.batch == 1) {
         const unsigned g = (unsigned)std::min<int64_t>(1024, (n_max + 255) / 256);
         hipLaunchKernelGGL(prune_reset_kernel, dim3(1), dim3(64), 0, s, j.prune);
-        hipLaunchKernelGGL(extent_kernel<D>, dim3(g), dim3(256), 0, s, j);
+        // few blocks: the extremes end in one set of atomics per block
+        hipLaunchKernelGGL(extent_kernel<D>, dim3(std::min(g, 64u)), dim3(256), 0, s, j);
         hipLaunchKernelGGL(prune_kernel<D>, dim3(g), dim3(256), 0, s, j);
         hipLaunchKernelGGL(pairs_max_kernel<D>, dim3(1024), dim3(kBuildThreads), 0, s, j);
     } else {

@@ -1057,29 +1057,52 @@ __global__ void decode_kernel(LoopArgs a, int32_t *mate_a, int32_t *mate_b, int3
 
 constexpr int kCompleteThreads = 1024;
 
-// Exclusive scan of one flag per element over [0, n), written as the list of
-// flagged indices in ascending order. One workgroup.
+// The ascending list of the indices i < n with mate[i] < 0, by one workgroup
+// of kCompleteThreads threads: tiles of kCompleteThreads consecutive indices
+// (coalesced), kListTiles tiles' loads in flight at a time, a ballot per
+// wave and an ordered prefix over the waves of the tiles. Returns the count.
+constexpr int kListTiles = 8;
+constexpr int kListWaves = kCompleteThreads / 64;
+
 __device__ int list_flags(const int32_t *mate, int n, int32_t *out, int *cnt)
 {
-    const int tid = threadIdx.x;
-    const int per = (n + kCompleteThreads - 1) / kCompleteThreads;
-    const int lo = min(n, tid * per), hi = min(n, lo + per);
-    int c = 0;
-    for (int i = lo; i < hi; ++i) c += mate[i] < 0;
-    cnt[tid] = c;
-    __syncthreads();
-    for (int off = 1; off < kCompleteThreads; off <<= 1) {
-        const int v = tid >= off ? cnt[tid - off] : 0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int base = 0;
+    for (int t0 = 0; t0 < n; t0 += kListTiles * kCompleteThreads) {
+        bool f[kListTiles];
+#pragma unroll
+        for (int q = 0; q < kListTiles; ++q) {
+            const int i = t0 + q * kCompleteThreads + tid;
+            f[q] = i < n && mate[i] < 0;
+        }
+        unsigned long long bal[kListTiles];
+#pragma unroll
+        for (int q = 0; q < kListTiles; ++q) {
+            bal[q] = __ballot(f[q]);
+            if (lane == 0) cnt[q * kListWaves + wv] = __popcll(bal[q]);
+        }
         __syncthreads();
-        cnt[tid] += v;
+        if (tid == 0) {
+            // index order: tile by tile, wave by wave within a tile
+            int run = 0;
+            for (int j = 0; j < kListTiles * kListWaves; ++j) {
+                const int c = cnt[j];
+                cnt[j] = run;
+                run += c;
+            }
+            cnt[kListTiles * kListWaves] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kListTiles; ++q)
+            if (f[q])
+                out[base + cnt[q * kListWaves + wv] + __popcll(bal[q] & below)] =
+                    t0 + q * kCompleteThreads + tid;
+        base += cnt[kListTiles * kListWaves];
         __syncthreads();
     }
-    int o = cnt[tid] - c;
-    for (int i = lo; i < hi; ++i)
-        if (mate[i] < 0) out[o++] = i;
-    const int total = cnt[kCompleteThreads - 1];
-    __syncthreads();
-    return total;
+    return base;
 }
 
 // Copies of the transport reduction: when the loop ends, every free copy
