@@ -218,6 +218,9 @@ int grid_for(prot_ctx *c, int64_t n, int64_t n_a, int *grid)
         c->grid_max = gm;
     }
     const int wpg = prot::kLoopThreads / 64;
+    // keys and free lists hold a row in 17 bits
+    if (n > 131071)
+        return fail(c, PROT_E_UNSUPPORTED, "%lld rows: at most 131,071", (long long)n);
     // every wave serves at most 64 rows of B' (one per lane)
     const int64_t min_grid = (n + 64 * wpg - 1) / (64 * wpg);
     if (min_grid > c->grid_max)

@@ -68,9 +68,10 @@ __device__ inline void wait_memory()
 // Value of a tagged list entry ((tag << 32) | value) once it carries `tag`.
 // The wait is bounded: on time-out bit 2 of the error word is raised and the
 // value is used as found. The value is clamped to [0, n) either way.
-// take_entry_from starts from a value v already loaded from p.
-__device__ inline int32_t take_entry_from(const unsigned long long *p, unsigned long long v,
-                                         uint32_t tag, int n, int32_t *err)
+// take_raw_from starts from a value v already loaded from p and returns the
+// 32-bit payload as found; take_entry_from clamps it to a row or column.
+__device__ inline uint32_t take_raw_from(const unsigned long long *p, unsigned long long v,
+                                        uint32_t tag, int32_t *err)
 {
     for (int spins = 0; (uint32_t)(v >> 32) != tag; v = ld_agent(p)) {
         if (++spins > kSpinLimit) {
@@ -79,7 +80,13 @@ __device__ inline int32_t take_entry_from(const unsigned long long *p, unsigned 
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    const int32_t x = (int32_t)(uint32_t)v;
+    return (uint32_t)v;
+}
+
+__device__ inline int32_t take_entry_from(const unsigned long long *p, unsigned long long v,
+                                         uint32_t tag, int n, int32_t *err)
+{
+    const int32_t x = (int32_t)take_raw_from(p, v, tag, err);
     return x < 0 ? 0 : (x >= n ? n - 1 : x);
 }
 
@@ -144,6 +151,29 @@ __device__ inline unsigned long long tagged(uint32_t tag, int32_t v)
 {
     return ((unsigned long long)tag << 32) | (uint32_t)v;
 }
+
+// A row and its dual travel together (rows < 2^17; |y| <= K + 2 <= 32767 as
+// eps allows, Lemma 3.2): a column's key is (round << 32) | (kRowMask - b)
+// << 15 | y(b), so the larger key wins a round and within a round the
+// smaller b; the free lists hold y(b) << 17 | b. A row that enters a phase,
+// or is evicted, thus brings its dual with it and nobody loads y(b).
+constexpr uint32_t kRowMask = (1u << 17) - 1u;
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+
+__device__ inline unsigned long long make_key(uint32_t r, int32_t b, int32_t y)
+{
+    return ((unsigned long long)r << 32) | ((unsigned long long)(kRowMask - (uint32_t)b) << 15) |
+           ((uint32_t)y & 0x7FFFu);
+}
+__device__ inline int32_t key_row(unsigned long long k)
+{
+    return (int32_t)(kRowMask - (((uint32_t)k >> 15) & kRowMask));
+}
+__device__ inline uint32_t key_free(unsigned long long k)
+{
+    return (((uint32_t)k & 0x7FFFu) << 17) | (uint32_t)key_row(k);
+}
+__device__ inline uint32_t free_val(int32_t b, int32_t y) { return ((uint32_t)y << 17) | (uint32_t)b; }
 
 // First admissible, unmarked column of this chunk (wave-wide, lowest column
 // first); -1 if none.
@@ -465,7 +495,7 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
                 a.t[i] = 0;
             } else {
                 const int32_t m = mate_a[i];
-                a.key[i] = m >= 0 ? (unsigned long long)(uint32_t)~(uint32_t)m : 0ull;
+                a.key[i] = m >= 0 ? make_key(0u, m, a.y_b[m]) : 0ull;
                 a.t[i] = (uint16_t)(-y_a[i]);
             }
         } else if (i < a.n_pad) {
@@ -475,7 +505,7 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
             if (a.skip) a.skip[i] = 0u;
             if (!warm) {
                 a.y_b[i] = 1;
-                a.F[0][i] = tagged(tag0, i);
+                a.F[0][i] = tagged(tag0, (int32_t)free_val(i, 1));
             } else {
                 is_free = mate_b[i] < 0;
             }
@@ -486,7 +516,8 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
                 uint32_t at = 0;
                 if (lane == 0) at = add_agent(&a.ctl->free0, (uint32_t)__popcll(bal));
                 at = __builtin_amdgcn_readfirstlane(at);
-                if (is_free) a.F[0][at + lanes_below(bal)] = tagged(tag0, i);
+                if (is_free)
+                    a.F[0][at + lanes_below(bal)] = tagged(tag0, (int32_t)free_val(i, a.y_b[i]));
             }
         }
     }
@@ -672,8 +703,9 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         apply_pending();
         __syncthreads();  // t of those columns and the team scratch are set
         if ((uint32_t)lane < nslots) {
-            s_b = take_entry_from(f_at, f_val, tag0 + (uint32_t)p, n, &ctl->err);
-            s_yb = ld_agent(y_b + s_b);
+            const uint32_t fv = take_raw_from(f_at, f_val, tag0 + (uint32_t)p, &ctl->err);
+            s_b = min((int32_t)(fv & kRowMask), n - 1);
+            s_yb = (int32_t)(fv >> 17);
             if constexpr (kCopies) {
                 // a free copy takes the largest dual of its point's copies
                 // (every y(b) update of the last phase is in ymax by now)
@@ -718,7 +750,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             }
             unsigned long long s_old = 0;  // key a proposal of this lane's slot replaced
             bool proposed = false;
-            int32_t my_f = -1;             // row this lane's slot puts on the next B'
+            uint32_t my_fv = kNoRow;       // row (and dual) this lane's slot puts on the next B'
             uint32_t n_prop = 0;
             // fast-forward: a full first-round scan that finds nothing records
             // the row's smallest slack
@@ -730,7 +762,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     if ((pre >> lane) & 1ull) {
                         st_agent(y_b + s_b, s_yb + 1);
                         st_agent(A.skip + s_b, s_skip - 1u);
-                        my_f = s_b;
+                        my_fv = free_val(s_b, s_yb + 1);
                     }
                     wave_scan += (unsigned long long)na * (unsigned long long)__popcll(pre);
                 }
@@ -761,8 +793,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     const bool lead = k_rank == 0;
                     if (j != kNoHit) {
                         const int a = v.origin + j < na ? v.origin + j : v.origin + j - na;
-                        const unsigned long long kn =
-                            ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
+                        const unsigned long long kn = make_key(r, b, yb);
                         if (lead) {
                             wave_scan += (unsigned long long)(j - pos + 1);
                             if (lane == 0) {
@@ -784,7 +815,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                             if (lane == 0) {
                                 st_agent(y_b + b, yb + 1);
                                 if constexpr (kCopies) raise_top(A.ymax + v.rb, p, yb + 1);
-                                my_f = b;
+                                my_fv = free_val(b, yb + 1);
                                 if (track) {
                                     const int slack = s_mn[team_local] - (yb - 1);
                                     if (slack >= 2)
@@ -840,8 +871,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                                       v.base + kChunk, yb - 1, lane, track ? &mn : nullptr);
                     if (h.j >= 0) {
                         wave_scan += (unsigned long long)(h.j - pos + 1);
-                        const unsigned long long kn =
-                            ((unsigned long long)r << 32) | (uint32_t)~(uint32_t)b;
+                        const unsigned long long kn = make_key(r, b, yb);
                         if (lane == s) {
                             // the slot's own lane proposes, so proposals of several
                             // slots are in flight together
@@ -860,7 +890,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         if (lane == s) {
                             st_agent(y_b + b, yb + 1);
                             if constexpr (kCopies) raise_top(A.ymax + v.rb, p, yb + 1);
-                            my_f = b;
+                            my_fv = free_val(b, yb + 1);
                             if (slack >= 2) st_agent(A.skip + b, (uint32_t)min(slack - 1, 1 << 30));
                         }
                         active &= ~(1ull << s);
@@ -873,9 +903,9 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             int32_t my_l = -1;
             if (proposed && (uint32_t)(s_old >> 32) < r) {
                 my_l = s_a;
-                if (s_old != 0ull) my_f = (int32_t)~(uint32_t)s_old;
+                if (s_old != 0ull) my_fv = key_free(s_old);
             }
-            const unsigned long long bl = __ballot(my_l >= 0), bf = __ballot(my_f >= 0);
+            const unsigned long long bl = __ballot(my_l >= 0), bf = __ballot(my_fv != kNoRow);
             uint32_t off_l = 0, off_f = 0;
             if (lane == 0) {
                 const uint32_t nl = (uint32_t)__popcll(bl), nf = (uint32_t)__popcll(bf);
@@ -923,8 +953,9 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 const uint32_t bl0 = s_base_l, bf0 = s_base_f;
                 if (my_l >= 0)
                     st_agent(Lc + grp * cap + bl0 + off_l + lanes_below(bl), tagged(tag, my_l));
-                if (my_f >= 0)
-                    st_agent(Fn + grp * cap + bf0 + off_f + lanes_below(bf), tagged(tag, my_f));
+                if (my_fv != kNoRow)
+                    st_agent(Fn + grp * cap + bf0 + off_f + lanes_below(bf),
+                             tagged(tag, (int32_t)my_fv));
             }
             if (threadIdx.x < kWave) {
                 // lane j < G polls the word of group j until every workgroup arrived
@@ -1048,7 +1079,7 @@ __global__ void decode_kernel(LoopArgs a, int32_t *mate_a, int32_t *mate_b, int3
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_a; i += gridDim.x * blockDim.x) {
         const unsigned long long kk = a.key[i];
-        const int32_t m = kk ? (int32_t)~(uint32_t)kk : -1;
+        const int32_t m = kk ? key_row(kk) : -1;
         mate_a[i] = m;
         if (m >= 0) mate_b[m] = i;
         y_a[i] = -(int32_t)a.t[i];
@@ -1222,7 +1253,7 @@ __global__ void team_init_kernel(TeamArgs T)
             a.key[i] = 0ull;
             a.t[i] = 0;
             y_b[i] = 1;
-            a.F[0][i] = tagged(tag0, i);
+            a.F[0][i] = tagged(tag0, (int32_t)free_val(i, 1));
             if (a.skip) a.skip[i] = 0u;
         } else {
             a.t[i] = 0;
@@ -1259,7 +1290,7 @@ __global__ void __launch_bounds__(kCompleteThreads) team_finish_kernel(TeamArgs 
     __syncthreads();
     for (int i = tid; i < n; i += kCompleteThreads) {
         const unsigned long long kk = a.key[i];
-        const int32_t b = kk ? (int32_t)~(uint32_t)kk : -1;
+        const int32_t b = kk ? key_row(kk) : -1;
         ma[i] = b;
         if (b >= 0) mb[b] = i;
         ya[i] = -(int32_t)a.t[i];
