@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -22,6 +23,14 @@
 
 using prot::Ctl;
 
+// Device block read back in one transfer after a solve: the control block
+// and the finalize pass's partial sums.
+struct Report {
+    Ctl ctl;
+    long long part_k[prot::kFinalizeBlocks];
+    double part_c[prot::kFinalizeBlocks];
+};
+
 struct prot_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -33,10 +42,11 @@ struct prot_ctx {
     int32_t *lists = nullptr;        // completion scratch (2n)
     unsigned long long *tlists = nullptr;  // tagged F0, F1, L0, L1 of the phase loop
     unsigned long long *words = nullptr;   // round words of the phase loop barrier
-    Ctl *ctl = nullptr;
+    Report *rep = nullptr;
+    Ctl *ctl = nullptr;              // &rep->ctl
     int64_t *trace = nullptr;
-    long long *part_k = nullptr;
-    double *part_c = nullptr;
+    long long *part_k = nullptr;     // rep->part_k
+    double *part_c = nullptr;        // rep->part_c
 
     int64_t cap_mat = 0;             // elements of the rounded-cost matrix
     int16_t *kmat = nullptr;
@@ -45,8 +55,10 @@ struct prot_ctx {
     char *prune_buf = nullptr;       // pruned-maximum workspace (d = 2, 3)
     int64_t prune_cap = 0;
     int64_t prune_min_n = 16384;     // PROT_PRUNE_MIN_N
+    float *mpart = nullptr;          // per-block maxima of the maximum pass (d = 2, 3)
+    int64_t mpart_cap = 0;
 
-    struct Stage {
+    struct Stage {                   // begins with the layout of Report
         Ctl ctl;
         long long part_k[prot::kFinalizeBlocks];
         double part_c[prot::kFinalizeBlocks];
@@ -264,6 +276,16 @@ int setup_mfma(prot_ctx *c, prot::PointsJob &j, int64_t n_max, float **buf, int6
 int setup_prune(prot_ctx *c, prot::PointsJob &j, int64_t n)  // n: max(rows, columns)
 {
     j.prune = prot::PruneAux{};
+    j.mpart = nullptr;
+    if ((j.d == 2 || j.d == 3) && j.metric != PROT_METRIC_L1_NORMALIZED) {
+        const int64_t need = prot::max_parts_cap(n);
+        if (need > c->mpart_cap || !c->mpart) {
+            int rc = dev_alloc(c, &c->mpart, (size_t)need);
+            if (rc) return rc;
+            c->mpart_cap = need;
+        }
+        j.mpart = c->mpart;
+    }
     // below this size the plain n^2 pass is cheaper than the four pruning
     // launches (measured: 28 us for n = 10,000, d = 2)
     if ((j.d != 2 && j.d != 3) || n < c->prune_min_n || j.metric == PROT_METRIC_L1_NORMALIZED)
@@ -411,20 +433,17 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
     HIP_TRY(c, prot::launch_loop(a, grid, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
     const int32_t complete = (o && o->no_completion) ? 0 : 1;
-    HIP_TRY(c, prot::launch_finish(a, complete, mate_a, mate_b, y_a, c->lists, c->stream));
+    HIP_TRY(c, prot::launch_finish(a, warm, complete, mate_a, mate_b, y_a, c->lists, c->stream));
     return PROT_OK;
 }
 
 int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kind,
             bool timed_build)
 {
-    HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
-                              c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->stage->part_k, c->part_k,
-                              sizeof(long long) * prot::kFinalizeBlocks, hipMemcpyDeviceToHost,
-                              c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->stage->part_c, c->part_c,
-                              sizeof(double) * prot::kFinalizeBlocks, hipMemcpyDeviceToHost,
+    static_assert(offsetof(prot_ctx::Stage, part_k) == offsetof(Report, part_k) &&
+                      offsetof(prot_ctx::Stage, part_c) == offsetof(Report, part_c),
+                  "the host stage begins with the device report's layout");
+    HIP_TRY(c, hipMemcpyAsync(c->stage, c->rep, sizeof(Report), hipMemcpyDeviceToHost,
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const Ctl &h = c->stage->ctl;
@@ -755,12 +774,15 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
         delete c;
         return PROT_E_HIP;
     }
-    int rc = dev_alloc(c, &c->ctl, 1);
-    if (!rc && hipMemset(c->ctl, 0, sizeof(Ctl)) != hipSuccess) rc = PROT_E_HIP;
+    int rc = dev_alloc(c, &c->rep, 1);
+    if (!rc && hipMemset(c->rep, 0, sizeof(Report)) != hipSuccess) rc = PROT_E_HIP;
+    if (!rc) {
+        c->ctl = &c->rep->ctl;
+        c->part_k = c->rep->part_k;
+        c->part_c = c->rep->part_c;
+    }
     if (!rc) rc = dev_alloc(c, &c->words, (size_t)3 * prot::kMaxGroups * prot::kWordStride);
     if (!rc) rc = dev_alloc(c, &c->trace, (size_t)4 * prot::kTraceCap);
-    if (!rc) rc = dev_alloc(c, &c->part_k, prot::kFinalizeBlocks);
-    if (!rc) rc = dev_alloc(c, &c->part_c, prot::kFinalizeBlocks);
     if (!rc && hipHostMalloc((void **)&c->stage, sizeof(prot_ctx::Stage), hipHostMallocDefault) !=
                    hipSuccess)
         rc = PROT_E_NOMEM;
@@ -801,11 +823,10 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->lists);
     (void)hipFree(c->tlists);
     (void)hipFree(c->prune_buf);
+    (void)hipFree(c->mpart);
     (void)hipFree(c->words);
-    (void)hipFree(c->ctl);
+    (void)hipFree(c->rep);
     (void)hipFree(c->trace);
-    (void)hipFree(c->part_k);
-    (void)hipFree(c->part_c);
     (void)hipFree(c->kmat);
     (void)hipFree(c->th);
     (void)hipFree(c->rtime);

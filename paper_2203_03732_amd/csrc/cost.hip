@@ -92,8 +92,11 @@ __global__ void build_reset_kernel(PointsJob j)
 // Low dimensions (d = 2, 3): the work is bound by the 2-byte writes of pass
 // 2, so pairs are computed straight from registers and LDS.
 // Pass 1: m = max over all pairs of the binary32 squared distance. Block =
-// 256 columns x kMaxRows rows of one instance; the rows' coordinates are
-// staged in LDS.
+// 256 columns x tiles of kMaxRows rows of one instance (tile y, y + grid.y,
+// ...); the rows' coordinates are staged in LDS. A batch combines the blocks'
+// maxima with an atomic max per instance. One instance stores one maximum
+// per block instead (thousands of atomics on one word queue up behind each
+// other at the memory side) and the thresholds pass reduces them.
 template <int D>
 __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
 {
@@ -102,28 +105,32 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
     __shared__ float red[kBuildThreads / 64];
     const Instance in = j.instance(blockIdx.z);
     const int64_t a = (int64_t)blockIdx.x * kBuildThreads + threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.y * kMaxRows;
-    if (b0 >= in.n || (int64_t)blockIdx.x * kBuildThreads >= in.na) return;
-    const int rows = (int)min<int64_t>(kMaxRows, in.n - b0);
     // A non-finite coordinate is caught where it is loaded; with finite
     // coordinates a distance can only overflow to +inf, which the maximum
     // keeps, so no per-pair test is needed.
     bool bad = false;
-    for (int i = threadIdx.x; i < rows * D; i += kBuildThreads) {
-        const float v = in.X[b0 * D + i];
-        bad |= !(fabsf(v) <= FLT_MAX);
-        xs[i] = v;
-    }
-    __syncthreads();
     float mx = 0.0f;
-    if (a < in.na) {
-        float y[D];
+    float y[D];
+    const bool col = a < in.na;
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-            y[q] = in.Y[a * D + q];
-            bad |= !(fabsf(y[q]) <= FLT_MAX);
+    for (int q = 0; q < D; ++q) {
+        y[q] = col ? in.Y[a * D + q] : 0.0f;
+        bad |= !(fabsf(y[q]) <= FLT_MAX);
+    }
+    if ((int64_t)blockIdx.x * kBuildThreads < in.na) {
+        for (int64_t b0 = (int64_t)blockIdx.y * kMaxRows; b0 < in.n;
+             b0 += (int64_t)gridDim.y * kMaxRows) {
+            const int rows = (int)min<int64_t>(kMaxRows, in.n - b0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < rows * D; i += kBuildThreads) {
+                const float v = in.X[b0 * D + i];
+                bad |= !(fabsf(v) <= FLT_MAX);
+                xs[i] = v;
+            }
+            __syncthreads();
+            if (col)
+                for (int r = 0; r < rows; ++r) mx = fmaxf(mx, sqdist<D>(xs + r * D, y, D));
         }
-        for (int r = 0; r < rows; ++r) mx = fmaxf(mx, sqdist<D>(xs + r * D, y, D));
         bad |= !(mx <= FLT_MAX);
     }
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
@@ -132,9 +139,14 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
     if (threadIdx.x == 0) {
         float m = red[0];
         for (int i = 1; i < kBuildThreads / 64; ++i) m = fmaxf(m, red[i]);
-        // squared distances are >= 0, so their bit patterns order as floats do
-        __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(&j.m[blockIdx.z]), __float_as_uint(m),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (j.mpart) {
+            j.mpart[blockIdx.y * gridDim.x + blockIdx.x] = m;
+        } else if (m > 0.0f) {
+            // squared distances are >= 0, so their bit patterns order as floats do
+            __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(&j.m[blockIdx.z]),
+                                   __float_as_uint(m), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     if (bad) __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -386,15 +398,32 @@ __global__ void __launch_bounds__(kBuildThreads) pairs_max_kernel(PointsJob j)
         for (int i = 1; i < kBuildThreads / 64; ++i) m = fmaxf(m, red[i]);
         if (!(m <= FLT_MAX))
             __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(j.m), __float_as_uint(m),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (j.mpart)
+            j.mpart[blockIdx.x] = m;
+        else if (m > 0.0f)
+            __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(j.m), __float_as_uint(m),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 // th[j] = smallest binary32 s >= 0 with k(s) >= j, for j = 0..K; th[K+1] = +inf.
+// With per-block maxima (one instance) every block first reduces them to m;
+// block 0 stores m for the later passes.
 __global__ void thresholds_kernel(PointsJob j)
 {
-    const float mf = j.m[blockIdx.z];
+    float mf;
+    if (j.mpart) {
+        __shared__ float red[4];
+        float v = 0.0f;
+        for (int i = threadIdx.x; i < j.nmpart; i += blockDim.x) v = fmaxf(v, j.mpart[i]);
+        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        mf = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        if (blockIdx.x == 0 && threadIdx.x == 0) j.m[0] = mf;
+    } else {
+        mf = j.m[blockIdx.z];
+    }
     const int32_t K = (mf > 0.0f) ? (int32_t)floor(1.0 / j.eps) : 0;
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && j.kmax_out && blockIdx.z == 0) *j.kmax_out = K;
@@ -681,20 +710,30 @@ void launch_points_tiled(const PointsJob &j, int64_t n_max, int64_t ldk_max, hip
 template <int D>
 void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s)
 {
+    PointsJob j_th = j;  // the thresholds pass: how many per-block maxima to reduce
     if (j.prune.cx && j.batch == 1) {
         const unsigned g = (unsigned)std::min<int64_t>(1024, (n_max + 255) / 256);
         hipLaunchKernelGGL(prune_reset_kernel, dim3(1), dim3(64), 0, s, j.prune);
         // few blocks: the extremes end in one set of atomics per block
         hipLaunchKernelGGL(extent_kernel<D>, dim3(std::min(g, 64u)), dim3(256), 0, s, j);
         hipLaunchKernelGGL(prune_kernel<D>, dim3(g), dim3(256), 0, s, j);
-        hipLaunchKernelGGL(pairs_max_kernel<D>, dim3(1024), dim3(kBuildThreads), 0, s, j);
+        PointsJob jm = j;
+        jm.nmpart = kPairsMaxBlocks;
+        hipLaunchKernelGGL(pairs_max_kernel<D>, dim3(kPairsMaxBlocks), dim3(kBuildThreads), 0, s,
+                           jm);
+        j_th.nmpart = kPairsMaxBlocks;
     } else {
         dim3 gmax((unsigned)((n_max + kBuildThreads - 1) / kBuildThreads),
                   (unsigned)((n_max + kMaxRows - 1) / kMaxRows), (unsigned)j.batch);
+        if (j.mpart) {
+            // row tiles strided so that at most max(kMaxParts, grid.x) maxima are stored
+            gmax.y = std::max(1u, std::min(gmax.y, (unsigned)kMaxParts / gmax.x));
+            j_th.nmpart = (int32_t)(gmax.x * gmax.y);
+        }
         hipLaunchKernelGGL(points_max_kernel<D>, gmax, dim3(kBuildThreads), 0, s, j);
     }
     hipLaunchKernelGGL(thresholds_kernel, dim3((j.kcap + 255) / 256, 1, j.batch), dim3(256), 0,
-                       s, j);
+                       s, j_th);
     if (j.no_matrix) return;
     const int64_t per_block = (int64_t)kBuildThreads * kColsPerThread;
     dim3 gk((unsigned)((ldk_max + per_block - 1) / per_block),

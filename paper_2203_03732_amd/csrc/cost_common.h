@@ -60,6 +60,8 @@ struct PointsJob {
     MfmaAux mfma;              // used when mfma.tile_max is set (d >= 16)
     int32_t no_matrix;         // 1: maximum and thresholds only (costs computed on the fly)
     PruneAux prune;            // used when prune.cx is set (one instance, d = 2, 3)
+    float *mpart;              // one instance, d = 2, 3: per-block maxima (else atomics on m)
+    int32_t nmpart;            // how many of them the thresholds pass reduces
 
     __device__ Instance instance(int i) const
     {

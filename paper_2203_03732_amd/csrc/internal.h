@@ -41,6 +41,16 @@ constexpr int kMaxGroups = 32;
 constexpr int kWordStride = 16;
 constexpr int kTraceCap = 65536;        // phases recorded in the trace
 constexpr int kFinalizeBlocks = 256;    // partial sums of the finalize kernel
+// Per-block maxima of the single-instance maximum pass (d = 2, 3): at most
+// max(kMaxParts, ceil(columns / 256)) of them; the pruned pass stores
+// kPairsMaxBlocks.
+constexpr int kMaxParts = 2048;
+constexpr int kPairsMaxBlocks = 1024;
+inline int64_t max_parts_cap(int64_t n_max)
+{
+    const int64_t cols = (n_max + 255) / 256;
+    return cols > kMaxParts ? cols : kMaxParts;
+}
 constexpr int kRoundTimeCap = 65536;    // rounds recorded by the round timer
 
 struct LoopArgs {
@@ -54,7 +64,7 @@ struct LoopArgs {
     int32_t origin;         // 0: diagonal, 1: zero
     int32_t pad;
     int64_t max_phases;
-    unsigned long long *key;  // per column: (round << 32) | ~b of its last winner
+    unsigned long long *key;  // per column: round, row and row dual of its last winner
     uint16_t *t;              // per column: -y(a) (number of phases it was taken in)
     int32_t *y_b;
     unsigned long long *F[2]; // free lists B', (phase tag << 32) | row (ping-pong by parity)
@@ -169,7 +179,7 @@ hipError_t launch_loss_bwd(const LossArgs &a, int64_t n_max, const float *grad_l
 
 // solve.hip
 hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
-                       const int32_t *mate_b, const int32_t *y_a, hipStream_t s);
+                       int32_t *mate_b, const int32_t *y_a, hipStream_t s);
 hipError_t launch_clear_err(Ctl *ctl, hipStream_t s);
 hipError_t launch_check_state(int64_t n, int64_t na, const int32_t *mate_a,
                               const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
@@ -184,8 +194,8 @@ hipError_t launch_team_init(const TeamArgs &t, int32_t n_pad_max, hipStream_t s)
 hipError_t launch_loop_multi(const LoopArgs *arr, int count, int team, int32_t n_pad_max,
                              int32_t *y_base, hipStream_t s);
 hipError_t launch_team_finish(const TeamArgs &t, hipStream_t s);
-hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a,
-                         int32_t *mate_b, int32_t *y_a, int32_t *scratch,
+hipError_t launch_finish(const LoopArgs &a, int32_t warm, int32_t complete,
+                         int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *scratch,
                          hipStream_t s);
 // cost_kind: 0 none, 1 cost matrix C (ldc), 2 points X, Y (d) with scale m.
 // With k == nullptr (points, costs on the fly) the rounded cost of each

@@ -7,8 +7,9 @@
 //       of the rounded-cost matrix (starting at its own column and wrapping,
 //       or at column 0) for the first column that is admissible,
 //       k[b][a] + 1 == y(a) + y(b), and was not taken before the round began;
-//       it proposes with an atomic max on that column's 64-bit key
-//       (round << 32 | ~b), so the lowest-index proposer of the round wins;
+//       it proposes with an atomic max on that column's 64-bit key (the
+//       round above, the row below in reverse order, so the lowest-index
+//       proposer of the round wins; the row's dual rides in the low bits);
 //   step (II) and (III) need no separate pass: the key of a column always
 //       names its current mate, so the first proposal to a column in a
 //       round appends the old mate (if any) to the next free list and the
@@ -35,8 +36,10 @@
 //     places its list entries;
 //   * list entries are written after the arrival, tagged with the phase, and
 //     a reader waits (bounded) until the entry carries the expected tag;
-//   * y(b) of a row that found nothing is stored before the arrival, and each
-//     wave waits for its stores to complete before the workgroup arrives.
+//   * a row re-enters the free list with its dual packed beside it, so a
+//     phase start needs no load of y(b); y(b) is also stored (for the
+//     results) before the arrival, and each wave waits for its stores to
+//     complete before the workgroup arrives.
 #include "device_common.h"
 #include "internal.h"
 
@@ -67,9 +70,9 @@ __device__ inline void wait_memory()
 
 // Value of a tagged list entry ((tag << 32) | value) once it carries `tag`.
 // The wait is bounded: on time-out bit 2 of the error word is raised and the
-// value is used as found. The value is clamped to [0, n) either way.
-// take_raw_from starts from a value v already loaded from p and returns the
-// 32-bit payload as found; take_entry_from clamps it to a row or column.
+// value is used as found. take_raw_from starts from a value v already loaded
+// from p and returns the 32-bit payload as found; take_entry_from and
+// take_entry clamp it to a row or column in [0, n).
 __device__ inline uint32_t take_raw_from(const unsigned long long *p, unsigned long long v,
                                         uint32_t tag, int32_t *err)
 {
@@ -479,9 +482,21 @@ __global__ void loop_reset_kernel(LoopArgs a)
 // Initial state: y(b) = 1, y(a) = 0, M empty (Section 2.2), or a warm start.
 // The free list of the first phase goes to F[0] with the launch's first tag
 // (one past the last tag of the previous launch), its length to ctl->free0.
+// A cold start also does the work of loop_reset_kernel (in block 0) and sets
+// every mate_b to -1 for the decode after the loop.
 __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
-                            const int32_t *mate_b, const int32_t *y_a)
+                            int32_t *mate_b, const int32_t *y_a)
 {
+    if (!warm && blockIdx.x == 0 && threadIdx.x < 3 * kMaxGroups)
+        a.words[threadIdx.x * kWordStride] = 0ull;
+    if (!warm && blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctl *c = a.ctl;
+        c->scanned = 0;
+        c->status = 0;
+        c->phases = c->sum_free = c->rounds = c->max_rounds = 0;
+        c->free_after = 0;
+        for (int i = 0; i < 4; ++i) a.trace[i] = 0;
+    }
     const int n = a.n, na = a.n_a;  // rows, columns
     const int lane = threadIdx.x & 63;
     const uint32_t tag0 = a.ctl->tag_last + 1u;
@@ -506,6 +521,7 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
             if (!warm) {
                 a.y_b[i] = 1;
                 a.F[0][i] = tagged(tag0, (int32_t)free_val(i, 1));
+                mate_b[i] = -1;
             } else {
                 is_free = mate_b[i] < 0;
             }
@@ -1114,15 +1130,21 @@ __device__ int list_flags(const int32_t *mate, int n, int32_t *out, int *cnt)
             if (lane == 0) cnt[q * kListWaves + wv] = __popcll(bal[q]);
         }
         __syncthreads();
-        if (tid == 0) {
-            // index order: tile by tile, wave by wave within a tile
-            int run = 0;
-            for (int j = 0; j < kListTiles * kListWaves; ++j) {
-                const int c = cnt[j];
-                cnt[j] = run;
-                run += c;
+        if (wv == 0) {
+            // exclusive prefix in index order (tile by tile, wave by wave
+            // within a tile): two counts per lane, then a scan over the lanes
+            static_assert(kListTiles * kListWaves == 2 * kWave, "two counts per lane");
+            const int c0 = cnt[2 * lane], c1 = cnt[2 * lane + 1];
+            int run = c0 + c1;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int v = __shfl_up(run, off);
+                if (lane >= off) run += v;
             }
-            cnt[kListTiles * kListWaves] = run;
+            const int before = run - c0 - c1;
+            cnt[2 * lane] = before;
+            cnt[2 * lane + 1] = before + c0;
+            if (lane == kWave - 1) cnt[kListTiles * kListWaves] = run;
         }
         __syncthreads();
 #pragma unroll
@@ -1365,9 +1387,10 @@ inline unsigned blocks_for(int64_t n, int threads)
 }  // namespace
 
 hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
-                       const int32_t *mate_b, const int32_t *y_a, hipStream_t s)
+                       int32_t *mate_b, const int32_t *y_a, hipStream_t s)
 {
-    hipLaunchKernelGGL(loop_reset_kernel, dim3(1), dim3(1), 0, s, a);
+    // a warm start counts its free rows with atomics on a word reset first
+    if (warm) hipLaunchKernelGGL(loop_reset_kernel, dim3(1), dim3(1), 0, s, a);
     hipLaunchKernelGGL(init_kernel, dim3(blocks_for(a.n_pad > a.n ? a.n_pad : a.n, 256)), dim3(256),
                        0, s, a, warm,
                        mate_a, mate_b, y_a);
@@ -1497,11 +1520,13 @@ hipError_t launch_team_finish(const TeamArgs &t, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const LoopArgs &a, int32_t complete, int32_t *mate_a, int32_t *mate_b,
-                         int32_t *y_a, int32_t *scratch, hipStream_t s)
+hipError_t launch_finish(const LoopArgs &a, int32_t warm, int32_t complete, int32_t *mate_a,
+                         int32_t *mate_b, int32_t *y_a, int32_t *scratch, hipStream_t s)
 {
-    hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, mate_b,
-                       (int64_t)a.n, -1);
+    // a cold start's init already set mate_b to -1
+    if (warm)
+        hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, mate_b,
+                           (int64_t)a.n, -1);
     hipLaunchKernelGGL(decode_kernel, dim3(blocks_for(a.n_a, 256)), dim3(256), 0, s, a, mate_a,
                        mate_b, y_a);
     if (a.rmap)
