@@ -27,7 +27,8 @@ namespace {
 constexpr int kColsPerThread = 8;
 constexpr int kBuildThreads = 256;
 constexpr int kRowsPerBlock = 16;
-constexpr int kMaxRows = 256;   // rows per block of the max pass
+constexpr int kMaxRows = 256;   // rows per tile of the max pass
+constexpr int kMaxCols = 4;     // columns per thread of the max pass
 constexpr int kMaxD = 3;        // largest d of the low-dimensional kernels
 
 // Eight rounded costs as bytes (uint8 matrix: every real entry is at most
@@ -92,8 +93,10 @@ __global__ void build_reset_kernel(PointsJob j)
 // Low dimensions (d = 2, 3): the work is bound by the 2-byte writes of pass
 // 2, so pairs are computed straight from registers and LDS.
 // Pass 1: m = max over all pairs of the binary32 squared distance. Block =
-// 256 columns x tiles of kMaxRows rows of one instance (tile y, y + grid.y,
-// ...); the rows' coordinates are staged in LDS. A batch combines the blocks'
+// 256 x kMaxCols columns (kMaxCols consecutive ones per thread, so that each
+// row read from LDS serves kMaxCols pairs) x tiles of kMaxRows rows of one
+// instance (tile y, y + grid.y, ...); the rows' coordinates are staged in
+// LDS. A batch combines the blocks'
 // maxima with an atomic max per instance. One instance stores one maximum
 // per block instead (thousands of atomics on one word queue up behind each
 // other at the memory side) and the thresholds pass reduces them.
@@ -104,20 +107,25 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
     __shared__ float xs[kMaxRows * D];
     __shared__ float red[kBuildThreads / 64];
     const Instance in = j.instance(blockIdx.z);
-    const int64_t a = (int64_t)blockIdx.x * kBuildThreads + threadIdx.x;
+    const int64_t a0 = ((int64_t)blockIdx.x * kBuildThreads + threadIdx.x) * kMaxCols;
     // A non-finite coordinate is caught where it is loaded; with finite
     // coordinates a distance can only overflow to +inf, which the maximum
-    // keeps, so no per-pair test is needed.
+    // keeps, so no per-pair test is needed. A missing column repeats the
+    // thread's first one (a0 < na whenever any of its columns exists).
     bool bad = false;
     float mx = 0.0f;
-    float y[D];
-    const bool col = a < in.na;
+    float y[kMaxCols][D];
+    const bool col = a0 < in.na;
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-        y[q] = col ? in.Y[a * D + q] : 0.0f;
-        bad |= !(fabsf(y[q]) <= FLT_MAX);
+    for (int e = 0; e < kMaxCols; ++e) {
+        const int64_t a = a0 + e < in.na ? a0 + e : a0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            y[e][q] = col ? in.Y[a * D + q] : 0.0f;
+            bad |= !(fabsf(y[e][q]) <= FLT_MAX);
+        }
     }
-    if ((int64_t)blockIdx.x * kBuildThreads < in.na) {
+    if ((int64_t)blockIdx.x * kBuildThreads * kMaxCols < in.na) {
         for (int64_t b0 = (int64_t)blockIdx.y * kMaxRows; b0 < in.n;
              b0 += (int64_t)gridDim.y * kMaxRows) {
             const int rows = (int)min<int64_t>(kMaxRows, in.n - b0);
@@ -129,7 +137,13 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
             }
             __syncthreads();
             if (col)
-                for (int r = 0; r < rows; ++r) mx = fmaxf(mx, sqdist<D>(xs + r * D, y, D));
+                for (int r = 0; r < rows; ++r) {
+                    float v[kMaxCols];
+#pragma unroll
+                    for (int e = 0; e < kMaxCols; ++e) v[e] = sqdist<D>(xs + r * D, y[e], D);
+#pragma unroll
+                    for (int e = 0; e < kMaxCols; ++e) mx = fmaxf(mx, v[e]);
+                }
         }
         bad |= !(mx <= FLT_MAX);
     }
@@ -723,7 +737,8 @@ void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStre
                            jm);
         j_th.nmpart = kPairsMaxBlocks;
     } else {
-        dim3 gmax((unsigned)((n_max + kBuildThreads - 1) / kBuildThreads),
+        const int64_t per_block = (int64_t)kBuildThreads * kMaxCols;
+        dim3 gmax((unsigned)((n_max + per_block - 1) / per_block),
                   (unsigned)((n_max + kMaxRows - 1) / kMaxRows), (unsigned)j.batch);
         if (j.mpart) {
             // row tiles strided so that at most max(kMaxParts, grid.x) maxima are stored
