@@ -28,7 +28,7 @@ constexpr int kColsPerThread = 8;
 constexpr int kBuildThreads = 256;
 constexpr int kRowsPerBlock = 16;
 constexpr int kMaxRows = 256;   // rows per tile of the max pass
-constexpr int kMaxCols = 4;     // columns per thread of the max pass
+constexpr int kMaxCols = 1;     // columns per thread of the max pass
 constexpr int kMaxD = 3;        // largest d of the low-dimensional kernels
 
 // Eight rounded costs as bytes (uint8 matrix: every real entry is at most
@@ -149,12 +149,14 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
     }
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-    __syncthreads();
+    // one instance: a block that met a non-finite value stores -1 as its
+    // maximum and the thresholds pass raises the error bit
+    const bool block_bad = __syncthreads_or(bad) != 0;
     if (threadIdx.x == 0) {
         float m = red[0];
         for (int i = 1; i < kBuildThreads / 64; ++i) m = fmaxf(m, red[i]);
         if (j.mpart) {
-            j.mpart[blockIdx.y * gridDim.x + blockIdx.x] = m;
+            j.mpart[blockIdx.y * gridDim.x + blockIdx.x] = block_bad ? -1.0f : m;
         } else if (m > 0.0f) {
             // squared distances are >= 0, so their bit patterns order as floats do
             __hip_atomic_fetch_max(reinterpret_cast<unsigned *>(&j.m[blockIdx.z]),
@@ -162,7 +164,7 @@ __global__ void __launch_bounds__(kBuildThreads) points_max_kernel(PointsJob j)
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    if (bad) __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bad && !j.mpart) __hip_atomic_fetch_or(j.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Pruned exact maximum (one instance, d = 2, 3). The maximum of the binary32
@@ -422,19 +424,29 @@ __global__ void __launch_bounds__(kBuildThreads) pairs_max_kernel(PointsJob j)
 
 // th[j] = smallest binary32 s >= 0 with k(s) >= j, for j = 0..K; th[K+1] = +inf.
 // With per-block maxima (one instance) every block first reduces them to m;
-// block 0 stores m for the later passes.
+// block 0 stores m for the later passes and, when the plain maximum pass
+// produced them (nmpart_err), sets the error word: bit 0 if a block met a
+// non-finite value, every other bit cleared for the solve that follows.
 __global__ void thresholds_kernel(PointsJob j)
 {
     float mf;
     if (j.mpart) {
         __shared__ float red[4];
         float v = 0.0f;
-        for (int i = threadIdx.x; i < j.nmpart; i += blockDim.x) v = fmaxf(v, j.mpart[i]);
+        bool bad = false;
+        for (int i = threadIdx.x; i < j.nmpart; i += blockDim.x) {
+            const float x = j.mpart[i];
+            bad |= x < 0.0f;
+            v = fmaxf(v, x);
+        }
         for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-        __syncthreads();
+        const bool any_bad = __syncthreads_or(bad) != 0;
         mf = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        if (blockIdx.x == 0 && threadIdx.x == 0) j.m[0] = mf;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            j.m[0] = mf;
+            if (j.nmpart_err) *j.err = any_bad ? 1 : 0;
+        }
     } else {
         mf = j.m[blockIdx.z];
     }
@@ -744,6 +756,7 @@ void launch_points_d(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStre
             // row tiles strided so that at most max(kMaxParts, grid.x) maxima are stored
             gmax.y = std::max(1u, std::min(gmax.y, (unsigned)kMaxParts / gmax.x));
             j_th.nmpart = (int32_t)(gmax.x * gmax.y);
+            j_th.nmpart_err = 1;
         }
         hipLaunchKernelGGL(points_max_kernel<D>, gmax, dim3(kBuildThreads), 0, s, j);
     }
@@ -777,7 +790,12 @@ hipError_t launch_round_costs(const float *C, int64_t n, int64_t na, int64_t ldc
 
 hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s)
 {
-    hipLaunchKernelGGL(build_reset_kernel, dim3((j.batch + 255) / 256), dim3(256), 0, s, j);
+    // The plain maximum pass of one instance (d = 2, 3) with per-block maxima
+    // needs no reset: the thresholds pass writes m, K and the error word.
+    const bool self_reset = j.mpart && !j.prune.cx && j.batch == 1 && n_max > 0 &&
+                            (j.d == 2 || j.d == 3) && j.metric != 2;
+    if (!self_reset)
+        hipLaunchKernelGGL(build_reset_kernel, dim3((j.batch + 255) / 256), dim3(256), 0, s, j);
     if (n_max == 0 || j.batch == 0) return hipGetLastError();
     if (j.metric == 2) launch_points_l1(j, n_max, ldk_max, s);
     else if (j.d == 2) launch_points_d<2>(j, n_max, ldk_max, s);

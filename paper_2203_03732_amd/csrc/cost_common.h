@@ -62,6 +62,7 @@ struct PointsJob {
     PruneAux prune;            // used when prune.cx is set (one instance, d = 2, 3)
     float *mpart;              // one instance, d = 2, 3: per-block maxima (else atomics on m)
     int32_t nmpart;            // how many of them the thresholds pass reduces
+    int32_t nmpart_err;        // 1: they carry the error flag (-1), the thresholds pass sets err
 
     __device__ Instance instance(int i) const
     {

@@ -1106,23 +1106,30 @@ constexpr int kCompleteThreads = 1024;
 
 // The ascending list of the indices i < n with mate[i] < 0, by one workgroup
 // of kCompleteThreads threads: tiles of kCompleteThreads consecutive indices
-// (coalesced), kListTiles tiles' loads in flight at a time, a ballot per
-// wave and an ordered prefix over the waves of the tiles. Returns the count.
-constexpr int kListTiles = 8;
+// (coalesced), kListTiles tiles' loads in flight at a time (every load is
+// issued, past the end clamped to index n - 1, so that none waits behind a
+// branch), a ballot per wave and an ordered prefix over the waves of the
+// tiles. Returns the count.
+constexpr int kListTiles = 16;
 constexpr int kListWaves = kCompleteThreads / 64;
 
-__device__ int list_flags(const int32_t *mate, int n, int32_t *out, int *cnt)
+__device__ __forceinline__ int list_flags(const int32_t *__restrict__ mate, int n,
+                                          int32_t *__restrict__ out, int *cnt)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     int base = 0;
     for (int t0 = 0; t0 < n; t0 += kListTiles * kCompleteThreads) {
-        bool f[kListTiles];
+        int32_t v[kListTiles];
 #pragma unroll
         for (int q = 0; q < kListTiles; ++q) {
             const int i = t0 + q * kCompleteThreads + tid;
-            f[q] = i < n && mate[i] < 0;
+            v[q] = mate[i < n ? i : n - 1];
         }
+        bool f[kListTiles];
+#pragma unroll
+        for (int q = 0; q < kListTiles; ++q)
+            f[q] = t0 + q * kCompleteThreads + tid < n && v[q] < 0;
         unsigned long long bal[kListTiles];
 #pragma unroll
         for (int q = 0; q < kListTiles; ++q) {
@@ -1132,18 +1139,29 @@ __device__ int list_flags(const int32_t *mate, int n, int32_t *out, int *cnt)
         __syncthreads();
         if (wv == 0) {
             // exclusive prefix in index order (tile by tile, wave by wave
-            // within a tile): two counts per lane, then a scan over the lanes
-            static_assert(kListTiles * kListWaves == 2 * kWave, "two counts per lane");
-            const int c0 = cnt[2 * lane], c1 = cnt[2 * lane + 1];
-            int run = c0 + c1;
+            // within a tile): kPer consecutive counts per lane, then a scan
+            // over the lanes
+            constexpr int kPer = kListTiles * kListWaves / kWave;
+            static_assert(kPer * kWave == kListTiles * kListWaves, "whole counts per lane");
+            int c[kPer];
+            int own = 0;
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+                c[e] = cnt[kPer * lane + e];
+                own += c[e];
+            }
+            int run = own;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
                 const int v = __shfl_up(run, off);
                 if (lane >= off) run += v;
             }
-            const int before = run - c0 - c1;
-            cnt[2 * lane] = before;
-            cnt[2 * lane + 1] = before + c0;
+            int before = run - own;
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+                cnt[kPer * lane + e] = before;
+                before += c[e];
+            }
             if (lane == kWave - 1) cnt[kListTiles * kListWaves] = run;
         }
         __syncthreads();
@@ -1176,9 +1194,10 @@ complete_kernel(int n, int n_a, int32_t *mate_a, int32_t *mate_b, int32_t *scrat
                 int32_t complete, const Ctl *ctl)
 {
     __shared__ int cnt[kCompleteThreads];
+    const int32_t stopped = ctl->status;  // read first: its latency hides behind the lists
     const int nb = list_flags(mate_b, n, scratch, cnt);
     const int na = list_flags(mate_a, n_a, scratch + n, cnt);
-    if (!complete || ctl->status) return;
+    if (!complete || stopped) return;
     const int m = min(nb, na);
     for (int i = threadIdx.x; i < m; i += kCompleteThreads) {
         const int b = scratch[i], a = scratch[n + i];

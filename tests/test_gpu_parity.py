@@ -70,6 +70,32 @@ def test_round_costs_bit_exact(ctx, n, eps):
     assert (kg[:, n:] == 0x7FFF).all()
 
 
+@pytest.mark.parametrize("n,d,storage", [(600, 2, "matrix"), (600, 3, "matrix"),
+                                         (600, 2, "on_the_fly"), (20000, 2, "auto"),
+                                         (20000, 3, "auto")])
+@pytest.mark.parametrize("where", ["X", "Y"])
+def test_points_reject_non_finite_then_recover(ctx, n, d, storage, where):
+    """A NaN or an infinite coordinate (the plain maximum pass, the pruned one
+    at n >= 16,384, either side) is refused; the solve after it, on clean
+    points, starts from a cleared error word and equals the oracle."""
+    import paper_2203_03732_amd as prot
+    X, Y = synth.uniform_points(n, d, seed=n + d)
+    for bad in (float("nan"), float("inf")):
+        Xb, Yb = X.copy(), Y.copy()
+        (Xb if where == "X" else Yb)[n // 3, d - 1] = bad
+        with pytest.raises(prot.ProtError) as e:
+            ctx.solve_points(dev(Xb), dev(Yb), 0.05, storage=storage)
+        assert e.value.name == "range"
+    gpu = ctx.solve_points(dev(X), dev(Y), 0.05, storage=storage)
+    if n <= 1000:
+        k, _ = oracle.round_points_f32(X, Y, 0.05)
+        ref = oracle.solve_rounded(k, oracle.threshold(0.05, n))
+        assert np.array_equal(host(gpu.mate_b), ref["mate_b"])
+        assert np.array_equal(host(gpu.y_b), ref["y_b"])
+    else:
+        check_matching(host(gpu.mate_a), host(gpu.mate_b))
+
+
 def test_round_costs_rejects_nan_and_range(ctx):
     import paper_2203_03732_amd as prot
     for bad in (float("nan"), -0.5, 1.5):
