@@ -249,6 +249,7 @@ class Context:
             raise ProtError(rc, "prot_ctx_create failed")
         self._h = h
         self._lib = lib
+        self._stream = stream  # the stream the library enqueues on
 
     def close(self):
         for plan in self.__dict__.pop("_plans", {}).values():
@@ -265,8 +266,10 @@ class Context:
 
     # -- helpers
     def _bind_stream(self):
-        torch = _torch()
-        self._lib.prot_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+        s = _torch().cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            self._lib.prot_set_stream(self._h, ctypes.c_void_p(s))
+            self._stream = s
 
     def _check(self, rc: int) -> int:
         if rc < 0:
@@ -287,12 +290,14 @@ class Context:
         return o
 
     def _outputs(self, n, n_a=None):
-        """mate_a, mate_b, y_a, y_b for n rows and n_a (default n) columns."""
+        """mate_a, mate_b, y_a, y_b for n rows and n_a (default n) columns:
+        views of one allocation, each starting on a 256-byte boundary."""
         torch = _torch()
         n_a = n if n_a is None else n_a
-        kw = dict(dtype=torch.int32, device=f"cuda:{self.device}")
-        return (torch.empty(n_a, **kw), torch.empty(n, **kw), torch.empty(n_a, **kw),
-                torch.empty(n, **kw))
+        pa, pb = -(-n_a // 64) * 64, -(-n // 64) * 64
+        buf = torch.empty(2 * (pa + pb), dtype=torch.int32, device=f"cuda:{self.device}")
+        return (buf[:n_a], buf[pa:pa + n], buf[pa + pb:pa + pb + n_a],
+                buf[2 * pa + pb:2 * pa + pb + n])
 
     # -- API
     def reserve(self, n_max: int, with_matrix: bool = True):
