@@ -208,7 +208,10 @@ int prot_solve_points(prot_ctx *ctx, const float *X, const float *Y,
  * n_a - n_b columns left unmatched). n_a < n_b returns PROT_E_ARG (transpose
  * the input). n_b = 0 with n_a > 0 writes the cold-start column state
  * (mate_a = -1, y_a = 0; untouched when warm). The square calls are these
- * with n_b = n_a = n. */
+ * with n_b = n_a = n. Limits of the phase loop (every solve call): the
+ * column duals of all n_a columns sit in one workgroup's LDS (n_a up to
+ * about 81,000 on MI355X) and a row index travels in 17 bits
+ * (n_b <= 131,071); beyond either the call returns PROT_E_UNSUPPORTED. */
 int prot_round_costs_rect(prot_ctx *ctx, const float *C, int64_t n_b, int64_t n_a,
                           int64_t ldc, double eps, int16_t *k, int64_t ldk);
 int prot_build_costs_rect(prot_ctx *ctx, const float *X, int64_t n_b, const float *Y,
