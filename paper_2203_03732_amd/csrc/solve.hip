@@ -613,6 +613,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     // team mode: best hit position of each team's row, by round parity
     __shared__ int s_best[2][kLoopThreads / kWave];
     __shared__ int s_mn[kLoopThreads / kWave];  // team mode: smallest k + t of a row's scan
+    // regrouping into teams within a phase: rows still looking (by round
+    // parity), slot of the next row handed over, the rows' scan states
+    __shared__ uint32_t s_nact[2], s_kact;
+    __shared__ int4 s_act[kLoopThreads / kWave / 2];
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wpg = blockDim.x / kWave;
@@ -632,6 +636,8 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     if (threadIdx.x == 0) {
         s_cnt_l = s_cnt_f = s_lose = 0;
         s_scan = 0;
+        s_nact[0] = s_nact[1] = 0;
+        s_kact = 0;
     }
     if (threadIdx.x < kMaxGroups) {
         // the first free list is one region (group 0)
@@ -695,14 +701,16 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             const uint32_t q = W / n_i;
             R = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : 2));
         }
-        const int wv = threadIdx.x / kWave;
-        const int team_local = wv / R, k_rank = wv % R;
+        // wave-uniform values, kept in scalar registers
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        int team_local = wv / R, k_rank = wv % R;
         const uint32_t team_id = wg * (uint32_t)(wpg / R) + (uint32_t)team_local;
         const uint32_t nslots = R == 1 ? (gw < n_i ? (n_i - gw + W - 1) / W : 0u)
                                        : (team_id < n_i ? 1u : 0u);
         if (threadIdx.x < 2 * (kLoopThreads / kWave))
             (&s_best[0][0])[threadIdx.x] = kNoHit;
         if (threadIdx.x < kLoopThreads / kWave) s_mn[threadIdx.x] = kNoHit;
+        if (threadIdx.x < 2) s_nact[threadIdx.x] = 0;
         int32_t s_b = -1, s_yb = 0, s_pos = 0, s_a = 0, s_rb = 0;
         uint32_t s_skip = 0;
         unsigned long long s_key = 0;
@@ -762,7 +770,38 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     else s_pos += 1;
                 }
                 active = __ballot(mine);
+                if (R == 1 && lane == 0 && active)
+                    atomicAdd(&s_nact[r & 1], (uint32_t)__popcll(active));
                 __syncthreads();
+                if (R == 1) {
+                    // Slot mode: once the workgroup's rows still looking fit in
+                    // half its waves, the rest of the phase runs in team mode
+                    // (the rows left are the ones whose scans run long): each
+                    // row's state goes to LDS and R = 2..16 waves take it.
+                    // Which wave scans a row does not change what it finds.
+                    const uint32_t nact = __builtin_amdgcn_readfirstlane(s_nact[r & 1]);
+                    if (threadIdx.x == 0) s_nact[(r + 1) & 1] = 0;
+                    if (nact > 0u && 2u * nact <= (uint32_t)wpg) {
+                        if ((active >> lane) & 1ull)
+                            s_act[atomicAdd(&s_kact, 1u)] = make_int4(s_b, s_pos, s_yb, s_rb);
+                        __syncthreads();
+                        const uint32_t q = (uint32_t)wpg / nact;
+                        R = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : 2));
+                        team_local = wv / R;
+                        k_rank = wv % R;
+                        active = 0ull;
+                        if ((uint32_t)team_local < nact) {
+                            const int4 st = s_act[team_local];
+                            s_b = st.x;
+                            s_pos = st.y;
+                            s_yb = st.z;
+                            s_rb = st.w;
+                            active = 1ull;
+                        }
+                        __syncthreads();
+                        if (threadIdx.x == 0) s_kact = 0;
+                    }
+                }
             }
             unsigned long long s_old = 0;  // key a proposal of this lane's slot replaced
             bool proposed = false;
