@@ -770,20 +770,30 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     else s_pos += 1;
                 }
                 active = __ballot(mine);
-                if (R == 1 && lane == 0 && active)
-                    atomicAdd(&s_nact[r & 1], (uint32_t)__popcll(active));
+                // rows of this workgroup still looking: a slot lane each, or
+                // one per team (its first wave counts it)
+                const bool counts = R == 1 ? (active != 0ull) : (k_rank == 0 && (active & 1ull));
+                if (R < 16 && lane == 0 && counts)
+                    atomicAdd(&s_nact[r & 1], R == 1 ? (uint32_t)__popcll(active) : 1u);
                 __syncthreads();
-                if (R == 1) {
-                    // Slot mode: once the workgroup's rows still looking fit in
-                    // half its waves, the rest of the phase runs in team mode
+                if (R < 16) {
+                    // Once the workgroup's rows still looking fit in half its
+                    // waves per team (or, in slot mode, in half its waves),
+                    // the phase continues with teams twice as large or more
                     // (the rows left are the ones whose scans run long): each
                     // row's state goes to LDS and R = 2..16 waves take it.
-                    // Which wave scans a row does not change what it finds.
+                    // Which waves scan a row does not change what they find.
                     const uint32_t nact = __builtin_amdgcn_readfirstlane(s_nact[r & 1]);
                     if (threadIdx.x == 0) s_nact[(r + 1) & 1] = 0;
-                    if (nact > 0u && 2u * nact <= (uint32_t)wpg) {
-                        if ((active >> lane) & 1ull)
+                    if (nact > 0u && 2u * (uint32_t)R * nact <= (uint32_t)wpg) {
+                        const bool mine_row = R == 1 ? ((active >> lane) & 1ull) != 0ull
+                                                     : (k_rank == 0 && lane == 0 && (active & 1ull));
+                        if (mine_row)
                             s_act[atomicAdd(&s_kact, 1u)] = make_int4(s_b, s_pos, s_yb, s_rb);
+                        // a team that stopped looking left its last best hit
+                        // in the buffer of this round's parity: start clean
+                        if (threadIdx.x < 2 * (kLoopThreads / kWave))
+                            (&s_best[0][0])[threadIdx.x] = kNoHit;
                         __syncthreads();
                         const uint32_t q = (uint32_t)wpg / nact;
                         R = q >= 16 ? 16 : (q >= 8 ? 8 : (q >= 4 ? 4 : 2));
