@@ -605,7 +605,8 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     extern __shared__ __align__(16) uint16_t t_lds[];
     __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose;
     __shared__ uint32_t s_base_l, s_base_f, s_ltot, s_over;
-    __shared__ unsigned long long s_scan;
+    __shared__ unsigned long long s_scan, s_pend_scan;
+    __shared__ int64_t s_pend_p;
     // per group: list lengths of the phase so far, last round's new taken
     // columns (start, count, prefix over groups), free-list prefix
     __shared__ uint32_t s_lcum[kMaxGroups], s_fcum[kMaxGroups], s_lstart[kMaxGroups],
@@ -636,6 +637,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     if (threadIdx.x == 0) {
         s_cnt_l = s_cnt_f = s_lose = 0;
         s_scan = 0;
+        s_pend_scan = 0;
         s_nact[0] = s_nact[1] = 0;
         s_kact = 0;
     }
@@ -659,6 +661,16 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     // the next free list, or when the loop ends.
     uint32_t pend = 0, pend_tag = 0;
     const unsigned long long *pend_L = nullptr;
+    // entries examined in the last finished phase (s_pend_scan, phase
+    // s_pend_p), added to the totals by thread 0 after a later arrival
+    auto flush_scan = [&]() {
+        const unsigned long long sc = s_pend_scan;
+        if (sc) {
+            add_agent(&ctl->scanned, sc);
+            if (A.trace && s_pend_p < kTraceCap) add_agent(&A.trace[4 * s_pend_p + 2], (int64_t)sc);
+            s_pend_scan = 0;
+        }
+    };
     auto apply_pending = [&]() {
         for (uint32_t i = threadIdx.x; i < pend; i += blockDim.x) {
             const int j = group_of(s_lpre, G, i);
@@ -1011,6 +1023,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         words + grp * kWordStride, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     s_base_l = s_lcum[grp] + (uint32_t)(o & kField);
                     s_base_f = s_fcum[grp] + (uint32_t)((o >> kShiftFree) & kField);
+                    flush_scan();
                 }
             }
             __syncthreads();
@@ -1075,12 +1088,12 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         if (lane == 0 && wave_scan) atomicAdd(&s_scan, wave_scan);
         __syncthreads();
         if (threadIdx.x == 0) {
-            const unsigned long long sc = s_scan;
+            // added to the totals after this workgroup's next arrival: every
+            // workgroup adds to the same two words, and a wave waits for its
+            // own atomics to complete before it arrives
+            s_pend_scan = s_scan;
+            s_pend_p = p;
             s_scan = 0;
-            if (sc) {
-                add_agent(&ctl->scanned, sc);
-                if (A.trace && p < kTraceCap) add_agent(&A.trace[4 * p + 2], (int64_t)sc);
-            }
         }
         if (leader) {
             st_rounds += phase_rounds;
@@ -1107,6 +1120,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         __syncthreads();
         p += 1;
     }
+    if (threadIdx.x == 0) flush_scan();
     if (leader) {
         // after a phase every workgroup has read tag_last (before arriving)
         if (p > 0) ctl->tag_last = tag0 + (uint32_t)p;
