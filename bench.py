@@ -285,8 +285,8 @@ def phase_report(prot, synth, torch, n, d, eps, seed):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--d", type=int, default=2)
     ap.add_argument("--eps", type=float, default=0.01)

@@ -784,11 +784,15 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 active = __ballot(mine);
                 // rows of this workgroup still looking: a slot lane each, or
                 // one per team (its first wave counts it)
+                // (not for the copies of the transport reduction: a copy that
+                // lost finds the next copy of the same column right after it,
+                // so its scans stay short and teams only add overhead)
+                constexpr bool kRegroup = !kCopies;
                 const bool counts = R == 1 ? (active != 0ull) : (k_rank == 0 && (active & 1ull));
-                if (R < 16 && lane == 0 && counts)
+                if (kRegroup && R < 16 && lane == 0 && counts)
                     atomicAdd(&s_nact[r & 1], R == 1 ? (uint32_t)__popcll(active) : 1u);
                 __syncthreads();
-                if (R < 16) {
+                if (kRegroup && R < 16) {
                     // Once the workgroup's rows still looking fit in half its
                     // waves per team (or, in slot mode, in half its waves),
                     // the phase continues with teams twice as large or more
