@@ -221,41 +221,66 @@ __global__ void __launch_bounds__(kPlanThreads) ot_count_kernel(OtPlanArgs a)
     if (threadIdx.x == 0) a.part_k[blockIdx.x] = t;
 }
 
-// One thread per demand point a: its column of the plan (1/theta per pair),
-// the excess over mu_a returned in ascending b, and the room left q_a.
-__global__ void ot_column_kernel(OtPlanArgs a)
+// One wave per demand point a: its column of the plan (1/theta per pair),
+// the excess over mu_a returned in ascending b, and the room left q_a. The
+// rows are read 64 at a time; only pairs with a nonzero count take part in
+// the sequential binary64 steps, which the whole wave runs in ascending b
+// (a zero entry gives nothing back and adding it leaves a sum unchanged), so
+// every value equals the row-by-row definition's.
+constexpr int kColWaves = 4;  // demand points per workgroup of ot_column_kernel
+__global__ void __launch_bounds__(64 * kColWaves) ot_column_kernel(OtPlanArgs a)
 {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (q >= a.n_a) return;
-    long long c_a = 0;
-    for (int64_t b = 0; b < a.n_b; ++b) {
-        const int32_t c = a.cnt[b * a.n_a + q];
-        c_a += c;
-        a.plan[b * a.ldp + q] = (double)c / a.theta;
-    }
-    double ex = (double)c_a / a.theta - a.mu[q];
-    for (int64_t b = 0; b < a.n_b && ex > 0.0; ++b) {
-        const double v = a.plan[b * a.ldp + q];
-        if (v <= 0.0) continue;
-        const double take = v < ex ? v : ex;
-        a.plan[b * a.ldp + q] = v - take;
-        ex = ex - take;
-    }
+    const int64_t q = blockIdx.x * (int64_t)kColWaves + threadIdx.x / 64;
+    if (q >= a.n_a) return;  // the whole wave
+    const int lane = threadIdx.x & 63;
+    long long mine = 0;
+    for (int64_t b0 = 0; b0 < a.n_b; b0 += 64)
+        if (b0 + lane < a.n_b) mine += a.cnt[(b0 + lane) * a.n_a + q];
+    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+    double ex = (double)mine / a.theta - a.mu[q];
     double got = 0.0;
-    for (int64_t b = 0; b < a.n_b; ++b) got += a.plan[b * a.ldp + q];
+    for (int64_t b0 = 0; b0 < a.n_b; b0 += 64) {
+        const int64_t b = b0 + lane;
+        const int32_t c = b < a.n_b ? a.cnt[b * a.n_a + q] : 0;
+        double mv = (double)c / a.theta;
+        unsigned long long nz = __ballot(c != 0);
+        while (nz) {
+            const int l = __ffsll((long long)nz) - 1;
+            nz &= nz - 1ull;
+            double v = (double)__shfl(c, l) / a.theta;
+            if (ex > 0.0) {
+                const double take = v < ex ? v : ex;
+                v = v - take;
+                ex = ex - take;
+            }
+            got += v;
+            if (lane == l) mv = v;
+        }
+        if (b < a.n_b) a.plan[b * a.ldp + q] = mv;
+    }
     const double room = a.mu[q] - got;
-    a.qv[q] = room > 0.0 ? room : 0.0;
+    if (lane == 0) a.qv[q] = room > 0.0 ? room : 0.0;
 }
 
-// One thread per supply point b: what it still has to send.
-__global__ void ot_row_kernel(OtPlanArgs a)
+// One wave per supply point b: what it still has to send (the row of the
+// plan summed in ascending q over its nonzero entries, read 64 at a time).
+__global__ void __launch_bounds__(64 * kColWaves) ot_row_kernel(OtPlanArgs a)
 {
-    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (b >= a.n_b) return;
+    const int64_t b = blockIdx.x * (int64_t)kColWaves + threadIdx.x / 64;
+    if (b >= a.n_b) return;  // the whole wave
+    const int lane = threadIdx.x & 63;
     double sent = 0.0;
-    for (int64_t q = 0; q < a.n_a; ++q) sent += a.plan[b * a.ldp + q];
+    for (int64_t q0 = 0; q0 < a.n_a; q0 += 64) {
+        const double v = q0 + lane < a.n_a ? a.plan[b * a.ldp + q0 + lane] : 0.0;
+        unsigned long long nz = __ballot(v != 0.0);
+        while (nz) {
+            const int l = __ffsll((long long)nz) - 1;
+            nz &= nz - 1ull;
+            sent += __shfl(v, l);
+        }
+    }
     const double left = a.nu[b] - sent;
-    a.rv[b] = left > 0.0 ? left : 0.0;
+    if (lane == 0) a.rv[b] = left > 0.0 ? left : 0.0;
 }
 
 __global__ void __launch_bounds__(kScaleThreads) ot_prefix_kernel(OtPlanArgs a)
@@ -357,8 +382,10 @@ hipError_t launch_ot_plan(const OtPlanArgs &a, hipStream_t s)
     hipLaunchKernelGGL(ot_fill_kernel, dim3(grid_of(a.n_b * a.n_a, 256, 4096u)), dim3(256), 0, s,
                        a.cnt, a.n_b * a.n_a, 0);
     hipLaunchKernelGGL(ot_count_kernel, dim3(kFinalizeBlocks), dim3(kPlanThreads), 0, s, a);
-    hipLaunchKernelGGL(ot_column_kernel, dim3(grid_of(a.n_a, 64)), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(ot_row_kernel, dim3(grid_of(a.n_b, 64)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(ot_column_kernel, dim3(grid_of(a.n_a, kColWaves)), dim3(64 * kColWaves), 0,
+                       s, a);
+    hipLaunchKernelGGL(ot_row_kernel, dim3(grid_of(a.n_b, kColWaves)), dim3(64 * kColWaves), 0, s,
+                       a);
     hipLaunchKernelGGL(ot_prefix_kernel, dim3(1), dim3(kScaleThreads), 0, s, a);
     hipLaunchKernelGGL(ot_route_kernel, dim3(kFinalizeBlocks), dim3(kPlanThreads), 0, s, a);
     return hipGetLastError();
