@@ -14,31 +14,52 @@ namespace prot {
 namespace {
 
 constexpr int kLossThreads = 256;
+constexpr int kFwdThreads = 1024;
+constexpr int kFwdUnroll = 4;
 
 // One block per instance; coordinate e of the instance is handled by thread
-// e mod 256, so consecutive lanes read consecutive floats. Binary64
-// accumulation, fixed-order block reduction.
-__global__ void __launch_bounds__(kLossThreads)
+// e mod kFwdThreads, so consecutive lanes read consecutive floats, with
+// kFwdUnroll coordinates' loads in flight per thread. Binary64 accumulation
+// (each thread in ascending e), fixed-order block reduction.
+__global__ void __launch_bounds__(kFwdThreads)
 ot_loss_fwd_kernel(LossArgs A, float *loss)
 {
-    __shared__ double red[kLossThreads];
+    __shared__ double red[kFwdThreads];
     const int inst = blockIdx.x;
     const int64_t n = A.n_arr[inst], off = A.pt_off[inst];
     const int d = A.d;
     const float *X = A.X + off * d, *Y = A.Y + off * d;
     const int32_t *mb = A.mate_b + off;
+    const int64_t total = n * d;
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < n * d; e += kLossThreads) {
-        const int64_t b = e / d;
-        const int j = (int)(e - b * d);
-        const int32_t a = mb[b];
-        if (a < 0) continue;
-        const double t = __dsub_rn((double)X[e], (double)Y[(int64_t)a * d + j]);
-        s = __dadd_rn(s, __dmul_rn(t, t));
+    for (int64_t e0 = threadIdx.x; e0 < total; e0 += (int64_t)kFwdUnroll * kFwdThreads) {
+        float x[kFwdUnroll], y[kFwdUnroll];
+        bool use[kFwdUnroll];
+#pragma unroll
+        for (int u = 0; u < kFwdUnroll; ++u) {
+            const int64_t e = e0 + (int64_t)u * kFwdThreads;
+            use[u] = false;
+            x[u] = y[u] = 0.0f;
+            if (e < total) {
+                const int64_t b = e / d;
+                const int32_t a = mb[b];
+                if (a >= 0) {
+                    use[u] = true;
+                    x[u] = X[e];
+                    y[u] = Y[(int64_t)a * d + (e - b * d)];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFwdUnroll; ++u)
+            if (use[u]) {
+                const double t = __dsub_rn((double)x[u], (double)y[u]);
+                s = __dadd_rn(s, __dmul_rn(t, t));
+            }
     }
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int o = kLossThreads / 2; o > 0; o >>= 1) {
+    for (int o = kFwdThreads / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] = __dadd_rn(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
@@ -69,7 +90,7 @@ ot_loss_bwd_kernel(LossArgs A, const float *grad_loss, float *dX, float *dY)
 hipError_t launch_loss_fwd(const LossArgs &a, float *loss, hipStream_t s)
 {
     if (a.batch > 0)
-        hipLaunchKernelGGL(ot_loss_fwd_kernel, dim3(a.batch), dim3(kLossThreads), 0, s, a, loss);
+        hipLaunchKernelGGL(ot_loss_fwd_kernel, dim3(a.batch), dim3(kFwdThreads), 0, s, a, loss);
     return hipGetLastError();
 }
 
