@@ -76,6 +76,8 @@ struct prot_ctx {
     int64_t rtime_start = 0;
     int wgs_per_cu = 1;              // PROT_LOOP_WGS_PER_CU (diagnostics)
     int max_grid = 0;                // PROT_LOOP_MAX_GRID: cap on the loop's workgroups (0: none)
+    int gate_cap = 0;                // PROT_LOOP_GATE_CAP: workgroups the loop's gate admits (0: all)
+    int cooperative = 0;             // PROT_LOOP_COOPERATIVE=1: cooperative launch of the loop
     int grid_npad = -1;
     int grid_max = 0;
     // optimal transport through copies (prot_ot_solve)
@@ -405,6 +407,8 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
     if ((rc = grid_for(c, n, n_a, &grid))) return rc;
     prot::LoopArgs a = loop_args(c, k, n, n_a, ldk, T, o, y_b);
     a.groups = std::min(c->loop_groups, grid);
+    a.gated = c->cooperative ? 0 : 1;
+    a.gate_cap = c->gate_cap;
     a.rmap = cp.rmap;
     a.ymax = cp.ymax;
     a.k8 = k8;
@@ -449,6 +453,9 @@ int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kin
     const Ctl &h = c->stage->ctl;
     if (h.err & 4) return fail(c, PROT_E_HIP, "phase loop: a list entry was not published in time");
     if (h.err & 8) return fail(c, PROT_E_UNSUPPORTED, "phase loop: more than 2^32 rounds");
+    if (h.err & 16)
+        return fail(c, PROT_E_HIP, "phase loop: too few workgroups resident for the rows "
+                                   "(the GPU is busy; PROT_LOOP_COOPERATIVE=1 waits for them)");
     if (!st) return PROT_OK;
     std::memset(st, 0, sizeof(*st));
     st->phases = h.phases;
@@ -791,6 +798,8 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
     if (const char *v = std::getenv("PROT_COST_PATH"))
         if (std::strcmp(v, "mfma") == 0) c->cost_path = PROT_COST_MATRIX_CORES;
     if (const char *v = std::getenv("PROT_PRUNE_MIN_N")) c->prune_min_n = std::atoll(v);
+    if (const char *v = std::getenv("PROT_LOOP_GATE_CAP")) c->gate_cap = std::max(0, std::atoi(v));
+    if (const char *v = std::getenv("PROT_LOOP_COOPERATIVE")) c->cooperative = std::atoi(v) == 1;
     if (const char *v = std::getenv("PROT_LOOP_GROUPS")) {
         const int g = std::atoi(v);
         if (g >= 1 && g <= prot::kMaxGroups) c->loop_groups = g;

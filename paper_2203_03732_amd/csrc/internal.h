@@ -10,7 +10,9 @@ namespace prot {
 
 // Device-side control block of one phase loop. Zeroed by the reset kernel.
 struct alignas(128) Ctl {
-    unsigned long long pad2[3];
+    uint32_t gate_count;          // phase loop, plain launch: tickets handed out
+    uint32_t gate;                // 0 open; else kGateClosed | workgroups taking part
+    unsigned long long pad2[2];
     uint32_t free0;               // |B'| of the first phase (set by the init kernel)
     uint32_t tag_last;            // last list tag used by a launch (kept across launches,
                                   // so that no entry of an earlier launch matches a tag)
@@ -18,7 +20,8 @@ struct alignas(128) Ctl {
     unsigned long long scanned;   // matrix entries examined
     int32_t status;               // 0 finished, 1 stopped at max_phases
     int32_t err;                  // bit 0: cost out of range / non-finite; bit 1: bad state;
-                                  // bit 2: a list entry did not arrive; bit 3: round ids exhausted
+                                  // bit 2: a list entry did not arrive; bit 3: round ids exhausted;
+                                  // bit 4: too few workgroups resident for the rows
     int64_t phases;
     int64_t sum_free;
     int64_t rounds;
@@ -99,7 +102,12 @@ struct LoopArgs {
     // itself takes m - 1.
     const int32_t *rmap;
     unsigned long long *ymax;
+    // 1: a plain launch whose resident workgroups agree on how many take part
+    // (Ctl::gate); 0: a cooperative launch. gate_cap > 0 closes the gate at
+    // that many workgroups (a test of the partial case).
+    int32_t gated, gate_cap;
 };
+constexpr uint32_t kGateClosed = 0x80000000u;
 
 // Per-instance results of the batched solver (layout of prot_instance_stats).
 struct InstanceStats {

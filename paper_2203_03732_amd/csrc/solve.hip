@@ -59,6 +59,7 @@ constexpr unsigned long long kField = (1ull << 21) - 1;
 constexpr uint16_t kTaken = 0x8000;            // mark: column taken earlier in the phase
 constexpr int kSpinLimit = 1 << 22;            // bounded waits for list entries
 constexpr uint32_t kRoundLimit = 0xFFFFFF00u;  // round ids must fit the key's 32 bits
+constexpr int kGateSpin = 256;                 // gate polls (~0.3 ms) before it closes early
 
 // Waits until this wave's earlier stores and atomics have completed.
 __device__ inline void wait_memory()
@@ -470,6 +471,8 @@ __global__ void loop_reset_kernel(LoopArgs a)
 {
     Ctl *c = a.ctl;
     for (int i = 0; i < 3 * kMaxGroups; ++i) a.words[i * kWordStride] = 0ull;
+    c->gate_count = 0;
+    c->gate = 0;
     c->free0 = 0;
     c->scanned = 0;
     c->status = 0;
@@ -491,6 +494,8 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
         a.words[threadIdx.x * kWordStride] = 0ull;
     if (!warm && blockIdx.x == 0 && threadIdx.x == 0) {
         Ctl *c = a.ctl;
+        c->gate_count = 0;
+        c->gate = 0;
         c->scanned = 0;
         c->status = 0;
         c->phases = c->sum_free = c->rounds = c->max_rounds = 0;
@@ -600,8 +605,55 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     int32_t *const y_b = kMulti ? y_base + A.y_off : A.y_b;
     const typename SrcOf<kSrcD>::type src = SrcOf<kSrcD>::make(A);
     // workgroups of this instance, and this workgroup's rank among them
-    const uint32_t nwg = kMulti ? (uint32_t)team : gridDim.x;
-    const uint32_t wg = kMulti ? blockIdx.x % (uint32_t)team : blockIdx.x;
+    uint32_t nwg = kMulti ? (uint32_t)team : gridDim.x;
+    uint32_t wg = kMulti ? blockIdx.x % (uint32_t)team : blockIdx.x;
+    if (!kMulti && A0.gated) {
+        // Plain launch: the workgroups that are resident take tickets; the
+        // grid's last ticket, or a workgroup that waited kGateSpin polls for
+        // the rest, closes the gate at the number of tickets handed out so
+        // far. Those ticket holders run the loop as workgroups 0 .. nwg - 1
+        // (all of them resident, so every round barrier completes); a later
+        // workgroup leaves without touching any state. Which workgroups serve
+        // which rows does not change the result.
+        __shared__ uint32_t s_gate[2];
+        if (threadIdx.x == 0) {
+            Ctl *c = A0.ctl;
+            const uint32_t cap = A0.gate_cap > 0 ? min((uint32_t)A0.gate_cap, gridDim.x) : gridDim.x;
+            const uint32_t t = __hip_atomic_fetch_add(&c->gate_count, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (t + 1u == cap) {
+                uint32_t expected = 0u;
+                __hip_atomic_compare_exchange_strong(&c->gate, &expected, kGateClosed | cap,
+                                                     __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            }
+            uint32_t g = ld_agent(&c->gate);
+            for (int spins = 0; g == 0u; ++spins) {
+                if (spins >= kGateSpin) {
+                    const uint32_t got = ld_agent(&c->gate_count);
+                    uint32_t expected = 0u;
+                    __hip_atomic_compare_exchange_strong(&c->gate, &expected,
+                                                         kGateClosed | min(got, cap),
+                                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __builtin_amdgcn_s_sleep(2);
+                g = ld_agent(&c->gate);
+            }
+            s_gate[0] = t;
+            s_gate[1] = g & ~kGateClosed;
+        }
+        __syncthreads();
+        wg = s_gate[0];
+        nwg = s_gate[1];
+        if (wg >= nwg) return;
+        // every wave serves at most 64 rows of B'
+        if ((int64_t)nwg * (kLoopThreads / kWave) * kWave < (int64_t)A0.n) {
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_or(&A0.ctl->err, 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+    }
     extern __shared__ __align__(16) uint16_t t_lds[];
     __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose;
     __shared__ uint32_t s_base_l, s_base_f, s_ltot, s_over;
@@ -1555,6 +1607,9 @@ hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
                                                  (int)lds);
         if (e != hipSuccess) return e;
     }
+    // a plain launch (a cooperative one costs ~20 us more here); the gate at
+    // the kernel's start makes it safe when not every workgroup is resident
+    if (a.gated) return hipLaunchKernel(fn, dim3(grid), dim3(kLoopThreads), args, lds, s);
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kLoopThreads), args, (unsigned)lds, s);
 }
 

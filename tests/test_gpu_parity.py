@@ -511,3 +511,52 @@ def test_byte_matrix_needs_small_k(ctx):
     gpu = ctx.solve_points(dev(X), dev(Y), 0.002)
     k, _ = oracle.round_points_f32(X, Y, 0.002)
     assert_same(gpu, oracle.solve_rounded(k, oracle.threshold(0.002, 300)), "auto K=500")
+
+
+@pytest.fixture(scope="module")
+def gate_ctx():
+    """A context whose phase-loop gate admits only three workgroups, as when
+    the rest of the grid is not resident (the plain launch's partial case)."""
+    import os
+    import paper_2203_03732_amd as prot
+    old = os.environ.get("PROT_LOOP_GATE_CAP")
+    os.environ["PROT_LOOP_GATE_CAP"] = "3"
+    try:
+        c = prot.Context(0)
+    finally:
+        if old is None:
+            del os.environ["PROT_LOOP_GATE_CAP"]
+        else:
+            os.environ["PROT_LOOP_GATE_CAP"] = old
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.mark.parametrize("n,eps,origin", [(1000, 0.01, "diag"), (2900, 0.02, "zero"), (64, 0.1, "diag")])
+def test_loop_with_few_workgroups_admitted(gate_ctx, n, eps, origin):
+    """Three workgroups (48 waves) serve every row: the result is the
+    oracle's, bit for bit, as with the whole grid."""
+    X, Y = synth.uniform_points(n, 2, seed=n)
+    gpu = gate_ctx.solve_points(dev(X), dev(Y), eps, origin=origin)
+    k, _ = oracle.round_points_f32(X, Y, eps)
+    orc = oracle.solve_rounded(k, oracle.threshold(eps, n), origin=origin)
+    for x in ("mate_a", "mate_b", "y_a", "y_b"):
+        assert np.array_equal(host(getattr(gpu, x)), orc[x]), x
+    for s in STAT_KEYS:
+        assert gpu.stats[s] == orc["stats"][s], s
+
+
+def test_loop_refuses_rows_beyond_the_admitted_workgroups(gate_ctx):
+    """3 workgroups x 16 waves x 64 lanes = 3,072 rows at most: more rows are
+    refused with an error, and the context still solves afterwards."""
+    import paper_2203_03732_amd as prot
+    X, Y = synth.uniform_points(4000, 2, seed=2)
+    with pytest.raises(prot.ProtError) as e:
+        gate_ctx.solve_points(dev(X), dev(Y), 0.05)
+    assert e.value.name == "hip"
+    X, Y = synth.uniform_points(500, 2, seed=3)
+    gpu = gate_ctx.solve_points(dev(X), dev(Y), 0.05)
+    k, _ = oracle.round_points_f32(X, Y, 0.05)
+    orc = oracle.solve_rounded(k, oracle.threshold(0.05, 500))
+    assert np.array_equal(host(gpu.mate_b), orc["mate_b"])
