@@ -1,6 +1,7 @@
 // The integer phase loop of arXiv:2203.03732, Section 2.2, on one GPU.
 //
-// One cooperative, persistent launch runs every phase. Per phase:
+// One persistent launch runs every phase (a plain launch; a gate at its
+// start admits the resident workgroups, see the kernel). Per phase:
 //   B'  (the free supply rows) is the list F[p & 1];
 //   step (I), a maximal matching M' in the admissible graph of B', is built
 //       by synchronous proposal rounds: every row still looking scans its row
