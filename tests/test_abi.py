@@ -47,3 +47,17 @@ def test_null_context_is_rejected():
     lib = prot.load()
     assert lib.prot_solve_rounded(None, None, 0, 0, 0, None, 0, None, None, None, None, None) == -1
     assert lib.prot_last_error(None) == b"null context"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message (the library has no
+    multi-GPU path), before touching any device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU only" in p.stderr
+    assert p.stdout == ""
