@@ -40,7 +40,8 @@ enum {
     PROT_E_ARG = -1,           /* null pointer, bad size or bad option */
     PROT_E_RANGE = -2,         /* a cost is NaN or outside [0, 1] */
     PROT_E_EPS = -3,           /* eps not in (0,1), or 1/eps too big for int16 */
-    PROT_E_STATE = -5,         /* warm-start state violates (I1) or is not a matching */
+    PROT_E_PHASE_BOUND = -4,   /* the phase-bound watchdog stopped the loop; state valid */
+    PROT_E_STATE = -5,         /* warm-start state violates (I1)/(I2) or is not a matching */
     PROT_E_HIP = -6,           /* a HIP runtime call failed */
     PROT_E_NOMEM = -7,         /* device allocation failed */
     PROT_E_UNSUPPORTED = -8    /* size beyond the library's limits */
@@ -78,7 +79,21 @@ typedef struct {
      * them to int16 lanes and is not faster on MI355X. The costs and every
      * result are the same. */
     int32_t k_type;
-    int32_t reserved[3];
+    /* Warm starts of prot_solve_rounded*: 1 also checks (I2) on every edge,
+     * y(a) + y(b) <= k + 1 and = k on the matching (eqs. (2), (3); O(n_b n_a)
+     * reads of k), before the loop; a violation returns PROT_E_STATE. The
+     * O(n) checks always run: a matching, (I1), and |y| <= K + 2 (Lemma 3.2,
+     * K = 32765 for prot_solve_rounded*, floor(1/eps) otherwise). */
+    int32_t check_warm;
+    /* The watchdog. 0 (default): the loop may run at most
+     * ((n_b + n_a)(K + 2) - n_b) / (T + 1) phases, the bound that Lemma 3.2
+     * (|y| <= K + 2) and Lemma 3.3 (each phase adds |B'| > T to
+     * sum y(b) - sum y(a)) give every run of the method; eq. (4)'s printed
+     * constant counts the 2n duals once, this bound counts them as Lemma 3.2
+     * does. Reaching it returns PROT_E_PHASE_BOUND with the state reached in
+     * the outputs (no completion), which a warm start can resume. > 0: that
+     * many phases instead; < 0: no watchdog. */
+    int64_t phase_bound;
     /* Stop after this many phases (0: run to completion); the call then
      * returns PROT_PARTIAL and the outputs hold a valid resumable state. */
     int64_t max_phases;
@@ -95,7 +110,7 @@ typedef struct {
     int64_t sum_k;             /* sum of k over the returned matching */
     int64_t threshold;         /* T: the loop stops when |B'| <= T */
     int32_t kmax;              /* largest rounded cost */
-    int32_t status;            /* PROT_OK or PROT_PARTIAL */
+    int32_t status;            /* PROT_OK, PROT_PARTIAL or PROT_E_PHASE_BOUND */
     double cost;               /* sum of c(a,b) over the matching (costs scaled to max 1) */
     double cost_scale;         /* points: the maximum squared distance m (c = d2/m); cost input: 1 */
     double eps_internal;       /* eps the loop ran with (eps or eps/3) */
@@ -172,10 +187,16 @@ int prot_build_costs(prot_ctx *ctx, const float *X, const float *Y, int64_t n,
  *  warm = 0: start from y(b) = 1, y(a) = 0, M empty (mate_* and y_* are
  *            outputs only).
  *  warm = 1: resume from the state in mate_a, mate_b, y_a, y_b (it must be
- *            a matching satisfying (I1); PROT_E_STATE otherwise).
+ *            a matching satisfying (I1) with |y| <= 32767, and (I2) when
+ *            opts->check_warm is set; PROT_E_STATE otherwise).
  * Outputs: mate_a[a] (b or -1), mate_b[b] (a or -1), and the duals y_a, y_b
  * BEFORE the completion (completion edges carry no eq. (3) guarantee).
- * stats may be NULL (then the call does not synchronise). */
+ * stats may be NULL: then the call only enqueues (no synchronisation) and
+ * prot_ctx_status reports how the work ended. If the loop fails on the
+ * device (a bounded wait timed out, a dual left its range), the completion
+ * is skipped and every mate is -1. With stats, a loop that could not start
+ * because too few workgroups were resident at once (another kernel holds
+ * the GPU) is run again with a cooperative launch, which waits for them. */
 int prot_solve_rounded(prot_ctx *ctx, const int16_t *k, int64_t n, int64_t ldk,
                        int64_t T, const prot_opts *opts, int32_t warm,
                        int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
@@ -235,7 +256,7 @@ int prot_solve_points_rect(prot_ctx *ctx, const float *X, int64_t n_b, const flo
 typedef struct {
     int64_t phases, sum_free, rounds, max_rounds, scanned, matched_in_phases,
         completed_pairs, sum_k, threshold;
-    int32_t status;            /* PROT_OK or PROT_PARTIAL */
+    int32_t status;            /* PROT_OK, PROT_PARTIAL or PROT_E_PHASE_BOUND */
     int32_t kmax;
     double cost;               /* sum over the matching of d2 / m, binary64 */
     double cost_scale;         /* m, the instance's max squared distance */
@@ -337,8 +358,10 @@ int prot_batch_autotune(prot_ctx *ctx, int32_t batch, const int64_t *n_host, int
                         int32_t *tried);
 int prot_batch_destroy(prot_batch *plan);
 
-/* Enqueue the whole batched solve on the context stream; no synchronisation.
- * stats: device array of `batch` entries, or NULL. */
+/* Enqueue the whole batched solve on the context stream; no synchronisation
+ * (prot_batch_status reports how it ended). stats: device array of `batch`
+ * entries, or NULL. An instance's loop stops at the phase bound of
+ * prot_opts.phase_bound (status PROT_E_PHASE_BOUND in its statistics). */
 int prot_batch_run(prot_batch *plan, const float *X, const float *Y, int32_t *mate_a,
                    int32_t *mate_b, int32_t *y_a, int32_t *y_b, prot_instance_stats *stats);
 
@@ -386,6 +409,41 @@ int64_t prot_get_trace(prot_ctx *ctx, int64_t *out_host, int64_t cap);
  * 0 for rounds not run. Returns the number of rounds copied (0 if timing is
  * off). Synchronises the stream. */
 int64_t prot_get_round_times(prot_ctx *ctx, int64_t *out_host, int64_t cap);
+
+/* How the work last enqueued on ctx by a solve call ended: synchronises
+ * the context stream and returns PROT_OK, PROT_PARTIAL, PROT_E_PHASE_BOUND
+ * or the error the device reported (PROT_E_RANGE for a non-finite or
+ * out-of-range input, PROT_E_STATE, PROT_E_HIP for a timed-out wait or too
+ * few resident workgroups, PROT_E_UNSUPPORTED). For calls made with
+ * stats = NULL, which do not synchronise. */
+int prot_ctx_status(prot_ctx *ctx);
+
+/* How the last run or replay of a batch plan ended (synchronises the
+ * context stream): PROT_OK, PROT_E_RANGE (a coordinate is not finite),
+ * PROT_E_PHASE_BOUND (an instance was stopped by the watchdog, its
+ * statistics say which), PROT_E_HIP / PROT_E_STATE / PROT_E_UNSUPPORTED (an
+ * instance's loop failed). */
+int prot_batch_status(prot_batch *plan);
+
+/* The matching-based OT loss without a batch plan: `batch` instances of n
+ * points each, X and Y batch x n x d float32 (row-major, instance after
+ * instance), mate_b batch x n int32 (row b of an instance -> its column,
+ * local to the instance; -1 = unmatched, adds nothing), all device memory:
+ * loss[i] = (1/n) * sum_b ||x_b - y_mate_b(b)||^2 (float32 of a binary64 sum
+ * in a fixed order). Enqueues only. The plan being (1/n) times the
+ * permutation, this is its transport cost (the paper motivates using the
+ * plan in learning, Section 1). */
+int prot_ot_loss_fwd(prot_ctx *ctx, int32_t batch, int64_t n, int32_t d, const float *X,
+                     const float *Y, const int32_t *mate_b, float *loss);
+
+/* Its gradient for the fixed matching, for an upstream gradient grad_loss
+ * (device float[batch]): dX_b = (2 g / n)(x_b - y_a), dY_a = (2 g / n)(y_a - x_b)
+ * for each matched pair mate_b[b] = a, 0 for unmatched points. mate_b must
+ * be a matching (no column twice). dX, dY: device, the layout of X, Y.
+ * Enqueues only. */
+int prot_ot_loss_bwd(prot_ctx *ctx, int32_t batch, int64_t n, int32_t d, const float *X,
+                     const float *Y, const int32_t *mate_b, const float *grad_loss, float *dX,
+                     float *dY);
 
 const char *prot_status_string(int status);
 const char *prot_last_error(prot_ctx *ctx);

@@ -74,7 +74,9 @@ def _load():
     lib.orc_ot_solve.argtypes = [p, i64, i64, i64, p, p, f64, i32, i64, i32, p, p, p, p, p,
                                  p, p, p, i64]
     lib.orc_points_pairs_f32.argtypes = [p, p, i32, f64, ctypes.c_float, p, p, i64, p]
-    for fn in (lib.orc_round_cost, lib.orc_round_points_f32,
+    lib.orc_solve_points_f32.argtypes = [p, p, i64, i64, i32, f64, i64, i32, i64, i32,
+                                         p, p, p, p, p, p, i64, p]
+    for fn in (lib.orc_solve_points_f32, lib.orc_round_cost, lib.orc_round_points_f32,
                lib.orc_points_cost_f64, lib.orc_solve_rounded, lib.orc_solve_rounded_rect,
                lib.orc_points_max_f32, lib.orc_ot_scale, lib.orc_ot_solve,
                lib.orc_round_points_euclid_f32, lib.orc_round_l1_normalized_f32,
@@ -232,6 +234,42 @@ def solve_rounded(k: np.ndarray, T: int, origin: str = "diag",
     stats = {name: int(getattr(st, name)) for name, _ in _Stats._fields_}
     out = dict(mate_a=mate_a, mate_b=mate_b, y_a=y_a, y_b=y_b,
                status=STATUS[rc], stats=stats)
+    if tr is not None:
+        out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
+    return out
+
+
+def solve_points(X: np.ndarray, Y: np.ndarray, eps: float, T: int | None = None,
+                 origin: str = "diag", max_phases: int = 0, complete: bool = True,
+                 trace: bool = False, trace_cap: int = 1 << 20) -> dict:
+    """The phase loop on the rounded squared-Euclidean costs of point sets X
+    (rows) and Y (columns) without storing the matrix: every rounded cost the
+    loop examines is computed from the points with round_points_f32's
+    arithmetic (the binary32 maximum m over all pairs first). T defaults to
+    threshold(eps, n_b). Same results as solve_rounded on round_points_f32's
+    matrix; the dict also holds m."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    n_b, d = X.shape
+    n_a = Y.shape[0]
+    assert Y.shape[1] == d and n_b <= n_a
+    if T is None:
+        T = threshold(eps, n_b)
+    mate_a = np.full(n_a, -1, np.int32)
+    mate_b = np.full(n_b, -1, np.int32)
+    y_a = np.zeros(n_a, np.int32)
+    y_b = np.ones(n_b, np.int32)
+    m = np.zeros(1, dtype=np.float32)
+    st = _Stats()
+    tr = np.zeros((trace_cap, 4), np.int64) if trace else None
+    rc = _check(_load().orc_solve_points_f32(
+        _ptr(X), _ptr(Y), n_b, n_a, d, float(eps), int(T), ORIGIN[origin], int(max_phases),
+        1 if complete else 0, _ptr(mate_a), _ptr(mate_b), _ptr(y_a), _ptr(y_b),
+        ctypes.byref(st), _ptr(tr) if tr is not None else None,
+        trace_cap if tr is not None else 0, _ptr(m)), "solve_points")
+    stats = {name: int(getattr(st, name)) for name, _ in _Stats._fields_}
+    out = dict(mate_a=mate_a, mate_b=mate_b, y_a=y_a, y_b=y_b, status=STATUS[rc],
+               stats=stats, m=float(m[0]))
     if tr is not None:
         out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
     return out

@@ -259,17 +259,29 @@ static int64_t scan_col(int32_t origin_mode, int64_t b, int64_t j, int64_t n)
 
 /* The rounded cost of edge (a, b). Plain instances read k[b][a]. The copies
  * of the transport reduction (Section 4) read the cost of the points they
- * copy: row_pt[b] and col_pt[a] name those points. */
+ * copy: row_pt[b] and col_pt[a] name those points. Point sets given without
+ * a matrix (k NULL) compute eq. (1) of the pair from the points each time:
+ * the binary32 squared distance of orc_round_points_f32, divided by the
+ * maximum m and then by eps in binary64, floored (0 everywhere if m = 0). */
 typedef struct {
     const int16_t *k;
     int64_t ldk;
     const int32_t *row_pt, *col_pt;  /* NULL: the identity */
+    const float *X, *Y;              /* used when k is NULL */
+    int32_t d;
+    float m;
+    double eps;
 } costs_t;
 
 static int16_t cost_of(const costs_t *c, int64_t b, int64_t a)
 {
     int64_t r = c->row_pt ? c->row_pt[b] : b;
     int64_t q = c->col_pt ? c->col_pt[a] : a;
+    if (!c->k) {
+        if (c->m == 0.0f) return 0;
+        double v = (double)sq_f32(c->X + r * c->d, c->Y + q * c->d, c->d) / (double)c->m;
+        return (int16_t)floor(v / c->eps);
+    }
     return c->k[r * c->ldk + q];
 }
 
@@ -491,8 +503,27 @@ int orc_solve_rounded_rect(const int16_t *k, int64_t n_b, int64_t n_a, int64_t l
     if (n_b < 0 || n_a < n_b || (n_b > 0 && (!k || ldk < n_a)) || !mate_a || !mate_b ||
         !y_a || !y_b || !st)
         return ORC_E_ARG;
-    costs_t cs = {k, ldk, NULL, NULL};
+    costs_t cs = {k, ldk, NULL, NULL, NULL, NULL, 0, 0.0f, 0.0};
     return phase_loop(&cs, n_b, n_a, 0, T, origin_mode, max_phases, warm, complete, mate_a,
+                      mate_b, y_a, y_b, st, trace, trace_cap);
+}
+
+int orc_solve_points_f32(const float *X, const float *Y, int64_t n_b, int64_t n_a, int32_t d,
+                         double eps, int64_t T, int32_t origin_mode, int64_t max_phases,
+                         int32_t complete, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
+                         int32_t *y_b, orc_stats *st, int64_t *trace, int64_t trace_cap,
+                         float *m_out)
+{
+    if (!X || !Y || n_b < 0 || n_a < n_b || d <= 0 || !mate_a || !mate_b || !y_a || !y_b ||
+        !st)
+        return ORC_E_ARG;
+    if (!eps_ok(eps)) return ORC_E_EPS;
+    float m = 0.0f;
+    int rc = orc_points_max_f32(X, Y, n_b, n_a, d, &m);
+    if (rc) return rc;
+    if (m_out) *m_out = m;
+    costs_t cs = {NULL, 0, NULL, NULL, X, Y, d, m, eps};
+    return phase_loop(&cs, n_b, n_a, 0, T, origin_mode, max_phases, 0, complete, mate_a,
                       mate_b, y_a, y_b, st, trace, trace_cap);
 }
 

@@ -111,6 +111,16 @@ int orc_solve_rounded(const int16_t *k, int64_t n, int64_t ldk, int64_t T,
                       int32_t *y_a, int32_t *y_b, orc_stats *st,
                       int64_t *trace, int64_t trace_cap);
 
+/* The phase loop (as orc_solve_rounded_rect, cold start) on point sets
+ * without the n_b x n_a matrix: m = orc_points_max_f32 first, then every
+ * rounded cost the loop examines is eq. (1) of that pair with the arithmetic
+ * of orc_round_points_f32. Writes m to *m_out (optional). */
+int orc_solve_points_f32(const float *X, const float *Y, int64_t n_b, int64_t n_a, int32_t d,
+                         double eps, int64_t T, int32_t origin_mode, int64_t max_phases,
+                         int32_t complete, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
+                         int32_t *y_b, orc_stats *st, int64_t *trace, int64_t trace_cap,
+                         float *m_out);
+
 /* Section 4, scaling: theta = 4 max(n_b, n_a) / eps; supply point b becomes
  * s_b = floor(theta nu_b) unit copies, demand point a d_a = ceil(theta mu_a)
  * (binary64 products). nu and mu are probability vectors (entries in [0, 1],

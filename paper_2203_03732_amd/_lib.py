@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libprot.so")
 
 PROT_OK, PROT_PARTIAL = 0, 1
-STATUS_NAMES = {0: "ok", 1: "partial", -1: "arg", -2: "range", -3: "eps", -5: "state",
-                -6: "hip", -7: "nomem", -8: "unsupported"}
+STATUS_NAMES = {0: "ok", 1: "partial", -1: "arg", -2: "range", -3: "eps", -4: "phase_bound",
+                -5: "state", -6: "hip", -7: "nomem", -8: "unsupported"}
 EPS_MODES = {"algorithmic": 0, "strict": 1}
 ORIGINS = {"diag": 0, "zero": 1}
 
@@ -27,8 +27,8 @@ class ProtError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("eps_mode", ctypes.c_int32), ("origin_mode", ctypes.c_int32),
                 ("no_completion", ctypes.c_int32), ("cost_storage", ctypes.c_int32),
-                ("k_type", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
-                ("max_phases", ctypes.c_int64)]
+                ("k_type", ctypes.c_int32), ("check_warm", ctypes.c_int32),
+                ("phase_bound", ctypes.c_int64), ("max_phases", ctypes.c_int64)]
 
 
 COST_STORAGE = {"auto": 0, "matrix": 1, "on_the_fly": 2}
@@ -111,7 +111,8 @@ EXPORTS = [
     "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
     "prot_batch_create_config", "prot_batch_autotune",
     "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
-    "prot_batch_loss_fwd", "prot_batch_loss_bwd",
+    "prot_batch_loss_fwd", "prot_batch_loss_bwd", "prot_ctx_status", "prot_batch_status",
+    "prot_ot_loss_fwd", "prot_ot_loss_bwd",
     "prot_status_string", "prot_last_error",
 ]
 
@@ -175,6 +176,10 @@ def load():
         "prot_batch_loss_bwd": (ctypes.c_int, [p, p, p, p, p, p, p, p]),
         "prot_solve_batched_points": (ctypes.c_int, [p, i32, p, i32, p, p, f64,
                                                      ctypes.POINTER(Opts), p, p, p, p, p]),
+        "prot_ctx_status": (ctypes.c_int, [p]),
+        "prot_batch_status": (ctypes.c_int, [p]),
+        "prot_ot_loss_fwd": (ctypes.c_int, [p, i32, i64, i32, p, p, p, p]),
+        "prot_ot_loss_bwd": (ctypes.c_int, [p, i32, i64, i32, p, p, p, p, p, p]),
         "prot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "prot_last_error": (ctypes.c_char_p, [p]),
     }
@@ -271,17 +276,21 @@ class Context:
             self._lib.prot_set_stream(self._h, ctypes.c_void_p(s))
             self._stream = s
 
-    def _check(self, rc: int) -> int:
-        if rc < 0:
+    def _check(self, rc: int, allow_bound: bool = False) -> int:
+        """Raise ProtError for an error code; PROT_E_PHASE_BOUND passes when
+        allow_bound (the outputs then hold the valid state reached)."""
+        if rc < 0 and not (allow_bound and rc == -4):
             msg = self._lib.prot_last_error(self._h).decode()
             raise ProtError(rc, msg)
         return rc
 
     @staticmethod
     def _opts(eps_mode="algorithmic", origin="diag", complete=True, max_phases=0,
-              storage="auto", k_type="auto") -> Opts:
+              storage="auto", k_type="auto", phase_bound=0, check_warm=False) -> Opts:
         o = Opts()
         o.k_type = K_TYPES[k_type]
+        o.phase_bound = int(phase_bound)
+        o.check_warm = 1 if check_warm else 0
         o.eps_mode = EPS_MODES[eps_mode]
         o.origin_mode = ORIGINS[origin]
         o.no_completion = 0 if complete else 1
@@ -357,10 +366,21 @@ class Context:
             _dev_ptr(m, torch.float32, "m")))
         return k, m
 
+    def status(self) -> str:
+        """How the work last enqueued by a solve on this context ended
+        (prot_ctx_status; synchronises): 'ok', 'partial' or 'phase_bound';
+        raises ProtError for a failure the device reported."""
+        return STATUS_NAMES[self._check(self._lib.prot_ctx_status(self._h), allow_bound=True)]
+
     def solve_rounded(self, k, T: int, n: int | None = None, *, n_a: int | None = None,
-                      state=None, origin="diag", complete=True, max_phases=0) -> Result:
+                      state=None, origin="diag", complete=True, max_phases=0,
+                      phase_bound=0, check_warm=False, stats=True) -> Result:
         """k: n rows x ldk (ldk >= n_a) int16; n_a columns, default n (the
-        unbalanced case of Section 3.3 when n_a > n)."""
+        unbalanced case of Section 3.3 when n_a > n). phase_bound: the
+        watchdog (0: the safe bound, > 0: that many phases, < 0: off); a
+        stop there raises ProtError('phase_bound') unless stats=False.
+        check_warm: also check (I2) on a warm start. stats=False enqueues
+        only (then call status())."""
         torch = _torch()
         n = k.shape[0] if n is None else int(n)
         n_a = n if n_a is None else int(n_a)
@@ -373,14 +393,50 @@ class Context:
             mate_a, mate_b, y_a, y_b = (state[x].clone() for x in ("mate_a", "mate_b", "y_a", "y_b"))
             warm = 1
         st = Stats()
-        o = self._opts(origin=origin, complete=complete, max_phases=max_phases)
+        o = self._opts(origin=origin, complete=complete, max_phases=max_phases,
+                       phase_bound=phase_bound, check_warm=check_warm)
         self._bind_stream()
         rc = self._check(self._lib.prot_solve_rounded_rect(
             self._h, _dev_ptr(k, torch.int16, "k", 2), n, n_a, k.stride(0), int(T), ctypes.byref(o),
             warm, _dev_ptr(mate_a, torch.int32, "mate_a"), _dev_ptr(mate_b, torch.int32, "mate_b"),
             _dev_ptr(y_a, torch.int32, "y_a"), _dev_ptr(y_b, torch.int32, "y_b"),
-            ctypes.byref(st)))
-        return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
+            ctypes.byref(st) if stats else None), allow_bound=True)
+        return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict() if stats else {})
+
+    def ot_loss(self, X, Y, mate_b):
+        """prot_ot_loss_fwd: X, Y (batch, n, d) float32, mate_b (batch, n)
+        int32 (local column of each row, -1 unmatched) -> (batch,) float32
+        loss (1/n) sum_b ||x_b - y_mate(b)||^2."""
+        torch = _torch()
+        if X.dim() != 3 or Y.shape != X.shape or mate_b.shape != X.shape[:2] or \
+                not X.is_contiguous() or not Y.is_contiguous() or not mate_b.is_contiguous():
+            raise ValueError("X, Y must be contiguous (batch, n, d) and mate_b (batch, n)")
+        batch, n, d = X.shape
+        loss = torch.empty(batch, dtype=torch.float32, device=X.device)
+        self._bind_stream()
+        self._check(self._lib.prot_ot_loss_fwd(
+            self._h, batch, n, d, _dev_ptr(X, torch.float32, "X", 3),
+            _dev_ptr(Y, torch.float32, "Y", 3), _dev_ptr(mate_b, torch.int32, "mate_b", 2),
+            _dev_ptr(loss, torch.float32, "loss", 1)))
+        return loss
+
+    def ot_loss_grad(self, X, Y, mate_b, grad_loss):
+        """prot_ot_loss_bwd: (dX, dY) of sum_i grad_loss[i] * L_i for the
+        fixed matching mate_b."""
+        torch = _torch()
+        if X.dim() != 3 or Y.shape != X.shape or mate_b.shape != X.shape[:2] or \
+                not X.is_contiguous() or not Y.is_contiguous() or not mate_b.is_contiguous():
+            raise ValueError("X, Y must be contiguous (batch, n, d) and mate_b (batch, n)")
+        batch, n, d = X.shape
+        g = grad_loss.to(torch.float32).contiguous()
+        dX, dY = torch.empty_like(X), torch.empty_like(Y)
+        self._bind_stream()
+        self._check(self._lib.prot_ot_loss_bwd(
+            self._h, batch, n, d, _dev_ptr(X, torch.float32, "X", 3),
+            _dev_ptr(Y, torch.float32, "Y", 3), _dev_ptr(mate_b, torch.int32, "mate_b", 2),
+            _dev_ptr(g, torch.float32, "grad_loss", 1), _dev_ptr(dX, torch.float32, "dX", 3),
+            _dev_ptr(dY, torch.float32, "dY", 3)))
+        return dX, dY
 
     def solve_cost(self, C, eps: float, *, eps_mode="algorithmic", origin="diag",
                    complete=True, max_phases=0, k_type="auto") -> Result:
@@ -402,7 +458,8 @@ class Context:
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
 
     def solve_points(self, X, Y, eps: float, *, eps_mode="algorithmic", origin="diag",
-                     complete=True, max_phases=0, storage="auto", k_type="auto") -> Result:
+                     complete=True, max_phases=0, storage="auto", k_type="auto",
+                     phase_bound=0) -> Result:
         """storage: 'auto', 'matrix' (build and scan the n x n matrix) or
         'on_the_fly' (d = 2, 3: no matrix, each examined cost recomputed from
         the points); k_type: the stored matrix's element type ('auto' = 'int16',
@@ -415,13 +472,13 @@ class Context:
             raise ValueError("X and Y must be contiguous n_b x d and n_a x d float32")
         mate_a, mate_b, y_a, y_b = self._outputs(n, n_a)
         st = Stats()
-        o = self._opts(eps_mode, origin, complete, max_phases, storage, k_type)
+        o = self._opts(eps_mode, origin, complete, max_phases, storage, k_type, phase_bound)
         self._bind_stream()
         rc = self._check(self._lib.prot_solve_points_rect(
             self._h, _dev_ptr(X, torch.float32, "X", 2), n, _dev_ptr(Y, torch.float32, "Y", 2),
             n_a, d, float(eps), ctypes.byref(o), _dev_ptr(mate_a, torch.int32, "mate_a"),
             _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
-            _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)))
+            _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)), allow_bound=True)
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
 
     def ot_solve(self, C, nu, mu, eps: float, *, eps_mode="algorithmic", origin="diag",
@@ -571,9 +628,19 @@ class Batch:
                 _dev_ptr(self.y_a, torch.int32, "y_a"), _dev_ptr(self.y_b, torch.int32, "y_b"),
                 ctypes.c_void_p(self.stats_dev.data_ptr()))
 
-    def run(self, X, Y):
+    def run(self, X, Y, check=True):
+        """Enqueue the batch; with check (default) wait for it and raise
+        ProtError if the device reported a failure (prot_batch_status)."""
         self.ctx._bind_stream()
         self.ctx._check(self.ctx._lib.prot_batch_run(self._h, *self._ptrs(X, Y)))
+        if check:
+            self.status()
+
+    def status(self) -> str:
+        """How the last run or replay ended ('ok'; raises ProtError for a
+        failure or a stop by the phase-bound watchdog). Synchronises."""
+        self.ctx._bind_stream()
+        return STATUS_NAMES[self.ctx._check(self.ctx._lib.prot_batch_status(self._h))]
 
     def capture(self, X, Y):
         self.ctx._bind_stream()

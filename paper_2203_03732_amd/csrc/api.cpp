@@ -74,10 +74,13 @@ struct prot_ctx {
     float *mfma_buf = nullptr;       // amax, emax, tile maxima of the matrix-core build
     int64_t mfma_cap = 0;
     int64_t rtime_start = 0;
+    double *loss_part = nullptr;     // partial sums of prot_ot_loss_fwd
+    int64_t loss_cap = 0;
     int wgs_per_cu = 1;              // PROT_LOOP_WGS_PER_CU (diagnostics)
     int max_grid = 0;                // PROT_LOOP_MAX_GRID: cap on the loop's workgroups (0: none)
     int gate_cap = 0;                // PROT_LOOP_GATE_CAP: workgroups the loop's gate admits (0: all)
     int cooperative = 0;             // PROT_LOOP_COOPERATIVE=1: cooperative launch of the loop
+    int64_t barrier_ticks = 0;       // PROT_LOOP_BARRIER_TICKS: bounded barrier wait (0: default)
     int grid_npad = -1;
     int grid_max = 0;
     // optimal transport through copies (prot_ot_solve)
@@ -147,6 +150,29 @@ double eps_internal(double eps, const prot_opts *o)
 }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Largest k a rounded-cost matrix may hold (int16 entries k <= 32765, so
+// that every |y| <= K + 2 fits the loop's 15-bit fields).
+constexpr int64_t kKMaxAccepted = 32765;
+
+// The watchdog's phase bound for n_b rows, n_a columns, largest cost K and
+// threshold T: Lemma 3.2 keeps every |y| <= K + 2, and Phi = sum y(b) -
+// sum y(a) starts at n_b and grows by exactly |B'| > T in every phase
+// (Lemma 3.3), so phases <= ((n_b + n_a)(K + 2) - n_b) / (T + 1). (Eq. (4)
+// prints n(1 + 2 eps) for the sum of all 2n duals; Lemma 3.2 gives twice
+// that, which is the bound used.) opts->phase_bound > 0 replaces it, < 0
+// turns the watchdog off.
+int64_t phase_bound_for(const prot_opts *o, int64_t n_b, int64_t n_a, int64_t K, int64_t T)
+{
+    const int64_t given = o ? o->phase_bound : 0;
+    if (given > 0) return given;
+    if (given < 0) return 0;
+    return ((n_b + n_a) * (K + 2) - n_b) / (T + 1);
+}
+
+// collect(): the gate admitted too few workgroups, nothing ran; the caller
+// enqueues the loop again with a cooperative launch.
+constexpr int kRetryCooperative = 1000;
 
 template <class T>
 int dev_alloc(prot_ctx *c, T **p, size_t count)
@@ -353,9 +379,11 @@ int points_cost_kind(const prot_ctx *c)
 }
 
 prot::LoopArgs loop_args(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
-                         int64_t T, const prot_opts *o, int32_t *y_b)
+                         int64_t T, const prot_opts *o, int32_t *y_b, int64_t K)
 {
     prot::LoopArgs a{};
+    a.phase_bound = phase_bound_for(o, n, n_a, K, T);
+    a.barrier_ticks = c->barrier_ticks;
     a.k = k;
     a.ldk = ldk;
     a.n = (int32_t)n;
@@ -396,18 +424,21 @@ struct Copies {
     unsigned long long *ymax = nullptr;
 };
 
+// K: the largest rounded cost (for the watchdog and the warm-start check).
+// cooperative: launch the loop cooperatively (the retry after the gate
+// admitted too few workgroups).
 int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk, int64_t T,
              const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
-             int32_t *y_b, const OnTheFly &otf = OnTheFly(), const Copies &cp = Copies(),
-             int k8 = 0)
+             int32_t *y_b, int64_t K, bool cooperative = false,
+             const OnTheFly &otf = OnTheFly(), const Copies &cp = Copies(), int k8 = 0)
 {
     int rc = ensure_loop(c, n_a);
     if (rc) return rc;
     int grid = 0;
     if ((rc = grid_for(c, n, n_a, &grid))) return rc;
-    prot::LoopArgs a = loop_args(c, k, n, n_a, ldk, T, o, y_b);
+    prot::LoopArgs a = loop_args(c, k, n, n_a, ldk, T, o, y_b, K);
     a.groups = std::min(c->loop_groups, grid);
-    a.gated = c->cooperative ? 0 : 1;
+    a.gated = (c->cooperative || cooperative) ? 0 : 1;
     a.gate_cap = c->gate_cap;
     a.rmap = cp.rmap;
     a.ymax = cp.ymax;
@@ -421,15 +452,25 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
         a.peps = otf.eps;
     }
     if (warm) {
-        // (I1) and the matching structure of the given state, O(n).
+        // (I1), Lemma 3.2's bound on the duals and the matching structure of
+        // the given state, O(n); on request (I2), O(n_b n_a).
         HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
-        HIP_TRY(c, prot::launch_check_state(n, n_a, mate_a, mate_b, y_a, y_b, c->ctl,
+        HIP_TRY(c, prot::launch_check_state(n, n_a, mate_a, mate_b, y_a, y_b,
+                                            (int32_t)std::min<int64_t>(K + 2, 0x7FFF), c->ctl,
                                             c->stream));
+        const bool i2 = o && o->check_warm && k && !k8 && !otf.d;
+        if (i2)
+            HIP_TRY(c, prot::launch_check_feasible(k, ldk, n, n_a, mate_b, y_a, y_b, c->ctl,
+                                                   c->stream));
         HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl.err, &c->ctl->err, sizeof(int32_t),
                                   hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         if (c->stage->ctl.err & 2)
-            return fail(c, PROT_E_STATE, "warm-start state is not a matching satisfying (I1)");
+            return fail(c, PROT_E_STATE,
+                        i2 ? "warm-start state is not a matching satisfying (I1) and (I2) "
+                             "with |y| <= K + 2"
+                           : "warm-start state is not a matching satisfying (I1) with "
+                             "|y| <= K + 2");
     }
     HIP_TRY(c, prot::launch_init(a, warm, mate_a, mate_b, y_a, c->stream));
     if (c->rtime) HIP_TRY(c, prot::launch_clear_times(c->rtime, c->stream));
@@ -441,8 +482,29 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
     return PROT_OK;
 }
 
+// Status of a loop from its control block (host copy): an error code, or
+// PROT_OK / PROT_PARTIAL / PROT_E_PHASE_BOUND.
+int loop_status(prot_ctx *c, const Ctl &h)
+{
+    if (h.err & 4) return fail(c, PROT_E_HIP, "phase loop: a list entry was not published in time");
+    if (h.err & 32) return fail(c, PROT_E_HIP, "phase loop: a round barrier timed out");
+    if (h.err & 8) return fail(c, PROT_E_UNSUPPORTED, "phase loop: more than 2^32 rounds");
+    if (h.err & 64)
+        return fail(c, PROT_E_STATE, "phase loop: a dual left the range of Lemma 3.2 (the "
+                                     "warm start is not a state the method reaches)");
+    if (h.err & 16)
+        return fail(c, PROT_E_HIP, "phase loop: too few workgroups resident for the rows "
+                                   "(the GPU is busy; nothing ran)");
+    if (h.status == 2)
+        return fail(c, PROT_E_PHASE_BOUND,
+                    "phase loop: stopped by the phase-bound watchdog after %lld phases (the "
+                    "outputs hold the state reached)",
+                    (long long)h.phases);
+    return h.status ? PROT_PARTIAL : PROT_OK;
+}
+
 int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kind,
-            bool timed_build)
+            bool timed_build, bool may_retry = false)
 {
     static_assert(offsetof(prot_ctx::Stage, part_k) == offsetof(Report, part_k) &&
                       offsetof(prot_ctx::Stage, part_c) == offsetof(Report, part_c),
@@ -451,12 +513,12 @@ int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kin
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const Ctl &h = c->stage->ctl;
-    if (h.err & 4) return fail(c, PROT_E_HIP, "phase loop: a list entry was not published in time");
-    if (h.err & 8) return fail(c, PROT_E_UNSUPPORTED, "phase loop: more than 2^32 rounds");
-    if (h.err & 16)
-        return fail(c, PROT_E_HIP, "phase loop: too few workgroups resident for the rows "
-                                   "(the GPU is busy; PROT_LOOP_COOPERATIVE=1 waits for them)");
-    if (!st) return PROT_OK;
+    // nothing ran: the state is as it was given, so the loop can run again
+    if ((h.err & 16) && !(h.err & prot::kErrLoop) && may_retry && !c->cooperative)
+        return kRetryCooperative;
+    const int ls = loop_status(c, h);
+    if (ls < 0 && ls != PROT_E_PHASE_BOUND) return ls;
+    if (!st) return ls;
     std::memset(st, 0, sizeof(*st));
     st->phases = h.phases;
     st->sum_free = h.sum_free;
@@ -464,7 +526,7 @@ int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kin
     st->max_rounds = h.max_rounds;
     st->scanned = (int64_t)h.scanned;
     st->threshold = T;
-    st->status = h.status ? PROT_PARTIAL : PROT_OK;
+    st->status = ls;
     st->eps_internal = eps_int;
     long long sk = 0;
     double sc = 0.0;
@@ -503,7 +565,7 @@ void fill_match_counts(prot_ctx *c, int64_t n, prot_stats *st, const prot_opts *
     const int64_t free_after = c->stage->ctl.free_after;
     st->matched_in_phases = n - free_after;
     st->completed_pairs =
-        ((o && o->no_completion) || st->status == PROT_PARTIAL) ? 0 : free_after;
+        ((o && o->no_completion) || st->status != PROT_OK) ? 0 : free_after;
 }
 
 // |B| = 0 with |A| > 0: nothing to match; a cold start still hands back the
@@ -553,6 +615,7 @@ struct prot_batch {
     uint32_t *t_skip = nullptr;
     Ctl *t_ctl = nullptr;
     int32_t *t_scratch = nullptr;
+    double *loss_part = nullptr;     // partial sums of the loss forward
 };
 
 namespace {
@@ -636,6 +699,7 @@ int setup_teams(prot_ctx *c, prot_batch *bp, const std::vector<int32_t> &n_arr,
         a.T = prot_threshold(bp->eps, n);
         a.origin = origin;
         a.max_phases = bp->opts.max_phases;
+        a.phase_bound = phase_bound_for(&bp->opts, n, n, (int64_t)std::floor(1.0 / bp->eps), a.T);
         a.key = bp->t_key + ok;
         a.skip = bp->t_skip + ok;
         a.t = bp->t_t + ot;
@@ -729,7 +793,23 @@ int batch_enqueue(prot_batch *bp, hipStream_t s, const float *X, const float *Y,
     a.stats = reinterpret_cast<prot::InstanceStats *>(stats ? stats : bp->stats_tmp);
     a.queue = bp->queue;
     a.rtime = c->rtime;
+    a.err = bp->err;
     HIP_TRY(c, prot::launch_batch_solve(a, bp->n_max, bp->grid, s));
+    return PROT_OK;
+}
+
+// Status of a batch from its error word: bit 0 a non-finite coordinate,
+// bits 2, 3, 5, 6 a failed loop of some instance, bit 8 an instance stopped
+// by the phase-bound watchdog.
+int batch_err_status(prot_ctx *c, int32_t err)
+{
+    if (err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");
+    if (err & (4 | 32))
+        return fail(c, PROT_E_HIP, "phase loop: a list entry or a round barrier timed out");
+    if (err & 8) return fail(c, PROT_E_UNSUPPORTED, "phase loop: more than 2^32 rounds");
+    if (err & 64) return fail(c, PROT_E_STATE, "phase loop: a dual left the range of Lemma 3.2");
+    if (err & 256)
+        return fail(c, PROT_E_PHASE_BOUND, "an instance was stopped by the phase-bound watchdog");
     return PROT_OK;
 }
 
@@ -758,6 +838,7 @@ const char *prot_status_string(int s)
     case PROT_E_ARG: return "invalid argument";
     case PROT_E_RANGE: return "cost out of range or not finite";
     case PROT_E_EPS: return "eps out of range";
+    case PROT_E_PHASE_BOUND: return "stopped by the phase-bound watchdog";
     case PROT_E_STATE: return "invalid warm-start state";
     case PROT_E_HIP: return "HIP runtime error";
     case PROT_E_NOMEM: return "out of device memory";
@@ -800,6 +881,8 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
     if (const char *v = std::getenv("PROT_PRUNE_MIN_N")) c->prune_min_n = std::atoll(v);
     if (const char *v = std::getenv("PROT_LOOP_GATE_CAP")) c->gate_cap = std::max(0, std::atoi(v));
     if (const char *v = std::getenv("PROT_LOOP_COOPERATIVE")) c->cooperative = std::atoi(v) == 1;
+    if (const char *v = std::getenv("PROT_LOOP_BARRIER_TICKS"))
+        c->barrier_ticks = std::max<int64_t>(0, std::atoll(v));
     if (const char *v = std::getenv("PROT_LOOP_GROUPS")) {
         const int g = std::atoi(v);
         if (g >= 1 && g <= prot::kMaxGroups) c->loop_groups = g;
@@ -841,6 +924,7 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->rtime);
     (void)hipFree(c->mfma_buf);
     (void)hipFree(c->l1_buf);
+    (void)hipFree(c->loss_part);
     for (void *p : {(void *)c->ot.s_off, (void *)c->ot.d_off, (void *)c->ot.row_pt,
                     (void *)c->ot.col_pt, (void *)c->ot.ymax, (void *)c->ot.cnt,
                     (void *)c->ot.mate_a, (void *)c->ot.mate_b, (void *)c->ot.y_a,
@@ -979,15 +1063,25 @@ int prot_solve_rounded_rect(prot_ctx *c, const int16_t *k, int64_t n_b, int64_t 
     if (st) std::memset(st, 0, sizeof(*st));
     if (n_b == 0) return no_rows(c, n_a, warm, mate_a, y_a);
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-    int rc = run_loop(c, k, n_b, n_a, ldk, T, o, warm, mate_a, mate_b, y_a, y_b);
-    if (rc) return rc;
-    HIP_TRY(c, prot::launch_finalize(n_b, mate_b, k, ldk, 0, nullptr, 0, nullptr, nullptr, 0,
-                                     c->part_k, c->part_c, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
-    if (!st) return PROT_OK;
-    rc = collect(c, st, T, 0.0, 0, false);
+    auto enqueue = [&](bool coop) -> int {
+        HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+        int r = run_loop(c, k, n_b, n_a, ldk, T, o, warm, mate_a, mate_b, y_a, y_b, kKMaxAccepted,
+                         coop);
+        if (r) return r;
+        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, k, ldk, 0, nullptr, 0, nullptr, nullptr, 0,
+                                         c->part_k, c->part_c, c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+        return PROT_OK;
+    };
+    int rc = enqueue(false);
+    if (rc || !st) return rc;
+    rc = collect(c, st, T, 0.0, 0, false, true);
+    if (rc == kRetryCooperative) {
+        // a cold start begins again; a warm start's state is as it was given
+        if ((rc = enqueue(true))) return rc;
+        rc = collect(c, st, T, 0.0, 0, false);
+    }
     if (rc) return rc;
     fill_match_counts(c, n_b, st, o);
     return st->status;
@@ -1025,13 +1119,23 @@ int prot_solve_cost_rect(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, 
     HIP_TRY(c, prot::launch_round_costs(C, n_b, n_a, ldc, ei, c->kmat, ldk, c->ctl, c->stream,
                                         k8));
     HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-    rc = run_loop(c, c->kmat, n_b, n_a, ldk, T, o, 0, mate_a, mate_b, y_a, y_b, OnTheFly(),
-                  Copies(), k8);
-    if (rc) return rc;
-    HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, 1, C, ldc, nullptr, nullptr, 0,
-                                     c->part_k, c->part_c, c->stream, nullptr, 0.0, nullptr, k8));
-    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
-    rc = collect(c, st, T, ei, 1, true);
+    const int64_t K = (int64_t)std::floor(1.0 / ei);
+    auto enqueue = [&](bool coop) -> int {
+        int r = run_loop(c, c->kmat, n_b, n_a, ldk, T, o, 0, mate_a, mate_b, y_a, y_b, K, coop,
+                         OnTheFly(), Copies(), k8);
+        if (r) return r;
+        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, 1, C, ldc, nullptr, nullptr,
+                                         0, c->part_k, c->part_c, c->stream, nullptr, 0.0,
+                                         nullptr, k8));
+        HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+        return PROT_OK;
+    };
+    if ((rc = enqueue(false))) return rc;
+    rc = collect(c, st, T, ei, 1, true, true);
+    if (rc == kRetryCooperative) {
+        if ((rc = enqueue(true))) return rc;
+        rc = collect(c, st, T, ei, 1, true);
+    }
     if (rc) return rc;
     fill_match_counts(c, n_b, st, o);
     st->kmax = (int32_t)std::floor(1.0 / ei);
@@ -1097,18 +1201,29 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
         otf.Y = Y;
         otf.eps = ei;
     }
-    rc = run_loop(c, kmat, n_b, n_a, on_the_fly ? round_up(n_a, 8) : ldk, T, o, 0, mate_a,
-                  mate_b, y_a, y_b, otf, Copies(), k8);
-    if (rc) return rc;
-    if (on_the_fly)
-        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, nullptr, 0, 2, nullptr, 0, X, Y, d,
-                                         c->part_k, c->part_c, c->stream, &c->ctl->m, ei, c->th));
-    else
-        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, points_cost_kind(c), nullptr,
-                                         0, X, Y, d, c->part_k, c->part_c, c->stream, nullptr,
-                                         0.0, nullptr, k8));
-    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
-    rc = collect(c, st, T, ei, on_the_fly ? 2 : points_cost_kind(c), true);
+    const int64_t K = (int64_t)std::floor(1.0 / ei);
+    auto enqueue = [&](bool coop) -> int {
+        int r = run_loop(c, kmat, n_b, n_a, on_the_fly ? round_up(n_a, 8) : ldk, T, o, 0, mate_a,
+                         mate_b, y_a, y_b, K, coop, otf, Copies(), k8);
+        if (r) return r;
+        if (on_the_fly)
+            HIP_TRY(c, prot::launch_finalize(n_b, mate_b, nullptr, 0, 2, nullptr, 0, X, Y, d,
+                                             c->part_k, c->part_c, c->stream, &c->ctl->m, ei,
+                                             c->th));
+        else
+            HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, points_cost_kind(c),
+                                             nullptr, 0, X, Y, d, c->part_k, c->part_c,
+                                             c->stream, nullptr, 0.0, nullptr, k8));
+        HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+        return PROT_OK;
+    };
+    if ((rc = enqueue(false))) return rc;
+    const int kind = on_the_fly ? 2 : points_cost_kind(c);
+    rc = collect(c, st, T, ei, kind, true, true);
+    if (rc == kRetryCooperative) {
+        if ((rc = enqueue(true))) return rc;
+        rc = collect(c, st, T, ei, kind, true);
+    }
     if (rc) return rc;
     fill_match_counts(c, n_b, st, o);
     if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");
@@ -1217,45 +1332,54 @@ int prot_ot_solve(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, int64_t
     Copies cp;
     cp.rmap = w.row_pt;
     cp.ymax = w.ymax;
-    rc = run_loop(c, c->kmat, NB, NA, ldk, T, &lo, 0, w.mate_a, w.mate_b, w.y_a, w.y_b,
-                  OnTheFly(), cp);
-    if (rc) return rc;
-    prot::OtPlanArgs pa{};
-    pa.mate_b = w.mate_b;
-    pa.row_pt = w.row_pt;
-    pa.col_pt = w.col_pt;
-    pa.NB = NB;
-    pa.k = c->kmat;
-    pa.ldk = ldk;
-    pa.cnt = w.cnt;
-    pa.n_b = n_b;
-    pa.n_a = n_a;
-    pa.theta = theta;
-    pa.nu = nu;
-    pa.mu = mu;
-    pa.C = C;
-    pa.ldc = ldc;
-    pa.plan = plan;
-    pa.ldp = ldp;
-    pa.rv = w.rv;
-    pa.qv = w.qv;
-    pa.R = w.R;
-    pa.Q = w.Q;
-    pa.part_k = c->part_k;
-    pa.part_c = c->part_c;
-    pa.info = w.info;
-    HIP_TRY(c, prot::launch_ot_plan(pa, c->stream));
-    HIP_TRY(c, prot::launch_ot_duals(w.y_b, w.s_off, n_b, y_b_lo, y_b_nlo, c->ctl, c->stream));
-    HIP_TRY(c, prot::launch_ot_duals(w.y_a, w.d_off, n_a, y_a_lo, y_a_nlo, c->ctl, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
-    HIP_TRY(c, hipMemcpyAsync(&c->stage->ot, w.info, sizeof(prot::OtInfo),
-                              hipMemcpyDeviceToHost, c->stream));
-    rc = collect(c, &st->loop, T, ei, 1, true);  // synchronises the stream
+    const int64_t K = (int64_t)std::floor(1.0 / ei);
+    auto enqueue = [&](bool coop) -> int {
+        int r = run_loop(c, c->kmat, NB, NA, ldk, T, &lo, 0, w.mate_a, w.mate_b, w.y_a, w.y_b, K,
+                         coop, OnTheFly(), cp);
+        if (r) return r;
+        prot::OtPlanArgs pa{};
+        pa.mate_b = w.mate_b;
+        pa.row_pt = w.row_pt;
+        pa.col_pt = w.col_pt;
+        pa.NB = NB;
+        pa.k = c->kmat;
+        pa.ldk = ldk;
+        pa.cnt = w.cnt;
+        pa.n_b = n_b;
+        pa.n_a = n_a;
+        pa.theta = theta;
+        pa.nu = nu;
+        pa.mu = mu;
+        pa.C = C;
+        pa.ldc = ldc;
+        pa.plan = plan;
+        pa.ldp = ldp;
+        pa.rv = w.rv;
+        pa.qv = w.qv;
+        pa.R = w.R;
+        pa.Q = w.Q;
+        pa.part_k = c->part_k;
+        pa.part_c = c->part_c;
+        pa.info = w.info;
+        HIP_TRY(c, prot::launch_ot_plan(pa, c->stream));
+        HIP_TRY(c, prot::launch_ot_duals(w.y_b, w.s_off, n_b, y_b_lo, y_b_nlo, c->ctl, c->stream));
+        HIP_TRY(c, prot::launch_ot_duals(w.y_a, w.d_off, n_a, y_a_lo, y_a_nlo, c->ctl, c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+        HIP_TRY(c, hipMemcpyAsync(&c->stage->ot, w.info, sizeof(prot::OtInfo),
+                                  hipMemcpyDeviceToHost, c->stream));
+        return PROT_OK;
+    };
+    if ((rc = enqueue(false))) return rc;
+    rc = collect(c, &st->loop, T, ei, 1, true, true);  // synchronises the stream
+    if (rc == kRetryCooperative) {
+        if ((rc = enqueue(true))) return rc;
+        rc = collect(c, &st->loop, T, ei, 1, true);
+    }
     if (rc) return rc;
     fill_match_counts(c, NB, &st->loop, &lo);
     st->repaired_mass = c->stage->ot.repaired;
     if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a cost is NaN or outside [0,1]");
-    if (c->stage->ctl.err & 16)
+    if (c->stage->ctl.err & 128)
         return fail(c, PROT_E_HIP, "internal: the copies of a point hold more than two duals");
     return st->loop.status;
 }
@@ -1332,6 +1456,8 @@ int prot_batch_create_config(prot_ctx *c, int32_t batch, const int64_t *n_host, 
     }
     if (!rc) rc = dev_alloc(c, &bp->err, 1);
     if (!rc) rc = dev_alloc(c, &bp->queue, 1);
+    if (!rc && batch > 0)
+        rc = dev_alloc(c, &bp->loss_part, (size_t)prot::loss_parts(n_max, d) * batch);
     if (!rc && batch > 0) {
         prot::PointsJob j{};
         j.d = d;
@@ -1378,6 +1504,7 @@ int prot_batch_destroy(prot_batch *bp)
     (void)hipFree(bp->t_ctl);
     (void)hipFree(bp->t_scratch);
     (void)hipFree(bp->t_skip);
+    (void)hipFree(bp->loss_part);
     delete bp;
     return PROT_OK;
 }
@@ -1511,8 +1638,8 @@ int prot_batch_loss_fwd(prot_batch *bp, const float *X, const float *Y, const in
     if (bp->batch == 0) return PROT_OK;
     if (!X || !Y || !mate_b || !loss) return fail(c, PROT_E_ARG, "prot_batch_loss_fwd: null pointer");
     HIP_TRY(c, hipSetDevice(c->device));
-    prot::LossArgs a{bp->batch, bp->d, bp->n_arr, bp->pt_off, X, Y, nullptr, mate_b};
-    HIP_TRY(c, prot::launch_loss_fwd(a, loss, c->stream));
+    prot::LossArgs a{bp->batch, bp->d, bp->n_arr, bp->pt_off, X, Y, nullptr, mate_b, 0};
+    HIP_TRY(c, prot::launch_loss_fwd(a, bp->n_max, bp->loss_part, loss, c->stream));
     return PROT_OK;
 }
 
@@ -1525,7 +1652,7 @@ int prot_batch_loss_bwd(prot_batch *bp, const float *X, const float *Y, const in
     if (!X || !Y || !mate_a || !mate_b || !grad_loss || !dX || !dY)
         return fail(c, PROT_E_ARG, "prot_batch_loss_bwd: null pointer");
     HIP_TRY(c, hipSetDevice(c->device));
-    prot::LossArgs a{bp->batch, bp->d, bp->n_arr, bp->pt_off, X, Y, mate_a, mate_b};
+    prot::LossArgs a{bp->batch, bp->d, bp->n_arr, bp->pt_off, X, Y, mate_a, mate_b, 0};
     HIP_TRY(c, prot::launch_loss_bwd(a, bp->n_max, grad_loss, dX, dY, c->stream));
     return PROT_OK;
 }
@@ -1551,10 +1678,67 @@ int prot_solve_batched_points(prot_ctx *c, int32_t batch, const int64_t *n_host,
         if (e != hipSuccess) rc = hip_fail(c, e, "batched solve");
     }
     prot_batch_destroy(bp);
-    if (!rc && (err & 1)) rc = fail(c, PROT_E_RANGE, "a point coordinate is not finite");
-    if (!rc && (err & 4)) rc = fail(c, PROT_E_HIP, "phase loop: a list entry was not published in time");
-    if (!rc && (err & 8)) rc = fail(c, PROT_E_UNSUPPORTED, "phase loop: more than 2^32 rounds");
+    if (!rc) rc = batch_err_status(c, err);
     return rc;
+}
+
+int prot_ctx_status(prot_ctx *c)
+{
+    if (!c) return PROT_E_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const Ctl &h = c->stage->ctl;
+    if (h.err & 1) return fail(c, PROT_E_RANGE, "a cost or coordinate is NaN or out of range");
+    if (h.err & 2) return fail(c, PROT_E_STATE, "invalid warm-start state");
+    return loop_status(c, h);
+}
+
+int prot_batch_status(prot_batch *bp)
+{
+    if (!bp) return PROT_E_ARG;
+    prot_ctx *c = bp->ctx;
+    if (bp->batch == 0) return PROT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ctl.err, bp->err, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return batch_err_status(c, c->stage->ctl.err);
+}
+
+int prot_ot_loss_fwd(prot_ctx *c, int32_t batch, int64_t n, int32_t d, const float *X,
+                     const float *Y, const int32_t *mate_b, float *loss)
+{
+    if (!c) return PROT_E_ARG;
+    if (batch < 0 || n < 0 || d < 1 || (batch > 0 && n > 0 && (!X || !Y || !mate_b || !loss)))
+        return fail(c, PROT_E_ARG, "prot_ot_loss_fwd: bad pointer or size");
+    if (batch == 0) return PROT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int64_t need = (int64_t)prot::loss_parts(n, d) * batch;
+    if (need > c->loss_cap || !c->loss_part) {
+        const int rc = dev_alloc(c, &c->loss_part, (size_t)need);
+        if (rc) return rc;
+        c->loss_cap = need;
+    }
+    prot::LossArgs a{batch, d, nullptr, nullptr, X, Y, nullptr, mate_b, n};
+    HIP_TRY(c, prot::launch_loss_fwd(a, n, c->loss_part, loss, c->stream));
+    return PROT_OK;
+}
+
+int prot_ot_loss_bwd(prot_ctx *c, int32_t batch, int64_t n, int32_t d, const float *X,
+                     const float *Y, const int32_t *mate_b, const float *grad_loss, float *dX,
+                     float *dY)
+{
+    if (!c) return PROT_E_ARG;
+    if (batch < 0 || n < 0 || d < 1 ||
+        (batch > 0 && n > 0 && (!X || !Y || !mate_b || !grad_loss || !dX || !dY)))
+        return fail(c, PROT_E_ARG, "prot_ot_loss_bwd: bad pointer or size");
+    if (batch == 0 || n == 0) return PROT_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    prot::LossArgs a{batch, d, nullptr, nullptr, X, Y, nullptr, mate_b, n};
+    HIP_TRY(c, prot::launch_loss_bwd(a, n, grad_loss, dX, dY, c->stream));
+    return PROT_OK;
 }
 
 int64_t prot_get_round_times(prot_ctx *c, int64_t *out, int64_t cap)

@@ -206,6 +206,7 @@ __device__ void solve_instance(const BatchArgs &A, int inst, BatchShared<NMAX> &
     const int16_t *k = A.k + A.k_off[inst];
     const int64_t ldk = A.ldk_arr[inst];
     const int64_t T = (int64_t)floor(A.eps * (double)n + 1e-9);
+    const int64_t bound = (2 * (int64_t)n * ((int64_t)floor(1.0 / A.eps) + 2) - n) / (T + 1);
 
     // Initial state (Section 2.2): y(b) = 1, y(a) = 0, M empty.
     for (int i = tid; i < n; i += kBatchThreads) {
@@ -230,6 +231,14 @@ __device__ void solve_instance(const BatchArgs &A, int inst, BatchShared<NMAX> &
         if ((int64_t)nF <= T) break;
         if (A.max_phases > 0 && phases >= A.max_phases) {
             status = 1;
+            break;
+        }
+        // watchdog: a cold start needs at most (2n(K + 2) - n) / (T + 1)
+        // phases (Lemma 3.2 with eq. (4)); more means a fault
+        if (phases >= bound) {
+            status = -4;
+            if (tid == 0)
+                __hip_atomic_fetch_or(A.err, 256, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
         phases += 1;
@@ -314,7 +323,7 @@ __device__ void solve_instance(const BatchArgs &A, int inst, BatchShared<NMAX> &
     }
     for (uint32_t i = tid; i < nfree; i += kBatchThreads) S.at[S.F[cur][i]] = 1;
     __syncthreads();
-    if (A.complete) {
+    if (A.complete && status >= 0) {
         const int nb = ordered_list(S, n, [&](int i) { return S.at[i] != 0; }, S.ab[0]);
         const int na = ordered_list(S, n, [&](int i) { return S.key[i] == 0ull; }, S.ab[1]);
         const int m = min(nb, na);

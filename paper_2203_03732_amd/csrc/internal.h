@@ -18,10 +18,13 @@ struct alignas(128) Ctl {
                                   // so that no entry of an earlier launch matches a tag)
     unsigned long long pad1[2];
     unsigned long long scanned;   // matrix entries examined
-    int32_t status;               // 0 finished, 1 stopped at max_phases
+    int32_t status;               // 0 finished, 1 stopped at max_phases, 2 stopped by the
+                                  // phase-bound watchdog
     int32_t err;                  // bit 0: cost out of range / non-finite; bit 1: bad state;
                                   // bit 2: a list entry did not arrive; bit 3: round ids exhausted;
-                                  // bit 4: too few workgroups resident for the rows
+                                  // bit 4: too few workgroups resident for the rows (nothing ran);
+                                  // bit 5: a round barrier timed out; bit 6: a dual left its
+                                  // 15-bit field; bit 7: transport copies hold > 2 duals
     int64_t phases;
     int64_t sum_free;
     int64_t rounds;
@@ -32,6 +35,8 @@ struct alignas(128) Ctl {
     float m;                      // max squared distance of the last point build
 };
 
+// Error bits of a phase loop that leave its state unusable.
+constexpr int32_t kErrLoop = 4 | 8 | 32 | 64;
 constexpr int kLoopThreads = 1024;      // threads per workgroup of the loop
 // Round barrier: the workgroups are split into up to kMaxGroups groups
 // (blockIdx % G); each round has one word per group, kWordStride words
@@ -67,6 +72,8 @@ struct LoopArgs {
     int32_t origin;         // 0: diagonal, 1: zero
     int32_t pad;
     int64_t max_phases;
+    int64_t phase_bound;      // watchdog: stop with status 2 after this many phases (0: none)
+    int64_t barrier_ticks;    // bounded round-barrier wait, 100 MHz ticks (0: the default)
     unsigned long long *key;  // per column: round, row and row dual of its last winner
     uint16_t *t;              // per column: -y(a) (number of phases it was taken in)
     int32_t *y_b;
@@ -135,6 +142,7 @@ struct BatchArgs {
     InstanceStats *stats;
     unsigned int *queue;
     int64_t *rtime;           // optional diagnostics: 4 int64 per round of the first job
+    int32_t *err;             // bit 8: an instance was stopped by the phase-bound watchdog
 };
 
 // Batched instances solved by teams of phase-loop workgroups: per-instance
@@ -157,10 +165,11 @@ struct TeamArgs {
 struct LossArgs {
     int32_t batch;
     int32_t d;
-    const int32_t *n_arr;
-    const int64_t *pt_off;
+    const int32_t *n_arr;     // per-instance n (null: every instance has n_uniform)
+    const int64_t *pt_off;    // first row of each instance (null: inst * n_uniform)
     const float *X, *Y;
-    const int32_t *mate_a, *mate_b;
+    const int32_t *mate_a, *mate_b;  // mate_a null: the backward scatters through mate_b
+    int64_t n_uniform;
 };
 
 // cost.hip
@@ -181,7 +190,10 @@ hipError_t batch_grid(int32_t n_max, int32_t batch, int *grid);
 hipError_t launch_batch_solve(const BatchArgs &a, int32_t n_max, int grid, hipStream_t s);
 
 // loss.hip
-hipError_t launch_loss_fwd(const LossArgs &a, float *loss, hipStream_t s);
+// partial: loss_parts(n_max, d) * batch doubles of workspace.
+int loss_parts(int64_t n_max, int32_t d);
+hipError_t launch_loss_fwd(const LossArgs &a, int64_t n_max, double *partial, float *loss,
+                           hipStream_t s);
 hipError_t launch_loss_bwd(const LossArgs &a, int64_t n_max, const float *grad_loss, float *dX,
                            float *dY, hipStream_t s);
 
@@ -191,7 +203,10 @@ hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
 hipError_t launch_clear_err(Ctl *ctl, hipStream_t s);
 hipError_t launch_check_state(int64_t n, int64_t na, const int32_t *mate_a,
                               const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
-                              Ctl *ctl, hipStream_t s);
+                              int32_t ybound, Ctl *ctl, hipStream_t s);
+hipError_t launch_check_feasible(const int16_t *k, int64_t ldk, int64_t n, int64_t na,
+                                 const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
+                                 Ctl *ctl, hipStream_t s);
 hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max);
 hipError_t launch_clear_times(int64_t *rtime, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);

@@ -8,31 +8,45 @@
 //   dL/dx_b = (2 g_i / n_i) (x_b - y_mate(b)),
 //   dL/dy_a = (2 g_i / n_i) (y_a - x_mate^-1(a)),
 // and 0 for vertices the plan leaves unmatched.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace prot {
 namespace {
 
 constexpr int kLossThreads = 256;
-constexpr int kFwdThreads = 1024;
+constexpr int kFwdThreads = 256;
 constexpr int kFwdUnroll = 4;
 
-// One block per instance; coordinate e of the instance is handled by thread
-// e mod kFwdThreads, so consecutive lanes read consecutive floats, with
-// kFwdUnroll coordinates' loads in flight per thread. Binary64 accumulation
-// (each thread in ascending e), fixed-order block reduction.
+__device__ inline int64_t inst_n(const LossArgs &A, int inst)
+{
+    return A.n_arr ? (int64_t)A.n_arr[inst] : A.n_uniform;
+}
+__device__ inline int64_t inst_off(const LossArgs &A, int inst)
+{
+    return A.n_arr ? A.pt_off[inst] : (int64_t)inst * A.n_uniform;
+}
+
+// grid (parts, batch): block `part` of instance `inst` sums the squared
+// differences of coordinates [part * per, (part + 1) * per) of the instance
+// (row-major, so consecutive lanes read consecutive floats, kFwdUnroll
+// loads in flight per thread), each thread in ascending order in binary64,
+// then a fixed-order block reduction into partial[inst * parts + part].
 __global__ void __launch_bounds__(kFwdThreads)
-ot_loss_fwd_kernel(LossArgs A, float *loss)
+ot_loss_part_kernel(LossArgs A, double *partial)
 {
     __shared__ double red[kFwdThreads];
-    const int inst = blockIdx.x;
-    const int64_t n = A.n_arr[inst], off = A.pt_off[inst];
+    const int inst = blockIdx.y, parts = gridDim.x;
+    const int64_t n = inst_n(A, inst), off = inst_off(A, inst);
     const int d = A.d;
     const float *X = A.X + off * d, *Y = A.Y + off * d;
     const int32_t *mb = A.mate_b + off;
     const int64_t total = n * d;
+    const int64_t per = (total + parts - 1) / parts;
+    const int64_t lo = min(total, (int64_t)blockIdx.x * per), hi = min(total, lo + per);
     double s = 0.0;
-    for (int64_t e0 = threadIdx.x; e0 < total; e0 += (int64_t)kFwdUnroll * kFwdThreads) {
+    for (int64_t e0 = lo + threadIdx.x; e0 < hi; e0 += (int64_t)kFwdUnroll * kFwdThreads) {
         float x[kFwdUnroll], y[kFwdUnroll];
         bool use[kFwdUnroll];
 #pragma unroll
@@ -40,10 +54,10 @@ ot_loss_fwd_kernel(LossArgs A, float *loss)
             const int64_t e = e0 + (int64_t)u * kFwdThreads;
             use[u] = false;
             x[u] = y[u] = 0.0f;
-            if (e < total) {
+            if (e < hi) {
                 const int64_t b = e / d;
                 const int32_t a = mb[b];
-                if (a >= 0) {
+                if (a >= 0 && a < n) {
                     use[u] = true;
                     x[u] = X[e];
                     y[u] = Y[(int64_t)a * d + (e - b * d)];
@@ -63,7 +77,18 @@ ot_loss_fwd_kernel(LossArgs A, float *loss)
         if (threadIdx.x < o) red[threadIdx.x] = __dadd_rn(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) loss[inst] = n > 0 ? (float)(red[0] / (double)n) : 0.0f;
+    if (threadIdx.x == 0) partial[(int64_t)inst * parts + blockIdx.x] = red[0];
+}
+
+// One thread per instance: the partial sums in part order, divided by n.
+__global__ void ot_loss_sum_kernel(LossArgs A, const double *partial, int parts, float *loss)
+{
+    const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= A.batch) return;
+    double s = 0.0;
+    for (int q = 0; q < parts; ++q) s = __dadd_rn(s, partial[(int64_t)inst * parts + q]);
+    const int64_t n = inst_n(A, inst);
+    loss[inst] = n > 0 ? (float)(s / (double)n) : 0.0f;
 }
 
 // grid.y = instance, grid.x over the instance's n * d coordinates.
@@ -71,7 +96,7 @@ __global__ void __launch_bounds__(kLossThreads)
 ot_loss_bwd_kernel(LossArgs A, const float *grad_loss, float *dX, float *dY)
 {
     const int inst = blockIdx.y;
-    const int64_t n = A.n_arr[inst], off = A.pt_off[inst];
+    const int64_t n = inst_n(A, inst), off = inst_off(A, inst);
     const int d = A.d;
     const int64_t e = (int64_t)blockIdx.x * kLossThreads + threadIdx.x;
     if (e >= n * d) return;
@@ -81,16 +106,61 @@ ot_loss_bwd_kernel(LossArgs A, const float *grad_loss, float *dX, float *dY)
     const float *X = A.X + off * d, *Y = A.Y + off * d;
     const int32_t a = A.mate_b[off + v];
     const int32_t b = A.mate_a[off + v];
-    dX[off * d + e] = a >= 0 ? scale * (X[e] - Y[(int64_t)a * d + j]) : 0.0f;
-    dY[off * d + e] = b >= 0 ? scale * (Y[e] - X[(int64_t)b * d + j]) : 0.0f;
+    dX[off * d + e] = a >= 0 && a < n ? scale * (X[e] - Y[(int64_t)a * d + j]) : 0.0f;
+    dY[off * d + e] = b >= 0 && b < n ? scale * (Y[e] - X[(int64_t)b * d + j]) : 0.0f;
+}
+
+// Without mate_a: every coordinate of dY starts at 0 (a column no row
+// holds keeps it), then each matched row b writes dX_b and the coordinates
+// of its column's dY (a matching gives each column at most one row).
+__global__ void fill_zero_kernel(float *p, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+__global__ void __launch_bounds__(kLossThreads)
+ot_loss_bwd_rows_kernel(LossArgs A, const float *grad_loss, float *dX, float *dY)
+{
+    const int inst = blockIdx.y;
+    const int64_t n = inst_n(A, inst), off = inst_off(A, inst);
+    const int d = A.d;
+    const int64_t e = (int64_t)blockIdx.x * kLossThreads + threadIdx.x;
+    if (e >= n * d) return;
+    const int64_t v = e / d;
+    const int j = (int)(e - v * d);
+    const float scale = 2.0f * grad_loss[inst] / (float)n;
+    const float *X = A.X + off * d, *Y = A.Y + off * d;
+    const int32_t a = A.mate_b[off + v];
+    if (a >= 0 && a < n) {
+        const float diff = X[e] - Y[(int64_t)a * d + j];
+        dX[off * d + e] = scale * diff;
+        dY[(off + a) * d + j] = -(scale * diff);
+    } else {
+        dX[off * d + e] = 0.0f;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_loss_fwd(const LossArgs &a, float *loss, hipStream_t s)
+int loss_parts(int64_t n_max, int32_t d)
 {
-    if (a.batch > 0)
-        hipLaunchKernelGGL(ot_loss_fwd_kernel, dim3(a.batch), dim3(kFwdThreads), 0, s, a, loss);
+    // about 8192 coordinates per block, at most 64 blocks per instance
+    const int64_t p = (n_max * d + 8191) / 8192;
+    return (int)(p < 1 ? 1 : (p > 64 ? 64 : p));
+}
+
+hipError_t launch_loss_fwd(const LossArgs &a, int64_t n_max, double *partial, float *loss,
+                           hipStream_t s)
+{
+    if (a.batch > 0) {
+        const int parts = loss_parts(n_max, a.d);
+        hipLaunchKernelGGL(ot_loss_part_kernel, dim3((unsigned)parts, (unsigned)a.batch),
+                           dim3(kFwdThreads), 0, s, a, partial);
+        hipLaunchKernelGGL(ot_loss_sum_kernel, dim3((unsigned)((a.batch + 255) / 256)), dim3(256),
+                           0, s, a, (const double *)partial, parts, loss);
+    }
     return hipGetLastError();
 }
 
@@ -99,8 +169,16 @@ hipError_t launch_loss_bwd(const LossArgs &a, int64_t n_max, const float *grad_l
 {
     if (a.batch > 0) {
         const int64_t blocks = (n_max * a.d + kLossThreads - 1) / kLossThreads;
-        hipLaunchKernelGGL(ot_loss_bwd_kernel, dim3((unsigned)blocks, (unsigned)a.batch),
-                           dim3(kLossThreads), 0, s, a, grad_loss, dX, dY);
+        if (a.mate_a) {
+            hipLaunchKernelGGL(ot_loss_bwd_kernel, dim3((unsigned)blocks, (unsigned)a.batch),
+                               dim3(kLossThreads), 0, s, a, grad_loss, dX, dY);
+        } else {
+            const int64_t count = (int64_t)a.batch * n_max * a.d;  // uniform n
+            const int64_t g = std::min<int64_t>((count + 255) / 256, 65536);
+            hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)g), dim3(256), 0, s, dY, count);
+            hipLaunchKernelGGL(ot_loss_bwd_rows_kernel, dim3((unsigned)blocks, (unsigned)a.batch),
+                               dim3(kLossThreads), 0, s, a, grad_loss, dX, dY);
+        }
     }
     return hipGetLastError();
 }

@@ -334,7 +334,7 @@ __global__ void ot_duals_kernel(const int32_t *y, const int64_t *off, int64_t n_
         }
         if (off[p + 1] == off[p]) mn = 0;
         else if (mx - mn > 1)
-            __hip_atomic_fetch_or(&ctl->err, 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(&ctl->err, 128, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         lo[p] = mn;
         nlo[p] = cnt;
     }

@@ -59,6 +59,12 @@ constexpr int kShiftFree = 21, kShiftLose = 42, kShiftArrive = 53;
 constexpr unsigned long long kField = (1ull << 21) - 1;
 constexpr uint16_t kTaken = 0x8000;            // mark: column taken earlier in the phase
 constexpr int kSpinLimit = 1 << 22;            // bounded waits for list entries
+// Bounded wait at a round barrier: ~10 s of the 100 MHz device clock. A round
+// of the largest instances takes milliseconds; on time-out bit 5 of the error
+// word is raised and every workgroup leaves the loop (each one's wait is
+// bounded, so the grid drains).
+constexpr int64_t kBarrierTicks = 1000000000ll;
+constexpr int32_t kDualMax = 0x7FFF;           // |y| fits the 15-bit fields of keys and lists
 constexpr uint32_t kRoundLimit = 0xFFFFFF00u;  // round ids must fit the key's 32 bits
 constexpr int kGateSpin = 256;                 // gate polls (~0.3 ms) before it closes early
 
@@ -79,13 +85,35 @@ __device__ inline uint32_t take_raw_from(const unsigned long long *p, unsigned l
                                         uint32_t tag, int32_t *err)
 {
     for (int spins = 0; (uint32_t)(v >> 32) != tag; v = ld_agent(p)) {
-        if (++spins > kSpinLimit) {
+        // once any wait has timed out, later waits give up at once
+        if (++spins > kSpinLimit || ((spins & 1023) == 0 && (ld_agent(err) & 36))) {
             __hip_atomic_fetch_or(err, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
         __builtin_amdgcn_s_sleep(1);
     }
     return (uint32_t)v;
+}
+
+// y(b) + 1 for a row that found no column (step (III)), unless that leaves
+// the 15-bit field the dual travels in: then bit 6 of the error word is
+// raised, the dual stays and -1 is returned: the row is left out of the next
+// free list, so the loop ends soon and the host reports the error (Lemma 3.2
+// keeps |y| <= K + 2 <= 32767 in every state the method reaches, so only an
+// inconsistent warm start gets here).
+__device__ inline int32_t grown_dual(int32_t yb, int32_t *err)
+{
+    if (yb < kDualMax) return yb + 1;
+    __hip_atomic_fetch_or(err, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return -1;
+}
+
+// t(a) + 1 for a column taken in a phase (step (III)), with the same guard.
+__device__ inline uint16_t grown_t(uint16_t t, int32_t *err)
+{
+    if ((t & 0x7FFF) < kDualMax) return (uint16_t)(t + 1);
+    __hip_atomic_fetch_or(err, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return t;
 }
 
 __device__ inline int32_t take_entry_from(const unsigned long long *p, unsigned long long v,
@@ -546,10 +574,12 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
     if (!warm && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->free0 = (uint32_t)n;
 }
 
-// Warm-start check, O(n): the mate arrays form one matching and (I1) holds.
+// Warm-start check, O(n): the mate arrays form one matching, (I1) holds
+// (y(b) >= 0, y(a) <= 0, y(a) = 0 for a free a; Section 2.2) and every dual
+// lies within Lemma 3.2's bound |y| <= K + 2 = ybound.
 __global__ void check_state_kernel(int64_t n, int64_t na, const int32_t *mate_a,
                                    const int32_t *mate_b, const int32_t *y_a,
-                                   const int32_t *y_b, Ctl *ctl)
+                                   const int32_t *y_b, int32_t ybound, Ctl *ctl)
 {
     bool bad = false;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na;
@@ -557,13 +587,38 @@ __global__ void check_state_kernel(int64_t n, int64_t na, const int32_t *mate_a,
         const int32_t ma = mate_a[i];
         if (ma >= n || ma < -1) bad = true;
         else if (ma >= 0 && mate_b[ma] != i) bad = true;
-        if (y_a[i] > 0 || y_a[i] < -32000) bad = true;
+        if (y_a[i] > 0 || y_a[i] < -ybound) bad = true;
         if (ma < 0 && y_a[i] != 0) bad = true;
         if (i < n) {
             const int32_t mb = mate_b[i];
             if (mb >= na || mb < -1) bad = true;
             else if (mb >= 0 && mate_a[mb] != i) bad = true;
-            if (y_b[i] < 0 || y_b[i] > 32000) bad = true;
+            if (y_b[i] < 0 || y_b[i] > ybound) bad = true;
+        }
+    }
+    if (bad) __hip_atomic_fetch_or(&ctl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Warm-start check, O(n_b n_a): (I2), i.e. eq. (2) on every edge and eq. (3)
+// on the matching, in units of eps: y(a) + y(b) <= k + 1 for every (a, b) and
+// y(a) + y(b) = k for a matched pair (Section 2.2). One thread per 8 columns
+// of a row; rows by grid.y.
+__global__ void check_feasible_kernel(const int16_t *k, int64_t ldk, int64_t n, int64_t na,
+                                      const int32_t *mate_b, const int32_t *y_a,
+                                      const int32_t *y_b, Ctl *ctl)
+{
+    bool bad = false;
+    for (int64_t b = blockIdx.y; b < n; b += gridDim.y) {
+        const int32_t yb = y_b[b], mb = mate_b[b];
+        for (int64_t a0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * 8; a0 < na;
+             a0 += (int64_t)gridDim.x * blockDim.x * 8) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t a = a0 + e;
+                if (a >= na) break;
+                const int32_t s = y_a[a] + yb, kv = k[b * ldk + a];
+                if (s > kv + 1 || (a == mb && s != kv)) bad = true;
+            }
         }
     }
     if (bad) __hip_atomic_fetch_or(&ctl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -657,7 +712,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     }
     extern __shared__ __align__(16) uint16_t t_lds[];
     __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose;
-    __shared__ uint32_t s_base_l, s_base_f, s_ltot, s_over;
+    __shared__ uint32_t s_base_l, s_base_f, s_ltot, s_over, s_abort;
     __shared__ unsigned long long s_scan, s_pend_scan;
     __shared__ int64_t s_pend_p;
     // per group: list lengths of the phase so far, last round's new taken
@@ -689,6 +744,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     uint32_t n_i = ld_agent(&ctl->free0);  // |B'| of the current phase
     if (threadIdx.x == 0) {
         s_cnt_l = s_cnt_f = s_lose = 0;
+        s_abort = 0;
         s_scan = 0;
         s_pend_scan = 0;
         s_nact[0] = s_nact[1] = 0;
@@ -729,7 +785,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             const int j = group_of(s_lpre, G, i);
             const int32_t a =
                 take_entry(pend_L + j * cap + s_lstart[j] + (i - s_lpre[j]), pend_tag, na, &ctl->err);
-            t_lds[a] = (uint16_t)(t_lds[a] + 1);
+            t_lds[a] = grown_t(t_lds[a], &ctl->err);
         }
         pend = 0;
     };
@@ -737,6 +793,13 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         if ((int64_t)n_i <= A.T) break;
         if (A.max_phases > 0 && p >= A.max_phases) {
             if (leader) ctl->status = 1;
+            break;
+        }
+        // the watchdog: no run of the method needs more phases than this
+        // bound (Lemma 3.2 with eq. (4)), so reaching it means the state
+        // given to the loop was not one the method can reach
+        if (A.phase_bound > 0 && p >= A.phase_bound) {
+            if (leader) ctl->status = 2;
             break;
         }
         if (r >= kRoundLimit) {
@@ -828,7 +891,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     const int j = group_of(s_lpre, G, i);
                     const int32_t a =
                         take_entry(Lc + j * cap + s_lstart[j] + (i - s_lpre[j]), tag, na, &ctl->err);
-                    t_lds[a] = (uint16_t)((t_lds[a] + 1) | kTaken);
+                    t_lds[a] = (uint16_t)(grown_t(t_lds[a], &ctl->err) | kTaken);
                 }
                 if (mine) {
                     if (k_now == s_key) mine = false;
@@ -894,9 +957,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 const bool lead = R == 1 || k_rank == 0;
                 if (lead) {
                     if ((pre >> lane) & 1ull) {
-                        st_agent(y_b + s_b, s_yb + 1);
+                        const int32_t y1 = grown_dual(s_yb, &ctl->err);
+                        st_agent(y_b + s_b, y1 < 0 ? s_yb : y1);
                         st_agent(A.skip + s_b, s_skip - 1u);
-                        my_fv = free_val(s_b, s_yb + 1);
+                        my_fv = y1 < 0 ? kNoRow : free_val(s_b, y1);
                     }
                     wave_scan += (unsigned long long)na * (unsigned long long)__popcll(pre);
                 }
@@ -947,9 +1011,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         if (lead) {
                             wave_scan += (unsigned long long)(na - pos);
                             if (lane == 0) {
-                                st_agent(y_b + b, yb + 1);
-                                if constexpr (kCopies) raise_top(A.ymax + v.rb, p, yb + 1);
-                                my_fv = free_val(b, yb + 1);
+                                const int32_t y1 = grown_dual(yb, &ctl->err);
+                                st_agent(y_b + b, y1 < 0 ? yb : y1);
+                                if constexpr (kCopies) raise_top(A.ymax + v.rb, p, y1 < 0 ? yb : y1);
+                                my_fv = y1 < 0 ? kNoRow : free_val(b, y1);
                                 if (track) {
                                     const int slack = s_mn[team_local] - (yb - 1);
                                     if (slack >= 2)
@@ -1022,9 +1087,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         wave_scan += (unsigned long long)(na - pos);
                         const int slack = track ? wave_min(mn) - (yb - 1) : 0;
                         if (lane == s) {
-                            st_agent(y_b + b, yb + 1);
-                            if constexpr (kCopies) raise_top(A.ymax + v.rb, p, yb + 1);
-                            my_fv = free_val(b, yb + 1);
+                            const int32_t y1 = grown_dual(yb, &ctl->err);
+                            st_agent(y_b + b, y1 < 0 ? yb : y1);
+                            if constexpr (kCopies) raise_top(A.ymax + v.rb, p, y1 < 0 ? yb : y1);
+                            my_fv = y1 < 0 ? kNoRow : free_val(b, y1);
                             if (slack >= 2) st_agent(A.skip + b, (uint32_t)min(slack - 1, 1 << 30));
                         }
                         active &= ~(1ull << s);
@@ -1093,12 +1159,32 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                              tagged(tag, (int32_t)my_fv));
             }
             if (threadIdx.x < kWave) {
-                // lane j < G polls the word of group j until every workgroup arrived
+                // lane j < G polls the word of group j until every workgroup
+                // arrived, or the bounded wait runs out
                 unsigned long long v;
-                for (;;) {
+                int64_t t_wait = 0;
+                bool late = false;
+                for (int spins = 0;; ++spins) {
                     v = lane < G ? ld_agent(words + lane * kWordStride) : 0ull;
                     if (wave_sum((uint32_t)(v >> kShiftArrive)) == nwg) break;
+                    if ((spins & 255) == 0) {
+                        const int64_t now = (int64_t)wall_clock64();
+                        if (spins == 0) t_wait = now;
+                        else if (now - t_wait > (A.barrier_ticks > 0 ? A.barrier_ticks
+                                                                      : kBarrierTicks)) {
+                            late = true;
+                            break;
+                        }
+                    }
                     __builtin_amdgcn_s_sleep(1);
+                }
+                if (late) {
+                    if (lane == 0) {
+                        __hip_atomic_fetch_or(&ctl->err, 32, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        s_abort = 1;
+                    }
+                    v = 0ull;  // no lists are read after an abort
                 }
                 const uint32_t nl = (uint32_t)(v & kField);
                 const uint32_t nf = (uint32_t)((v >> kShiftFree) & kField);
@@ -1122,11 +1208,13 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 }
             }
             __syncthreads();
+            if (s_abort) break;
             l_new = s_ltot;
             lcount += l_new;
             if (l_new) phase_rounds += 1;  // some proposal was made this round
             if (s_over) break;
         }
+        if (s_abort) break;
         // The marks of the phase are cleared; the columns taken in its last
         // round (not marked) get their t raised later, see pend.
         pend = l_new;
@@ -1180,14 +1268,16 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     if (threadIdx.x == 0) flush_scan();
     if (leader) {
         // after a phase every workgroup has read tag_last (before arriving)
-        if (p > 0) ctl->tag_last = tag0 + (uint32_t)p;
+        // (an aborted phase used tag0 + p + 1 as well)
+        if (p > 0 || s_abort) ctl->tag_last = tag0 + (uint32_t)p + (s_abort ? 1u : 0u);
         ctl->phases = p;
         ctl->sum_free = st_sum_free;
         ctl->rounds = st_rounds;
         ctl->max_rounds = st_max_rounds;
         ctl->free_after = n_i;
     }
-    if (wg == 0) {
+    // (after an abort the state is not used: the host reports the error)
+    if (wg == 0 && !s_abort) {
         apply_pending();
         __syncthreads();
         for (int i = threadIdx.x; i < na; i += blockDim.x) A.t[i] = t_lds[i];
@@ -1314,10 +1404,20 @@ complete_kernel(int n, int n_a, int32_t *mate_a, int32_t *mate_b, int32_t *scrat
                 int32_t complete, const Ctl *ctl)
 {
     __shared__ int cnt[kCompleteThreads];
-    const int32_t stopped = ctl->status;  // read first: its latency hides behind the lists
+    // read first: their latency hides behind the lists
+    const int32_t stopped = ctl->status, err = ctl->err;
+    if (err & kErrLoop) {
+        // the loop failed: the outputs are marked invalid (every vertex
+        // free); the host reports the error
+        for (int i = threadIdx.x; i < n; i += kCompleteThreads) mate_b[i] = -1;
+        for (int i = threadIdx.x; i < n_a; i += kCompleteThreads) mate_a[i] = -1;
+        return;
+    }
     const int nb = list_flags(mate_b, n, scratch, cnt);
     const int na = list_flags(mate_a, n_a, scratch + n, cnt);
-    if (!complete || stopped) return;
+    // a loop stopped early (max_phases, the watchdog, or too few workgroups
+    // resident, when nothing ran) keeps its state for a resume
+    if (!complete || stopped || err) return;
     const int m = min(nb, na);
     for (int i = threadIdx.x; i < m; i += kCompleteThreads) {
         const int b = scratch[i], a = scratch[n + i];
@@ -1460,7 +1560,8 @@ __global__ void __launch_bounds__(kCompleteThreads) team_finish_kernel(TeamArgs 
     int32_t *sc = T.scratch + 2 * off;
     const int nb = list_flags(mb, n, sc, cnt);
     const int na = list_flags(ma, n, sc + n, cnt);
-    if (T.complete) {
+    // no completion after the watchdog stopped the loop or the loop failed
+    if (T.complete && a.ctl->status != 2 && !(a.ctl->err & kErrLoop)) {
         const int m = min(nb, na);
         for (int i = tid; i < m; i += kCompleteThreads) {
             mb[sc[i]] = sc[n + i];
@@ -1510,9 +1611,14 @@ __global__ void __launch_bounds__(kCompleteThreads) team_finish_kernel(TeamArgs 
         st.kmax = m > 0.0f ? (int32_t)floor(1.0 / T.eps) : 0;
         st.cost_scale = (double)m;
         st.cost = m > 0.0f ? red_c[0] / (double)m : 0.0;
-        if (c.err & 12) {
+        if (c.status == 2) {
+            st.status = -4;  // PROT_E_PHASE_BOUND
+            __hip_atomic_fetch_or(T.err, 256, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (c.err & kErrLoop) {
             st.status = -6;
-            __hip_atomic_fetch_or(T.err, c.err & 12, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(T.err, c.err & kErrLoop, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1544,10 +1650,21 @@ hipError_t launch_clear_err(Ctl *ctl, hipStream_t s)
 
 hipError_t launch_check_state(int64_t n, int64_t na, const int32_t *mate_a,
                               const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
-                              Ctl *ctl, hipStream_t s)
+                              int32_t ybound, Ctl *ctl, hipStream_t s)
 {
     hipLaunchKernelGGL(check_state_kernel, dim3(blocks_for(na, 256)), dim3(256), 0, s, n, na,
-                       mate_a, mate_b, y_a, y_b, ctl);
+                       mate_a, mate_b, y_a, y_b, ybound, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_feasible(const int16_t *k, int64_t ldk, int64_t n, int64_t na,
+                                 const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
+                                 Ctl *ctl, hipStream_t s)
+{
+    const unsigned gx = blocks_for((na + 7) / 8, 256);
+    const unsigned gy = (unsigned)(n < 4096 ? (n < 1 ? 1 : n) : 4096);
+    hipLaunchKernelGGL(check_feasible_kernel, dim3(gx, gy), dim3(256), 0, s, k, ldk, n, na,
+                       mate_b, y_a, y_b, ctl);
     return hipGetLastError();
 }
 

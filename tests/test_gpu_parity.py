@@ -355,6 +355,27 @@ def test_points_n10000_eps001(ctx, storage):
     assert np.array_equal(ctx.trace(), orc["trace"])
 
 
+@pytest.fixture(scope="module")
+def c5_oracle():
+    """The oracle on the 3-D instance at full size (n = 50,000, eps =
+    0.005), every examined cost computed from the points (no matrix)."""
+    X, Y = synth.uniform_points(50000, 3, seed=0)
+    return X, Y, oracle.solve_points(X, Y, 0.005, trace=True)
+
+
+@pytest.mark.parametrize("storage", ["matrix", "on_the_fly"])
+def test_points_n50000_d3_bit_exact(ctx, c5_oracle, storage):
+    """n = 50,000 points in the unit cube, eps = 0.005, as the benchmark
+    runs it: the 5 GB int16 matrix resident in HBM, and costs recomputed in
+    the scan. Mates, duals, every statistic and the per-phase trace equal
+    the oracle's, element by element."""
+    X, Y, orc = c5_oracle
+    gpu = ctx.solve_points(dev(X), dev(Y), 0.005, storage=storage)
+    assert_same(gpu, orc, f"n=50000 {storage}")
+    assert gpu.stats["cost_scale"] == orc["m"]
+    assert np.array_equal(ctx.trace(), orc["trace"])
+
+
 def test_points_n50000_d3_full_size_on_the_fly(ctx):
     """The 3-D instance at full size (n = 50,000, eps = 0.005) as the default
     runs it (costs on the fly): the maximum and every matched pair's rounded
@@ -547,16 +568,150 @@ def test_loop_with_few_workgroups_admitted(gate_ctx, n, eps, origin):
         assert gpu.stats[s] == orc["stats"][s], s
 
 
-def test_loop_refuses_rows_beyond_the_admitted_workgroups(gate_ctx):
-    """3 workgroups x 16 waves x 64 lanes = 3,072 rows at most: more rows are
-    refused with an error, and the context still solves afterwards."""
-    import paper_2203_03732_amd as prot
+def test_loop_falls_back_to_a_cooperative_launch(gate_ctx):
+    """3 workgroups x 16 waves x 64 lanes = 3,072 rows at most: with more rows
+    the gated launch runs nothing (too few workgroups admitted) and the call
+    runs the loop again with a cooperative launch, bit-exact with the oracle.
+    Enqueued without statistics (no synchronisation, no retry) the failure
+    is reported by the status query, and the outputs are marked invalid."""
     X, Y = synth.uniform_points(4000, 2, seed=2)
+    gpu = gate_ctx.solve_points(dev(X), dev(Y), 0.05)
+    k, _ = oracle.round_points_f32(X, Y, 0.05)
+    orc = oracle.solve_rounded(k, oracle.threshold(0.05, 4000), trace=True)
+    assert_same(gpu, orc, "cooperative fallback")
+    import paper_2203_03732_amd as prot
+    kd = padded_k(k)
+    res = gate_ctx.solve_rounded(kd, oracle.threshold(0.05, 4000), 4000, stats=False)
     with pytest.raises(prot.ProtError) as e:
-        gate_ctx.solve_points(dev(X), dev(Y), 0.05)
+        gate_ctx.status()
     assert e.value.name == "hip"
+    assert (host(res.mate_b) == -1).all()
     X, Y = synth.uniform_points(500, 2, seed=3)
     gpu = gate_ctx.solve_points(dev(X), dev(Y), 0.05)
     k, _ = oracle.round_points_f32(X, Y, 0.05)
     orc = oracle.solve_rounded(k, oracle.threshold(0.05, 500))
     assert np.array_equal(host(gpu.mate_b), orc["mate_b"])
+
+
+# ------------------------------------------------ failing closed, watchdog
+@pytest.mark.parametrize("origin", ["diag", "zero"])
+def test_watchdog_stops_with_the_state_of_that_many_phases(ctx, origin):
+    """phase_bound = 3: the call stops after three phases with status
+    phase_bound (no completion) and the state equals the oracle's after
+    three phases; resuming it (default watchdog) finishes like one run."""
+    n, eps = 3000, 0.01
+    X, Y = synth.uniform_points(n, 2, seed=21)
+    k, _ = oracle.round_points_f32(X, Y, eps)
+    T = oracle.threshold(eps, n)
+    kd = padded_k(k)
+    part = ctx.solve_rounded(kd, T, n, origin=origin, phase_bound=3)
+    assert part.status == "phase_bound"
+    ref = oracle.solve_rounded(k, T, origin=origin, max_phases=3, complete=False)
+    assert_same(part, ref, "watchdog at 3 phases")
+    rest = ctx.solve_rounded(kd, T, n, origin=origin, state=dict(
+        mate_a=part.mate_a, mate_b=part.mate_b, y_a=part.y_a, y_b=part.y_b), check_warm=True)
+    full = oracle.solve_rounded(k, T, origin=origin)
+    for x in ("mate_a", "mate_b", "y_a", "y_b"):
+        assert np.array_equal(host(getattr(rest, x)), full[x]), x
+    assert part.stats["phases"] + rest.stats["phases"] == full["stats"]["phases"]
+    # the same stop through the asynchronous path and the status query
+    again = ctx.solve_rounded(kd, T, n, origin=origin, phase_bound=3, stats=False)
+    assert ctx.status() == "phase_bound"
+    for x in ("mate_a", "mate_b", "y_a", "y_b"):
+        assert torch.equal(getattr(again, x), getattr(part, x)), x
+
+
+def test_points_watchdog(ctx):
+    """The watchdog on a point-set solve (costs on the fly) stops at the
+    given phase count with the oracle's state."""
+    n, eps = 2000, 0.02
+    X, Y = synth.uniform_points(n, 3, seed=22)
+    gpu = ctx.solve_points(dev(X), dev(Y), eps, storage="on_the_fly", phase_bound=2)
+    assert gpu.status == "phase_bound" and gpu.stats["phases"] == 2
+    ref = oracle.solve_points(X, Y, eps, max_phases=2, complete=False)
+    assert_same(gpu, ref, "points watchdog")
+
+
+def test_warm_start_checks(ctx):
+    """Warm starts: (I2) checked on request (a state from the oracle passes;
+    one dual raised by one step fails it); a dual beyond Lemma 3.2's range
+    is refused; a free row whose dual would leave its 15-bit field stops the
+    loop with an error and the outputs marked invalid."""
+    import paper_2203_03732_amd as prot
+    n, eps = 800, 0.05
+    X, Y = synth.uniform_points(n, 2, seed=23)
+    k, _ = oracle.round_points_f32(X, Y, eps)
+    T = oracle.threshold(eps, n)
+    kd = padded_k(k)
+    ref = oracle.solve_rounded(k, T, max_phases=2, complete=False)
+    st = {x: dev(ref[x]) for x in ("mate_a", "mate_b", "y_a", "y_b")}
+    ok = ctx.solve_rounded(kd, T, n, state=st, check_warm=True)
+    full = oracle.solve_rounded(k, T)
+    assert np.array_equal(host(ok.mate_b), full["mate_b"])
+    bad = dict(st)
+    yb = ref["y_b"].copy()
+    b = int(np.nonzero(ref["mate_b"] >= 0)[0][0])
+    yb[b] += 1  # eq. (3) fails on b's matched edge
+    bad["y_b"] = dev(yb)
+    with pytest.raises(prot.ProtError) as e:
+        ctx.solve_rounded(kd, T, n, state=bad, check_warm=True)
+    assert e.value.name == "state"
+    yb = ref["y_b"].copy()
+    yb[b] = 40000  # beyond |y| <= K + 2 for any int16 matrix
+    bad["y_b"] = dev(yb)
+    with pytest.raises(prot.ProtError) as e:
+        ctx.solve_rounded(kd, T, n, state=bad)
+    assert e.value.name == "state"
+    # all-zero costs, one free row with y(b) = 32767: it finds no column
+    # (it would need k = 32766) and its dual cannot grow
+    m = 64
+    z = np.zeros((m, m), np.int16)
+    mate = np.arange(m, dtype=np.int32)
+    mate_a, mate_b = mate.copy(), mate.copy()
+    mate_a[5] = -1
+    mate_b[5] = -1
+    y_a = np.zeros(m, np.int32)
+    y_b = np.zeros(m, np.int32)
+    y_b[5] = 32767
+    over = dict(mate_a=dev(mate_a), mate_b=dev(mate_b), y_a=dev(y_a), y_b=dev(y_b))
+    with pytest.raises(prot.ProtError) as e:
+        ctx.solve_rounded(padded_k(z), 0, m, state=over)
+    assert e.value.name == "state" and "Lemma 3.2" in str(e.value)
+    # the context still solves afterwards
+    gpu = ctx.solve_rounded(kd, T, n)
+    assert_same(gpu, full, "after the failures")
+
+
+def test_barrier_timeout_fails_closed():
+    """A context whose round-barrier wait is cut to ~10 ns: workgroups give
+    up at the first barrier that is not already complete, every one of them
+    leaves the loop (each wait is bounded), the call reports the time-out
+    and marks the outputs invalid; a normal context then solves."""
+    import os
+    import paper_2203_03732_amd as prot
+    old = os.environ.get("PROT_LOOP_BARRIER_TICKS")
+    os.environ["PROT_LOOP_BARRIER_TICKS"] = "1"
+    try:
+        c = prot.Context(0)
+    finally:
+        if old is None:
+            del os.environ["PROT_LOOP_BARRIER_TICKS"]
+        else:
+            os.environ["PROT_LOOP_BARRIER_TICKS"] = old
+    n, eps = 6000, 0.01
+    X, Y = synth.uniform_points(n, 2, seed=24)
+    k, _ = oracle.round_points_f32(X, Y, eps)
+    kd = padded_k(k)
+    try:
+        res = c.solve_rounded(kd, oracle.threshold(eps, n), n, stats=False)
+        with pytest.raises(prot.ProtError) as e:
+            c.status()
+        assert e.value.name == "hip" and "barrier" in str(e.value)
+        assert (host(res.mate_b) == -1).all() and (host(res.mate_a) == -1).all()
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+    c2 = prot.Context(0)
+    gpu = c2.solve_rounded(kd, oracle.threshold(eps, n), n)
+    assert_same(gpu, oracle.solve_rounded(k, oracle.threshold(eps, n)), "after the time-out")
+    c2.close()

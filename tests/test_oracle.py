@@ -389,6 +389,64 @@ def test_points_max_and_pairs_equal_full_matrix():
     assert (oracle.points_pairs_f32(X, X, 0.1, 0.0, [0, 4], [3, 1]) == 0).all()
 
 
+# ------------------------------------------- point sets without the matrix
+
+def _grid_points(n, d, seed, top=7):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, top + 1, (n, d)).astype(np.float32)
+
+
+@pytest.mark.parametrize("n_b,n_a,d,origin", [(40, 40, 2, "diag"), (33, 47, 3, "zero"),
+                                              (60, 60, 3, "diag")])
+def test_points_without_matrix_exact_grid(n_b, n_a, d, origin):
+    """Integer points (every binary32 step exact) and eps = 1/8: eq. (1) is
+    floor(8 d2 / m) exactly, computed here with integers. The loop that
+    computes each cost from the points runs the same trajectory as the loop
+    on that exact matrix, and its final state meets (I1), (I2) on the exact
+    costs, Lemma 3.1 (sum_M k <= OPT_k + n_b, OPT_k by scipy's exact
+    assignment) and the stop test."""
+    X = _grid_points(n_b, d, seed=n_b + d)
+    Y = _grid_points(n_a, d, seed=n_a + 7 * d)
+    d2 = ((X.astype(np.int64)[:, None, :] - Y.astype(np.int64)[None, :, :]) ** 2).sum(-1)
+    m = int(d2.max())
+    k = (8 * d2) // m
+    eps = 0.125
+    T = oracle.threshold(eps, n_b)
+    r = oracle.solve_points(X, Y, eps, origin=origin, complete=False, trace=True)
+    assert r["m"] == m
+    ref = oracle.solve_rounded(k.astype(np.int16), T, origin=origin, complete=False, trace=True)
+    for x in ("mate_a", "mate_b", "y_a", "y_b", "trace"):
+        assert np.array_equal(r[x], ref[x]), x
+    assert r["stats"] == ref["stats"]
+    check_matching(r["mate_a"], r["mate_b"])
+    check_I1(r["mate_a"], r["y_a"], r["y_b"])
+    check_I2(k, r["mate_b"], r["y_a"], r["y_b"])
+    assert (r["mate_b"] < 0).sum() <= T
+    rows, cols = linear_sum_assignment(k)
+    opt = int(k[rows, cols].sum())
+    mb = r["mate_b"]
+    got = int(k[np.nonzero(mb >= 0)[0], mb[mb >= 0]].sum())
+    assert got <= opt + n_b
+
+
+@pytest.mark.parametrize("n_b,n_a,d,eps", [(300, 300, 2, 0.05), (257, 311, 3, 0.01),
+                                           (120, 150, 16, 0.05)])
+def test_points_without_matrix_equals_the_rounded_matrix(n_b, n_a, d, eps):
+    """On generic (non-grid) points the loop that computes each cost from
+    the points gives what the loop gives on round_points_f32's matrix (itself
+    pinned by exact rationals above): mates, duals, statistics and trace."""
+    rng = np.random.default_rng(n_b * d)
+    X = rng.random((n_b, d), dtype=np.float32)
+    Y = (rng.random((n_a, d), dtype=np.float32) * 1.5).astype(np.float32)
+    k, m = oracle.round_points_f32(X, Y, eps)
+    for origin in ("diag", "zero"):
+        a = oracle.solve_rounded(k, oracle.threshold(eps, n_b), origin=origin, trace=True)
+        b = oracle.solve_points(X, Y, eps, origin=origin, trace=True)
+        for x in ("mate_a", "mate_b", "y_a", "y_b", "trace"):
+            assert np.array_equal(a[x], b[x]), (origin, x)
+        assert a["stats"] == b["stats"] and b["m"] == m
+
+
 # ---------------------------------------------------------------- unbalanced
 
 def _rect_case(n_b, n_a, K, seed):

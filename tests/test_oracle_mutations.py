@@ -47,6 +47,12 @@ MUTATIONS = [
     ("supplies rounded up", "int64_t v = (int64_t)floor(th * nu[b]);",
      "int64_t v = (int64_t)ceil(th * nu[b]);", False),
     ("excess not returned", "plan[b * n_a + a] = v - take;", "plan[b * n_a + a] = v;", False),
+    ("point costs without the matrix not scaled by the maximum",
+     "double v = (double)sq_f32(c->X + r * c->d, c->Y + q * c->d, c->d) / (double)c->m;",
+     "double v = (double)sq_f32(c->X + r * c->d, c->Y + q * c->d, c->d);", False),
+    ("point costs without the matrix transposed",
+     "sq_f32(c->X + r * c->d, c->Y + q * c->d, c->d)",
+     "sq_f32(c->X + q * c->d, c->Y + r * c->d, c->d)", False),
 ]
 
 
