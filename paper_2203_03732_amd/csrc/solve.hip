@@ -1162,19 +1162,16 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 // lane j < G polls the word of group j until every workgroup
                 // arrived, or the bounded wait runs out
                 unsigned long long v;
-                int64_t t_wait = 0;
+                const int64_t t_wait = (int64_t)wall_clock64();
                 bool late = false;
                 for (int spins = 0;; ++spins) {
                     v = lane < G ? ld_agent(words + lane * kWordStride) : 0ull;
                     if (wave_sum((uint32_t)(v >> kShiftArrive)) == nwg) break;
-                    if ((spins & 255) == 0) {
-                        const int64_t now = (int64_t)wall_clock64();
-                        if (spins == 0) t_wait = now;
-                        else if (now - t_wait > (A.barrier_ticks > 0 ? A.barrier_ticks
-                                                                      : kBarrierTicks)) {
-                            late = true;
-                            break;
-                        }
+                    if ((spins & 63) == 1 &&
+                        (int64_t)wall_clock64() - t_wait >
+                            (A.barrier_ticks > 0 ? A.barrier_ticks : kBarrierTicks)) {
+                        late = true;
+                        break;
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
