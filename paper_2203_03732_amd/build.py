@@ -4,6 +4,7 @@ Usage: python -m paper_2203_03732_amd.build   (or call build()).
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -27,17 +28,22 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     outdir = os.path.join(HERE, "_build")
     os.makedirs(outdir, exist_ok=True)
-    for src in SOURCES:
+
+    def compile_one(src: str) -> str:
         obj = os.path.join(outdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+        return obj
+
+    # the sources compile independently; a few at a time
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "4"))))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        objs = list(pool.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

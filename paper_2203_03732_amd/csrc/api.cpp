@@ -472,6 +472,9 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
                            : "warm-start state is not a matching satisfying (I1) with "
                              "|y| <= K + 2");
     }
+    // a relaunch after the gate admitted too few workgroups: that attempt ran
+    // nothing, only its error bit goes
+    if (cooperative) HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream, 16));
     HIP_TRY(c, prot::launch_init(a, warm, mate_a, mate_b, y_a, c->stream));
     if (c->rtime) HIP_TRY(c, prot::launch_clear_times(c->rtime, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));

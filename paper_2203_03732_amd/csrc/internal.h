@@ -200,7 +200,7 @@ hipError_t launch_loss_bwd(const LossArgs &a, int64_t n_max, const float *grad_l
 // solve.hip
 hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
                        int32_t *mate_b, const int32_t *y_a, hipStream_t s);
-hipError_t launch_clear_err(Ctl *ctl, hipStream_t s);
+hipError_t launch_clear_err(Ctl *ctl, hipStream_t s, int32_t mask = -1);
 hipError_t launch_check_state(int64_t n, int64_t na, const int32_t *mate_a,
                               const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
                               int32_t ybound, Ctl *ctl, hipStream_t s);

@@ -1281,7 +1281,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     }
 }
 
-__global__ void clear_err_kernel(Ctl *ctl) { ctl->err = 0; }
+// Clears the bits `mask` of the error word (all of them, or only the
+// too-few-workgroups bit before a cooperative relaunch, keeping what the cost
+// build reported).
+__global__ void clear_err_kernel(Ctl *ctl, int32_t mask) { ctl->err &= ~mask; }
 
 __global__ void fill64_kernel(int64_t *p, int64_t n, int64_t v)
 {
@@ -1639,9 +1642,9 @@ hipError_t launch_init(const LoopArgs &a, int32_t warm, const int32_t *mate_a,
     return hipGetLastError();
 }
 
-hipError_t launch_clear_err(Ctl *ctl, hipStream_t s)
+hipError_t launch_clear_err(Ctl *ctl, hipStream_t s, int32_t mask)
 {
-    hipLaunchKernelGGL(clear_err_kernel, dim3(1), dim3(1), 0, s, ctl);
+    hipLaunchKernelGGL(clear_err_kernel, dim3(1), dim3(1), 0, s, ctl, mask);
     return hipGetLastError();
 }
 
