@@ -445,7 +445,26 @@ int prot_ot_loss_bwd(prot_ctx *ctx, int32_t batch, int64_t n, int32_t d, const f
                      const float *Y, const int32_t *mate_b, const float *grad_loss, float *dX,
                      float *dY);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): prot_ot_loss_fwd
+ * without a context. Same arguments, layout and result (bit for bit); the
+ * work is enqueued on hip_stream (a hipStream_t, NULL = the null stream) of
+ * the device current on the calling thread. Its partial sums live in a fixed
+ * device array of the library, 65,536 doubles (512 KiB) per device, held
+ * until the process ends (its address is looked up on the first call on a
+ * device); nothing is allocated or freed, and no partial sum needs clearing
+ * (every call writes all it reads). Every call on one device shares that
+ * array: calls that overlap in time on one GPU (other streams, other
+ * threads) race. Errors: PROT_E_ARG (bad pointer or size),
+ * PROT_E_UNSUPPORTED when batch x ceil(n d / 8192) (at most 64 per
+ * instance) exceeds 65,536 partial sums, PROT_E_HIP; the message is
+ * prot_last_error(NULL) on the calling thread. Enqueues only. */
+int prot_ot_loss_fwd_static(int32_t batch, int64_t n, int32_t d, const float *X, const float *Y,
+                            const int32_t *mate_b, float *loss, void *hip_stream);
+
 const char *prot_status_string(int status);
+/* The message of ctx's last failed call; with ctx = NULL, that of the last
+ * failed context-free call on this thread ("null context" if none). */
 const char *prot_last_error(prot_ctx *ctx);
 
 #ifdef __cplusplus

@@ -112,7 +112,7 @@ EXPORTS = [
     "prot_batch_create_config", "prot_batch_autotune",
     "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
     "prot_batch_loss_fwd", "prot_batch_loss_bwd", "prot_ctx_status", "prot_batch_status",
-    "prot_ot_loss_fwd", "prot_ot_loss_bwd",
+    "prot_ot_loss_fwd", "prot_ot_loss_bwd", "prot_ot_loss_fwd_static",
     "prot_status_string", "prot_last_error",
 ]
 
@@ -180,6 +180,7 @@ def load():
         "prot_batch_status": (ctypes.c_int, [p]),
         "prot_ot_loss_fwd": (ctypes.c_int, [p, i32, i64, i32, p, p, p, p]),
         "prot_ot_loss_bwd": (ctypes.c_int, [p, i32, i64, i32, p, p, p, p, p, p]),
+        "prot_ot_loss_fwd_static": (ctypes.c_int, [i32, i64, i32, p, p, p, p, p]),
         "prot_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "prot_last_error": (ctypes.c_char_p, [p]),
     }
@@ -692,6 +693,32 @@ class Batch:
 
 
 _default: dict[int, Context] = {}
+
+
+def ot_loss_static(X, Y, mate_b, loss=None):
+    """prot_ot_loss_fwd_static: the loss of Context.ot_loss without a context
+    and without any device allocation by the library (its partial sums live
+    in a fixed device array; calls that overlap on one GPU race). X, Y
+    (batch, n, d) float32, mate_b (batch, n) int32, loss (batch,) float32
+    (allocated here by torch when not given); the current torch stream and
+    device."""
+    torch = _torch()
+    if X.dim() != 3 or Y.shape != X.shape or mate_b.shape != X.shape[:2] or \
+            not X.is_contiguous() or not Y.is_contiguous() or not mate_b.is_contiguous():
+        raise ValueError("X, Y must be contiguous (batch, n, d) and mate_b (batch, n)")
+    batch, n, d = X.shape
+    if loss is None:
+        loss = torch.empty(batch, dtype=torch.float32, device=X.device)
+    lib = load()
+    with torch.cuda.device(X.device):
+        s = torch.cuda.current_stream(X.device).cuda_stream
+        rc = lib.prot_ot_loss_fwd_static(
+            batch, n, d, _dev_ptr(X, torch.float32, "X", 3), _dev_ptr(Y, torch.float32, "Y", 3),
+            _dev_ptr(mate_b, torch.int32, "mate_b", 2), _dev_ptr(loss, torch.float32, "loss", 1),
+            ctypes.c_void_p(s))
+    if rc < 0:
+        raise ProtError(rc, lib.prot_last_error(None).decode())
+    return loss
 
 
 def context(device: int | None = None) -> Context:

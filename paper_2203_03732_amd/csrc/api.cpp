@@ -850,7 +850,14 @@ const char *prot_status_string(int s)
     }
 }
 
-const char *prot_last_error(prot_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+// Message of the last failed call that takes no context, on this thread.
+static thread_local std::string g_free_err;
+
+const char *prot_last_error(prot_ctx *ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_free_err.empty() ? "null context" : g_free_err.c_str();
+}
 
 int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
 {
@@ -1726,6 +1733,35 @@ int prot_ot_loss_fwd(prot_ctx *c, int32_t batch, int64_t n, int32_t d, const flo
     }
     prot::LossArgs a{batch, d, nullptr, nullptr, X, Y, nullptr, mate_b, n};
     HIP_TRY(c, prot::launch_loss_fwd(a, n, c->loss_part, loss, c->stream));
+    return PROT_OK;
+}
+
+int prot_ot_loss_fwd_static(int32_t batch, int64_t n, int32_t d, const float *X, const float *Y,
+                            const int32_t *mate_b, float *loss, void *hip_stream)
+{
+    auto bad = [](int code, const std::string &msg) {
+        g_free_err = msg;
+        return code;
+    };
+    if (batch < 0 || n < 0 || d < 1 || (batch > 0 && n > 0 && (!X || !Y || !mate_b || !loss)))
+        return bad(PROT_E_ARG, "prot_ot_loss_fwd_static: bad pointer or size");
+    if (batch == 0) return PROT_OK;
+    const int64_t need = (int64_t)prot::loss_parts(n, d) * batch;
+    if (need > prot::kStaticLossParts)
+        return bad(PROT_E_UNSUPPORTED,
+                   "prot_ot_loss_fwd_static: " + std::to_string(batch) + " instances need " +
+                       std::to_string(need) + " partial sums; the fixed array holds " +
+                       std::to_string(prot::kStaticLossParts));
+    double *partial = nullptr;
+    hipError_t e = prot::static_loss_partials(&partial);
+    if (e != hipSuccess)
+        return bad(PROT_E_HIP, std::string("prot_ot_loss_fwd_static: address of the fixed "
+                                           "array: ") + hipGetErrorString(e));
+    prot::LossArgs a{batch, d, nullptr, nullptr, X, Y, nullptr, mate_b, n};
+    e = prot::launch_loss_fwd(a, n, partial, loss, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return bad(PROT_E_HIP, std::string("prot_ot_loss_fwd_static: launch: ") +
+                                   hipGetErrorString(e));
     return PROT_OK;
 }
 

@@ -194,6 +194,10 @@ hipError_t launch_batch_solve(const BatchArgs &a, int32_t n_max, int grid, hipSt
 int loss_parts(int64_t n_max, int32_t d);
 hipError_t launch_loss_fwd(const LossArgs &a, int64_t n_max, double *partial, float *loss,
                            hipStream_t s);
+// Partial sums (instances x blocks) that prot_ot_loss_fwd_static can hold in
+// the library's fixed array (512 KiB per device).
+constexpr int64_t kStaticLossParts = 65536;
+hipError_t static_loss_partials(double **out);
 hipError_t launch_loss_bwd(const LossArgs &a, int64_t n_max, const float *grad_loss, float *dX,
                            float *dY, hipStream_t s);
 

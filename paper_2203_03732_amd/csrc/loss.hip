@@ -9,8 +9,14 @@
 //   dL/dy_a = (2 g_i / n_i) (y_a - x_mate^-1(a)),
 // and 0 for vertices the plan leaves unmatched.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
+
+// Partial sums of prot_ot_loss_fwd_static: a fixed array of the library, one
+// copy per device, so that the call allocates nothing. In host code its name
+// is only a handle: kernels get the device address from static_loss_partials.
+static __device__ __align__(256) double scratch[prot::kStaticLossParts];
 
 namespace prot {
 namespace {
@@ -162,6 +168,28 @@ hipError_t launch_loss_fwd(const LossArgs &a, int64_t n_max, double *partial, fl
                            0, s, a, (const double *)partial, parts, loss);
     }
     return hipGetLastError();
+}
+
+// Device address of this device's copy of `scratch` (the device current on
+// the calling thread), looked up once per device.
+hipError_t static_loss_partials(double **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<double *>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_loss_bwd(const LossArgs &a, int64_t n_max, const float *grad_loss, float *dX,
