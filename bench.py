@@ -50,19 +50,43 @@ def measured_traffic(n, d, kernel):
     return round(k["fetch_bytes"] + k["write_bytes"], 1)
 
 
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0)), os.cpu_count()
+
+
 def cpu_baseline(X, Y, eps, reps):
+    """The single-threaded C oracle on the same instance, pinned to one host
+    core (the last one this process may use) while it runs."""
     import oracle
     n = X.shape[0]
-    times = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        k, _ = oracle.round_points_f32(X, Y, eps)
-        oracle.solve_rounded(k, oracle.threshold(eps, n))
-        times.append(time.perf_counter() - t0)
+    model, allowed, total = host_cpu()
+    before = os.sched_getaffinity(0)
+    core = max(before)
+    os.sched_setaffinity(0, {core})
+    try:
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            k, _ = oracle.round_points_f32(X, Y, eps)
+            oracle.solve_rounded(k, oracle.threshold(eps, n))
+            times.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, before)
     ms = 1e3 * sum(times) / len(times)
     return {"value": round(ms, 3), "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": f"{reps} whole solve(s) of the same instance (binary32 cost build "
-                      f"+ phase loop + completion), single-threaded C"}
+                      f"+ phase loop + completion), single-threaded C pinned to core {core}",
+            "host_cpu": model, "host_cores_allowed": allowed, "host_cores_total": total}
 
 
 def bench_batched(prot, synth, torch, reps=10):
@@ -104,6 +128,13 @@ def bench_batched(prot, synth, torch, reps=10):
         ctx.solve_points(x, y, 0.05)
     torch.cuda.synchronize()
     loop_ms = 1e3 * (time.perf_counter() - t0)
+    # the same loop enqueuing only (no statistics, no synchronisation per
+    # solve), one synchronisation at the end
+    t0 = time.perf_counter()
+    for x, y in zip(Xl, Yl):
+        ctx.solve_points(x, y, 0.05, stats=False)
+    torch.cuda.synchronize()
+    enq_ms = 1e3 * (time.perf_counter() - t0)
     st = plan.stats()
     plan.close()
     ctx.close()
@@ -113,6 +144,8 @@ def bench_batched(prot, synth, torch, reps=10):
             "plain_loop_ms": round(loop_ms, 3),
             "plain_loop_solves_per_s": round(512 / (loop_ms * 1e-3), 1),
             "ratio_vs_plain_loop": round(loop_ms / replay_ms, 2),
+            "plain_loop_enqueue_only_ms": round(enq_ms, 3),
+            "ratio_vs_plain_loop_enqueue_only": round(enq_ms / replay_ms, 2),
             "autotuned_config": cfg, "configs_timed": tried,
             "default_config_replay_ms": round(default_ms, 4),
             "mean_phases": round(float(np.mean([s["phases"] for s in st])), 2)}
@@ -138,6 +171,62 @@ def bench_large(prot, synth, torch, reps=5):
             "ms_per_solve": round(ms, 4), "ms_build": round(st["ms_build"], 4),
             "ms_loop": round(st["ms_loop_kernel"], 4), "phases": st["phases"],
             "scanned": st["scanned"], "cost": st["cost"]}
+
+
+def bench_large_matrix(prot, synth, torch, reps=5):
+    """The same 50,000-point instance with its 5.06 GB int16 rounded-cost
+    matrix built and resident in HBM (far beyond the 256 MB Infinity Cache):
+    whole solves, and the phase loop's useful scan rate (2 B per entry
+    examined over the loop kernel's device time) against 8 TB/s."""
+    X, Y = synth.uniform_points(50000, 3, seed=0)
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    ctx = prot.Context(0)
+    ctx.reserve(50000, with_matrix=True)
+    ctx.solve_points(Xd, Yd, 0.005, storage="matrix")
+    torch.cuda.synchronize()
+    loop_ms, build_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ctx.solve_points(Xd, Yd, 0.005, storage="matrix")
+        loop_ms.append(r.stats["ms_loop_kernel"])
+        build_ms.append(r.stats["ms_build"])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    st = r.stats
+    ctx.close()
+    lm, bm = sum(loop_ms) / reps, sum(build_ms) / reps
+    scan_gbs = 2.0 * st["scanned"] / (lm * 1e-3) / 1e9
+    write_gbs = 2.0 * 50000 * prot.pitch(50000) / (bm * 1e-3) / 1e9
+    return {"workload": "n=50000 points U[0,1]^3 squared-Euclidean eps=0.005 seed=0, "
+                        "int16 matrix (5.06 GB) resident in HBM",
+            "ms_per_solve": round(ms, 4), "ms_build": round(bm, 4), "ms_loop": round(lm, 4),
+            "phases": st["phases"], "rounds": st["rounds"], "scanned": st["scanned"],
+            "loop_scan_GBps": round(scan_gbs, 1), "loop_frac_of_hbm_peak": round(scan_gbs / HBM_PEAK_GBS, 4),
+            "build_write_GBps": round(write_gbs, 1), "cost": st["cost"]}
+
+
+def bench_uniform_costs(prot, synth, torch, reps=20):
+    """1000 x 1000 costs i.i.d. uniform in [0, 1), eps = 0.1: whole solves
+    of the cost-matrix entry point (rounding by eq. (1), phase loop,
+    completion), C resident in HBM."""
+    C = synth.uniform_costs(1000, seed=0)
+    Cd = torch.from_numpy(C).cuda()
+    ctx = prot.Context(0)
+    ctx.solve_cost(Cd, 0.1)
+    torch.cuda.synchronize()
+    loop_ms = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = ctx.solve_cost(Cd, 0.1)
+        loop_ms.append(r.stats["ms_loop_kernel"])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    st = r.stats
+    ctx.close()
+    return {"workload": "assignment 1000 x 1000 costs U[0,1) eps=0.1 seed=0",
+            "ms_per_solve": round(ms, 4), "ms_round": round(st["ms_build"], 4),
+            "ms_loop": round(sum(loop_ms) / reps, 4), "phases": st["phases"],
+            "rounds": st["rounds"], "scanned": st["scanned"], "cost": st["cost"]}
 
 
 def bench_unbalanced(prot, synth, torch, reps=5):
@@ -238,11 +327,26 @@ def bench_ot_loss(prot, synth, torch, reps=5):
         prot.ot_match_loss(Xd, Yd, 0.01).sum().backward()
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / reps
+    # the batched solve alone (the plan the loss reuses), and what it did
+    import numpy as np
+    plan = prot.context(0).cached_batch([2048] * 64, 64, 0.01)
+    Xp, Yp = Xd.detach().view(64 * 2048, 64), Yd.detach().view(64 * 2048, 64)
+    plan.run(Xp, Yp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run(Xp, Yp, check=False)
+    torch.cuda.synchronize()
+    solve_ms = 1e3 * (time.perf_counter() - t0) / reps
+    st = plan.stats()
     return {"workload": "64 x n=2048, R^64, X~N(0,I), Y~N(0.5,I), eps=0.01",
-            "fwd_bwd_ms": round(ms, 3)}
+            "fwd_bwd_ms": round(ms, 3), "batched_solve_ms": round(solve_ms, 3),
+            "mean_phases": round(float(np.mean([x["phases"] for x in st])), 2),
+            "mean_rounds": round(float(np.mean([x["rounds"] for x in st])), 2),
+            "scanned_total": int(sum(x["scanned"] for x in st))}
 
 
-def phase_report(prot, synth, torch, n, d, eps, seed):
+def phase_report(prot, synth, torch, n, d, eps, seed, storage="auto", rounds_of=None):
     """Per-phase evidence for the phase loop: |B'|, proposal rounds, entries
     examined, |M'|, the phase's device time from the per-round timestamps
     (PROT_DEBUG_ROUND_TIMES; the timestamps add a little time of their own)
@@ -252,8 +356,10 @@ def phase_report(prot, synth, torch, n, d, eps, seed):
     X, Y = synth.uniform_points(n, d, seed=seed)
     Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
     ctx = prot.Context(0)
+    if storage == "matrix":
+        ctx.reserve(n, with_matrix=True)
     for _ in range(3):
-        res = ctx.solve_points(Xd, Yd, eps)
+        res = ctx.solve_points(Xd, Yd, eps, storage=storage)
     torch.cuda.synchronize()
     tr = ctx.trace()
     rt = ctx.round_times()
@@ -269,14 +375,24 @@ def phase_report(prot, synth, torch, n, d, eps, seed):
         if p in ends and p - 1 in ends:
             dur[p] = (ends[p] - ends[p - 1]) / 100.0
     dur[0] = max(loop_us - dur[1:].sum(), 0.0)  # phase 0 also holds the launch
-    print(f"# per-phase report: n={n} d={d} eps={eps} seed={seed}; loop {loop_us:.1f} us "
-          f"with round timestamps on", flush=True)
+    print(f"# per-phase report: n={n} d={d} eps={eps} seed={seed} storage={storage}; "
+          f"loop {loop_us:.1f} us with round timestamps on", flush=True)
     print(f"{'phase':>5s} {'|B_i|':>7s} {'rounds':>6s} {'entries':>11s} {'|M_i|':>6s} "
           f"{'us':>8s} {'GB/s':>8s}")
     for p in range(phases):
         gbs = 2.0 * tr[p, 2] / (dur[p] * 1e-6) / 1e9 if dur[p] > 0 else 0.0
         print(f"{p:5d} {tr[p, 0]:7d} {tr[p, 1]:6d} {tr[p, 2]:11d} {tr[p, 3]:6d} {dur[p]:8.1f} "
               f"{gbs:8.1f}")
+    if rounds_of is not None:
+        # round r's exit minus the previous round's exit (the first round of
+        # the phase: minus the previous phase's last exit)
+        prev = None
+        print(f"# rounds of phase {rounds_of}: exit-to-exit us, latest arrival to exit us")
+        for i, (arr, ex, ph) in enumerate(rt):
+            if int(ph) == rounds_of and ex > 0 and prev is not None:
+                print(f"round {i:4d}  {(ex - prev) / 100.0:8.2f}  {(ex - arr) / 100.0:8.2f}")
+            if ex > 0:
+                prev = int(ex)
     tot = 2.0 * tr[:, 2].sum()
     print(f"total: {tr[:, 2].sum()} entries, {tot / 1e6:.1f} MB useful in {loop_us:.1f} us = "
           f"{tot / (loop_us * 1e-6) / 1e9:.1f} GB/s (bytes-weighted over the phases)", flush=True)
@@ -297,6 +413,15 @@ def main():
                     help="skip the batched and OT-loss measurements")
     ap.add_argument("--phase-report", action="store_true",
                     help="print a per-phase table of the phase loop instead of the bench line")
+    ap.add_argument("--storage", default="auto", choices=["auto", "matrix", "on_the_fly"],
+                    help="rounded costs of --phase-report: as the library chooses, the stored "
+                         "matrix, or recomputed in the scan")
+    ap.add_argument("--only", default=None,
+                    choices=["batched", "ot_loss", "uniform_costs", "large", "large_matrix",
+                             "unbalanced", "transport", "cost_variants"],
+                    help="run only this extra measurement and print its JSON (for profiling)")
+    ap.add_argument("--rounds-of", type=int, default=None,
+                    help="with --phase-report: also list the rounds of this phase")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the bench, run 5 plain device copies of this many MiB "
                          "(reference kernel for scaling memory counters)")
@@ -316,7 +441,14 @@ def main():
     torch.cuda.set_device(0)
     n, d, eps = args.n, args.d, args.eps
     if args.phase_report:
-        phase_report(prot, synth, torch, n, d, eps, args.seed)
+        phase_report(prot, synth, torch, n, d, eps, args.seed, args.storage, args.rounds_of)
+        return
+    legs = {"batched": bench_batched, "ot_loss": bench_ot_loss,
+            "uniform_costs": bench_uniform_costs, "large": bench_large,
+            "large_matrix": bench_large_matrix, "unbalanced": bench_unbalanced,
+            "transport": bench_transport, "cost_variants": bench_cost_variants}
+    if args.only:
+        print(json.dumps({args.only: legs[args.only](prot, synth, torch)}), flush=True)
         return
     X, Y = synth.uniform_points(n, d, seed=args.seed)
     Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
@@ -381,12 +513,8 @@ def main():
     }
     ctx.close()
     if not args.no_extras:
-        out["batched"] = bench_batched(prot, synth, torch)
-        out["ot_loss"] = bench_ot_loss(prot, synth, torch)
-        out["large"] = bench_large(prot, synth, torch)
-        out["unbalanced"] = bench_unbalanced(prot, synth, torch)
-        out["transport"] = bench_transport(prot, synth, torch)
-        out["cost_variants"] = bench_cost_variants(prot, synth, torch)
+        for name, leg in legs.items():
+            out[name] = leg(prot, synth, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, Y, eps, args.cpu_reps)
     print(json.dumps(out), flush=True)

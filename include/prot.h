@@ -212,7 +212,8 @@ int prot_solve_cost(prot_ctx *ctx, const float *C, int64_t n, int64_t ldc,
 
 /* Point-set input: prot_build_costs into workspace, then as above;
  * stats->cost is sum_b d2_64(b, mate_b[b]) / m in binary64 (normalised),
- * stats->cost_scale = m. */
+ * stats->cost_scale = m. stats = NULL enqueues only (no synchronisation,
+ * no cooperative retry); prot_ctx_status then reports how the solve ended. */
 int prot_solve_points(prot_ctx *ctx, const float *X, const float *Y,
                       int64_t n, int32_t d, double eps, const prot_opts *opts,
                       int32_t *mate_a, int32_t *mate_b, int32_t *y_a,

@@ -460,12 +460,13 @@ class Context:
 
     def solve_points(self, X, Y, eps: float, *, eps_mode="algorithmic", origin="diag",
                      complete=True, max_phases=0, storage="auto", k_type="auto",
-                     phase_bound=0) -> Result:
+                     phase_bound=0, stats=True) -> Result:
         """storage: 'auto', 'matrix' (build and scan the n x n matrix) or
         'on_the_fly' (d = 2, 3: no matrix, each examined cost recomputed from
         the points); k_type: the stored matrix's element type ('auto' = 'int16',
         or 'uint8' for floor(1/eps) <= 253: half the memory). All give the same
-        result."""
+        result. stats=False enqueues only (no statistics, no synchronisation;
+        Context.status() reports how the solve ended)."""
         torch = _torch()
         n, d = X.shape
         n_a = Y.shape[0]
@@ -479,8 +480,9 @@ class Context:
             self._h, _dev_ptr(X, torch.float32, "X", 2), n, _dev_ptr(Y, torch.float32, "Y", 2),
             n_a, d, float(eps), ctypes.byref(o), _dev_ptr(mate_a, torch.int32, "mate_a"),
             _dev_ptr(mate_b, torch.int32, "mate_b"), _dev_ptr(y_a, torch.int32, "y_a"),
-            _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st)), allow_bound=True)
-        return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict())
+            _dev_ptr(y_b, torch.int32, "y_b"), ctypes.byref(st) if stats else None),
+            allow_bound=True)
+        return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict() if stats else {})
 
     def ot_solve(self, C, nu, mu, eps: float, *, eps_mode="algorithmic", origin="diag",
                  max_phases=0, plan=None) -> OTResult:

@@ -1171,6 +1171,9 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
         return fail(c, PROT_E_ARG, "prot_solve_points: bad pointer or size (|B| <= |A| required)");
     if (!eps_valid(eps_internal(eps, o)))
         return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    // stats = NULL: enqueue only (no synchronisation, no cooperative retry);
+    // prot_ctx_status reports how the solve ended
+    const bool enqueue_only = st == nullptr;
     prot_stats local;
     if (!st) st = &local;
     std::memset(st, 0, sizeof(*st));
@@ -1228,6 +1231,7 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
         return PROT_OK;
     };
     if ((rc = enqueue(false))) return rc;
+    if (enqueue_only) return PROT_OK;
     const int kind = on_the_fly ? 2 : points_cost_kind(c);
     rc = collect(c, st, T, ei, kind, true, true);
     if (rc == kRetryCooperative) {

@@ -96,6 +96,29 @@ def test_points_reject_non_finite_then_recover(ctx, n, d, storage, where):
         check_matching(host(gpu.mate_a), host(gpu.mate_b))
 
 
+def test_points_enqueue_only(ctx):
+    """Without statistics a point solve only enqueues: the status query
+    reports how it ended, the outputs equal the oracle's, and a non-finite
+    coordinate is reported by the status query."""
+    import paper_2203_03732_amd as prot
+    X, Y = synth.uniform_points(3000, 2, seed=40)
+    res = ctx.solve_points(dev(X), dev(Y), 0.01, stats=False)
+    assert res.stats == {}
+    assert ctx.status() == "ok"
+    k, _ = oracle.round_points_f32(X, Y, 0.01)
+    orc = oracle.solve_rounded(k, oracle.threshold(0.01, 3000))
+    for x in ("mate_a", "mate_b", "y_a", "y_b"):
+        assert np.array_equal(host(getattr(res, x)), orc[x]), x
+    Xb = X.copy()
+    Xb[7, 1] = float("nan")
+    ctx.solve_points(dev(Xb), dev(Y), 0.01, stats=False)
+    with pytest.raises(prot.ProtError) as e:
+        ctx.status()
+    assert e.value.name == "range"
+    res = ctx.solve_points(dev(X), dev(Y), 0.01)
+    assert np.array_equal(host(res.mate_b), orc["mate_b"])
+
+
 def test_round_costs_rejects_nan_and_range(ctx):
     import paper_2203_03732_amd as prot
     for bad in (float("nan"), -0.5, 1.5):
@@ -112,7 +135,8 @@ def test_round_costs_rejects_nan_and_range(ctx):
 @pytest.mark.parametrize("path", ["direct", "matrix_cores"])
 @pytest.mark.parametrize("n,d,eps", [(1, 2, 0.1), (50, 2, 0.01), (1000, 2, 0.01),
                                      (513, 3, 0.005), (200, 5, 0.05), (300, 16, 0.05),
-                                     (150, 17, 0.02), (130, 64, 0.01), (65, 4, 0.3)])
+                                     (150, 17, 0.02), (130, 64, 0.01), (65, 4, 0.3),
+                                     (700, 40, 0.01), (260, 96, 0.02)])
 def test_build_costs_bit_exact(ctx, n, d, eps, path):
     X, Y = synth.uniform_points(n, d, seed=7 + d)
     ctx.set_cost_path(path)
