@@ -48,7 +48,7 @@ enum {
 };
 
 enum { PROT_EPS_ALGORITHMIC = 0, PROT_EPS_STRICT = 1 };
-enum { PROT_COST_DIRECT = 0, PROT_COST_MATRIX_CORES = 1 };
+enum { PROT_COST_DIRECT = 0, PROT_COST_MATRIX_CORES = 1, PROT_COST_AUTO = 2 };
 enum { PROT_COSTS_AUTO = 0, PROT_COSTS_MATRIX = 1, PROT_COSTS_ON_THE_FLY = 2 };
 enum { PROT_ORIGIN_DIAG = 0, PROT_ORIGIN_ZERO = 1 };
 enum { PROT_KTYPE_AUTO = 0, PROT_KTYPE_INT16 = 1, PROT_KTYPE_UINT8 = 2 };
@@ -127,15 +127,19 @@ int prot_ctx_destroy(prot_ctx *ctx);
 int prot_set_stream(prot_ctx *ctx, void *hip_stream);
 
 /* How later point-set cost builds on ctx (and batches created afterwards)
- * compute the squared distances; both give the same result, bit for bit.
- * PROT_COST_DIRECT (default): every distance as the fma-accumulated sum of
- * squared coordinate differences, the definition itself (Section 2.1 rounds
- * these costs by eq. (1)). PROT_COST_MATRIX_CORES: for d >= 16,
- * |x|^2 + |y|^2 - 2 x.y with FP32 matrix-core products plus a rounding-error
- * bound; entries the bound cannot place in their rounding cell, and the
- * tiles that may hold the maximum, are recomputed directly. On MI355X the FP32
- * matrix rate equals the FP32 vector rate, so this path is not faster; it is
- * kept for comparison. Returns PROT_E_ARG for an unknown path. */
+ * compute the squared distances; all give the same result, bit for bit.
+ * PROT_COST_DIRECT: every distance as the fma-accumulated sum of squared
+ * coordinate differences, the definition itself (Section 2.1 rounds these
+ * costs by eq. (1)); two vector instructions per coordinate and pair.
+ * PROT_COST_MATRIX_CORES: for d >= 16, |x|^2 + |y|^2 - 2 x.y with FP32
+ * matrix-core products (one multiply-add per coordinate and pair, at twice
+ * the FP32 rate of the unpacked vector units this library uses) plus a
+ * rounding-error bound; entries the bound cannot place in their rounding
+ * cell, and the pairs that may hold the maximum, are recomputed directly.
+ * PROT_COST_AUTO (default): the matrix cores from d = 48 on, where they
+ * measured faster on MI355X, the direct path below. The matrix cores serve
+ * the squared cost of balanced instances and batches; other builds take the
+ * direct path. Returns PROT_E_ARG for an unknown path. */
 int prot_set_cost_path(prot_ctx *ctx, int32_t path);
 /* The cost of a pair in later single-instance point-set builds and solves on
  * ctx (prot_build_costs*, prot_solve_points*; batches always use the squared
@@ -331,8 +335,8 @@ int prot_batch_create(prot_ctx *ctx, int32_t batch, const int64_t *n_host, int32
  *   team     TEAMS: workgroups per instance, 1..8 (0: as many as fit);
  *            PROT_E_UNSUPPORTED if fewer than ceil(n_max / 1024) or more
  *            than fit next to each other on the GPU.
- *   cost_path  PROT_COST_DIRECT / PROT_COST_MATRIX_CORES, or -1 for the
- *            context's setting. */
+ *   cost_path  PROT_COST_DIRECT / PROT_COST_MATRIX_CORES / PROT_COST_AUTO, or
+ *            -1 for the context's setting. */
 enum { PROT_BATCH_ENGINE_AUTO = 0, PROT_BATCH_ENGINE_LDS = 1, PROT_BATCH_ENGINE_TEAMS = 2 };
 typedef struct {
     int32_t engine;

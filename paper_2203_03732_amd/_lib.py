@@ -335,11 +335,12 @@ class Context:
             _dev_ptr(k, torch.int16, "k", 2), k.stride(0)))
         return k
 
-    COST_PATHS = {"direct": 0, "matrix_cores": 1}
+    COST_PATHS = {"direct": 0, "matrix_cores": 1, "auto": 2}
 
     def set_cost_path(self, path: str) -> None:
-        """'direct' (default) or 'matrix_cores' for later point-set builds;
-        both give the same result (include/prot.h, prot_set_cost_path)."""
+        """'auto' (default: the matrix cores from d = 48), 'direct' or
+        'matrix_cores' for later point-set builds; all give the same result
+        (include/prot.h, prot_set_cost_path)."""
         self._check(self._lib.prot_set_cost_path(self._h, self.COST_PATHS[path]))
 
     COST_METRICS = {"sqeuclidean": 0, "euclidean": 1, "l1_normalized": 2}

@@ -66,7 +66,7 @@ struct prot_ctx {
     } *stage = nullptr;              // pinned host memory
 
     int64_t *rtime = nullptr;        // round timer (PROT_DEBUG_ROUND_TIMES=1)
-    int32_t cost_path = PROT_COST_DIRECT;  // prot_set_cost_path
+    int32_t cost_path = PROT_COST_AUTO;    // prot_set_cost_path
     int32_t cost_metric = PROT_METRIC_SQEUCLIDEAN;  // prot_set_cost_metric
     float *l1_buf = nullptr;         // normalised vectors of the L1 image cost
     int64_t l1_cap = 0;
@@ -279,7 +279,10 @@ int grid_for(prot_ctx *c, int64_t n, int64_t n_a, int *grid)
 int setup_mfma(prot_ctx *c, prot::PointsJob &j, int64_t n_max, float **buf, int64_t *cap)
 {
     j.mfma = prot::MfmaAux{};
-    if (j.d < prot::kMfmaMinD || c->cost_path != PROT_COST_MATRIX_CORES || j.na_single ||
+    const int32_t from_d = c->cost_path == PROT_COST_MATRIX_CORES ? prot::kMfmaMinD
+                           : c->cost_path == PROT_COST_AUTO       ? prot::kMfmaAutoD
+                                                                  : INT32_MAX;
+    if (j.d < from_d || j.na_single ||
         j.metric != PROT_METRIC_SQEUCLIDEAN || j.k8)
         return PROT_OK;  // (unbalanced instances and other metrics take the direct path)
     const int64_t tx = (n_max + prot::kMfmaTile - 1) / prot::kMfmaTile;
@@ -887,7 +890,9 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
     for (int i = 0; i < 5 && !rc; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) rc = PROT_E_HIP;
     if (const char *v = std::getenv("PROT_COST_PATH"))
-        if (std::strcmp(v, "mfma") == 0) c->cost_path = PROT_COST_MATRIX_CORES;
+        c->cost_path = std::strcmp(v, "mfma") == 0     ? PROT_COST_MATRIX_CORES
+                       : std::strcmp(v, "direct") == 0 ? PROT_COST_DIRECT
+                                                       : PROT_COST_AUTO;
     if (const char *v = std::getenv("PROT_PRUNE_MIN_N")) c->prune_min_n = std::atoll(v);
     if (const char *v = std::getenv("PROT_LOOP_GATE_CAP")) c->gate_cap = std::max(0, std::atoi(v));
     if (const char *v = std::getenv("PROT_LOOP_COOPERATIVE")) c->cooperative = std::atoi(v) == 1;
@@ -961,7 +966,7 @@ int prot_set_cost_metric(prot_ctx *c, int32_t metric)
 int prot_set_cost_path(prot_ctx *c, int32_t path)
 {
     if (!c) return PROT_E_ARG;
-    if (path != PROT_COST_DIRECT && path != PROT_COST_MATRIX_CORES)
+    if (path != PROT_COST_DIRECT && path != PROT_COST_MATRIX_CORES && path != PROT_COST_AUTO)
         return fail(c, PROT_E_ARG, "unknown cost path %d", (int)path);
     c->cost_path = path;
     return PROT_OK;
@@ -1414,7 +1419,7 @@ int prot_batch_create_config(prot_ctx *c, int32_t batch, const int64_t *n_host, 
     if (!out || batch < 0 || (batch > 0 && !n_host) || d < 1)
         return fail(c, PROT_E_ARG, "prot_batch_create: bad arguments");
     if (cfg && (cfg->engine < PROT_BATCH_ENGINE_AUTO || cfg->engine > PROT_BATCH_ENGINE_TEAMS ||
-                cfg->team < 0 || cfg->cost_path < -1 || cfg->cost_path > PROT_COST_MATRIX_CORES))
+                cfg->team < 0 || cfg->cost_path < -1 || cfg->cost_path > PROT_COST_AUTO))
         return fail(c, PROT_E_ARG, "prot_batch_create: bad configuration");
     *out = nullptr;
     const double ei = eps_internal(eps, o);

@@ -178,8 +178,9 @@ hipError_t launch_round_costs(const float *C, int64_t n, int64_t na, int64_t ldc
 hipError_t launch_points(const PointsJob &j, int64_t n_max, int64_t ldk_max, hipStream_t s);
 
 // cost_mfma.hip
-constexpr int32_t kMfmaMinD = 16;          // d from which the matrix cores are used
-constexpr int64_t kMfmaTile = 64;
+constexpr int32_t kMfmaMinD = 16;          // d from which the matrix cores can be used
+constexpr int32_t kMfmaAutoD = 48;         // d from which PROT_COST_AUTO uses them
+constexpr int64_t kMfmaTile = 128;      // tile rows and columns of the matrix-core build
 float mfma_error_constant(int32_t d);
 hipError_t launch_points_mfma(const PointsJob &j, const MfmaAux &x, int64_t n_max,
                               int64_t ldk_max, hipStream_t s);

@@ -73,8 +73,23 @@ def test_batched_matrix_core_build_bit_exact(ctx):
     try:
         out = ctx.solve_batched_points(ns, pack(Xs), pack(Ys), eps)
     finally:
-        ctx.set_cost_path("direct")
+        ctx.set_cost_path("auto")
     check_instances(ns, Xs, Ys, eps, out[:4], out[4])
+
+
+def test_batched_matrix_core_build_shifted_gaussians(ctx):
+    """Instances of the differentiable-loss workload's shape (n = 2048,
+    d = 64, X ~ N(0, I), Y ~ N(0.5, I), eps = 0.01) built on the matrix cores
+    and solved by teams: every instance equals the oracle's."""
+    X, Y = synth.shifted_gaussian_batch(3, 2048, 64, 0.5, seed=5)
+    ns = [2048] * 3
+    Xs, Ys = list(X), list(Y)
+    ctx.set_cost_path("matrix_cores")
+    try:
+        out = ctx.solve_batched_points(ns, pack(Xs), pack(Ys), 0.01)
+    finally:
+        ctx.set_cost_path("auto")
+    check_instances(ns, Xs, Ys, 0.01, out[:4], out[4])
 
 
 @pytest.mark.parametrize("origin", ["diag", "zero"])

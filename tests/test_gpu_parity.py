@@ -132,7 +132,7 @@ def test_round_costs_rejects_nan_and_range(ctx):
     assert e.value.name == "eps"
 
 
-@pytest.mark.parametrize("path", ["direct", "matrix_cores"])
+@pytest.mark.parametrize("path", ["direct", "matrix_cores", "auto"])
 @pytest.mark.parametrize("n,d,eps", [(1, 2, 0.1), (50, 2, 0.01), (1000, 2, 0.01),
                                      (513, 3, 0.005), (200, 5, 0.05), (300, 16, 0.05),
                                      (150, 17, 0.02), (130, 64, 0.01), (65, 4, 0.3),
@@ -143,7 +143,7 @@ def test_build_costs_bit_exact(ctx, n, d, eps, path):
     try:
         k, m = ctx.build_costs(dev(X), dev(Y), eps)
     finally:
-        ctx.set_cost_path("direct")
+        ctx.set_cost_path("auto")
     torch.cuda.synchronize()
     ko, mo = oracle.round_points_f32(X, Y, eps)
     assert float(host(m)[0]) == mo
@@ -165,7 +165,7 @@ def test_build_costs_matrix_core_path_far_from_origin(ctx):
         try:
             k, m = ctx.build_costs(dev(X), dev(Y), eps)
         finally:
-            ctx.set_cost_path("direct")
+            ctx.set_cost_path("auto")
         torch.cuda.synchronize()
         ko, mo = oracle.round_points_f32(X, Y, eps)
         assert float(host(m)[0]) == mo

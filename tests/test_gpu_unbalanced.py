@@ -185,7 +185,7 @@ def test_build_costs_rect_bit_exact(ctx, n_b, n_a, d, eps, path):
         k, m = ctx.build_costs(dev(X), dev(Y), eps)
         torch.cuda.synchronize()
     finally:
-        ctx.set_cost_path("direct")
+        ctx.set_cost_path("auto")
     ko, mo = oracle.round_points_f32(X, Y, eps)
     assert float(host(m)[0]) == mo
     assert np.array_equal(host(k)[:, :n_a], ko)
