@@ -24,7 +24,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 ORIGIN = {"diag": 0, "zero": 1}
-STATUS = {0: "ok", 1: "partial", -1: "arg", -2: "range", -3: "eps", -7: "nomem"}
+STATUS = {0: "ok", 1: "partial", -1: "arg", -2: "range", -3: "eps", -7: "nomem",
+          -8: "state"}
 
 
 class OracleError(RuntimeError):
@@ -74,13 +75,18 @@ def _load():
     lib.orc_ot_solve.argtypes = [p, i64, i64, i64, p, p, f64, i32, i64, i32, p, p, p, p, p,
                                  p, p, p, i64]
     lib.orc_points_pairs_f32.argtypes = [p, p, i32, f64, ctypes.c_float, p, p, i64, p]
+    lib.orc_ot_clustered_rounded.argtypes = [p, i64, i64, i64, p, p, i64, i32, i64, i32, i32,
+                                             p, p, p, p, p, p, p, p, p, i64]
+    lib.orc_ot_solve_clustered.argtypes = [p, i64, i64, i64, p, p, f64, i32, i64, i32, p, p,
+                                           p, p, p, p, p, p, p, i64]
     lib.orc_solve_points_f32.argtypes = [p, p, i64, i64, i32, f64, i64, i32, i64, i32,
                                          p, p, p, p, p, p, i64, p]
     for fn in (lib.orc_solve_points_f32, lib.orc_round_cost, lib.orc_round_points_f32,
                lib.orc_points_cost_f64, lib.orc_solve_rounded, lib.orc_solve_rounded_rect,
                lib.orc_points_max_f32, lib.orc_ot_scale, lib.orc_ot_solve,
                lib.orc_round_points_euclid_f32, lib.orc_round_l1_normalized_f32,
-               lib.orc_points_pairs_f32):
+               lib.orc_points_pairs_f32, lib.orc_ot_clustered_rounded,
+               lib.orc_ot_solve_clustered):
         fn.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -326,6 +332,119 @@ def ot_solve(C: np.ndarray, nu, mu, eps: float, origin: str = "diag", max_phases
     out = dict(plan=plan if rc == 0 else None, mate_a=mate_a, mate_b=mate_b, y_a=y_a, y_b=y_b,
                s=s, d=d, theta=float(info[0]), cost=float(info[1]), repaired=float(info[2]),
                T=int(info[3]), status=STATUS[rc], stats=stats)
+    if tr is not None:
+        out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Section 4 with Lemma 4.1: the copies of every point kept as clusters (at
+# most two dual levels per point). State in eps steps: Y[b] (top dual of b's
+# copies, where its F[b] free copies sit), Z[a] (top dual of a's copies, G[a]
+# of them free at 0), w[b, a, p] (pairs whose demand copy's level has parity
+# p; Z[a] and Z[a] - 1 differ in parity).
+
+_CLUSTER_KEYS = ("Y", "F", "Z", "G", "w")
+
+
+def _cluster_state(n_b, n_a, state):
+    if state is None:
+        return (np.ones(n_b, np.int32), np.zeros(n_b, np.int64), np.zeros(n_a, np.int32),
+                np.zeros(n_a, np.int64), np.zeros((n_b, n_a, 2), np.int64)), 0
+    dt = (np.int32, np.int64, np.int32, np.int64, np.int64)
+    return tuple(np.array(state[x], dtype=t, copy=True) for x, t in zip(_CLUSTER_KEYS, dt)), 1
+
+
+def cluster_levels(k, Z):
+    """The level of the demand copies in each parity slot: lev[a, p]."""
+    Z = np.asarray(Z, np.int64)
+    lev = np.empty((len(Z), 2), np.int64)
+    for p in (0, 1):
+        lev[:, p] = np.where((Z & 1) == p, Z, Z - 1)
+    return lev
+
+
+def cluster_counts(k, Y, Z, G, F, w):
+    """Copies per dual level: (b_hi, b_lo, a_top, a_bottom) = copies of b at
+    Y_b and at Y_b - 1, copies of a at Z_a and at Z_a - 1."""
+    k = np.asarray(k, np.int64)
+    lev = cluster_levels(k, Z)
+    Y = np.asarray(Y, np.int64)
+    b_hi = np.asarray(F, np.int64).copy()
+    b_lo = np.zeros_like(b_hi)
+    a_top = np.where(np.asarray(Z) == 0, np.asarray(G, np.int64), 0)
+    a_bot = np.zeros_like(a_top)
+    for p in (0, 1):
+        yb = k - lev[None, :, p]
+        hi = yb == Y[:, None]
+        b_hi += (w[:, :, p] * hi).sum(1)
+        b_lo += (w[:, :, p] * ~hi).sum(1)
+        top = (lev[:, p] == np.asarray(Z, np.int64))
+        a_top += (w[:, :, p].sum(0) * top)
+        a_bot += (w[:, :, p].sum(0) * ~top)
+    return b_hi, b_lo, a_top, a_bot
+
+
+def ot_clustered_rounded(k: np.ndarray, s, d, T: int, origin: str = "diag",
+                         max_phases: int = 0, complete: bool = True, state: dict | None = None,
+                         want_last: bool = False, trace: bool = False,
+                         trace_cap: int = 1 << 20) -> dict:
+    """The clustered copies' phase loop on rounded costs k (n_b x n_a) with
+    s[b] supply and d[a] demand copies per point. Returns the state (Y, F, Z,
+    G, w), flow (pairs per point pair, completion included when complete),
+    m_last (M' of the last phase, when want_last), status and stats."""
+    k = np.ascontiguousarray(k, dtype=np.int16)
+    n_b, n_a = k.shape
+    s = np.ascontiguousarray(s, dtype=np.int64)
+    d = np.ascontiguousarray(d, dtype=np.int64)
+    (Y, F, Z, G, w), warm = _cluster_state(n_b, n_a, state)
+    flow = np.zeros((n_b, n_a), np.int64)
+    m_last = np.zeros((n_b, n_a), np.int64) if want_last else None
+    st = _Stats()
+    tr = np.zeros((trace_cap, 4), np.int64) if trace else None
+    rc = _check(_load().orc_ot_clustered_rounded(
+        _ptr(k), n_b, n_a, n_a, _ptr(s), _ptr(d), int(T), ORIGIN[origin], int(max_phases),
+        warm, int(bool(complete)), _ptr(Y), _ptr(F), _ptr(Z), _ptr(G), _ptr(w), _ptr(flow),
+        _ptr(m_last) if m_last is not None else None, ctypes.byref(st),
+        _ptr(tr) if tr is not None else None, trace_cap if tr is not None else 0),
+        "ot_clustered_rounded")
+    stats = {name: int(getattr(st, name)) for name, _ in _Stats._fields_}
+    out = dict(Y=Y, F=F, Z=Z, G=G, w=w, flow=flow, m_last=m_last, status=STATUS[rc],
+               stats=stats)
+    if tr is not None:
+        out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
+    return out
+
+
+def ot_solve_clustered(C: np.ndarray, nu, mu, eps: float, origin: str = "diag",
+                       max_phases: int = 0, state: dict | None = None, trace: bool = False,
+                       trace_cap: int = 1 << 20) -> dict:
+    """ot_solve with the copies kept as clusters: the plan (None unless the
+    loop finished), the cluster state (Y, F, Z, G, w), the copies per dual
+    level (b_hi, b_lo, a_top, a_bot), s, d, theta, cost, repaired, T, status
+    and stats."""
+    C = np.ascontiguousarray(C, dtype=np.float32)
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    n_b, n_a = C.shape
+    s, d, theta = ot_scale(nu, mu, eps)
+    (Y, F, Z, G, w), warm = _cluster_state(n_b, n_a, state)
+    plan = np.zeros((n_b, n_a), np.float64)
+    info = np.zeros(4, np.float64)
+    st = _Stats()
+    tr = np.zeros((trace_cap, 4), np.int64) if trace else None
+    rc = _check(_load().orc_ot_solve_clustered(
+        _ptr(C), n_b, n_a, n_a, _ptr(nu), _ptr(mu), float(eps), ORIGIN[origin],
+        int(max_phases), warm, _ptr(Y), _ptr(F), _ptr(Z), _ptr(G), _ptr(w), _ptr(plan),
+        ctypes.byref(st), _ptr(info), _ptr(tr) if tr is not None else None,
+        trace_cap if tr is not None else 0), "ot_solve_clustered")
+    stats = {name: int(getattr(st, name)) for name, _ in _Stats._fields_}
+    k = round_cost(C, eps)
+    b_hi, b_lo, a_top, a_bot = cluster_counts(k, Y, Z, G, F, w)
+    out = dict(plan=plan if rc == 0 else None, Y=Y, F=F, Z=Z, G=G, w=w, b_hi=b_hi, b_lo=b_lo,
+               a_top=a_top, a_bot=a_bot, s=s, d=d, theta=float(info[0]),
+               cost=float(info[1]), repaired=float(info[2]), T=int(info[3]),
+               status=STATUS[rc], stats=stats)
     if tr is not None:
         out["trace"] = tr[:min(stats["phases"], trace_cap)].copy()
     return out

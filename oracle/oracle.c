@@ -579,6 +579,64 @@ int orc_ot_scale(const double *nu, int64_t n_b, const double *mu, int64_t n_a, d
     return ORC_OK;
 }
 
+/* The plan of Section 4 from the number of matched pairs of copies between
+ * each supply point b and demand point a (cnt, n_b x n_a): every pair carries
+ * 1/theta. Then the feasibility repair (the paper leaves it implicit): a
+ * demand point that received more than mu_a (its copies were rounded up)
+ * gives the excess back, taken from its edges in ascending b, and the mass
+ * still to be sent (what the rounding down of the supplies kept back, plus
+ * the excess) is paired with the room left at the demand points in order of
+ * index (north-west corner rule on the running totals). r and q are scratch
+ * of n_b + 1 and n_a + 1 entries. Writes info[1] (cost) and info[2] (mass
+ * moved by the repair). */
+static void plan_from_counts(const int64_t *cnt, const float *C, int64_t ldc, int64_t n_b,
+                             int64_t n_a, const double *nu, const double *mu, double theta,
+                             double *plan, double *r, double *q, double *info)
+{
+    for (int64_t i = 0; i < n_b * n_a; ++i) plan[i] = (double)cnt[i] / theta;
+    for (int64_t a = 0; a < n_a; ++a) {
+        int64_t c_a = 0;
+        for (int64_t b = 0; b < n_b; ++b) c_a += cnt[b * n_a + a];
+        double ex = (double)c_a / theta - mu[a];
+        for (int64_t b = 0; b < n_b && ex > 0.0; ++b) {
+            double v = plan[b * n_a + a];
+            if (v <= 0.0) continue;
+            double take = v < ex ? v : ex;
+            plan[b * n_a + a] = v - take;
+            ex = ex - take;
+        }
+    }
+    /* what each supply point still has to send, and the room each demand
+     * point has left ... */
+    r[0] = 0.0;
+    for (int64_t b = 0; b < n_b; ++b) {
+        double sent = 0.0;
+        for (int64_t a = 0; a < n_a; ++a) sent += plan[b * n_a + a];
+        double left = nu[b] - sent;
+        r[b + 1] = r[b] + (left > 0.0 ? left : 0.0);
+    }
+    q[0] = 0.0;
+    for (int64_t a = 0; a < n_a; ++a) {
+        double got = 0.0;
+        for (int64_t b = 0; b < n_b; ++b) got += plan[b * n_a + a];
+        double room = mu[a] - got;
+        q[a + 1] = q[a] + (room > 0.0 ? room : 0.0);
+    }
+    /* ... are paired in order: supply b's share [r_b, r_{b+1}) of the
+     * running total meets demand a's [q_a, q_{a+1}). */
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) {
+            double lo = r[b] > q[a] ? r[b] : q[a];
+            double hi = r[b + 1] < q[a + 1] ? r[b + 1] : q[a + 1];
+            if (hi > lo) plan[b * n_a + a] += hi - lo;
+        }
+    double cost = 0.0;
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) cost += plan[b * n_a + a] * (double)C[b * ldc + a];
+    info[1] = cost;
+    info[2] = r[n_b];
+}
+
 int orc_ot_solve(const float *C, int64_t n_b, int64_t n_a, int64_t ldc, const double *nu,
                  const double *mu, double eps, int32_t origin_mode, int64_t max_phases,
                  int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,
@@ -635,54 +693,305 @@ int orc_ot_solve(const float *C, int64_t n_b, int64_t n_a, int64_t ldc, const do
     /* The plan: every matched pair of copies carries 1/theta. */
     for (int64_t b = 0; b < NB; ++b)
         if (mate_b[b] >= 0) cnt[row_pt[b] * n_a + col_pt[mate_b[b]]] += 1;
-    for (int64_t i = 0; i < n_b * n_a; ++i) plan[i] = (double)cnt[i] / theta;
-
-    /* Feasibility repair (the paper leaves it implicit). A demand point that
-     * received more than mu_a (its copies were rounded up) gives the excess
-     * back, taken from its edges in ascending b. */
-    for (int64_t a = 0; a < n_a; ++a) {
-        int64_t c_a = 0;
-        for (int64_t b = 0; b < n_b; ++b) c_a += cnt[b * n_a + a];
-        double ex = (double)c_a / theta - mu[a];
-        for (int64_t b = 0; b < n_b && ex > 0.0; ++b) {
-            double v = plan[b * n_a + a];
-            if (v <= 0.0) continue;
-            double take = v < ex ? v : ex;
-            plan[b * n_a + a] = v - take;
-            ex = ex - take;
-        }
-    }
-    /* What each supply point still has to send, and the room each demand
-     * point has left ... */
-    r[0] = 0.0;
-    for (int64_t b = 0; b < n_b; ++b) {
-        double sent = 0.0;
-        for (int64_t a = 0; a < n_a; ++a) sent += plan[b * n_a + a];
-        double left = nu[b] - sent;
-        r[b + 1] = r[b] + (left > 0.0 ? left : 0.0);
-    }
-    q[0] = 0.0;
-    for (int64_t a = 0; a < n_a; ++a) {
-        double got = 0.0;
-        for (int64_t b = 0; b < n_b; ++b) got += plan[b * n_a + a];
-        double room = mu[a] - got;
-        q[a + 1] = q[a] + (room > 0.0 ? room : 0.0);
-    }
-    /* ... are paired in order (north-west corner rule): supply b's share
-     * [r_b, r_{b+1}) of the running total meets demand a's [q_a, q_{a+1}). */
-    for (int64_t b = 0; b < n_b; ++b)
-        for (int64_t a = 0; a < n_a; ++a) {
-            double lo = r[b] > q[a] ? r[b] : q[a];
-            double hi = r[b + 1] < q[a + 1] ? r[b + 1] : q[a + 1];
-            if (hi > lo) plan[b * n_a + a] += hi - lo;
-        }
-    double cost = 0.0;
-    for (int64_t b = 0; b < n_b; ++b)
-        for (int64_t a = 0; a < n_a; ++a) cost += plan[b * n_a + a] * (double)C[b * ldc + a];
-    info[1] = cost;
-    info[2] = r[n_b];
+    plan_from_counts(cnt, C, ldc, n_b, n_a, nu, mu, theta, plan, r, q, info);
 
 out:
     free(s); free(d); free(row_pt); free(col_pt); free(k); free(cnt); free(r); free(q);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 4 with Lemma 4.1: the copies kept as two clusters per point. */
+/* ------------------------------------------------------------------ */
+
+/* The level (dual in eps steps) of the demand copies of point a stored in
+ * parity slot p: its two levels Z_a and Z_a - 1 differ in parity. */
+static int32_t a_level(int32_t Z, int32_t p)
+{
+    return ((Z & 1) == p) ? Z : Z - 1;
+}
+
+/* Lemma 4.1 and eqs. (1)-(2) on the clusters: every matched pair is tight
+ * (its supply copy sits at k - its demand copy's level), and that level is
+ * Y_b or Y_b - 1; a point with free demand copies has its top at 0. */
+static int clusters_ok(const int16_t *k, int64_t ldk, int64_t n_b, int64_t n_a,
+                       const int32_t *Y, const int32_t *Z, const int64_t *G, const int64_t *w)
+{
+    for (int64_t a = 0; a < n_a; ++a)
+        if (G[a] > 0 && Z[a] != 0) return 0;
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a)
+            for (int32_t p = 0; p < 2; ++p) {
+                if (w[(b * n_a + a) * 2 + p] == 0) continue;
+                int64_t yb = (int64_t)k[b * ldk + a] - a_level(Z[a], p);
+                if (yb != Y[b] && yb != (int64_t)Y[b] - 1) return 0;
+            }
+    return 1;
+}
+
+int orc_ot_clustered_rounded(const int16_t *k, int64_t n_b, int64_t n_a, int64_t ldk,
+                             const int64_t *s, const int64_t *d, int64_t T,
+                             int32_t origin_mode, int64_t max_phases, int32_t warm,
+                             int32_t complete, int32_t *Y, int64_t *F, int32_t *Z, int64_t *G,
+                             int64_t *w, int64_t *flow, int64_t *m_last, orc_stats *st,
+                             int64_t *trace, int64_t trace_cap)
+{
+    if (!k || n_b < 1 || n_a < 1 || ldk < n_a || !s || !d || T < 0 || !Y || !F || !Z ||
+        !G || !w || !st)
+        return ORC_E_ARG;
+    if (origin_mode != ORC_ORIGIN_DIAG && origin_mode != ORC_ORIGIN_ZERO) return ORC_E_ARG;
+    int64_t NB = 0, NA = 0;
+    for (int64_t b = 0; b < n_b; ++b) {
+        if (s[b] < 0) return ORC_E_ARG;
+        NB += s[b];
+    }
+    for (int64_t a = 0; a < n_a; ++a) {
+        if (d[a] < 0) return ORC_E_ARG;
+        NA += d[a];
+    }
+    if (NB > NA) return ORC_E_ARG;
+    memset(st, 0, sizeof(*st));
+
+    /* Initialisation: every supply copy free at y = eps, every demand copy
+     * free at 0, no pairs. */
+    if (!warm) {
+        for (int64_t b = 0; b < n_b; ++b) {
+            Y[b] = 1;
+            F[b] = s[b];
+        }
+        for (int64_t a = 0; a < n_a; ++a) {
+            Z[a] = 0;
+            G[a] = d[a];
+        }
+        memset(w, 0, sizeof(int64_t) * (size_t)(n_b * n_a * 2));
+    }
+
+    int64_t *top = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_a);
+    int64_t *cap = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_a);
+    int64_t *want = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_b);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_b);
+    int64_t *target = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_b);
+    int64_t *evicted = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_b);
+    char *active = (char *)malloc((size_t)n_b);
+    int64_t *m = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_b * n_a));
+    if (!top || !cap || !want || !pos || !target || !evicted || !active || !m) {
+        free(top); free(cap); free(want); free(pos); free(target); free(evicted);
+        free(active); free(m);
+        return ORC_E_NOMEM;
+    }
+
+    int status = ORC_OK;
+    if (m_last) memset(m_last, 0, sizeof(int64_t) * (size_t)(n_b * n_a));
+    for (;;) {
+        /* |B'|: the free supply copies */
+        int64_t n_free = 0;
+        for (int64_t b = 0; b < n_b; ++b) n_free += F[b];
+        if (n_free <= T) break;
+        if (max_phases > 0 && st->phases == max_phases) {
+            status = ORC_PARTIAL;
+            break;
+        }
+        st->phases += 1;
+        st->sum_free += n_free;
+        int64_t phase_scanned = 0, phase_rounds = 0, phase_matched = 0;
+
+        /* Step (I) on the clusters. The free copies of b all sit at Y_b (the
+         * raise), the copies of a at Z_a or Z_a - 1. Edge (a, b) is
+         * admissible when k + 1 = Z_a + Y_b; the lower level of a never is,
+         * as (I1) on the upper level's copies gives Z_a + Y_b <= k + 1. So a
+         * offers its top-level copies: the free ones (top = 0) and those
+         * matched at Z_a. Reading used here: point-level synchronous rounds.
+         * Every b with copies still looking proposes to the first point in
+         * its scan order (DIAG: from column b mod n_a, as supply points may
+         * outnumber demand points) that is admissible and had top copies left when the
+         * round began, asking for all its looking copies; each point serves
+         * its proposers in ascending b, each as far as its copies go; a b
+         * served in part, or not at all, goes on scanning after that point.
+         * A b that finds nothing keeps its remaining copies free in M'. */
+        for (int64_t a = 0; a < n_a; ++a) {
+            int64_t t = (Z[a] == 0) ? G[a] : 0;
+            for (int64_t b = 0; b < n_b; ++b) t += w[(b * n_a + a) * 2 + (Z[a] & 1)];
+            top[a] = t;
+            cap[a] = t;
+        }
+        for (int64_t b = 0; b < n_b; ++b) {
+            want[b] = F[b];
+            pos[b] = 0;
+            active[b] = F[b] > 0;
+            evicted[b] = 0;
+        }
+        memset(m, 0, sizeof(int64_t) * (size_t)(n_b * n_a));
+        for (;;) {
+            int64_t proposals = 0;
+            /* (i) propose, against the top copies left at the round's start */
+            for (int64_t b = 0; b < n_b; ++b) {
+                if (!active[b]) continue;
+                target[b] = -1;
+                int64_t j;
+                for (j = pos[b]; j < n_a; ++j) {
+                    int64_t a = scan_col(origin_mode, b % n_a, j, n_a);
+                    if (cap[a] > 0 && (int64_t)k[b * ldk + a] + 1 == (int64_t)Z[a] + Y[b]) {
+                        target[b] = a;
+                        break;
+                    }
+                }
+                if (target[b] < 0) {
+                    phase_scanned += n_a - pos[b];
+                    active[b] = 0;
+                } else {
+                    phase_scanned += j - pos[b] + 1;
+                    pos[b] = j;
+                    proposals += 1;
+                }
+            }
+            if (proposals == 0) break;
+            /* (ii) each point serves its proposers in ascending b */
+            for (int64_t b = 0; b < n_b; ++b) {
+                if (!active[b]) continue;
+                int64_t a = target[b];
+                int64_t g = want[b] < cap[a] ? want[b] : cap[a];
+                want[b] -= g;
+                cap[a] -= g;
+                m[b * n_a + a] += g;
+                phase_matched += g;
+                if (want[b] == 0)
+                    active[b] = 0;
+                else
+                    pos[b] += 1;  /* the point has no top copies left */
+            }
+            phase_rounds += 1;
+        }
+
+        /* Step (II): each point a hands out the top copies M' took: the free
+         * ones first, then those matched at Z_a in ascending order of their
+         * partner's point, whose partner copies become free (A'' and M''). The
+         * taken copies form the new pairs; after (III a) they sit at Z_a - 1,
+         * and a point whose top copies are all taken has Z_a - 1 as its top. */
+        for (int64_t a = 0; a < n_a; ++a) {
+            int64_t taken = top[a] - cap[a];
+            if (taken == 0) continue;
+            int32_t p = Z[a] & 1;
+            if (Z[a] == 0) {
+                int64_t u = taken < G[a] ? taken : G[a];
+                G[a] -= u;
+                taken -= u;
+            }
+            for (int64_t b = 0; b < n_b && taken > 0; ++b) {
+                int64_t *x = &w[(b * n_a + a) * 2 + p];
+                int64_t v = taken < *x ? taken : *x;
+                *x -= v;
+                evicted[b] += v;
+                taken -= v;
+            }
+            int32_t q = (Z[a] - 1) & 1;
+            for (int64_t b = 0; b < n_b; ++b) w[(b * n_a + a) * 2 + q] += m[b * n_a + a];
+            if (cap[a] == 0) Z[a] -= 1;  /* step (III a) for the whole top */
+        }
+        /* Step (III b) and the raise: copies of b left free by M' go up one
+         * step, so Y_b grows by one when there are any; the evicted copies
+         * are free again and take the largest dual of their point, Y_b. */
+        for (int64_t b = 0; b < n_b; ++b) {
+            if (want[b] > 0) Y[b] += 1;
+            F[b] = want[b] + evicted[b];
+        }
+        if (!clusters_ok(k, ldk, n_b, n_a, Y, Z, G, w)) {
+            status = ORC_E_STATE;
+            break;
+        }
+        if (m_last) memcpy(m_last, m, sizeof(int64_t) * (size_t)(n_b * n_a));
+
+        st->rounds += phase_rounds;
+        if (phase_rounds > st->max_rounds) st->max_rounds = phase_rounds;
+        st->scanned += phase_scanned;
+        if (trace && st->phases <= trace_cap) {
+            int64_t *t = trace + 4 * (st->phases - 1);
+            t[0] = n_free;
+            t[1] = phase_rounds;
+            t[2] = phase_scanned;
+            t[3] = phase_matched;
+        }
+    }
+
+    int64_t matched = 0, sum_k = 0;
+    for (int64_t b = 0; b < n_b; ++b)
+        for (int64_t a = 0; a < n_a; ++a) {
+            int64_t c = w[(b * n_a + a) * 2] + w[(b * n_a + a) * 2 + 1];
+            matched += c;
+            sum_k += c * (int64_t)k[b * ldk + a];
+            if (flow) flow[b * n_a + a] = c;
+        }
+    st->matched_in_phases = matched;
+
+    /* Completion: the free supply copies, in order of their point, take the
+     * free demand copies in order of theirs (north-west corner rule on the
+     * counts F and G; with one copy per point this is the i-th free b taking
+     * the i-th free a). The clusters are left as the phase loop ended. */
+    if (complete && status == ORC_OK) {
+        int64_t a = 0, g = n_a > 0 ? G[0] : 0;
+        for (int64_t b = 0; b < n_b; ++b) {
+            int64_t f = F[b];
+            while (f > 0) {
+                while (g == 0 && a + 1 < n_a) g = G[++a];
+                if (g == 0) break;
+                int64_t v = f < g ? f : g;
+                if (flow) flow[b * n_a + a] += v;
+                sum_k += v * (int64_t)k[b * ldk + a];
+                st->completed_pairs += v;
+                f -= v;
+                g -= v;
+            }
+        }
+    }
+    st->sum_k = sum_k;
+
+    free(top); free(cap); free(want); free(pos); free(target); free(evicted);
+    free(active); free(m);
+    return status;
+}
+
+int orc_ot_solve_clustered(const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                           const double *nu, const double *mu, double eps, int32_t origin_mode,
+                           int64_t max_phases, int32_t warm, int32_t *Y, int64_t *F, int32_t *Z,
+                           int64_t *G, int64_t *w, double *plan, orc_stats *st, double *info,
+                           int64_t *trace, int64_t trace_cap)
+{
+    if (!C || ldc < n_a || !Y || !F || !Z || !G || !w || !plan || !st || !info)
+        return ORC_E_ARG;
+    double theta = 0.0;
+    int64_t NB = 0, NA = 0;
+    int64_t *s = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_b > 0 ? n_b : 1));
+    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_a > 0 ? n_a : 1));
+    if (!s || !d) {
+        free(s); free(d);
+        return ORC_E_NOMEM;
+    }
+    int rc = orc_ot_scale(nu, n_b, mu, n_a, eps, s, d, &theta, &NB, &NA);
+    if (rc) {
+        free(s); free(d);
+        return rc;
+    }
+    int16_t *k = (int16_t *)malloc(sizeof(int16_t) * (size_t)(n_b * n_a));
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_b * n_a));
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n_b + 1));
+    double *q = (double *)malloc(sizeof(double) * (size_t)(n_a + 1));
+    if (!k || !cnt || !r || !q) {
+        rc = ORC_E_NOMEM;
+        goto out;
+    }
+    rc = orc_round_cost(C, n_b, n_a, ldc, eps, k, n_a);
+    if (rc) goto out;
+    /* the same stop as the explicit copies: |B'| <= eps |B copies| */
+    const int64_t T = (int64_t)floor(eps * (double)NB + 1e-9);
+    rc = orc_ot_clustered_rounded(k, n_b, n_a, n_a, s, d, T, origin_mode, max_phases, warm, 1,
+                                  Y, F, Z, G, w, cnt, NULL, st, trace, trace_cap);
+    info[0] = theta;
+    info[1] = 0.0;
+    info[2] = 0.0;
+    info[3] = (double)T;
+    if (rc != ORC_OK) goto out;
+    plan_from_counts(cnt, C, ldc, n_b, n_a, nu, mu, theta, plan, r, q, info);
+
+out:
+    free(s); free(d); free(k); free(cnt); free(r); free(q);
     return rc;
 }

@@ -27,7 +27,8 @@ enum {
     ORC_E_ARG = -1,
     ORC_E_RANGE = -2,     /* a cost is NaN or outside [0, 1] */
     ORC_E_EPS = -3,       /* eps outside (0, 1) or 1/eps too large for int16 */
-    ORC_E_NOMEM = -7
+    ORC_E_NOMEM = -7,
+    ORC_E_STATE = -8      /* the clusters broke Lemma 4.1 or eq. (2) (a defect) */
 };
 
 enum { ORC_ORIGIN_DIAG = 0, ORC_ORIGIN_ZERO = 1 };
@@ -151,6 +152,39 @@ int orc_ot_solve(const float *C, int64_t n_b, int64_t n_a, int64_t ldc, const do
                  const double *mu, double eps, int32_t origin_mode, int64_t max_phases,
                  int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,
                  double *plan, orc_stats *st, double *info, int64_t *trace, int64_t trace_cap);
+
+/* Section 4 with Lemma 4.1: the transport copies kept as clusters. Supply
+ * point b has s[b] copies, demand point a d[a] (sum s <= sum d); a copy's
+ * rounded cost is its points' k. State, all in eps steps:
+ *   Y[b] : the largest dual among b's copies; its free copies sit there and
+ *          its matched ones at Y[b] or Y[b] - 1
+ *   F[b] : b's free copies
+ *   Z[a] : the largest dual among a's copies; they sit at Z[a] or Z[a] - 1
+ *   G[a] : a's free copies (dual 0; G[a] > 0 only when Z[a] = 0)
+ *   w    : n_b x n_a x 2, w[(b*n_a + a)*2 + p] = pairs between copies of b
+ *          and copies of a whose demand copy's level has parity p; the
+ *          supply copy of such a pair sits at k[b][a] minus that level
+ * A phase is steps (I)-(III) of Section 2.2 on the copies with the free-copy
+ * raise of Section 4, taken point by point (the reading is stated in the
+ * code); phases run while sum F > T. flow (optional, n_b x n_a) receives the
+ * pairs per point pair, plus the completion's when complete is set; m_last
+ * (optional, n_b x n_a) the pairs M' formed in the last phase. warm resumes
+ * from Y, F, Z, G, w. ORC_E_STATE when a check of Lemma 4.1 fails. */
+int orc_ot_clustered_rounded(const int16_t *k, int64_t n_b, int64_t n_a, int64_t ldk,
+                             const int64_t *s, const int64_t *d, int64_t T,
+                             int32_t origin_mode, int64_t max_phases, int32_t warm,
+                             int32_t complete, int32_t *Y, int64_t *F, int32_t *Z, int64_t *G,
+                             int64_t *w, int64_t *flow, int64_t *m_last, orc_stats *st,
+                             int64_t *trace, int64_t trace_cap);
+
+/* orc_ot_solve with the copies kept as clusters (orc_ot_clustered_rounded):
+ * same scaling, rounding, stop threshold, completion reading, plan and
+ * repair, and the same info. */
+int orc_ot_solve_clustered(const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                           const double *nu, const double *mu, double eps, int32_t origin_mode,
+                           int64_t max_phases, int32_t warm, int32_t *Y, int64_t *F, int32_t *Z,
+                           int64_t *G, int64_t *w, double *plan, orc_stats *st, double *info,
+                           int64_t *trace, int64_t trace_cap);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PINS = [os.path.join(HERE, f) for f in ("test_oracle.py", "test_oracle_ot.py",
-                                        "test_oracle_costs.py")]
+                                        "test_oracle_costs.py", "test_oracle_ot_clustered.py")]
 
 # (name, text in oracle.c, replacement, every occurrence?)
 MUTATIONS = [
@@ -50,6 +50,22 @@ MUTATIONS = [
     ("point costs without the matrix not scaled by the maximum",
      "double v = (double)sq_f32(c->X + r * c->d, c->Y + q * c->d, c->d) / (double)c->m;",
      "double v = (double)sq_f32(c->X + r * c->d, c->Y + q * c->d, c->d);", False),
+    ("clusters: evictions from the lower level's slot",
+     "int32_t p = Z[a] & 1;\n            if (Z[a] == 0) {",
+     "int32_t p = (Z[a] - 1) & 1;\n            if (Z[a] == 0) {", False),
+    ("clusters: new pairs at the top level",
+     "int32_t q = (Z[a] - 1) & 1;", "int32_t q = Z[a] & 1;", False),
+    ("clusters: Z kept when the top runs out", "if (cap[a] == 0) Z[a] -= 1;", "(void)0;", False),
+    ("clusters: copies left over rise by two", "if (want[b] > 0) Y[b] += 1;",
+     "if (want[b] > 0) Y[b] += 2;", False),
+    ("clusters: evicted copies lost", "F[b] = want[b] + evicted[b];", "F[b] = want[b];", False),
+    ("clusters: free demand copies not first",
+     "int64_t u = taken < G[a] ? taken : G[a];", "int64_t u = 0;", False),
+    ("clusters: proposers served in descending b",
+     "            /* (ii) each point serves its proposers in ascending b */\n            for (int64_t b = 0; b < n_b; ++b) {",
+     "            /* (ii) each point serves its proposers in ascending b */\n            for (int64_t b = n_b - 1; b >= 0; --b) {",
+     False),
+    ("clusters: completion dropped", "if (flow) flow[b * n_a + a] += v;", "(void)0;", False),
     ("point costs without the matrix transposed",
      "sq_f32(c->X + r * c->d, c->Y + q * c->d, c->d)",
      "sq_f32(c->X + q * c->d, c->Y + r * c->d, c->d)", False),
