@@ -311,6 +311,41 @@ int prot_ot_solve(prot_ctx *ctx, const float *C, int64_t n_b, int64_t n_a, int64
                   double *plan, int64_t ldp, int32_t *y_b_lo, int32_t *y_b_nlo,
                   int32_t *y_a_lo, int32_t *y_a_nlo, prot_ot_stats *stats);
 
+/* Optimal transport (Section 4) with the copies of every point kept as two
+ * dual clusters (Lemma 4.1), so that the state is O(n_b + n_a) per side
+ * plus the pair counts, whatever theta. Same problem, arguments, outputs and
+ * errors as prot_ot_solve, and the same scaling, rounding, stop threshold,
+ * completion reading, plan and repair; the phases are taken point by point:
+ *   - supply point b keeps Y_b (the larger dual of its copies; its free
+ *     copies sit there after the free-copy raise) and its free count; demand
+ *     point a keeps Z_a (the larger dual of its copies) and its free count;
+ *     a matched pair of copies is tight (eq. (2)), so the pairs between b
+ *     and a are counted by the parity of the demand copy's level;
+ *   - step (I): edge (a, b) is admissible for b's free copies exactly when
+ *     k + 1 = Z_a + Y_b (the lower level of a never is, by (I1)). In
+ *     synchronous rounds every b with copies still looking asks the first
+ *     admissible point in its scan order (DIAG: from column b mod n_a) that
+ *     had top-level copies left when the round began for all of them; a
+ *     point serves its proposers in ascending b as far as its top copies
+ *     go; a b served in part or not at all goes on after that point;
+ *   - step (II): a point hands out the copies taken from its free ones
+ *     first, then from those matched at Z_a in ascending order of the
+ *     partner point, whose copies become free;
+ *   - step (III): the taken copies drop one step (Z_a drops when all top
+ *     copies went); a b with copies left over rises one step; freed copies
+ *     take the largest dual of their point.
+ * This is one admissible run of the copies' algorithm (a maximal M' in
+ * every phase), so the guarantees of prot_ot_solve hold; the matching it
+ * picks differs from prot_ot_solve's copy-by-copy rounds. Limits: at most
+ * 4096 points a side (the points' state is held by one workgroup);
+ * sum ceil(theta mu_a) < 2^31. loop.scanned counts the positions the
+ * point-level scans pass, as in a scan of the n_a columns of each point. */
+int prot_ot_solve_clustered(prot_ctx *ctx, const float *C, int64_t n_b, int64_t n_a,
+                            int64_t ldc, const double *nu, const double *mu, double eps,
+                            const prot_opts *opts, double *plan, int64_t ldp, int32_t *y_b_lo,
+                            int32_t *y_b_nlo, int32_t *y_a_lo, int32_t *y_a_nlo,
+                            prot_ot_stats *stats);
+
 typedef struct prot_batch prot_batch;
 
 /* Largest n of one instance in a batch. */

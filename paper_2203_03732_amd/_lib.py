@@ -106,7 +106,8 @@ EXPORTS = [
     "prot_threshold", "prot_max_n", "prot_round_costs", "prot_build_costs",
     "prot_solve_rounded", "prot_solve_cost", "prot_solve_points",
     "prot_round_costs_rect", "prot_build_costs_rect", "prot_solve_rounded_rect",
-    "prot_solve_cost_rect", "prot_solve_points_rect", "prot_ot_solve", "prot_set_cost_metric",
+    "prot_solve_cost_rect", "prot_solve_points_rect", "prot_ot_solve", "prot_ot_solve_clustered",
+    "prot_set_cost_metric",
     "prot_get_trace",
     "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
     "prot_batch_create_config", "prot_batch_autotune",
@@ -157,6 +158,9 @@ def load():
                                                   ctypes.POINTER(Stats)]),
         "prot_ot_solve": (ctypes.c_int, [p, p, i64, i64, i64, p, p, f64, ctypes.POINTER(Opts),
                                          p, i64, p, p, p, p, ctypes.POINTER(OTStats)]),
+        "prot_ot_solve_clustered": (ctypes.c_int, [p, p, i64, i64, i64, p, p, f64,
+                                                   ctypes.POINTER(Opts), p, i64, p, p, p, p,
+                                                   ctypes.POINTER(OTStats)]),
         "prot_set_cost_metric": (ctypes.c_int, [p, i32]),
         "prot_get_trace": (i64, [p, p, i64]),
         "prot_get_round_times": (i64, [p, p, i64]),
@@ -486,10 +490,11 @@ class Context:
         return Result(mate_a, mate_b, y_a, y_b, STATUS_NAMES[rc], st.as_dict() if stats else {})
 
     def ot_solve(self, C, nu, mu, eps: float, *, eps_mode="algorithmic", origin="diag",
-                 max_phases=0, plan=None) -> OTResult:
+                 max_phases=0, plan=None, clustered=False) -> OTResult:
         """Optimal transport (Section 4) from supplies nu (rows of C) to
         demands mu (columns): C n_b x n_a float32 in [0, 1], nu and mu float64
-        probability vectors, all on the device."""
+        probability vectors, all on the device. clustered: keep each point's
+        copies as two dual clusters (Lemma 4.1; prot_ot_solve_clustered)."""
         torch = _torch()
         if C.dim() != 2 or C.stride(1) != 1:
             raise ValueError("C must be a row-major n_b x n_a float32 matrix")
@@ -508,7 +513,8 @@ class Context:
         st = OTStats()
         o = self._opts(eps_mode, origin, True, max_phases)
         self._bind_stream()
-        rc = self._check(self._lib.prot_ot_solve(
+        fn = self._lib.prot_ot_solve_clustered if clustered else self._lib.prot_ot_solve
+        rc = self._check(fn(
             self._h, _dev_ptr(C, torch.float32, "C", 2), n_b, n_a, C.stride(0),
             _dev_ptr(nu, torch.float64, "nu", 1), _dev_ptr(mu, torch.float64, "mu", 1),
             float(eps), ctypes.byref(o),

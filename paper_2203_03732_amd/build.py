@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libprot.so")
 SOURCES = ["cost.hip", "cost_mfma.hip", "solve.hip", "batch.hip", "loss.hip", "ot.hip",
-           "api.cpp"]
+           "ot_cluster.hip", "api.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

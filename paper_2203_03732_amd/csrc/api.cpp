@@ -92,6 +92,14 @@ struct prot_ctx {
         int32_t *mate_a = nullptr, *mate_b = nullptr, *y_a = nullptr, *y_b = nullptr;
         double *rv = nullptr, *qv = nullptr, *R = nullptr, *Q = nullptr;
         prot::OtInfo *info = nullptr;
+        // the copies kept as clusters (prot_ot_solve_clustered)
+        int64_t ccap_b = 0, ccap_a = 0, ccap_cells = 0, ccap_mask = 0;
+        int2 *cw = nullptr;
+        unsigned long long *cmask = nullptr;
+        uint16_t *clist = nullptr;
+        int32_t *cY = nullptr, *cF = nullptr, *cZ = nullptr, *ctop = nullptr, *cbot = nullptr,
+                *cG = nullptr;
+        int64_t *cPF = nullptr, *cPG = nullptr;
     } ot;
     // 0 build start, 1 build end, 2 loop start, 3 loop end, 4 all done
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -944,7 +952,10 @@ int prot_ctx_destroy(prot_ctx *c)
                     (void *)c->ot.col_pt, (void *)c->ot.ymax, (void *)c->ot.cnt,
                     (void *)c->ot.mate_a, (void *)c->ot.mate_b, (void *)c->ot.y_a,
                     (void *)c->ot.y_b, (void *)c->ot.rv, (void *)c->ot.qv, (void *)c->ot.R,
-                    (void *)c->ot.Q, (void *)c->ot.info})
+                    (void *)c->ot.Q, (void *)c->ot.info, (void *)c->ot.cw, (void *)c->ot.cmask,
+                    (void *)c->ot.clist, (void *)c->ot.cY, (void *)c->ot.cF, (void *)c->ot.cZ,
+                    (void *)c->ot.ctop, (void *)c->ot.cbot, (void *)c->ot.cG, (void *)c->ot.cPF,
+                    (void *)c->ot.cPG})
         (void)hipFree(p);
     if (c->stage) (void)hipHostFree(c->stage);
     for (int i = 0; i < 5; ++i)
@@ -1395,6 +1406,164 @@ int prot_ot_solve(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, int64_t
         rc = collect(c, &st->loop, T, ei, 1, true);
     }
     if (rc) return rc;
+    fill_match_counts(c, NB, &st->loop, &lo);
+    st->repaired_mass = c->stage->ot.repaired;
+    if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a cost is NaN or outside [0,1]");
+    if (c->stage->ctl.err & 128)
+        return fail(c, PROT_E_HIP, "internal: the copies of a point hold more than two duals");
+    return st->loop.status;
+}
+
+namespace {
+
+int ensure_clusters(prot_ctx *c, int64_t n_b, int64_t n_a)
+{
+    prot_ctx::Ot &w = c->ot;
+    int rc = PROT_OK;
+    if (n_b > w.ccap_b) {
+        if ((rc = dev_alloc(c, &w.cY, (size_t)n_b)) || (rc = dev_alloc(c, &w.cF, (size_t)n_b)) ||
+            (rc = dev_alloc(c, &w.cPF, (size_t)n_b + 1)))
+            return rc;
+        w.ccap_b = n_b;
+    }
+    if (n_a > w.ccap_a) {
+        if ((rc = dev_alloc(c, &w.cZ, (size_t)n_a)) || (rc = dev_alloc(c, &w.ctop, (size_t)n_a)) ||
+            (rc = dev_alloc(c, &w.cbot, (size_t)n_a)) || (rc = dev_alloc(c, &w.cG, (size_t)n_a)) ||
+            (rc = dev_alloc(c, &w.cPG, (size_t)n_a + 1)))
+            return rc;
+        w.ccap_a = n_a;
+    }
+    if (n_b * n_a > w.ccap_cells) {
+        if ((rc = dev_alloc(c, &w.cw, (size_t)(n_b * n_a))) ||
+            (rc = dev_alloc(c, &w.clist, (size_t)(n_b * n_a))))
+            return rc;
+        w.ccap_cells = n_b * n_a;
+    }
+    const int64_t words = n_a * ((n_b + 63) / 64);
+    if (words > w.ccap_mask) {
+        if ((rc = dev_alloc(c, &w.cmask, (size_t)words))) return rc;
+        w.ccap_mask = words;
+    }
+    return PROT_OK;
+}
+
+}  // namespace
+
+int prot_ot_solve_clustered(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, int64_t ldc,
+                            const double *nu, const double *mu, double eps, const prot_opts *o,
+                            double *plan, int64_t ldp, int32_t *y_b_lo, int32_t *y_b_nlo,
+                            int32_t *y_a_lo, int32_t *y_a_nlo, prot_ot_stats *st)
+{
+    if (!c) return PROT_E_ARG;
+    if (n_b < 1 || n_a < 1 || !C || ldc < n_a || !nu || !mu || !plan || ldp < n_a || !y_b_lo ||
+        !y_b_nlo || !y_a_lo || !y_a_nlo)
+        return fail(c, PROT_E_ARG, "prot_ot_solve_clustered: bad pointer or size");
+    if (n_b > prot::kClusterMaxPoints || n_a > prot::kClusterMaxPoints)
+        return fail(c, PROT_E_UNSUPPORTED, "prot_ot_solve_clustered: at most %lld points a side",
+                    (long long)prot::kClusterMaxPoints);
+    const double ei = eps_internal(eps, o);
+    if (!eps_valid(ei)) return fail(c, PROT_E_EPS, "eps=%g not in (0,1) or too small", eps);
+    const int64_t lds_fixed = prot::cluster_lds_fixed(n_b, n_a);
+    if (lds_fixed > prot::kClusterLdsBytes)
+        return fail(c, PROT_E_UNSUPPORTED, "prot_ot_solve_clustered: the points' state exceeds LDS");
+    prot_ot_stats local;
+    if (!st) st = &local;
+    std::memset(st, 0, sizeof(*st));
+    HIP_TRY(c, hipSetDevice(c->device));
+    const double theta = 4.0 * (double)std::max(n_b, n_a) / ei;
+    int rc = ensure_ot(c, n_b, n_a, 0, 0);
+    if (!rc) rc = ensure_clusters(c, n_b, n_a);
+    if (!rc) rc = ensure_matrix(c, n_b, n_a);
+    if (rc) return rc;
+    prot_ctx::Ot &w = c->ot;
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    HIP_TRY(c, prot::launch_ot_scale(nu, n_b, mu, n_a, theta, w.s_off, w.d_off, w.info,
+                                     c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ot, w.info, sizeof(prot::OtInfo),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const prot::OtInfo info = c->stage->ot;
+    if (info.err & 1)
+        return fail(c, PROT_E_RANGE, "nu and mu must be probability vectors (entries in [0,1], "
+                                     "sums within 1e-9 of 1)");
+    if (info.err & 2) return fail(c, PROT_E_UNSUPPORTED, "too many copies");
+    const int64_t NB = info.copies_b, NA = info.copies_a;
+    st->theta = theta;
+    st->copies_b = NB;
+    st->copies_a = NA;
+    const int64_t ldk = prot_pitch(n_a);
+    HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
+    // eq. (1) on the points' costs
+    HIP_TRY(c, prot::launch_round_costs(C, n_b, n_a, ldc, ei, c->kmat, ldk, c->ctl, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    const int64_t T = prot_threshold(ei, NB);
+    const int64_t K = (int64_t)std::floor(1.0 / ei);
+    prot::ClusterArgs A{};
+    A.k = c->kmat;
+    A.ldk = ldk;
+    A.n_b = (int32_t)n_b;
+    A.n_a = (int32_t)n_a;
+    A.s_off = w.s_off;
+    A.d_off = w.d_off;
+    A.T = T;
+    A.origin = o ? o->origin_mode : 0;
+    A.max_phases = o ? o->max_phases : 0;
+    // the potential of the copies grows by more than T in every phase
+    A.phase_bound = phase_bound_for(o, NB, NA, K, T);
+    A.G = w.cG;
+    A.Yo = w.cY;
+    A.Fo = w.cF;
+    A.Zo = w.cZ;
+    A.topo = w.ctop;
+    A.boto = w.cbot;
+    A.w = w.cw;
+    A.mask = w.cmask;
+    A.nwb = (int32_t)((n_b + 63) / 64);
+    A.list = w.clist;
+    A.PF = w.cPF;
+    A.PG = w.cPG;
+    A.trace = (long long *)c->trace;
+    A.ctl = c->ctl;
+    A.lds_bytes = prot::kClusterLdsBytes;
+    // PROT_CLUSTER_LIST_CAP: admissible-list entries kept in LDS (a test of
+    // the global overflow area)
+    if (const char *e = std::getenv("PROT_CLUSTER_LIST_CAP")) {
+        const long long cap = std::atoll(e);
+        if (cap >= 0) A.lds_bytes = std::min<int64_t>(A.lds_bytes, lds_fixed + 2 * cap);
+    }
+    HIP_TRY(c, prot::launch_cluster_init(A, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    HIP_TRY(c, prot::launch_cluster_loop(A, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    HIP_TRY(c, prot::launch_cluster_counts(A, w.cnt, c->part_k, 1, c->stream));
+    prot::OtPlanArgs pa{};
+    pa.cnt = w.cnt;
+    pa.n_b = n_b;
+    pa.n_a = n_a;
+    pa.theta = theta;
+    pa.nu = nu;
+    pa.mu = mu;
+    pa.C = C;
+    pa.ldc = ldc;
+    pa.plan = plan;
+    pa.ldp = ldp;
+    pa.rv = w.rv;
+    pa.qv = w.qv;
+    pa.R = w.R;
+    pa.Q = w.Q;
+    pa.part_k = c->part_k;
+    pa.part_c = c->part_c;
+    pa.info = w.info;
+    HIP_TRY(c, prot::launch_ot_plan_finish(pa, c->stream));
+    HIP_TRY(c, prot::launch_cluster_duals(A, y_b_lo, y_b_nlo, y_a_lo, y_a_nlo, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&c->stage->ot, w.info, sizeof(prot::OtInfo),
+                              hipMemcpyDeviceToHost, c->stream));
+    rc = collect(c, &st->loop, T, ei, 1, true);  // synchronises the stream
+    if (rc) return rc;
+    prot_opts lo{};
+    if (o) lo = *o;
+    lo.no_completion = 0;
     fill_match_counts(c, NB, &st->loop, &lo);
     st->repaired_mass = c->stage->ot.repaired;
     if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a cost is NaN or outside [0,1]");

@@ -272,7 +272,41 @@ hipError_t launch_ot_prepare(const float *C, int64_t n_b, int64_t n_a, int64_t l
                              int32_t *row_pt, int32_t *col_pt, int16_t *k, int64_t ldk,
                              unsigned long long *ymax, Ctl *ctl, hipStream_t s);
 hipError_t launch_ot_plan(const OtPlanArgs &a, hipStream_t s);
+// The plan from pair counts already in a.cnt (column, row, running totals, route).
+hipError_t launch_ot_plan_finish(const OtPlanArgs &a, hipStream_t s);
 hipError_t launch_ot_duals(const int32_t *y, const int64_t *off, int64_t n_pts, int32_t *lo,
                            int32_t *nlo, Ctl *ctl, hipStream_t s);
+
+// ot_cluster.hip: transport with the copies kept as clusters (Lemma 4.1).
+constexpr int64_t kClusterMaxPoints = 4096;   // points per side (one workgroup)
+constexpr int64_t kClusterLdsBytes = 159 * 1024;
+struct ClusterArgs {
+    const int16_t *k;              // n_b x ldk rounded costs of the points
+    int64_t ldk;
+    int32_t n_b, n_a;
+    const int64_t *s_off, *d_off;  // copy offsets (n + 1 entries each)
+    int64_t T;                     // stop once at most T supply copies are free
+    int32_t origin;                // 0: scan of b from column b mod n_a; 1: from 0
+    int64_t max_phases;            // 0: no limit (status 1 when reached)
+    int64_t phase_bound;           // watchdog (status 2 when reached; 0: none)
+    int32_t *G;                    // n_a: free demand copies
+    int32_t *Yo, *Fo;              // n_b: final Y and free copies
+    int32_t *Zo, *topo, *boto;     // n_a: final Z and copies at Z and Z - 1
+    int2 *w;                       // n_b x n_a pair counts by parity of the demand level
+    unsigned long long *mask;      // n_a x nwb: supply points with a pair
+    int32_t nwb;
+    uint16_t *list;                // n_b x n_a: admissible lists that LDS cannot hold
+    int64_t *PF, *PG;              // running totals of F and G (n_b + 1, n_a + 1)
+    long long *trace;              // kTraceCap x 4 per-phase record, or null
+    Ctl *ctl;
+    int64_t lds_bytes;             // dynamic LDS of the loop
+};
+int64_t cluster_lds_fixed(int64_t n_b, int64_t n_a);
+hipError_t launch_cluster_init(const ClusterArgs &A, hipStream_t s);
+hipError_t launch_cluster_loop(const ClusterArgs &A, hipStream_t s);
+hipError_t launch_cluster_counts(const ClusterArgs &A, int32_t *cnt, long long *part_k,
+                                 int complete, hipStream_t s);
+hipError_t launch_cluster_duals(const ClusterArgs &A, int32_t *b_lo, int32_t *b_nlo,
+                                int32_t *a_lo, int32_t *a_nlo, hipStream_t s);
 
 }  // namespace prot

@@ -382,6 +382,13 @@ hipError_t launch_ot_plan(const OtPlanArgs &a, hipStream_t s)
     hipLaunchKernelGGL(ot_fill_kernel, dim3(grid_of(a.n_b * a.n_a, 256, 4096u)), dim3(256), 0, s,
                        a.cnt, a.n_b * a.n_a, 0);
     hipLaunchKernelGGL(ot_count_kernel, dim3(kFinalizeBlocks), dim3(kPlanThreads), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_ot_plan_finish(a, s);
+}
+
+hipError_t launch_ot_plan_finish(const OtPlanArgs &a, hipStream_t s)
+{
     hipLaunchKernelGGL(ot_column_kernel, dim3(grid_of(a.n_a, kColWaves)), dim3(64 * kColWaves), 0,
                        s, a);
     hipLaunchKernelGGL(ot_row_kernel, dim3(grid_of(a.n_b, kColWaves)), dim3(64 * kColWaves), 0, s,
