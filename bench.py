@@ -281,6 +281,41 @@ def bench_transport(prot, synth, torch, reps=5):
             "repaired_mass": st["repaired_mass"]}
 
 
+CLUSTER_EPS = (0.1, 0.01)  # --cluster-eps narrows it (one workload per kernel trace)
+
+
+def bench_transport_clustered(prot, synth, torch, reps=5):
+    """Optimal transport with each point's copies kept as two dual clusters
+    (Section 4, Lemma 4.1) on the clouds of the transport leg: eps = 0.1
+    (beside the explicit copies) and eps = 0.01 (theta = 400,000 copies a
+    side, past what explicit copies allow). Whole solves, inputs in HBM."""
+    C, nu, mu = synth.transport_clouds(1000, 1000, seed=11, shift=1.0)
+    Cd, nud, mud = (torch.from_numpy(x).cuda() for x in (C, nu, mu))
+    ctx = prot.Context(0)
+    out = {}
+    for eps in CLUSTER_EPS:
+        r = ctx.ot_solve(Cd, nud, mud, eps, clustered=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = ctx.ot_solve(Cd, nud, mud, eps, plan=r.plan, clustered=True)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        st = r.stats
+        out[f"eps_{eps}"] = {
+            "workload": "optimal transport, 1000 x 1000 points U[0,1]^2 vs U[1,2]x[0,1], "
+                        f"random masses, squared-Euclidean, eps={eps} seed=11, copies as "
+                        "two dual clusters per point",
+            "ms_per_solve": round(ms, 4), "ms_prepare": round(st["ms_build"], 4),
+            "ms_loop": round(st["ms_loop_kernel"], 4), "copies_b": st["copies_b"],
+            "copies_a": st["copies_a"], "phases": st["phases"], "rounds": st["rounds"],
+            "us_per_phase": round(1e3 * st["ms_loop_kernel"] / max(1, st["phases"]), 2),
+            "scanned": st["scanned"], "cost": st["cost"],
+            "repaired_mass": st["repaired_mass"]}
+    ctx.close()
+    return out
+
+
 def bench_cost_variants(prot, synth, torch, reps=5):
     """Section 5's two workloads with their own costs: n = 10,000 uniform
     points in the unit square with the plain Euclidean cost (eps = 0.01),
@@ -418,8 +453,11 @@ def main():
                          "matrix, or recomputed in the scan")
     ap.add_argument("--only", default=None,
                     choices=["batched", "ot_loss", "uniform_costs", "large", "large_matrix",
-                             "unbalanced", "transport", "cost_variants"],
+                             "unbalanced", "transport", "transport_clustered",
+                             "cost_variants"],
                     help="run only this extra measurement and print its JSON (for profiling)")
+    ap.add_argument("--cluster-eps", type=float, default=None,
+                    help="run the clustered-transport leg at this eps only")
     ap.add_argument("--rounds-of", type=int, default=None,
                     help="with --phase-report: also list the rounds of this phase")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -439,6 +477,9 @@ def main():
     from paper_2203_03732_amd import synth
 
     torch.cuda.set_device(0)
+    if args.cluster_eps is not None:
+        global CLUSTER_EPS
+        CLUSTER_EPS = (args.cluster_eps,)
     n, d, eps = args.n, args.d, args.eps
     if args.phase_report:
         phase_report(prot, synth, torch, n, d, eps, args.seed, args.storage, args.rounds_of)
@@ -446,7 +487,8 @@ def main():
     legs = {"batched": bench_batched, "ot_loss": bench_ot_loss,
             "uniform_costs": bench_uniform_costs, "large": bench_large,
             "large_matrix": bench_large_matrix, "unbalanced": bench_unbalanced,
-            "transport": bench_transport, "cost_variants": bench_cost_variants}
+            "transport": bench_transport, "transport_clustered": bench_transport_clustered,
+            "cost_variants": bench_cost_variants}
     if args.only:
         print(json.dumps({args.only: legs[args.only](prot, synth, torch)}), flush=True)
         return

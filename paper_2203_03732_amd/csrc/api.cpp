@@ -95,10 +95,12 @@ struct prot_ctx {
         // the copies kept as clusters (prot_ot_solve_clustered)
         int64_t ccap_b = 0, ccap_a = 0, ccap_cells = 0, ccap_mask = 0;
         int2 *cw = nullptr;
-        unsigned long long *cmask = nullptr;
-        uint16_t *clist = nullptr;
+        unsigned long long *cmask = nullptr, *cmsum = nullptr;
+        uint16_t *cstage = nullptr;
         int32_t *cY = nullptr, *cF = nullptr, *cZ = nullptr, *ctop = nullptr, *cbot = nullptr,
-                *cG = nullptr;
+                *cG = nullptr, *cact = nullptr, *cneed = nullptr, *czt = nullptr,
+                *cloff = nullptr, *cllen = nullptr;
+        uint32_t *csync = nullptr;
         int64_t *cPF = nullptr, *cPG = nullptr;
     } ot;
     // 0 build start, 1 build end, 2 loop start, 3 loop end, 4 all done
@@ -952,8 +954,10 @@ int prot_ctx_destroy(prot_ctx *c)
                     (void *)c->ot.col_pt, (void *)c->ot.ymax, (void *)c->ot.cnt,
                     (void *)c->ot.mate_a, (void *)c->ot.mate_b, (void *)c->ot.y_a,
                     (void *)c->ot.y_b, (void *)c->ot.rv, (void *)c->ot.qv, (void *)c->ot.R,
-                    (void *)c->ot.Q, (void *)c->ot.info, (void *)c->ot.cw, (void *)c->ot.cmask,
-                    (void *)c->ot.clist, (void *)c->ot.cY, (void *)c->ot.cF, (void *)c->ot.cZ,
+                    (void *)c->ot.Q, (void *)c->ot.info, (void *)c->ot.cw, (void *)c->ot.cmask, (void *)c->ot.cmsum,
+                    (void *)c->ot.cstage, (void *)c->ot.cact, (void *)c->ot.cneed,
+                    (void *)c->ot.czt, (void *)c->ot.cloff, (void *)c->ot.cllen,
+                    (void *)c->ot.csync, (void *)c->ot.cY, (void *)c->ot.cF, (void *)c->ot.cZ,
                     (void *)c->ot.ctop, (void *)c->ot.cbot, (void *)c->ot.cG, (void *)c->ot.cPF,
                     (void *)c->ot.cPG})
         (void)hipFree(p);
@@ -1422,23 +1426,28 @@ int ensure_clusters(prot_ctx *c, int64_t n_b, int64_t n_a)
     int rc = PROT_OK;
     if (n_b > w.ccap_b) {
         if ((rc = dev_alloc(c, &w.cY, (size_t)n_b)) || (rc = dev_alloc(c, &w.cF, (size_t)n_b)) ||
-            (rc = dev_alloc(c, &w.cPF, (size_t)n_b + 1)))
+            (rc = dev_alloc(c, &w.cPF, (size_t)n_b + 1)) ||
+            (rc = dev_alloc(c, &w.cact, (size_t)n_b)) || (rc = dev_alloc(c, &w.cneed, (size_t)n_b)) ||
+            (rc = dev_alloc(c, &w.cloff, (size_t)n_b)) || (rc = dev_alloc(c, &w.cllen, (size_t)n_b)))
             return rc;
         w.ccap_b = n_b;
     }
     if (n_a > w.ccap_a) {
         if ((rc = dev_alloc(c, &w.cZ, (size_t)n_a)) || (rc = dev_alloc(c, &w.ctop, (size_t)n_a)) ||
             (rc = dev_alloc(c, &w.cbot, (size_t)n_a)) || (rc = dev_alloc(c, &w.cG, (size_t)n_a)) ||
+            (rc = dev_alloc(c, &w.cmsum, (size_t)n_a)) ||
+            (rc = dev_alloc(c, &w.czt, (size_t)((n_a + 7) & ~7ll))) ||
             (rc = dev_alloc(c, &w.cPG, (size_t)n_a + 1)))
             return rc;
         w.ccap_a = n_a;
     }
     if (n_b * n_a > w.ccap_cells) {
         if ((rc = dev_alloc(c, &w.cw, (size_t)(n_b * n_a))) ||
-            (rc = dev_alloc(c, &w.clist, (size_t)(n_b * n_a))))
+            (rc = dev_alloc(c, &w.cstage, (size_t)(n_b * n_a + 8))))
             return rc;
         w.ccap_cells = n_b * n_a;
     }
+    if (!w.csync && (rc = dev_alloc(c, &w.csync, (size_t)prot::kSyncWords))) return rc;
     const int64_t words = n_a * ((n_b + 63) / 64);
     if (words > w.ccap_mask) {
         if ((rc = dev_alloc(c, &w.cmask, (size_t)words))) return rc;
@@ -1518,8 +1527,16 @@ int prot_ot_solve_clustered(prot_ctx *c, const float *C, int64_t n_b, int64_t n_
     A.boto = w.cbot;
     A.w = w.cw;
     A.mask = w.cmask;
+    A.msum = w.cmsum;
     A.nwb = (int32_t)((n_b + 63) / 64);
-    A.list = w.clist;
+    A.act = w.cact;
+    A.need = w.cneed;
+    A.zt = w.czt;
+    A.stage = w.cstage;
+    A.loff = w.cloff;
+    A.llen = w.cllen;
+    A.sync = w.csync;
+    A.staged = (int32_t *)(w.csync + prot::kSyncStaged);
     A.PF = w.cPF;
     A.PG = w.cPG;
     A.trace = (long long *)c->trace;
@@ -1533,7 +1550,13 @@ int prot_ot_solve_clustered(prot_ctx *c, const float *C, int64_t n_b, int64_t n_
     }
     HIP_TRY(c, prot::launch_cluster_init(A, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-    HIP_TRY(c, prot::launch_cluster_loop(A, c->stream));
+    int grid = 1;
+    HIP_TRY(c, prot::cluster_grid(A.n_b, &grid));
+    if (const char *e = std::getenv("PROT_CLUSTER_GRID")) {
+        const int g = std::atoi(e);
+        if (g >= 1 && g < grid) grid = g;
+    }
+    HIP_TRY(c, prot::launch_cluster_loop(A, grid, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
     HIP_TRY(c, prot::launch_cluster_counts(A, w.cnt, c->part_k, 1, c->stream));
     prot::OtPlanArgs pa{};

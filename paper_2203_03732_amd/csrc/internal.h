@@ -280,6 +280,8 @@ hipError_t launch_ot_duals(const int32_t *y, const int64_t *off, int64_t n_pts, 
 // ot_cluster.hip: transport with the copies kept as clusters (Lemma 4.1).
 constexpr int64_t kClusterMaxPoints = 4096;   // points per side (one workgroup)
 constexpr int64_t kClusterLdsBytes = 159 * 1024;
+constexpr int kSyncWords = 256;              // hand-over words of the cluster loop
+constexpr int kSyncStaged = 128;             // the word counting staged list entries
 struct ClusterArgs {
     const int16_t *k;              // n_b x ldk rounded costs of the points
     int64_t ldk;
@@ -294,8 +296,15 @@ struct ClusterArgs {
     int32_t *Zo, *topo, *boto;     // n_a: final Z and copies at Z and Z - 1
     int2 *w;                       // n_b x n_a pair counts by parity of the demand level
     unsigned long long *mask;      // n_a x nwb: supply points with a pair
+    unsigned long long *msum;      // n_a: bit i set iff word i of the point's mask is nonzero
     int32_t nwb;
-    uint16_t *list;                // n_b x n_a: admissible lists that LDS cannot hold
+    // the phase's lists, built by every workgroup of the loop
+    int32_t *act, *need;           // n_b: rows with free copies, their Y - 1
+    int32_t *zt;                   // n_a rounded up to 8: top level, or a never-met level
+    uint16_t *stage;               // n_b x n_a + 8: the lists, one block per row
+    int32_t *loff, *llen;          // n_b: a row's block
+    uint32_t *sync;                // kSyncWords hand-over words
+    int32_t *staged;               // = sync + kSyncStaged: entries staged
     int64_t *PF, *PG;              // running totals of F and G (n_b + 1, n_a + 1)
     long long *trace;              // kTraceCap x 4 per-phase record, or null
     Ctl *ctl;
@@ -303,7 +312,8 @@ struct ClusterArgs {
 };
 int64_t cluster_lds_fixed(int64_t n_b, int64_t n_a);
 hipError_t launch_cluster_init(const ClusterArgs &A, hipStream_t s);
-hipError_t launch_cluster_loop(const ClusterArgs &A, hipStream_t s);
+hipError_t cluster_grid(int32_t n_b, int *grid);  // workgroups of the loop
+hipError_t launch_cluster_loop(const ClusterArgs &A, int grid, hipStream_t s);
 hipError_t launch_cluster_counts(const ClusterArgs &A, int32_t *cnt, long long *part_k,
                                  int complete, hipStream_t s);
 hipError_t launch_cluster_duals(const ClusterArgs &A, int32_t *b_lo, int32_t *b_nlo,

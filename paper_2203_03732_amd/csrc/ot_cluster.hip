@@ -33,52 +33,65 @@
 // the counts), and the plan kernels of ot.hip turn the pair counts into the
 // plan.
 //
-// Everything the phases touch lives in one workgroup: the demand points'
-// levels and capacities and the supply points' duals in LDS, each supply
-// point's round state in the registers of the thread that owns it, the
-// admissible lists in LDS while they fit (else in a global overflow area),
-// the pair counts and a bitmap of each demand point's partners in global
-// memory (read back through this workgroup's cache). With the state of a
-// point held by one thread and every step of a round separated by a
-// workgroup barrier, a round costs a few hundred nanoseconds instead of a
-// grid-wide barrier, which is what the O(n^2 / eps^2) method needs at the
-// few thousand points it is meant for.
+// Workgroup 0 of the loop holds the points' state: the demand points' levels
+// and capacities and the supply points' duals in LDS, each supply point's
+// round state in the registers of the thread that owns it, the pair counts
+// and a bitmap of each demand point's partners in global memory. With every
+// step of a round separated by a workgroup barrier, a round costs a few
+// hundred nanoseconds instead of a grid-wide barrier. Listing the admissible
+// points reads every row with free copies (n_a rounded costs each), which
+// one workgroup cannot do fast enough: it publishes the rows and the demand
+// levels, and every workgroup of the grid lists a share of the rows into a
+// global staging area, which workgroup 0 then copies into its LDS when it
+// fits. The two hand-overs per phase are a flag and an arrival counter,
+// each wait bounded.
 #include "internal.h"
 #include "device_common.h"
 
 namespace prot {
 namespace {
 
-constexpr int kCT = 1024;                            // threads of the cluster loop
-constexpr int kPer = (int)(kClusterMaxPoints / kCT);  // points per thread
-constexpr int kVisits = 2;                           // 8-column chunks per lane per step
-constexpr uint32_t kGlobalList = 0x80000000u;        // list info: the row's list is global
+constexpr int kCT = 1024;                                // threads per workgroup
+constexpr int kPerMax = (int)(kClusterMaxPoints / kCT);  // supply points per thread
+constexpr int32_t kNever = 0x40000000;                   // a level no edge reaches
+constexpr uint32_t kDone = 0xFFFFFFFFu;                  // epoch: the loop has ended
+// Bounded waits of the hand-overs: ~2 s of the 100 MHz device clock (a phase
+// takes microseconds); on time-out bit 5 of the error word is raised and
+// every workgroup leaves.
+constexpr int64_t kWaitTicks = 200000000ll;
 
-// LDS layout (32-bit words), for n_a demand and n_b supply points.
+// Hand-over words (each on its own 256-byte line of ClusterArgs::sync; the
+// entries staged in the current phase are word kSyncStaged).
+constexpr int kEpoch = 0;     // phase published by workgroup 0 (kDone at the end)
+constexpr int kArrive = 64;   // workgroups done listing, cumulative
+constexpr int kRowCount = 192;  // rows to list in the current phase
+
+// LDS of workgroup 0 (32-bit words), for n_a demand and n_b supply points;
+// the demand arrays have n_a rounded up to 8 entries. req holds, while the
+// lists are built, each demand point's top level (kNever if it has no top
+// copies), read 8 at a time; the other workgroups keep only that array.
 struct Lds {
-    int32_t *Z, *top, *bot, *cap, *req, *minb;  // n_a each
+    int32_t *Z, *top, *bot, *cap, *req, *minb, *G;  // n_a each
     int32_t *Y, *evict;                         // n_b each
-    uint32_t *linfo;                            // n_b: list base and length
-    uint16_t *act;                              // n_b: supply points with free copies
-    uint16_t *list;                             // the rest: admissible scan positions
+    uint16_t *list;                             // the rest: the phase's lists
     int64_t list_cap;
 };
 
 __device__ inline Lds lds_layout(char *base, int64_t n_b, int64_t n_a, int64_t bytes)
 {
     Lds L;
+    const int64_t na8 = (n_a + 7) & ~7ll;
     int32_t *p = reinterpret_cast<int32_t *>(base);
     L.Z = p;
-    L.top = p + n_a;
-    L.bot = p + 2 * n_a;
-    L.cap = p + 3 * n_a;
-    L.req = p + 4 * n_a;
-    L.minb = p + 5 * n_a;
-    L.Y = p + 6 * n_a;
+    L.top = p + na8;
+    L.bot = p + 2 * na8;
+    L.cap = p + 3 * na8;
+    L.req = p + 4 * na8;
+    L.minb = p + 5 * na8;
+    L.G = p + 6 * na8;
+    L.Y = p + 7 * na8;
     L.evict = L.Y + n_b;
-    L.linfo = reinterpret_cast<uint32_t *>(L.evict + n_b);
-    L.act = reinterpret_cast<uint16_t *>(L.linfo + n_b);
-    const int64_t used = (6 * n_a + 3 * n_b) * 4 + ((n_b * 2 + 15) & ~15ll);
+    const int64_t used = ((7 * na8 + 2 * n_b) * 4 + 15) & ~15ll;
     L.list = reinterpret_cast<uint16_t *>(base + used);
     L.list_cap = (bytes - used) / 2;
     return L;
@@ -90,12 +103,6 @@ __device__ inline int col_of(int b, int j, int n_a, int origin)
     if (origin != 0) return j;
     const int a = b % n_a + j;
     return a >= n_a ? a - n_a : a;
-}
-
-__device__ inline int list_at(const ClusterArgs &A, const Lds &L, int b, uint32_t info, int i)
-{
-    if (info & kGlobalList) return A.list[(int64_t)b * A.n_a + i];
-    return L.list[(info >> 13) + i];
 }
 
 // Block-wide sum (all threads call); the result is valid in every thread.
@@ -111,124 +118,234 @@ __device__ long long block_sum64(long long v, long long *red)
     return t;
 }
 
-// The admissible list of supply point b (free copies at y) in its scan
-// order, built by one wave: lane l looks at chunks (8 columns) l * kVisits
-// .. of the visit order, which starts at the chunk holding b's first
-// column, wraps around, and ends with that chunk again (its columns below
-// the start).
-__device__ void build_list(const ClusterArgs &A, Lds &L, int b, int y, int *lds_used)
+// Thread 0 waits until *word >= want (or holds kDone, for the epoch);
+// false on time-out (err bit 5 raised).
+__device__ bool wait_at_least(uint32_t *word, uint32_t want, Ctl *ctl, uint32_t *seen)
 {
-    const int lane = threadIdx.x & 63;
-    const int n_a = A.n_a;
-    const int s0 = A.origin == 0 ? b % n_a : 0;
-    const int nch = (n_a + 7) >> 3, c0 = s0 >> 3;
-    const int V = nch + 1;
-    const int need = y - 1;  // k + 1 == Z + y  <=>  k - Z == y - 1
-    const int16_t *krow = A.k + (int64_t)b * A.ldk;
-    constexpr int kMaxSteps = (int)((kClusterMaxPoints / 8 + 1 + 64 * kVisits - 1) / (64 * kVisits));
-    uint32_t bits[kMaxSteps][kVisits];
-    int excl[kMaxSteps];  // entries before this lane's chunks within each step
-    int step_base[kMaxSteps];
-    const int steps = (V + 64 * kVisits - 1) / (64 * kVisits);
-    int len = 0;
+    const int64_t t0 = (int64_t)wall_clock64();
+    for (int spins = 0;; ++spins) {
+        const uint32_t v = ld_agent(word);
+        if (v >= want) {
+            *seen = v;
+            return true;
+        }
+        if ((spins & 63) == 63 && (int64_t)wall_clock64() - t0 > kWaitTicks) {
+            __hip_atomic_fetch_or(&ctl->err, 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *seen = kDone;
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// Every store that another workgroup reads is an agent-scope store (coherent
+// across the chip's caches without a cache write-back); a wave waits for its
+// stores to complete before the workgroup barrier that precedes a flag.
+__device__ inline void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Bit e set iff k[e] - zt[e] == need (k: 8 int16 in kv, zt: 8 levels).
+__device__ inline uint32_t level_hits(uint4 kv, int4 z0, int4 z1, int need)
+{
+    const uint32_t kw[4] = {kv.x, kv.y, kv.z, kv.w};
+    const int z[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
+    uint32_t m = 0;
 #pragma unroll
-    for (int st = 0; st < kMaxSteps; ++st) {
-        excl[st] = 0;
-        step_base[st] = len;
-        if (st >= steps) continue;
-        int mine = 0;
+    for (int e = 0; e < 8; ++e) {
+        const int kk = (int)(int16_t)((kw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        m |= (uint32_t)(kk - z[e] == need) << e;
+    }
+    return m;
+}
+
+constexpr int kSegVisits = 128;  // chunk visits per row per step (2 per lane)
+
+// The admissible lists of rows [r_lo, r_hi) of the phase (row r: supply
+// point act[r], whose free copies sit at need[r] + 1), each in its scan
+// order: column a is admissible when k - Z_a = need and a has top copies
+// (zt holds Z_a, or kNever). A wave takes kRowsPerWave rows at once; in a
+// step, lane l looks at chunks (8 columns) 2l and 2l + 1 of each row's
+// visit order, which starts at the chunk holding the row's first column,
+// wraps around, and ends with that chunk again (its columns below the
+// start), so lane order is scan order. A row's entries (scan positions) go
+// to a block of the staging area taken with one atomic; its offset and
+// length to loff[b], llen[b]. Rows longer than one step (n_a > 1016) are
+// read twice: once to count, once to write.
+template <int kRowsPerWave>
+__device__ void build_lists(const ClusterArgs &A, const int32_t *zt, int r_lo, int r_hi)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n_a = A.n_a, nch = (n_a + 7) >> 3, V = nch + 1;
+    const int nseg = (V + kSegVisits - 1) / kSegVisits;
+    for (int r0 = r_lo + wave * kRowsPerWave; r0 < r_hi; r0 += (kCT / 64) * kRowsPerWave) {
+        int b[kRowsPerWave], s0[kRowsPerWave], c0[kRowsPerWave], need[kRowsPerWave];
+        int len[kRowsPerWave], off[kRowsPerWave];
 #pragma unroll
-        for (int u = 0; u < kVisits; ++u) {
-            const int v = (st * 64 + lane) * kVisits + u;
-            uint32_t m = 0;
-            if (v < V) {
-                int c = c0 + v;
-                if (c >= nch) c -= nch;
-                const int col0 = c * 8;
-                const uint4 kv = *reinterpret_cast<const uint4 *>(krow + col0);
-                const uint32_t kw[4] = {kv.x, kv.y, kv.z, kv.w};
-                const int lo = v == 0 ? s0 : 0;
-                const int hi = v == nch ? s0 : n_a;
+        for (int g = 0; g < kRowsPerWave; ++g) {
+            b[g] = r0 + g < r_hi ? ld_agent(A.act + r0 + g) : -1;
+            need[g] = b[g] >= 0 ? ld_agent(A.need + r0 + g) : 0;
+            s0[g] = (b[g] >= 0 && A.origin == 0) ? b[g] % n_a : 0;
+            c0[g] = s0[g] >> 3;
+            len[g] = 0;
+            off[g] = 0;
+        }
+        // pass 0 counts (rows of several steps), pass 1 writes; a one-step
+        // row is counted and written from the same registers
+        for (int pass = nseg == 1 ? 1 : 0; pass < 2; ++pass) {
+            int run[kRowsPerWave];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int a = col0 + e;
-                    if (a < lo || a >= hi) continue;
-                    const int kk = (int)(int16_t)((kw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                    if (L.top[a] > 0 && kk - L.Z[a] == need) m |= 1u << e;
+            for (int g = 0; g < kRowsPerWave; ++g) run[g] = 0;
+            for (int seg = 0; seg < nseg; ++seg) {
+                uint4 kv[kRowsPerWave][2];
+                int cc[kRowsPerWave][2];
+#pragma unroll
+                for (int g = 0; g < kRowsPerWave; ++g)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int v = seg * kSegVisits + lane * 2 + u;
+                        int c = c0[g] + v;
+                        if (c >= nch) c -= nch;
+                        cc[g][u] = c;
+                        kv[g][u] = make_uint4(0, 0, 0, 0);
+                        if (b[g] >= 0 && v < V)
+                            kv[g][u] = *reinterpret_cast<const uint4 *>(
+                                A.k + (int64_t)b[g] * A.ldk + c * 8);
+                    }
+                uint32_t m[kRowsPerWave][2];
+#pragma unroll
+                for (int g = 0; g < kRowsPerWave; ++g)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int v = seg * kSegVisits + lane * 2 + u;
+                        m[g][u] = 0;
+                        if (b[g] < 0 || v >= V) continue;
+                        const int c = cc[g][u];
+                        const int4 z0 = *reinterpret_cast<const int4 *>(zt + c * 8);
+                        const int4 z1 = *reinterpret_cast<const int4 *>(zt + c * 8 + 4);
+                        const int lo = v == 0 ? s0[g] : 0;
+                        const int hi = v == nch ? s0[g] : n_a;
+                        m[g][u] =
+                            level_hits(kv[g][u], z0, z1, need[g]) & range_mask(c * 8, lo, hi);
+                    }
+#pragma unroll
+                for (int g = 0; g < kRowsPerWave; ++g) {
+                    if (b[g] < 0) continue;  // the whole wave
+                    const int mine = __builtin_popcount(m[g][0]) + __builtin_popcount(m[g][1]);
+                    int incl = mine;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int t = __shfl_up(incl, o);
+                        if (lane >= o) incl += t;
+                    }
+                    const int seg_len = __shfl(incl, 63);
+                    if (pass == 0) {
+                        len[g] += seg_len;
+                        continue;
+                    }
+                    if (nseg == 1) {
+                        len[g] = seg_len;
+                        int x = 0;
+                        if (lane == 0 && seg_len > 0) x = add_agent(A.staged, seg_len);
+                        off[g] = __shfl(x, 0);
+                    }
+                    int at = off[g] + run[g] + incl - mine;
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        uint32_t mm = m[g][u];
+                        while (mm) {
+                            const int e = __builtin_ctz(mm);
+                            mm &= mm - 1u;
+                            int j = cc[g][u] * 8 + e - s0[g];  // (a - s0) mod n_a
+                            if (j < 0) j += n_a;
+                            st_agent(A.stage + at++, (uint16_t)j);
+                        }
+                    }
+                    run[g] += seg_len;
                 }
             }
-            bits[st][u] = m;
-            mine += __builtin_popcount(m);
-        }
-        // prefix of the lanes' counts within the step (lane order = visit order)
-        int incl = mine;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int t = __shfl_up(incl, off);
-            if (lane >= off) incl += t;
-        }
-        excl[st] = incl - mine;
-        len += __shfl(incl, 63);
-    }
-    int base = 0;
-    uint32_t info = kGlobalList;
-    if (lane == 0 && len > 0) {
-        const int at = atomicAdd(lds_used, len);
-        if ((int64_t)at + len <= L.list_cap) info = ((uint32_t)at << 13);
-    }
-    info = __shfl(info, 0);
-    if (!(info & kGlobalList)) base = (int)(info >> 13);
-    if (lane == 0) L.linfo[b] = len == 0 ? 0u : (info | (uint32_t)len);
-    // the scan position of column a is (a - s0) mod n_a
+            if (pass == 0) {
 #pragma unroll
-    for (int st = 0; st < kMaxSteps; ++st) {
-        if (st >= steps) break;
-        int at = step_base[st] + excl[st];
-#pragma unroll
-        for (int u = 0; u < kVisits; ++u) {
-            uint32_t m = bits[st][u];
-            if (!m) continue;
-            const int v = (st * 64 + lane) * kVisits + u;
-            int c = c0 + v;
-            if (c >= nch) c -= nch;
-            while (m) {
-                const int e = __builtin_ctz(m);
-                m &= m - 1u;
-                int j = c * 8 + e - s0;
-                if (j < 0) j += n_a;
-                if (info & kGlobalList) A.list[(int64_t)b * n_a + at] = (uint16_t)j;
-                else L.list[base + at] = (uint16_t)j;
-                ++at;
+                for (int g = 0; g < kRowsPerWave; ++g) {
+                    int x = 0;
+                    if (lane == 0 && b[g] >= 0 && len[g] > 0) x = add_agent(A.staged, len[g]);
+                    off[g] = __shfl(x, 0);
+                }
             }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int g = 0; g < kRowsPerWave; ++g)
+                if (b[g] >= 0) {
+                    st_agent(A.loff + b[g], off[g]);
+                    st_agent(A.llen + b[g], len[g]);
+                }
         }
     }
 }
 
+// Workgroups other than 0: wait for a phase, list a share of its rows,
+// arrive; until workgroup 0 ends the loop.
+template <int kRows>
+__device__ void helper_loop(const ClusterArgs &A, char *lds_raw)
+{
+    __shared__ uint32_t s_epoch;
+    __shared__ int s_rows;
+    int32_t *zt = reinterpret_cast<int32_t *>(lds_raw);
+    const int na8 = (A.n_a + 7) & ~7;
+    const int P = gridDim.x, w = blockIdx.x;
+    for (uint32_t ph = 1;; ++ph) {
+        if (threadIdx.x == 0) {
+            uint32_t e;
+            wait_at_least(A.sync + kEpoch, ph, A.ctl, &e);
+            s_epoch = e;
+            s_rows = ld_agent((int *)(A.sync + kRowCount));
+        }
+        __syncthreads();
+        if (s_epoch == kDone) return;
+        for (int a = threadIdx.x; a < na8; a += kCT) zt[a] = ld_agent(A.zt + a);
+        const int n = s_rows;
+        __syncthreads();
+        build_lists<kRows>(A, zt, (int)((int64_t)n * w / P), (int)((int64_t)n * (w + 1) / P));
+        stores_done();
+        __syncthreads();
+        if (threadIdx.x == 0) add_agent(A.sync + kArrive, 1u);
+    }
+}
+
+// kPer supply points per thread (b = tid + s * kCT), kRows rows listed at
+// once by a wave: (2, 2) up to 2048 supply points, (4, 1) up to 4096 (more
+// registers per thread leave room for fewer rows in flight).
+template <int kPer, int kRows>
 __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
 {
     extern __shared__ __align__(16) char lds_raw[];
+    if (blockIdx.x != 0) {
+        helper_loop<kRows>(A, lds_raw);
+        return;
+    }
     __shared__ long long red[kCT / 64];
-    __shared__ int n_act, lds_used;
+    __shared__ int n_act, lds_lists, s_abort;
     __shared__ unsigned long long ph_scanned, ph_matched;
     Lds L = lds_layout(lds_raw, A.n_b, A.n_a, A.lds_bytes);
     const int tid = threadIdx.x;
     const int n_b = A.n_b, n_a = A.n_a;
+    const uint32_t P = gridDim.x;
 
     // the state: cold start (every copy free, y(b) = 1, y(a) = 0)
-    for (int a = tid; a < n_a; a += kCT) {
-        const int32_t d = (int32_t)(A.d_off[a + 1] - A.d_off[a]);
+    const int na8 = (n_a + 7) & ~7;
+    for (int a = tid; a < na8; a += kCT) {
+        const int32_t d = a < n_a ? (int32_t)(A.d_off[a + 1] - A.d_off[a]) : 0;
         L.Z[a] = 0;
         L.top[a] = d;
         L.bot[a] = 0;
         L.minb[a] = 0x7FFFFFFF;
-        L.req[a] = 0;
-        A.G[a] = d;
+        L.G[a] = d;
     }
     for (int b = tid; b < n_b; b += kCT) {
         L.Y[b] = 1;
         L.evict[b] = 0;
     }
-    int32_t F[kPer], want[kPer], pos[kPer], li[kPer], tgt[kPer], jp[kPer];
-    uint32_t info[kPer];
+    if (tid == 0) s_abort = 0;
+    int32_t F[kPer], want[kPer], pos[kPer], li[kPer], tgt[kPer], jp[kPer], loff[kPer],
+        llen[kPer];
     bool act[kPer], prop[kPer], contest[kPer];
 #pragma unroll
     for (int s = 0; s < kPer; ++s) {
@@ -255,10 +372,9 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
         phases += 1;
         sum_free += n_free;
 
-        // Step (I): the admissible lists of the points with free copies
+        // Step (I): publish the rows with free copies and the demand levels
         if (tid == 0) {
             n_act = 0;
-            lds_used = 0;
             ph_scanned = 0;
             ph_matched = 0;
         }
@@ -266,14 +382,49 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
 #pragma unroll
         for (int s = 0; s < kPer; ++s) {
             const int b = tid + s * kCT;
-            if (b < n_b && F[s] > 0) L.act[atomicAdd(&n_act, 1)] = (uint16_t)b;
+            if (b < n_b && F[s] > 0) {
+                const int r = atomicAdd(&n_act, 1);
+                st_agent(A.act + r, b);
+                st_agent(A.need + r, L.Y[b] - 1);
+            }
+        }
+        for (int a = tid; a < na8; a += kCT) {
+            const int32_t z = L.top[a] > 0 ? L.Z[a] : kNever;
+            L.req[a] = z;
+            st_agent(A.zt + a, z);
+        }
+        stores_done();
+        __syncthreads();
+        if (tid == 0) {
+            st_agent(A.staged, 0);
+            st_agent((int *)(A.sync + kRowCount), n_act);
+            stores_done();
+            st_agent(A.sync + kEpoch, (uint32_t)phases);
+        }
+        // ... list this workgroup's share, wait for the others ...
+        build_lists<kRows>(A, L.req, 0, (int)((int64_t)n_act / P));
+        stores_done();
+        __syncthreads();
+        if (tid == 0) {
+            add_agent(A.sync + kArrive, 1u);
+            uint32_t seen;
+            if (!wait_at_least(A.sync + kArrive, P * (uint32_t)phases, A.ctl, &seen))
+                s_abort = 1;
+            const int staged = ld_agent(A.staged);
+            lds_lists = (int64_t)((staged + 7) & ~7) <= L.list_cap;
         }
         __syncthreads();
-        for (int r = tid >> 6; r < n_act; r += kCT / 64) {
-            const int b = L.act[r];
-            build_list(A, L, b, L.Y[b], &lds_used);
+        if (s_abort) {
+            status = 3;
+            break;
         }
-        __syncthreads();
+        // ... and take the staged lists into LDS when they fit
+        if (lds_lists) {
+            const int staged = ld_agent(A.staged);
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(A.stage);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(L.list);
+            for (int i = tid; i < (staged + 1) / 2; i += kCT) dst[i] = ld_agent(src + i);
+        }
 #pragma unroll
         for (int s = 0; s < kPer; ++s) {
             const int b = tid + s * kCT;
@@ -281,10 +432,15 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
             pos[s] = 0;
             li[s] = 0;
             act[s] = b < n_b && F[s] > 0;
-            info[s] = act[s] ? L.linfo[b] : 0u;
+            loff[s] = act[s] ? ld_agent(A.loff + b) : 0;
+            llen[s] = act[s] ? ld_agent(A.llen + b) : 0;
         }
-        for (int a = tid; a < n_a; a += kCT) L.cap[a] = L.top[a];
+        for (int a = tid; a < na8; a += kCT) {
+            L.cap[a] = L.top[a];
+            L.req[a] = 0;
+        }
         __syncthreads();
+        const bool in_lds = lds_lists;
 
         long long ph_rounds = 0;
         for (;;) {
@@ -296,15 +452,14 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
                 prop[s] = false;
                 if (!act[s]) continue;
                 const int b = tid + s * kCT;
-                const int len = (int)(info[s] & 0x1FFFu);
                 int i = li[s], a = -1, j = -1;
-                for (; i < len; ++i) {
-                    j = list_at(A, L, b, info[s], i);
+                for (; i < llen[s]; ++i) {
+                    j = in_lds ? L.list[loff[s] + i] : ld_agent(A.stage + loff[s] + i);
                     a = col_of(b, j, n_a, A.origin);
                     if (L.cap[a] > 0) break;
                 }
                 li[s] = i;
-                if (i >= len) {
+                if (i >= llen[s]) {
                     my_scan += n_a - pos[s];
                     act[s] = false;
                     continue;
@@ -375,9 +530,9 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
                 const int32_t g = grant[s];
                 if (g > 0) {
                     int2 *cell = A.w + (int64_t)b * n_a + a;
-                    if (((L.Z[a] - 1) & 1) == 0) cell->x += g;
-                    else cell->y += g;
+                    atomicAdd(((L.Z[a] - 1) & 1) == 0 ? &cell->x : &cell->y, g);
                     atomicOr(A.mask + (int64_t)a * A.nwb + (b >> 6), 1ull << (b & 63));
+                    atomicOr(A.msum + a, 1ull << (b >> 6));
                     my_match += g;
                 }
                 want[s] -= g;
@@ -399,14 +554,18 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
             const int32_t z = L.Z[a];
             int32_t rem = taken;
             if (z == 0) {
-                const int32_t g = A.G[a];
+                const int32_t g = L.G[a];
                 const int32_t u = rem < g ? rem : g;
-                A.G[a] = g - u;
+                L.G[a] = g - u;
                 rem -= u;
             }
             const int p = z & 1;
             unsigned long long *mrow = A.mask + (int64_t)a * A.nwb;
-            for (int wd = 0; wd < A.nwb && rem > 0; ++wd) {
+            const unsigned long long sum0 = A.msum[a];
+            unsigned long long words = sum0, sum = sum0;
+            while (words && rem > 0) {
+                const int wd = __builtin_ctzll(words);
+                words &= words - 1ull;
                 unsigned long long bits = mrow[wd], keep = bits;
                 while (bits && rem > 0) {
                     const int b = wd * 64 + __builtin_ctzll(bits);
@@ -422,8 +581,12 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
                     atomicAdd(&L.evict[b], e);
                     if (v.x == 0 && v.y == 0) keep &= ~(1ull << (b & 63));
                 }
-                if (keep != mrow[wd]) mrow[wd] = keep;
+                if (keep != mrow[wd]) {
+                    mrow[wd] = keep;
+                    if (!keep) sum &= ~(1ull << wd);
+                }
             }
+            if (sum != sum0) A.msum[a] = sum;
             // step (III a)
             if (L.cap[a] == 0) {
                 L.Z[a] = z - 1;
@@ -456,9 +619,12 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
         }
         __syncthreads();
     }
+    // the other workgroups leave
+    if (tid == 0) st_agent(A.sync + kEpoch, kDone);
 
     // the state the later kernels read
     for (int a = tid; a < n_a; a += kCT) {
+        A.G[a] = L.G[a];
         A.Zo[a] = L.Z[a];
         A.topo[a] = L.top[a];
         A.boto[a] = L.bot[a];
@@ -478,7 +644,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
         c->rounds = rounds;
         c->max_rounds = max_rounds;
         c->scanned = (unsigned long long)scanned;
-        c->status = status;
+        c->status = status == 3 ? 1 : status;  // an aborted loop is not complete
         c->free_after = n_free;
     }
 }
@@ -648,7 +814,8 @@ __global__ void cluster_zero_kernel(unsigned long long *p, int64_t n)
 
 int64_t cluster_lds_fixed(int64_t n_b, int64_t n_a)
 {
-    return (6 * n_a + 3 * n_b) * 4 + ((n_b * 2 + 15) & ~15ll);
+    const int64_t na8 = (n_a + 7) & ~7ll;
+    return ((7 * na8 + 2 * n_b) * 4 + 15) & ~15ll;
 }
 
 hipError_t launch_cluster_init(const ClusterArgs &A, hipStream_t s)
@@ -658,21 +825,51 @@ hipError_t launch_cluster_init(const ClusterArgs &A, hipStream_t s)
                        reinterpret_cast<unsigned long long *>(A.w), (int64_t)A.n_b * A.n_a);
     hipLaunchKernelGGL(cluster_zero_kernel, dim3(256), dim3(256), 0, s, A.mask,
                        (int64_t)A.n_a * A.nwb);
+    hipLaunchKernelGGL(cluster_zero_kernel, dim3(16), dim3(256), 0, s, A.msum, (int64_t)A.n_a);
+    hipLaunchKernelGGL(cluster_zero_kernel, dim3(1), dim3(128), 0, s,
+                       reinterpret_cast<unsigned long long *>(A.sync), (int64_t)kSyncWords / 2);
     static bool attr_set = false;
     if (!attr_set) {
-        const hipError_t e = hipFuncSetAttribute((const void *)cluster_loop_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)kClusterLdsBytes);
-        if (e != hipSuccess) return e;
+        for (const void *fn : {(const void *)cluster_loop_kernel<2, 2>,
+                               (const void *)cluster_loop_kernel<kPerMax, 1>}) {
+            const hipError_t e = hipFuncSetAttribute(
+                fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kClusterLdsBytes);
+            if (e != hipSuccess) return e;
+        }
         attr_set = true;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_cluster_loop(const ClusterArgs &A, hipStream_t s)
+const void *cluster_loop_fn(int32_t n_b)
 {
-    hipLaunchKernelGGL(cluster_loop_kernel, dim3(1), dim3(kCT), (size_t)A.lds_bytes, s, A);
-    return hipGetLastError();
+    return n_b <= 2 * kCT ? (const void *)cluster_loop_kernel<2, 2>
+                          : (const void *)cluster_loop_kernel<kPerMax, 1>;
+}
+
+hipError_t cluster_grid(int32_t n_b, int *grid)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cluster_loop_fn(n_b), kCT,
+                                                                (size_t)kClusterLdsBytes);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    // about one batch of rows (16 waves x 2 rows) per workgroup when every
+    // supply point has free copies
+    int want = (n_b + 31) / 32;
+    const int most = per_cu * cus;
+    *grid = want < 1 ? 1 : (want > most ? most : want);
+    return hipSuccess;
+}
+
+hipError_t launch_cluster_loop(const ClusterArgs &A, int grid, hipStream_t s)
+{
+    ClusterArgs copy = A;
+    void *args[] = {&copy};
+    return hipLaunchCooperativeKernel(cluster_loop_fn(A.n_b), dim3(grid), dim3(kCT), args,
+                                      (unsigned)A.lds_bytes, s);
 }
 
 hipError_t launch_cluster_counts(const ClusterArgs &A, int32_t *cnt, long long *part_k, int complete,
