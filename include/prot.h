@@ -234,10 +234,14 @@ int prot_solve_points(prot_ctx *ctx, const float *X, const float *Y,
  * n_a - n_b columns left unmatched). n_a < n_b returns PROT_E_ARG (transpose
  * the input). n_b = 0 with n_a > 0 writes the cold-start column state
  * (mate_a = -1, y_a = 0; untouched when warm). The square calls are these
- * with n_b = n_a = n. Limits of the phase loop (every solve call): the
- * column duals of all n_a columns sit in one workgroup's LDS (n_a up to
- * about 81,000 on MI355X) and a row index travels in 17 bits
- * (n_b <= 131,071); beyond either the call returns PROT_E_UNSUPPORTED. */
+ * with n_b = n_a = n. Sizes of the phase loop (every solve call): each
+ * workgroup keeps the duals of all n_a columns in its LDS up to about 81,000
+ * columns on MI355X, and in global memory beyond (2 * n_a bytes per
+ * workgroup of the loop, allocated by the context); a row index travels in 17
+ * bits up to n_b = 131,071 and in 18 bits up to 262,143, where the row duals
+ * must stay below 16,384 (eps >= 1/16381 for point sets; a given matrix
+ * whose duals outgrow that stops with PROT_E_STATE). Larger n_b returns
+ * PROT_E_UNSUPPORTED. */
 int prot_round_costs_rect(prot_ctx *ctx, const float *C, int64_t n_b, int64_t n_a,
                           int64_t ldc, double eps, int16_t *k, int64_t ldk);
 int prot_build_costs_rect(prot_ctx *ctx, const float *X, int64_t n_b, const float *Y,

@@ -82,7 +82,12 @@ struct prot_ctx {
     int cooperative = 0;             // PROT_LOOP_COOPERATIVE=1: cooperative launch of the loop
     int64_t barrier_ticks = 0;       // PROT_LOOP_BARRIER_TICKS: bounded barrier wait (0: default)
     int grid_npad = -1;
+    int grid_tg = -1;
     int grid_max = 0;
+    int t_global = 0;                // PROT_LOOP_T_GLOBAL=1: column duals in global memory always
+    int wide_rows = 0;               // PROT_LOOP_WIDE_ROWS=1: 18-bit rows at every size
+    uint16_t *tpriv = nullptr;       // per-workgroup column duals beyond LDS
+    int64_t tpriv_cap = 0;
     // optimal transport through copies (prot_ot_solve)
     struct Ot {
         int64_t cap_b = 0, cap_a = 0, cap_cb = 0, cap_ca = 0, cap_cells = 0;
@@ -245,32 +250,39 @@ bool auto_on_the_fly(int32_t d, int64_t n_b, int64_t n_a)
     return (d == 2 || d == 3) && 2 * n_b * prot_pitch(n_a) > ((int64_t)256 << 20);
 }
 
-// rows n (slots), columns n_a (LDS duals)
-int grid_for(prot_ctx *c, int64_t n, int64_t n_a, int *grid)
+// rows n (slots), columns n_a. The column duals live in LDS, 2 bytes per
+// column (plus ~1 KB of state), while they fit; beyond that (or with
+// PROT_LOOP_T_GLOBAL=1) each workgroup keeps its copy in global memory and
+// *t_global is set.
+int grid_for(prot_ctx *c, int64_t n, int64_t n_a, int *grid, bool *t_global = nullptr)
 {
     const int n_pad = (int)round_up(n_a, 8);
-    if (c->grid_npad != n_pad) {
-        int lds_max = 0;
-        HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                                         c->device));
-        // the column duals live in LDS, 2 bytes per column (plus ~1 KB of state)
-        if ((int64_t)n_pad * 2 + 2048 > lds_max)
-            return fail(c, PROT_E_UNSUPPORTED,
-                        "%lld columns: the column duals (2 bytes each) exceed the %d bytes of LDS",
-                        (long long)n_a, lds_max);
+    int lds_max = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                     c->device));
+    const bool tg = (t_global && (c->t_global || c->wide_rows)) ||
+                    (int64_t)n_pad * 2 + 2048 > lds_max;
+    if (tg && !t_global)
+        return fail(c, PROT_E_UNSUPPORTED,
+                    "%lld columns: the column duals (2 bytes each) exceed the %d bytes of LDS",
+                    (long long)n_a, lds_max);
+    if (t_global) *t_global = tg;
+    if (c->grid_npad != n_pad || c->grid_tg != (int)tg) {
         int gm = 0;
-        hipError_t e = prot::loop_grid(n_pad, c->wgs_per_cu, &gm);
+        hipError_t e = tg ? prot::loop_grid_tg(c->wgs_per_cu, &gm)
+                          : prot::loop_grid(n_pad, c->wgs_per_cu, &gm);
         if (e != hipSuccess) return hip_fail(c, e, "occupancy query");
         if (gm <= 0)
             return fail(c, PROT_E_UNSUPPORTED, "%lld columns: the column duals do not fit in LDS",
                         (long long)n_a);
         c->grid_npad = n_pad;
+        c->grid_tg = (int)tg;
         c->grid_max = gm;
     }
     const int wpg = prot::kLoopThreads / 64;
-    // keys and free lists hold a row in 17 bits
-    if (n > 131071)
-        return fail(c, PROT_E_UNSUPPORTED, "%lld rows: at most 131,071", (long long)n);
+    // keys and free lists hold a row in 17 bits, or 18 with duals up to 16,383
+    if (n > 262143)
+        return fail(c, PROT_E_UNSUPPORTED, "%lld rows: at most 262,143", (long long)n);
     // every wave serves at most 64 rows of B' (one per lane)
     const int64_t min_grid = (n + 64 * wpg - 1) / (64 * wpg);
     if (min_grid > c->grid_max)
@@ -448,8 +460,27 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
     int rc = ensure_loop(c, n_a);
     if (rc) return rc;
     int grid = 0;
-    if ((rc = grid_for(c, n, n_a, &grid))) return rc;
+    bool tg = false;
+    if ((rc = grid_for(c, n, n_a, &grid, &tg))) return rc;
+    // more than 131,071 rows travel in 18 bits, their duals in 14 (a matrix
+    // given as rounded costs has no known K: a dual that outgrows 14 bits
+    // then stops the loop with PROT_E_STATE)
+    const bool wide = n > 131071 || c->wide_rows;  // n_a >= n: then tg holds too
+    if (wide && K + 2 > 0x3FFF && K < kKMaxAccepted)
+        return fail(c, PROT_E_UNSUPPORTED,
+                    "%lld rows: above 131,071 rows the duals must stay below 16,384 "
+                    "(largest rounded cost %lld; eps >= 1/16381)",
+                    (long long)n, (long long)K);
+    if (tg) {
+        const int64_t need = (int64_t)grid * round_up(n_a, 8);
+        if (need > c->tpriv_cap) {
+            if ((rc = dev_alloc(c, &c->tpriv, (size_t)need))) return rc;
+            c->tpriv_cap = need;
+        }
+    }
     prot::LoopArgs a = loop_args(c, k, n, n_a, ldk, T, o, y_b, K);
+    a.wide = wide ? 1 : 0;
+    a.tpriv = tg ? c->tpriv : nullptr;
     a.groups = std::min(c->loop_groups, grid);
     a.gated = (c->cooperative || cooperative) ? 0 : 1;
     a.gate_cap = c->gate_cap;
@@ -469,8 +500,8 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
         // the given state, O(n); on request (I2), O(n_b n_a).
         HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream));
         HIP_TRY(c, prot::launch_check_state(n, n_a, mate_a, mate_b, y_a, y_b,
-                                            (int32_t)std::min<int64_t>(K + 2, 0x7FFF), c->ctl,
-                                            c->stream));
+                                            (int32_t)std::min<int64_t>(K + 2, wide ? 0x3FFF : 0x7FFF),
+                                            c->ctl, c->stream));
         const bool i2 = o && o->check_warm && k && !k8 && !otf.d;
         if (i2)
             HIP_TRY(c, prot::launch_check_feasible(k, ldk, n, n_a, mate_b, y_a, y_b, c->ctl,
@@ -917,6 +948,9 @@ int prot_ctx_create(prot_ctx **out, int device, void *hip_stream)
         if (w >= 1 && w <= 8) c->wgs_per_cu = w;
     }
     if (const char *v = std::getenv("PROT_LOOP_MAX_GRID")) c->max_grid = std::atoi(v);
+    if (const char *v = std::getenv("PROT_LOOP_T_GLOBAL")) c->t_global = std::atoi(v) == 1;
+    // 18-bit rows at every size (with the column duals in global memory)
+    if (const char *v = std::getenv("PROT_LOOP_WIDE_ROWS")) c->wide_rows = std::atoi(v) == 1;
     if (!rc) {
         const char *v = std::getenv("PROT_DEBUG_ROUND_TIMES");
         if (v && v[0] == '1') rc = dev_alloc(c, &c->rtime, (size_t)3 * prot::kRoundTimeCap);
@@ -945,6 +979,7 @@ int prot_ctx_destroy(prot_ctx *c)
     (void)hipFree(c->rep);
     (void)hipFree(c->trace);
     (void)hipFree(c->kmat);
+    (void)hipFree(c->tpriv);
     (void)hipFree(c->th);
     (void)hipFree(c->rtime);
     (void)hipFree(c->mfma_buf);
@@ -1351,7 +1386,15 @@ int prot_ot_solve(prot_ctx *c, const float *C, int64_t n_b, int64_t n_a, int64_t
     st->copies_b = NB;
     st->copies_a = NA;
     int grid = 0;
-    if ((rc = grid_for(c, NB, NA, &grid))) return rc;
+    bool tg = false;
+    if ((rc = grid_for(c, NB, NA, &grid, &tg))) return rc;
+    // the copies' columns beyond LDS: prot_ot_solve_clustered is the way
+    // (the global column duals serve this path only when forced, as a test)
+    if (tg && !c->t_global)
+        return fail(c, PROT_E_UNSUPPORTED,
+                    "%lld demand copies: their column duals exceed LDS; the clustered "
+                    "transport (prot_ot_solve_clustered) has no such limit",
+                    (long long)NA);
     if ((rc = ensure_ot(c, n_b, n_a, NB, NA))) return rc;
     if ((rc = ensure_matrix(c, n_b, NA))) return rc;
     const int64_t ldk = prot_pitch(NA);

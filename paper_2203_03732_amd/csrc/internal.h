@@ -67,7 +67,7 @@ struct LoopArgs {
     int32_t n;              // rows |B|
     int32_t n_pad;          // n_a rounded up to 8 (LDS dual array length)
     int32_t n_a;            // columns |A| >= |B| (Section 3.3; = n when balanced)
-    int32_t pad4;
+    int32_t wide;           // 1: rows travel in 18 bits (n > 131,071; duals <= 16,383)
     int64_t T;
     int32_t origin;         // 0: diagonal, 1: zero
     int32_t pad;
@@ -113,6 +113,9 @@ struct LoopArgs {
     // (Ctl::gate); 0: a cooperative launch. gate_cap > 0 closes the gate at
     // that many workgroups (a test of the partial case).
     int32_t gated, gate_cap;
+    // Column duals in global memory (null: in LDS): each workgroup keeps its
+    // copy of t in tpriv + blockIdx.x * n_pad, for columns beyond LDS.
+    uint16_t *tpriv;
 };
 constexpr uint32_t kGateClosed = 0x80000000u;
 
@@ -213,6 +216,7 @@ hipError_t launch_check_feasible(const int16_t *k, int64_t ldk, int64_t n, int64
                                  const int32_t *mate_b, const int32_t *y_a, const int32_t *y_b,
                                  Ctl *ctl, hipStream_t s);
 hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max);
+hipError_t loop_grid_tg(int wgs_per_cu, int *grid_max);  // column duals in global memory
 hipError_t launch_clear_times(int64_t *rtime, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s);

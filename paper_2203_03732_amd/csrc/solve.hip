@@ -64,8 +64,7 @@ constexpr int kSpinLimit = 1 << 22;            // bounded waits for list entries
 // word is raised and every workgroup leaves the loop (each one's wait is
 // bounded, so the grid drains).
 constexpr int64_t kBarrierTicks = 1000000000ll;
-constexpr int32_t kDualMax = 0x7FFF;           // |y| fits the 15-bit fields of keys and lists
-constexpr uint32_t kRoundLimit = 0xFFFFFF00u;  // round ids must fit the key's 32 bits
+constexpr int32_t kDualMax = 0x7FFF;           // t (-y(a)) fits its 15-bit field
 constexpr int kGateSpin = 256;                 // gate polls (~0.3 ms) before it closes early
 
 // Waits until this wave's earlier stores and atomics have completed.
@@ -96,14 +95,15 @@ __device__ inline uint32_t take_raw_from(const unsigned long long *p, unsigned l
 }
 
 // y(b) + 1 for a row that found no column (step (III)), unless that leaves
-// the 15-bit field the dual travels in: then bit 6 of the error word is
-// raised, the dual stays and -1 is returned: the row is left out of the next
-// free list, so the loop ends soon and the host reports the error (Lemma 3.2
-// keeps |y| <= K + 2 <= 32767 in every state the method reaches, so only an
-// inconsistent warm start gets here).
-__device__ inline int32_t grown_dual(int32_t yb, int32_t *err)
+// the field the dual travels in (dual_max, see RowPack): then bit 6 of the
+// error word is raised, the dual stays and -1 is returned: the row is left
+// out of the next free list, so the loop ends soon and the host reports the
+// error (Lemma 3.2 keeps |y| <= K + 2 in every state the method reaches, and
+// the host admits only K + 2 <= dual_max, so only an inconsistent warm start
+// gets here).
+__device__ inline int32_t grown_dual(int32_t yb, int32_t dual_max, int32_t *err)
 {
-    if (yb < kDualMax) return yb + 1;
+    if (yb < dual_max) return yb + 1;
     __hip_atomic_fetch_or(err, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return -1;
 }
@@ -185,28 +185,42 @@ __device__ inline unsigned long long tagged(uint32_t tag, int32_t v)
     return ((unsigned long long)tag << 32) | (uint32_t)v;
 }
 
-// A row and its dual travel together (rows < 2^17; |y| <= K + 2 <= 32767 as
-// eps allows, Lemma 3.2): a column's key is (round << 32) | (kRowMask - b)
-// << 15 | y(b), so the larger key wins a round and within a round the
-// smaller b; the free lists hold y(b) << 17 | b. A row that enters a phase,
-// or is evicted, thus brings its dual with it and nobody loads y(b).
-constexpr uint32_t kRowMask = (1u << 17) - 1u;
+// A row and its dual travel together (|y| <= K + 2, Lemma 3.2): a column's
+// key is (round << (15 + rb)) | (mask - b) << 15 | y(b), so the larger key
+// wins a round and within a round the smaller b; the free lists hold
+// y(b) << rb | b. A row that enters a phase, or is evicted, thus brings its
+// dual with it and nobody loads y(b). rb = 17 row bits (up to 131,071 rows;
+// duals up to 32,767; round ids below 2^32) or 18 (up to 262,143 rows;
+// duals up to 16,383; round ids below 2^31).
+struct RowPack {
+    uint32_t rb, mask;
+    int32_t dual_max;
+    uint32_t round_limit;
+};
+__device__ inline RowPack row_pack(int32_t wide)
+{
+    return wide ? RowPack{18u, (1u << 18) - 1u, 0x3FFF, 0x7FFFFF00u}
+                : RowPack{17u, (1u << 17) - 1u, 0x7FFF, 0xFFFFFF00u};
+}
 constexpr uint32_t kNoRow = 0xFFFFFFFFu;
 
-__device__ inline unsigned long long make_key(uint32_t r, int32_t b, int32_t y)
+__device__ inline unsigned long long make_key(uint32_t r, int32_t b, int32_t y, const RowPack &P)
 {
-    return ((unsigned long long)r << 32) | ((unsigned long long)(kRowMask - (uint32_t)b) << 15) |
-           ((uint32_t)y & 0x7FFFu);
+    return ((unsigned long long)r << (15 + P.rb)) |
+           ((unsigned long long)(P.mask - (uint32_t)b) << 15) | ((uint32_t)y & 0x7FFFu);
 }
-__device__ inline int32_t key_row(unsigned long long k)
+__device__ inline int32_t key_row(unsigned long long k, const RowPack &P)
 {
-    return (int32_t)(kRowMask - (((uint32_t)k >> 15) & kRowMask));
+    return (int32_t)(P.mask - ((uint32_t)(k >> 15) & P.mask));
 }
-__device__ inline uint32_t key_free(unsigned long long k)
+__device__ inline uint32_t key_free(unsigned long long k, const RowPack &P)
 {
-    return (((uint32_t)k & 0x7FFFu) << 17) | (uint32_t)key_row(k);
+    return (((uint32_t)k & 0x7FFFu) << P.rb) | (uint32_t)key_row(k, P);
 }
-__device__ inline uint32_t free_val(int32_t b, int32_t y) { return ((uint32_t)y << 17) | (uint32_t)b; }
+__device__ inline uint32_t free_val(int32_t b, int32_t y, const RowPack &P)
+{
+    return ((uint32_t)y << P.rb) | (uint32_t)b;
+}
 
 // First admissible, unmarked column of this chunk (wave-wide, lowest column
 // first); -1 if none.
@@ -534,6 +548,7 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
     const int n = a.n, na = a.n_a;  // rows, columns
     const int lane = threadIdx.x & 63;
     const uint32_t tag0 = a.ctl->tag_last + 1u;
+    const RowPack P = row_pack(a.wide);
     const int top = a.n_pad > n ? a.n_pad : n;
     for (int base = blockIdx.x * blockDim.x; base < top; base += gridDim.x * blockDim.x) {
         const int i = base + threadIdx.x;
@@ -544,7 +559,7 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
                 a.t[i] = 0;
             } else {
                 const int32_t m = mate_a[i];
-                a.key[i] = m >= 0 ? make_key(0u, m, a.y_b[m]) : 0ull;
+                a.key[i] = m >= 0 ? make_key(0u, m, a.y_b[m], P) : 0ull;
                 a.t[i] = (uint16_t)(-y_a[i]);
             }
         } else if (i < a.n_pad) {
@@ -554,7 +569,7 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
             if (a.skip) a.skip[i] = 0u;
             if (!warm) {
                 a.y_b[i] = 1;
-                a.F[0][i] = tagged(tag0, (int32_t)free_val(i, 1));
+                a.F[0][i] = tagged(tag0, (int32_t)free_val(i, 1, P));
                 mate_b[i] = -1;
             } else {
                 is_free = mate_b[i] < 0;
@@ -567,7 +582,8 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
                 if (lane == 0) at = add_agent(&a.ctl->free0, (uint32_t)__popcll(bal));
                 at = __builtin_amdgcn_readfirstlane(at);
                 if (is_free)
-                    a.F[0][at + lanes_below(bal)] = tagged(tag0, (int32_t)free_val(i, a.y_b[i]));
+                    a.F[0][at + lanes_below(bal)] =
+                        tagged(tag0, (int32_t)free_val(i, a.y_b[i], P));
             }
         }
     }
@@ -649,7 +665,9 @@ struct SrcOf<1> {
 // kSrcD: 0 reads the rounded-cost matrix (1: stored as bytes); 2 or 3 computes it from points of
 // that dimension (matrix-free). kFF: exact fast-forward through A.skip.
 // kCopies: the rows are copies of the transport reduction (A.rmap, A.ymax).
-template <bool kMulti, int kSrcD, bool kFF, bool kCopies = false>
+// kTG: the workgroup's copy of the column duals is its slice of A.tpriv in
+// global memory (only this workgroup touches it) instead of LDS.
+template <bool kMulti, int kSrcD, bool kFF, bool kCopies = false, bool kTG = false>
 __global__ void __launch_bounds__(kLoopThreads)
 phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32_t *y_base)
 {
@@ -660,6 +678,9 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     const LoopArgs &A = kMulti ? arr[blockIdx.x / team] : A0;
     int32_t *const y_b = kMulti ? y_base + A.y_off : A.y_b;
     const typename SrcOf<kSrcD>::type src = SrcOf<kSrcD>::make(A);
+    // rows beyond 17 bits come with columns beyond LDS (n_a >= n), so the
+    // LDS instantiations keep the 17-bit packing as constants
+    const RowPack P = row_pack(kTG ? A.wide : 0);
     // workgroups of this instance, and this workgroup's rank among them
     uint32_t nwg = kMulti ? (uint32_t)team : gridDim.x;
     uint32_t wg = kMulti ? blockIdx.x % (uint32_t)team : blockIdx.x;
@@ -710,7 +731,8 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             return;
         }
     }
-    extern __shared__ __align__(16) uint16_t t_lds[];
+    extern __shared__ __align__(16) uint16_t t_smem[];
+    uint16_t *const t_lds = kTG ? A.tpriv + (int64_t)blockIdx.x * A.n_pad : t_smem;
     __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose;
     __shared__ uint32_t s_base_l, s_base_f, s_ltot, s_over, s_abort;
     __shared__ unsigned long long s_scan, s_pend_scan;
@@ -802,7 +824,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             if (leader) ctl->status = 2;
             break;
         }
-        if (r >= kRoundLimit) {
+        if (r >= P.round_limit) {
             if (leader) __hip_atomic_fetch_or(&ctl->err, 8, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
@@ -856,8 +878,8 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         __syncthreads();  // t of those columns and the team scratch are set
         if ((uint32_t)lane < nslots) {
             const uint32_t fv = take_raw_from(f_at, f_val, tag0 + (uint32_t)p, &ctl->err);
-            s_b = min((int32_t)(fv & kRowMask), n - 1);
-            s_yb = (int32_t)(fv >> 17);
+            s_b = min((int32_t)(fv & P.mask), n - 1);
+            s_yb = (int32_t)(fv >> P.rb);
             if constexpr (kCopies) {
                 // a free copy takes the largest dual of its point's copies
                 // (every y(b) update of the last phase is in ymax by now)
@@ -957,10 +979,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 const bool lead = R == 1 || k_rank == 0;
                 if (lead) {
                     if ((pre >> lane) & 1ull) {
-                        const int32_t y1 = grown_dual(s_yb, &ctl->err);
+                        const int32_t y1 = grown_dual(s_yb, P.dual_max, &ctl->err);
                         st_agent(y_b + s_b, y1 < 0 ? s_yb : y1);
                         st_agent(A.skip + s_b, s_skip - 1u);
-                        my_fv = y1 < 0 ? kNoRow : free_val(s_b, y1);
+                        my_fv = y1 < 0 ? kNoRow : free_val(s_b, y1, P);
                     }
                     wave_scan += (unsigned long long)na * (unsigned long long)__popcll(pre);
                 }
@@ -991,7 +1013,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     const bool lead = k_rank == 0;
                     if (j != kNoHit) {
                         const int a = v.origin + j < na ? v.origin + j : v.origin + j - na;
-                        const unsigned long long kn = make_key(r, b, yb);
+                        const unsigned long long kn = make_key(r, b, yb, P);
                         if (lead) {
                             wave_scan += (unsigned long long)(j - pos + 1);
                             if (lane == 0) {
@@ -1011,10 +1033,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         if (lead) {
                             wave_scan += (unsigned long long)(na - pos);
                             if (lane == 0) {
-                                const int32_t y1 = grown_dual(yb, &ctl->err);
+                                const int32_t y1 = grown_dual(yb, P.dual_max, &ctl->err);
                                 st_agent(y_b + b, y1 < 0 ? yb : y1);
                                 if constexpr (kCopies) raise_top(A.ymax + v.rb, p, y1 < 0 ? yb : y1);
-                                my_fv = y1 < 0 ? kNoRow : free_val(b, y1);
+                                my_fv = y1 < 0 ? kNoRow : free_val(b, y1, P);
                                 if (track) {
                                     const int slack = s_mn[team_local] - (yb - 1);
                                     if (slack >= 2)
@@ -1070,7 +1092,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                                       v.base + kChunk, yb - 1, lane, track ? &mn : nullptr);
                     if (h.j >= 0) {
                         wave_scan += (unsigned long long)(h.j - pos + 1);
-                        const unsigned long long kn = make_key(r, b, yb);
+                        const unsigned long long kn = make_key(r, b, yb, P);
                         if (lane == s) {
                             // the slot's own lane proposes, so proposals of several
                             // slots are in flight together
@@ -1087,10 +1109,10 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                         wave_scan += (unsigned long long)(na - pos);
                         const int slack = track ? wave_min(mn) - (yb - 1) : 0;
                         if (lane == s) {
-                            const int32_t y1 = grown_dual(yb, &ctl->err);
+                            const int32_t y1 = grown_dual(yb, P.dual_max, &ctl->err);
                             st_agent(y_b + b, y1 < 0 ? yb : y1);
                             if constexpr (kCopies) raise_top(A.ymax + v.rb, p, y1 < 0 ? yb : y1);
-                            my_fv = y1 < 0 ? kNoRow : free_val(b, y1);
+                            my_fv = y1 < 0 ? kNoRow : free_val(b, y1, P);
                             if (slack >= 2) st_agent(A.skip + b, (uint32_t)min(slack - 1, 1 << 30));
                         }
                         active &= ~(1ull << s);
@@ -1101,9 +1123,9 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             // whoever wins it, so step (II) evicts its old mate (if any) and
             // the column joins this phase's taken list.
             int32_t my_l = -1;
-            if (proposed && (uint32_t)(s_old >> 32) < r) {
+            if (proposed && (uint32_t)(s_old >> (15 + P.rb)) < r) {
                 my_l = s_a;
-                if (s_old != 0ull) my_fv = key_free(s_old);
+                if (s_old != 0ull) my_fv = key_free(s_old, P);
             }
             const unsigned long long bl = __ballot(my_l >= 0), bf = __ballot(my_fv != kNoRow);
             uint32_t off_l = 0, off_f = 0;
@@ -1305,7 +1327,7 @@ __global__ void decode_kernel(LoopArgs a, int32_t *mate_a, int32_t *mate_b, int3
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_a; i += gridDim.x * blockDim.x) {
         const unsigned long long kk = a.key[i];
-        const int32_t m = kk ? key_row(kk) : -1;
+        const int32_t m = kk ? key_row(kk, row_pack(a.wide)) : -1;
         mate_a[i] = m;
         if (m >= 0) mate_b[m] = i;
         y_a[i] = -(int32_t)a.t[i];
@@ -1514,7 +1536,7 @@ __global__ void team_init_kernel(TeamArgs T)
             a.key[i] = 0ull;
             a.t[i] = 0;
             y_b[i] = 1;
-            a.F[0][i] = tagged(tag0, (int32_t)free_val(i, 1));
+            a.F[0][i] = tagged(tag0, (int32_t)free_val(i, 1, row_pack(a.wide)));
             if (a.skip) a.skip[i] = 0u;
         } else {
             a.t[i] = 0;
@@ -1551,7 +1573,7 @@ __global__ void __launch_bounds__(kCompleteThreads) team_finish_kernel(TeamArgs 
     __syncthreads();
     for (int i = tid; i < n; i += kCompleteThreads) {
         const unsigned long long kk = a.key[i];
-        const int32_t b = kk ? key_row(kk) : -1;
+        const int32_t b = kk ? key_row(kk, row_pack(a.wide)) : -1;
         ma[i] = b;
         if (b >= 0) mb[b] = i;
         ya[i] = -(int32_t)a.t[i];
@@ -1707,6 +1729,22 @@ hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max)
     return hipSuccess;
 }
 
+// Occupancy-limited grid of the loop with its column duals in global memory.
+hipError_t loop_grid_tg(int wgs_per_cu, int *grid_max)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, phase_loop_kernel<false, 0, false, false, true>, kLoopThreads, 0);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    if (per_cu > wgs_per_cu) per_cu = wgs_per_cu;
+    *grid_max = per_cu * cus;
+    if (*grid_max > 2047) *grid_max = 2047;
+    return hipSuccess;
+}
+
 hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
 {
     LoopArgs copy = a;
@@ -1714,13 +1752,19 @@ hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s)
     int team = 1;
     int32_t *no_base = nullptr;
     void *args[] = {&copy, &none, &team, &no_base};
-    const size_t lds = (size_t)a.n_pad * sizeof(uint16_t);
-    const void *fn = a.rmap      ? (const void *)phase_loop_kernel<false, 0, false, true>
-                     : a.pd == 2 ? (const void *)phase_loop_kernel<false, 2, false>
-                     : a.pd == 3 ? (const void *)phase_loop_kernel<false, 3, false>
-                     : a.k8      ? (const void *)phase_loop_kernel<false, 1, false>
-                                 : (const void *)phase_loop_kernel<false, 0, false>;
-    if ((a.pd || a.rmap || a.k8) && lds > 64 * 1024) {
+    const size_t lds = a.tpriv ? 0 : (size_t)a.n_pad * sizeof(uint16_t);
+    const void *fn =
+        a.tpriv ? (a.rmap      ? (const void *)phase_loop_kernel<false, 0, false, true, true>
+                   : a.pd == 2 ? (const void *)phase_loop_kernel<false, 2, false, false, true>
+                   : a.pd == 3 ? (const void *)phase_loop_kernel<false, 3, false, false, true>
+                   : a.k8      ? (const void *)phase_loop_kernel<false, 1, false, false, true>
+                               : (const void *)phase_loop_kernel<false, 0, false, false, true>)
+        : a.rmap    ? (const void *)phase_loop_kernel<false, 0, false, true>
+        : a.pd == 2 ? (const void *)phase_loop_kernel<false, 2, false>
+        : a.pd == 3 ? (const void *)phase_loop_kernel<false, 3, false>
+        : a.k8      ? (const void *)phase_loop_kernel<false, 1, false>
+                    : (const void *)phase_loop_kernel<false, 0, false>;
+    if (!a.tpriv && (a.pd || a.rmap || a.k8) && lds > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  (int)lds);
         if (e != hipSuccess) return e;

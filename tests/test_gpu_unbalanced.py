@@ -281,8 +281,8 @@ def test_points_rect_large_auto(ctx):
 
 def test_rect_at_the_column_limit(ctx):
     """The column duals live in one workgroup's LDS (2 bytes each): 80,000
-    columns is close to the limit and runs; 90,000 are refused."""
-    import paper_2203_03732_amd as prot
+    columns is close to the limit and runs there; 90,000 go past it, and
+    each workgroup keeps its copy of the duals in global memory."""
     n_b, n_a, K, T = 200, 80000, 10, 2
     k = (20 + synth.random_k(n_b, K, seed=41, n_a=n_a)).astype(np.int16)  # ~20 empty phases
     orc = oracle.solve_rounded(k, T)
@@ -293,6 +293,9 @@ def test_rect_at_the_column_limit(ctx):
     kk, m = oracle.round_points_f32(X, Y, 0.01)
     assert_same(gpu, oracle.solve_rounded(kk, oracle.threshold(0.01, 300)), "80000 on the fly")
     X, Y = synth.uniform_points(10, 2, seed=43, n_a=90000)
-    with pytest.raises(prot.ProtError) as e:
-        ctx.solve_points(dev(X), dev(Y), 0.1)
-    assert e.value.name == "unsupported"
+    gpu = ctx.solve_points(dev(X), dev(Y), 0.1)
+    kk, m = oracle.round_points_f32(X, Y, 0.1)
+    assert_same(gpu, oracle.solve_rounded(kk, oracle.threshold(0.1, 10)), "90000 columns")
+    k = (20 + synth.random_k(n_b, K, seed=44, n_a=90000)).astype(np.int16)
+    gpu = ctx.solve_rounded(padded_k(k), T, n_b, n_a=90000)
+    assert_same(gpu, oracle.solve_rounded(k, T), "90000 columns, matrix")
