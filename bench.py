@@ -519,7 +519,8 @@ def main():
     mean_loop, mean_build = float(np.mean(loop_ms)), float(np.mean(build_ms))
     # names as the kernel trace shows them
     kernels = {
-        "phase_loop_kernel<false, 0, false, false>": {"bound": "hbm", "ms": mean_loop, "bytes": loop_bytes},
+        "phase_loop_kernel<false, 0, false, false, false>": {"bound": "hbm", "ms": mean_loop,
+                                                             "bytes": loop_bytes},
         "cost_build": {"bound": "hbm", "ms": mean_build, "bytes": build_bytes},
     }
     dom_name = max(kernels, key=lambda k: kernels[k]["ms"])

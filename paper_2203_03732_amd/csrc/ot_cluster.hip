@@ -477,10 +477,12 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
             ph_rounds += 1;
             // (ii) a point asked for no more than it has serves everyone;
             // the others serve in ascending b
+            // (the lowest contending b of each such point is selected at once)
             int my_contest = 0;
 #pragma unroll
             for (int s = 0; s < kPer; ++s) {
                 contest[s] = prop[s] && L.req[tgt[s]] > L.cap[tgt[s]];
+                if (contest[s]) atomicMin(&L.minb[tgt[s]], tid + s * kCT);
                 my_contest |= contest[s];
             }
             const int contested = __syncthreads_or(my_contest);
@@ -495,10 +497,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
             }
             if (contested) {
                 for (;;) {
-#pragma unroll
-                    for (int s = 0; s < kPer; ++s)
-                        if (contest[s]) atomicMin(&L.minb[tgt[s]], tid + s * kCT);
-                    __syncthreads();
+                    // the selected b is served as far as the point's copies go
 #pragma unroll
                     for (int s = 0; s < kPer; ++s) {
                         if (!contest[s] || L.minb[tgt[s]] != tid + s * kCT) continue;
@@ -510,11 +509,18 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
                         L.minb[a] = 0x7FFFFFFF;
                     }
                     __syncthreads();
+                    // the rest of a point with nothing left get nothing; the
+                    // others select their next lowest b
                     int left = 0;
 #pragma unroll
                     for (int s = 0; s < kPer; ++s) {
-                        if (contest[s] && L.cap[tgt[s]] == 0) contest[s] = false;  // nothing left
-                        left |= contest[s];
+                        if (!contest[s]) continue;
+                        if (L.cap[tgt[s]] == 0) {
+                            contest[s] = false;
+                        } else {
+                            atomicMin(&L.minb[tgt[s]], tid + s * kCT);
+                            left = 1;
+                        }
                     }
                     if (!__syncthreads_or(left)) break;
                 }
