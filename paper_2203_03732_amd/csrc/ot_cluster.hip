@@ -61,10 +61,13 @@ constexpr uint32_t kDone = 0xFFFFFFFFu;                  // epoch: the loop has 
 constexpr int64_t kWaitTicks = 200000000ll;
 
 // Hand-over words (each on its own 256-byte line of ClusterArgs::sync; the
-// entries staged in the current phase are word kSyncStaged).
-constexpr int kEpoch = 0;     // phase published by workgroup 0 (kDone at the end)
-constexpr int kArrive = 64;   // workgroups done listing, cumulative
-constexpr int kRowCount = 192;  // rows to list in the current phase
+// entries staged in phase p are counted in word kSyncStaged + p % 2).
+// 64-bit: (phase published by workgroup 0, kDone at the end) << 32 | its rows
+constexpr int kEpoch = 0;
+// 64-bit: (workgroups done listing) << 40 | (list entries they staged), both
+// cumulative over the phases
+constexpr int kArrive = 64;
+constexpr unsigned long long kStagedMask = (1ull << 40) - 1ull;
 
 // LDS of workgroup 0 (32-bit words), for n_a demand and n_b supply points;
 // the demand arrays have n_a rounded up to 8 entries. req holds, while the
@@ -118,20 +121,22 @@ __device__ long long block_sum64(long long v, long long *red)
     return t;
 }
 
-// Thread 0 waits until *word >= want (or holds kDone, for the epoch);
-// false on time-out (err bit 5 raised).
-__device__ bool wait_at_least(uint32_t *word, uint32_t want, Ctl *ctl, uint32_t *seen)
+// Thread 0 waits until *word >= want (or holds kDone, for the epoch), or
+// for the arrival word until its count field reaches want; false on
+// time-out (err bit 5 raised).
+template <class W>
+__device__ bool wait_at_least(W *word, W want, Ctl *ctl, W *seen, int shift = 0)
 {
     const int64_t t0 = (int64_t)wall_clock64();
     for (int spins = 0;; ++spins) {
-        const uint32_t v = ld_agent(word);
-        if (v >= want) {
+        const W v = ld_agent(word);
+        if ((v >> shift) >= want) {
             *seen = v;
             return true;
         }
         if ((spins & 63) == 63 && (int64_t)wall_clock64() - t0 > kWaitTicks) {
             __hip_atomic_fetch_or(&ctl->err, 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            *seen = kDone;
+            *seen = shift ? ((W)kDone << shift) : (W)kDone;
             return false;
         }
         __builtin_amdgcn_s_sleep(2);
@@ -159,8 +164,8 @@ __device__ inline uint32_t level_hits(uint4 kv, int4 z0, int4 z1, int need)
 
 constexpr int kSegVisits = 128;  // chunk visits per row per step (2 per lane)
 
-// The admissible lists of rows [r_lo, r_hi) of the phase (row r: supply
-// point act[r], whose free copies sit at need[r] + 1), each in its scan
+// The admissible lists of rows [0, count) of this workgroup's share (row i:
+// supply point rb[i], whose free copies sit at rneed[i] + 1), each in its scan
 // order: column a is admissible when k - Z_a = need and a has top copies
 // (zt holds Z_a, or kNever). A wave takes kRowsPerWave rows at once; in a
 // step, lane l looks at chunks (8 columns) 2l and 2l + 1 of each row's
@@ -170,19 +175,21 @@ constexpr int kSegVisits = 128;  // chunk visits per row per step (2 per lane)
 // to a block of the staging area taken with one atomic; its offset and
 // length to loff[b], llen[b]. Rows longer than one step (n_a > 1016) are
 // read twice: once to count, once to write.
-template <int kRowsPerWave>
-__device__ void build_lists(const ClusterArgs &A, const int32_t *zt, int r_lo, int r_hi)
+template <int kRowsPerWave, class RowAt>
+__device__ void build_lists(const ClusterArgs &A, const int32_t *zt, int count, RowAt row_at,
+                            int *total, int32_t *staged)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n_a = A.n_a, nch = (n_a + 7) >> 3, V = nch + 1;
     const int nseg = (V + kSegVisits - 1) / kSegVisits;
-    for (int r0 = r_lo + wave * kRowsPerWave; r0 < r_hi; r0 += (kCT / 64) * kRowsPerWave) {
+    for (int r0 = wave * kRowsPerWave; r0 < count; r0 += (kCT / 64) * kRowsPerWave) {
         int b[kRowsPerWave], s0[kRowsPerWave], c0[kRowsPerWave], need[kRowsPerWave];
         int len[kRowsPerWave], off[kRowsPerWave];
 #pragma unroll
         for (int g = 0; g < kRowsPerWave; ++g) {
-            b[g] = r0 + g < r_hi ? ld_agent(A.act + r0 + g) : -1;
-            need[g] = b[g] >= 0 ? ld_agent(A.need + r0 + g) : 0;
+            b[g] = -1;
+            need[g] = 0;
+            if (r0 + g < count) row_at(r0 + g, &b[g], &need[g]);
             s0[g] = (b[g] >= 0 && A.origin == 0) ? b[g] % n_a : 0;
             c0[g] = s0[g] >> 3;
             len[g] = 0;
@@ -243,7 +250,7 @@ __device__ void build_lists(const ClusterArgs &A, const int32_t *zt, int r_lo, i
                     if (nseg == 1) {
                         len[g] = seg_len;
                         int x = 0;
-                        if (lane == 0 && seg_len > 0) x = add_agent(A.staged, seg_len);
+                        if (lane == 0 && seg_len > 0) x = add_agent(staged, seg_len);
                         off[g] = __shfl(x, 0);
                     }
                     int at = off[g] + run[g] + incl - mine;
@@ -265,7 +272,7 @@ __device__ void build_lists(const ClusterArgs &A, const int32_t *zt, int r_lo, i
 #pragma unroll
                 for (int g = 0; g < kRowsPerWave; ++g) {
                     int x = 0;
-                    if (lane == 0 && b[g] >= 0 && len[g] > 0) x = add_agent(A.staged, len[g]);
+                    if (lane == 0 && b[g] >= 0 && len[g] > 0) x = add_agent(staged, len[g]);
                     off[g] = __shfl(x, 0);
                 }
             }
@@ -276,6 +283,7 @@ __device__ void build_lists(const ClusterArgs &A, const int32_t *zt, int r_lo, i
                 if (b[g] >= 0) {
                     st_agent(A.loff + b[g], off[g]);
                     st_agent(A.llen + b[g], len[g]);
+                    atomicAdd(total, len[g]);
                 }
         }
     }
@@ -283,30 +291,45 @@ __device__ void build_lists(const ClusterArgs &A, const int32_t *zt, int r_lo, i
 
 // Workgroups other than 0: wait for a phase, list a share of its rows,
 // arrive; until workgroup 0 ends the loop.
+// Workgroups other than 0 list the rows (workgroup 0 only when it is alone).
+// A share of the rows, and the demand levels, are read into LDS together.
 template <int kRows>
 __device__ void helper_loop(const ClusterArgs &A, char *lds_raw)
 {
     __shared__ uint32_t s_epoch;
-    __shared__ int s_rows;
-    int32_t *zt = reinterpret_cast<int32_t *>(lds_raw);
+    __shared__ int s_rows, s_total;
     const int na8 = (A.n_a + 7) & ~7;
-    const int P = gridDim.x, w = blockIdx.x;
+    int32_t *zt = reinterpret_cast<int32_t *>(lds_raw);
+    int32_t *rb = zt + na8, *rneed = rb + A.n_b;
+    const int H = gridDim.x - 1, w = blockIdx.x - 1;
     for (uint32_t ph = 1;; ++ph) {
         if (threadIdx.x == 0) {
-            uint32_t e;
-            wait_at_least(A.sync + kEpoch, ph, A.ctl, &e);
-            s_epoch = e;
-            s_rows = ld_agent((int *)(A.sync + kRowCount));
+            unsigned long long e;
+            wait_at_least<unsigned long long>(reinterpret_cast<unsigned long long *>(A.sync + kEpoch),
+                                              ph, A.ctl, &e, 32);
+            s_epoch = (uint32_t)(e >> 32);
+            s_rows = (int)(uint32_t)e;
+            s_total = 0;
         }
         __syncthreads();
         if (s_epoch == kDone) return;
-        for (int a = threadIdx.x; a < na8; a += kCT) zt[a] = ld_agent(A.zt + a);
         const int n = s_rows;
+        const int lo = (int)((int64_t)n * w / H), cnt = (int)((int64_t)n * (w + 1) / H) - lo;
+        for (int a = threadIdx.x; a < na8; a += kCT) zt[a] = ld_agent(A.zt + a);
+        for (int i = threadIdx.x; i < cnt; i += kCT) {
+            rb[i] = ld_agent(A.act + lo + i);
+            rneed[i] = ld_agent(A.need + lo + i);
+        }
         __syncthreads();
-        build_lists<kRows>(A, zt, (int)((int64_t)n * w / P), (int)((int64_t)n * (w + 1) / P));
+        build_lists<kRows>(A, zt, cnt, [&](int i, int *b, int *need) {
+            *b = rb[i];
+            *need = rneed[i];
+        }, &s_total, A.staged + (ph & 1));
         stores_done();
         __syncthreads();
-        if (threadIdx.x == 0) add_agent(A.sync + kArrive, 1u);
+        if (threadIdx.x == 0)
+            add_agent(reinterpret_cast<unsigned long long *>(A.sync + kArrive),
+                      (1ull << 40) | (unsigned long long)s_total);
     }
 }
 
@@ -322,7 +345,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
         return;
     }
     __shared__ long long red[kCT / 64];
-    __shared__ int n_act, lds_lists, s_abort;
+    __shared__ int n_act, lds_lists, s_abort, s_total, s_staged;
     __shared__ unsigned long long ph_scanned, ph_matched;
     Lds L = lds_layout(lds_raw, A.n_b, A.n_a, A.lds_bytes);
     const int tid = threadIdx.x;
@@ -355,6 +378,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
     long long phases = 0, sum_free = 0, rounds = 0, max_rounds = 0, scanned = 0;
     int status = 0;
     long long n_free = 0;
+    unsigned long long staged_before = 0;  // entries staged in earlier phases (thread 0)
     for (;;) {
         long long mine = 0;
 #pragma unroll
@@ -375,6 +399,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
         // Step (I): publish the rows with free copies and the demand levels
         if (tid == 0) {
             n_act = 0;
+            s_total = 0;
             ph_scanned = 0;
             ph_matched = 0;
         }
@@ -393,47 +418,66 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
             L.req[a] = z;
             st_agent(A.zt + a, z);
         }
+        // (the staging count of the next phase starts at zero: it was last
+        // used in the previous phase, which every workgroup has finished)
+        if (tid == 0) st_agent(A.staged + ((phases + 1) & 1), 0);
         stores_done();
         __syncthreads();
-        if (tid == 0) {
-            st_agent(A.staged, 0);
-            st_agent((int *)(A.sync + kRowCount), n_act);
+        if (tid == 0)
+            st_agent(reinterpret_cast<unsigned long long *>(A.sync + kEpoch),
+                     ((unsigned long long)phases << 32) | (uint32_t)n_act);
+        // ... the other workgroups list the rows (this one only when alone) ...
+        if (P == 1) {
+            build_lists<kRows>(A, L.req, n_act, [&](int i, int *b, int *need) {
+                *b = ld_agent(A.act + i);
+                *need = ld_agent(A.need + i);
+            }, &s_total, A.staged + (phases & 1));
             stores_done();
-            st_agent(A.sync + kEpoch, (uint32_t)phases);
+            __syncthreads();
         }
-        // ... list this workgroup's share, wait for the others ...
-        build_lists<kRows>(A, L.req, 0, (int)((int64_t)n_act / P));
-        stores_done();
-        __syncthreads();
         if (tid == 0) {
-            add_agent(A.sync + kArrive, 1u);
-            uint32_t seen;
-            if (!wait_at_least(A.sync + kArrive, P * (uint32_t)phases, A.ctl, &seen))
-                s_abort = 1;
-            const int staged = ld_agent(A.staged);
+            int staged = s_total;
+            if (P > 1) {
+                unsigned long long seen;
+                if (!wait_at_least<unsigned long long>(
+                        reinterpret_cast<unsigned long long *>(A.sync + kArrive),
+                        (unsigned long long)(P - 1) * (unsigned long long)phases, A.ctl, &seen, 40))
+                    s_abort = 1;
+                staged = (int)((seen & kStagedMask) - staged_before);
+                staged_before = seen & kStagedMask;
+            }
+            s_staged = staged;
             lds_lists = (int64_t)((staged + 7) & ~7) <= L.list_cap;
+        }
+        // (each supply point's list block, read while thread 0 waits)
+#pragma unroll
+        for (int s = 0; s < kPer; ++s) {
+            const int b = tid + s * kCT;
+            act[s] = b < n_b && F[s] > 0;
         }
         __syncthreads();
         if (s_abort) {
             status = 3;
             break;
         }
+#pragma unroll
+        for (int s = 0; s < kPer; ++s) {
+            const int b = tid + s * kCT;
+            loff[s] = act[s] ? ld_agent(A.loff + b) : 0;
+            llen[s] = act[s] ? ld_agent(A.llen + b) : 0;
+        }
         // ... and take the staged lists into LDS when they fit
         if (lds_lists) {
-            const int staged = ld_agent(A.staged);
+            const int staged = s_staged;
             const uint32_t *src = reinterpret_cast<const uint32_t *>(A.stage);
             uint32_t *dst = reinterpret_cast<uint32_t *>(L.list);
             for (int i = tid; i < (staged + 1) / 2; i += kCT) dst[i] = ld_agent(src + i);
         }
 #pragma unroll
         for (int s = 0; s < kPer; ++s) {
-            const int b = tid + s * kCT;
             want[s] = F[s];
             pos[s] = 0;
             li[s] = 0;
-            act[s] = b < n_b && F[s] > 0;
-            loff[s] = act[s] ? ld_agent(A.loff + b) : 0;
-            llen[s] = act[s] ? ld_agent(A.llen + b) : 0;
         }
         for (int a = tid; a < na8; a += kCT) {
             L.cap[a] = L.top[a];
@@ -626,7 +670,9 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
         __syncthreads();
     }
     // the other workgroups leave
-    if (tid == 0) st_agent(A.sync + kEpoch, kDone);
+    if (tid == 0)
+        st_agent(reinterpret_cast<unsigned long long *>(A.sync + kEpoch),
+                 (unsigned long long)kDone << 32);
 
     // the state the later kernels read
     for (int a = tid; a < n_a; a += kCT) {

@@ -168,3 +168,16 @@ def test_clustered_rejections(ctx):
     C[1, 1] = 1.5
     with pytest.raises(prot.ProtError, match="range"):
         ctx.ot_solve(dev(C), dev(nu), dev(mu), 0.1, clustered=True)
+
+
+@pytest.mark.parametrize("grid", ["1", "2", "3"])
+def test_clustered_small_grids(ctx, grid):
+    """Workgroup 0 alone lists the rows (grid 1), or one or two others do:
+    the results do not depend on who lists them."""
+    C, nu, mu = _instance(300, 280, 51, points=True, shift=0.4)
+    os.environ["PROT_CLUSTER_GRID"] = grid
+    try:
+        gpu, orc = _run(ctx, C, nu, mu, 0.02)
+    finally:
+        del os.environ["PROT_CLUSTER_GRID"]
+    _compare(ctx, gpu, orc, f"grid {grid}")
