@@ -611,29 +611,60 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
             }
             const int p = z & 1;
             unsigned long long *mrow = A.mask + (int64_t)a * A.nwb;
-            const unsigned long long sum0 = A.msum[a];
+            const unsigned long long sum0 = rem > 0 ? A.msum[a] : 0ull;
             unsigned long long words = sum0, sum = sum0;
+            // partners in ascending b: four bitmap words, then four pair
+            // cells, loaded at once
             while (words && rem > 0) {
-                const int wd = __builtin_ctzll(words);
-                words &= words - 1ull;
-                unsigned long long bits = mrow[wd], keep = bits;
-                while (bits && rem > 0) {
-                    const int b = wd * 64 + __builtin_ctzll(bits);
-                    bits &= bits - 1ull;
-                    int2 *cell = A.w + (int64_t)b * n_a + a;
-                    int2 v = *cell;
-                    int32_t &c = p ? v.y : v.x;
-                    if (c == 0) continue;
-                    const int32_t e = rem < c ? rem : c;
-                    c -= e;
-                    rem -= e;
-                    *cell = v;
-                    atomicAdd(&L.evict[b], e);
-                    if (v.x == 0 && v.y == 0) keep &= ~(1ull << (b & 63));
+                int wd[4];
+                unsigned long long wv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    wd[q] = -1;
+                    wv[q] = 0ull;
+                    if (words) {
+                        wd[q] = __builtin_ctzll(words);
+                        words &= words - 1ull;
+                    }
                 }
-                if (keep != mrow[wd]) {
-                    mrow[wd] = keep;
-                    if (!keep) sum &= ~(1ull << wd);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (wd[q] >= 0) wv[q] = mrow[wd[q]];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (wd[q] < 0 || rem == 0) continue;
+                    unsigned long long bits = wv[q], keep = bits;
+                    while (bits && rem > 0) {
+                        int bb[4];
+                        int2 cv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            bb[u] = -1;
+                            if (bits) {
+                                bb[u] = wd[q] * 64 + __builtin_ctzll(bits);
+                                bits &= bits - 1ull;
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            cv[u] = bb[u] >= 0 ? A.w[(int64_t)bb[u] * n_a + a] : make_int2(0, 0);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (bb[u] < 0 || rem == 0) continue;
+                            int32_t &c = p ? cv[u].y : cv[u].x;
+                            if (c == 0) continue;
+                            const int32_t e = rem < c ? rem : c;
+                            c -= e;
+                            rem -= e;
+                            A.w[(int64_t)bb[u] * n_a + a] = cv[u];
+                            atomicAdd(&L.evict[bb[u]], e);
+                            if (cv[u].x == 0 && cv[u].y == 0) keep &= ~(1ull << (bb[u] & 63));
+                        }
+                    }
+                    if (keep != wv[q]) {
+                        mrow[wd[q]] = keep;
+                        if (!keep) sum &= ~(1ull << wd[q]);
+                    }
                 }
             }
             if (sum != sum0) A.msum[a] = sum;
