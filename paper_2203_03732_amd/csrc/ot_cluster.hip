@@ -121,6 +121,20 @@ __device__ long long block_sum64(long long v, long long *red)
     return t;
 }
 
+// Whether pred holds in any thread of the workgroup, with one barrier
+// (all threads call, the same number of times). Call c raises flag c % 4 and
+// reads it after the barrier; thread 0 clears flag (c + 2) % 4 before it:
+// its readers (call c - 2) passed the barrier of call c - 1 before, its
+// writers (call c + 2) come after the barrier of call c + 1.
+__device__ inline int block_any(int pred, int *flags, uint32_t &calls)
+{
+    const uint32_t c = calls++;
+    if (threadIdx.x == 0) flags[(c + 2) & 3] = 0;
+    if (__ballot(pred) && (threadIdx.x & 63) == 0) flags[c & 3] = 1;
+    __syncthreads();
+    return flags[c & 3];
+}
+
 // Thread 0 waits until *word >= want (or holds kDone, for the epoch), or
 // for the arrival word until its count field reaches want; false on
 // time-out (err bit 5 raised).
@@ -347,6 +361,8 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
     __shared__ long long red[kCT / 64];
     __shared__ int n_act, lds_lists, s_abort, s_total, s_staged;
     __shared__ unsigned long long ph_scanned, ph_matched;
+    __shared__ int any_flags[4];
+    uint32_t any_calls = 0;
     Lds L = lds_layout(lds_raw, A.n_b, A.n_a, A.lds_bytes);
     const int tid = threadIdx.x;
     const int n_b = A.n_b, n_a = A.n_a;
@@ -367,6 +383,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
         L.evict[b] = 0;
     }
     if (tid == 0) s_abort = 0;
+    if (tid < 4) any_flags[tid] = 0;
     int32_t F[kPer], want[kPer], pos[kPer], li[kPer], tgt[kPer], jp[kPer], loff[kPer],
         llen[kPer];
     bool act[kPer], prop[kPer], contest[kPer];
@@ -517,7 +534,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
                 atomicAdd(&L.req[a], want[s]);
             }
             if (my_scan) atomicAdd(&ph_scanned, (unsigned long long)my_scan);
-            if (!__syncthreads_or(my_prop)) break;
+            if (!block_any(my_prop, any_flags, any_calls)) break;
             ph_rounds += 1;
             // (ii) a point asked for no more than it has serves everyone;
             // the others serve in ascending b
@@ -529,7 +546,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
                 if (contest[s]) atomicMin(&L.minb[tgt[s]], tid + s * kCT);
                 my_contest |= contest[s];
             }
-            const int contested = __syncthreads_or(my_contest);
+            const int contested = block_any(my_contest, any_flags, any_calls);
             int32_t grant[kPer];
 #pragma unroll
             for (int s = 0; s < kPer; ++s) {
@@ -566,7 +583,7 @@ __global__ void __launch_bounds__(kCT) cluster_loop_kernel(ClusterArgs A)
                             left = 1;
                         }
                     }
-                    if (!__syncthreads_or(left)) break;
+                    if (!block_any(left, any_flags, any_calls)) break;
                 }
             }
             // (iii) the grants become pairs (at the demand copies' next level)
