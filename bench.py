@@ -80,13 +80,23 @@ def cpu_baseline(X, Y, eps, reps):
             k, _ = oracle.round_points_f32(X, Y, eps)
             oracle.solve_rounded(k, oracle.threshold(eps, n))
             times.append(time.perf_counter() - t0)
+        # the clustered transport of the transport_clustered leg at eps = 0.01
+        from paper_2203_03732_amd import synth
+        C, nu, mu = synth.transport_clouds(1000, 1000, seed=11, shift=1.0)
+        t0 = time.perf_counter()
+        oracle.ot_solve_clustered(C, nu, mu, 0.01)
+        ot_ms = 1e3 * (time.perf_counter() - t0)
     finally:
         os.sched_setaffinity(0, before)
     ms = 1e3 * sum(times) / len(times)
     return {"value": round(ms, 3), "unit": "ms", "cores": 1, "kind": "oracle",
             "sample": f"{reps} whole solve(s) of the same instance (binary32 cost build "
                       f"+ phase loop + completion), single-threaded C pinned to core {core}",
-            "host_cpu": model, "host_cores_allowed": allowed, "host_cores_total": total}
+            "host_cpu": model, "host_cores_allowed": allowed, "host_cores_total": total,
+            "transport_clustered_eps_0.01": {
+                "value": round(ot_ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                "sample": "one whole solve of the transport_clustered leg's eps = 0.01 "
+                          "workload (scaling, rounding, clustered phases, plan and repair)"}}
 
 
 def bench_batched(prot, synth, torch, reps=10):
@@ -311,6 +321,12 @@ def bench_transport_clustered(prot, synth, torch, reps=5):
             "copies_a": st["copies_a"], "phases": st["phases"], "rounds": st["rounds"],
             "us_per_phase": round(1e3 * st["ms_loop_kernel"] / max(1, st["phases"]), 2),
             "scanned": st["scanned"], "cost": st["cost"],
+            # the loop reads each scanned position's int16 cost once: its rate
+            # against the HBM peak (the loop is bound by hand-over and barrier
+            # latency, not by bytes)
+            "scan_GBps": round(2.0 * st["scanned"] / (st["ms_loop_kernel"] * 1e-3) / 1e9, 2),
+            "scan_frac_of_hbm_peak": round(2.0 * st["scanned"] / (st["ms_loop_kernel"] * 1e-3)
+                                           / 1e9 / HBM_PEAK_GBS, 6),
             "repaired_mass": st["repaired_mass"]}
     ctx.close()
     return out

@@ -29,7 +29,8 @@ MUTATIONS = [
     ("y(b) rises by two", "if (!won[i]) y_b[B_prime[i]] += 1;",
      "if (!won[i]) y_b[B_prime[i]] += 2;", False),
     ("stop test strict", "if (n_i <= T) break;", "if (n_i < T) break;", False),
-    ("no completion", "if (complete && status == ORC_OK) {", "if (0) {", False),
+    ("no completion", "if (complete && status == ORC_OK) {\n        int64_t ia = 0;",
+     "if (0) {\n        int64_t ia = 0;", False),
     ("eq. (1) rounds up",
      "if (!(c >= 0.0 && c <= 1.0)) return ORC_E_RANGE;\n            k[b * ldk + a] = (int16_t)floor(c / eps);",
      "if (!(c >= 0.0 && c <= 1.0)) return ORC_E_RANGE;\n            k[b * ldk + a] = (int16_t)ceil(c / eps);",
