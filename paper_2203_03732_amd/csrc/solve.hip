@@ -39,8 +39,11 @@
 //     a reader waits (bounded) until the entry carries the expected tag;
 //   * a row re-enters the free list with its dual packed beside it, so a
 //     phase start needs no load of y(b); y(b) is also stored (for the
-//     results) before the arrival, and each wave waits for its stores to
-//     complete before the workgroup arrives.
+//     results), and the wave waits for that store to complete before it
+//     writes the row's next free-list entry;
+//   * when the last round of a phase is over, the poll that saw it also
+//     lays out the next free list, so a phase boundary costs one workgroup
+//     barrier besides the rounds'.
 #include "device_common.h"
 #include "internal.h"
 
@@ -733,7 +736,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
     }
     extern __shared__ __align__(16) uint16_t t_smem[];
     uint16_t *const t_lds = kTG ? A.tpriv + (int64_t)blockIdx.x * A.n_pad : t_smem;
-    __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose;
+    __shared__ uint32_t s_cnt_l, s_cnt_f, s_lose, s_nnext;
     __shared__ uint32_t s_base_l, s_base_f, s_ltot, s_over, s_abort;
     __shared__ unsigned long long s_scan, s_pend_scan;
     __shared__ int64_t s_pend_p;
@@ -1137,7 +1140,14 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             }
             off_l = __builtin_amdgcn_readfirstlane(off_l);
             off_f = __builtin_amdgcn_readfirstlane(off_f);
-            wait_memory();  // y(b) stores of this wave are complete
+            // Stores another workgroup reads in the next phase (the largest
+            // dual of a point's copies, skip counts) are complete before the
+            // arrival. The plain loop's y(b) stores are read only after the
+            // launch; they complete before the row's entry of the next free
+            // list is written (below), so a later store to the same y(b),
+            // which follows a read of that entry, cannot overtake them.
+            constexpr bool kStoresBeforeArrival = kCopies || kFF || kMulti;
+            if (kStoresBeforeArrival) wait_memory();
             __syncthreads();
 
             // Arrival: the returned word is the sum over the workgroups of this
@@ -1174,6 +1184,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             __syncthreads();
             {
                 const uint32_t bl0 = s_base_l, bf0 = s_base_f;
+                if (!kStoresBeforeArrival && bf != 0ull) wait_memory();
                 if (my_l >= 0)
                     st_agent(Lc + grp * cap + bl0 + off_l + lanes_below(bl), tagged(tag, my_l));
                 if (my_fv != kNoRow)
@@ -1210,16 +1221,30 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 const uint32_t lose = (uint32_t)((v >> kShiftLose) & 0x7FFull);
                 const uint32_t lpre = wave_exclusive_scan(nl, lane);
                 const uint32_t ltot = wave_sum(nl), losers = wave_sum(lose);
+                uint32_t fc = 0u;
                 if (lane < G) {
                     s_lnew[lane] = nl;
                     s_lpre[lane] = lpre;
                     s_lstart[lane] = s_lcum[lane];
                     s_lcum[lane] += nl;
-                    s_fcum[lane] += nf;
+                    fc = s_fcum[lane] + nf;
+                    s_fcum[lane] = fc;
                 }
                 if (lane == 0) {
                     s_ltot = ltot;
                     s_over = losers == 0u;
+                }
+                if (losers == 0u) {
+                    // the phase is over: the next free list is the group
+                    // regions of Fn, in group order
+                    const uint32_t fpre = wave_exclusive_scan(fc, lane);
+                    const uint32_t ftot = wave_sum(fc);
+                    if (lane < G) {
+                        s_fpre[lane] = fpre;
+                        s_fcum[lane] = 0;
+                        s_lcum[lane] = 0;
+                    }
+                    if (lane == 0) s_nnext = ftot;
                 }
                 if (timed && leader) {
                     A.rtime[3 * (r - 1) + 1] = (int64_t)wall_clock64();
@@ -1267,21 +1292,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                 A.trace[4 * p + 3] = lcount;
             }
         }
-        // the next free list: group regions of Fn, in group order
-        if (threadIdx.x < kWave) {
-            const uint32_t f = lane < G ? s_fcum[lane] : 0u;
-            const uint32_t pre = wave_exclusive_scan(f, lane);
-            const uint32_t total = wave_sum(f);  // all lanes take part in the shuffles
-            if (lane < G) {
-                s_fpre[lane] = pre;
-                s_fcum[lane] = 0;
-                s_lcum[lane] = 0;
-            }
-            if (lane == 0) s_ltot = total;
-        }
-        __syncthreads();
-        n_i = s_ltot;
-        __syncthreads();
+        n_i = s_nnext;
         p += 1;
     }
     if (threadIdx.x == 0) flush_scan();
