@@ -1156,9 +1156,7 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
             const bool timed = A.rtime != nullptr && r <= (uint32_t)kRoundTimeCap;
             unsigned long long *words = A.words + (r % 3) * kMaxGroups * kWordStride;
             if (threadIdx.x < kWave) {
-                if (timed && threadIdx.x == 0)
-                    __hip_atomic_fetch_max(&A.rtime[3 * (r - 1)], (int64_t)wall_clock64(),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int64_t t_arrive = timed ? (int64_t)wall_clock64() : 0;
                 // the words of round r + 1 were last read in round r - 2, which
                 // every workgroup has left
                 if (wg == 0) {
@@ -1179,6 +1177,12 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
                     s_base_l = s_lcum[grp] + (uint32_t)(o & kField);
                     s_base_f = s_fcum[grp] + (uint32_t)((o >> kShiftFree) & kField);
                     flush_scan();
+                    // the last arrival of each group records its time (one
+                    // atomic per group rather than per workgroup)
+                    if (timed && (uint32_t)(o >> kShiftArrive) + 1u ==
+                                     nwg / (uint32_t)G + ((uint32_t)grp < nwg % (uint32_t)G ? 1u : 0u))
+                        __hip_atomic_fetch_max(&A.rtime[3 * (r - 1)], t_arrive, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             __syncthreads();
