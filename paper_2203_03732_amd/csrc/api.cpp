@@ -521,9 +521,7 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
     if (cooperative) HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream, 16));
     HIP_TRY(c, prot::launch_init(a, warm, mate_a, mate_b, y_a, c->stream));
     if (c->rtime) HIP_TRY(c, prot::launch_clear_times(c->rtime, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-    HIP_TRY(c, prot::launch_loop(a, grid, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    HIP_TRY(c, prot::launch_loop(a, grid, c->stream, c->ev[2], c->ev[3]));
     const int32_t complete = (o && o->no_completion) ? 0 : 1;
     HIP_TRY(c, prot::launch_finish(a, warm, complete, mate_a, mate_b, y_a, c->lists, c->stream));
     return PROT_OK;

@@ -219,7 +219,9 @@ hipError_t loop_grid(int32_t n_pad, int wgs_per_cu, int *grid_max);
 hipError_t loop_grid_tg(int wgs_per_cu, int *grid_max);  // column duals in global memory
 hipError_t launch_clear_times(int64_t *rtime, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
-hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s);
+// ev_start / ev_stop (may be null) take the loop launch's start and end.
+hipError_t launch_loop(const LoopArgs &a, int grid, hipStream_t s, hipEvent_t ev_start,
+                       hipEvent_t ev_stop);
 // Teams: workgroups a cooperative launch of the multi-instance loop can hold.
 hipError_t loop_grid_multi(int32_t n_pad_max, int wgs_per_cu, int *grid_max);
 hipError_t launch_team_init(const TeamArgs &t, int32_t n_pad_max, hipStream_t s);
