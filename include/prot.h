@@ -454,6 +454,15 @@ int64_t prot_get_trace(prot_ctx *ctx, int64_t *out_host, int64_t cap);
  * off). Synchronises the stream. */
 int64_t prot_get_round_times(prot_ctx *ctx, int64_t *out_host, int64_t cap);
 
+/* Device times (ms) of the last `count` phase-loop launches on ctx, oldest
+ * first, from events that the launches themselves carry (each solve, warm
+ * start or transport call launches the loop once; the context keeps the
+ * last 1,024). For timing solves enqueued with stats = NULL, which report no
+ * statistics. ms_out: host array of at least `count` floats. Synchronises the
+ * stream; returns the number of times written (<= count), or
+ * PROT_E_ARG / PROT_E_HIP. */
+int32_t prot_loop_times(prot_ctx *ctx, float *ms_out, int32_t count);
+
 /* How the work last enqueued on ctx by a solve call ended: synchronises
  * the context stream and returns PROT_OK, PROT_PARTIAL, PROT_E_PHASE_BOUND
  * or the error the device reported (PROT_E_RANGE for a non-finite or

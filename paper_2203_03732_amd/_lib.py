@@ -109,7 +109,7 @@ EXPORTS = [
     "prot_solve_cost_rect", "prot_solve_points_rect", "prot_ot_solve", "prot_ot_solve_clustered",
     "prot_set_cost_metric",
     "prot_get_trace",
-    "prot_get_round_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
+    "prot_get_round_times", "prot_loop_times", "prot_batch_max_n", "prot_batch_create", "prot_batch_destroy",
     "prot_batch_create_config", "prot_batch_autotune",
     "prot_batch_run", "prot_batch_capture", "prot_batch_replay", "prot_solve_batched_points",
     "prot_batch_loss_fwd", "prot_batch_loss_bwd", "prot_ctx_status", "prot_batch_status",
@@ -181,6 +181,7 @@ def load():
         "prot_solve_batched_points": (ctypes.c_int, [p, i32, p, i32, p, p, f64,
                                                      ctypes.POINTER(Opts), p, p, p, p, p]),
         "prot_ctx_status": (ctypes.c_int, [p]),
+        "prot_loop_times": (i32, [p, p, i32]),
         "prot_batch_status": (ctypes.c_int, [p]),
         "prot_ot_loss_fwd": (ctypes.c_int, [p, i32, i64, i32, p, p, p, p]),
         "prot_ot_loss_bwd": (ctypes.c_int, [p, i32, i64, i32, p, p, p, p, p, p]),
@@ -371,6 +372,17 @@ class Context:
             n_a, d, float(eps), _dev_ptr(k, torch.int16, "k", 2), k.stride(0),
             _dev_ptr(m, torch.float32, "m")))
         return k, m
+
+    def loop_times(self, count: int):
+        """Device times (ms) of the last `count` phase-loop launches on this
+        context, oldest first (prot_loop_times; synchronises): the timing of
+        solves enqueued with stats=False."""
+        import numpy as np
+        out = np.zeros(max(int(count), 0), np.float32)
+        m = self._lib.prot_loop_times(self._h, out.ctypes.data_as(ctypes.c_void_p), len(out))
+        if m < 0:
+            self._check(m)
+        return out[:m].astype(np.float64)
 
     def status(self) -> str:
         """How the work last enqueued by a solve on this context ended

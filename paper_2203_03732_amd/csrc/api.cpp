@@ -108,8 +108,15 @@ struct prot_ctx {
         uint32_t *csync = nullptr;
         int64_t *cPF = nullptr, *cPG = nullptr;
     } ot;
-    // 0 build start, 1 build end, 2 loop start, 3 loop end, 4 all done
+    // 0 build start, 1 build end, 4 all done (2, 3 unused: the loop's own
+    // events are in loop_ev)
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // start and end of the last kLoopEvents phase-loop launches (a ring;
+    // loop_slot is the latest, loop_launches counts them all)
+    static constexpr int kLoopEvents = 1024;
+    hipEvent_t loop_ev[kLoopEvents][2] = {};
+    int loop_slot = -1;
+    int64_t loop_launches = 0;
 };
 
 namespace {
@@ -452,6 +459,20 @@ struct Copies {
 // K: the largest rounded cost (for the watchdog and the warm-start check).
 // cooperative: launch the loop cooperatively (the retry after the gate
 // admitted too few workgroups).
+// The events of the next phase-loop launch: the ring's next slot (its
+// events created on first use).
+int next_loop_events(prot_ctx *c, hipEvent_t **out)
+{
+    const int slot = (c->loop_slot + 1) % prot_ctx::kLoopEvents;
+    for (hipEvent_t &e : c->loop_ev[slot])
+        if (!e && hipEventCreate(&e) != hipSuccess)
+            return fail(c, PROT_E_HIP, "event creation failed");
+    c->loop_slot = slot;
+    c->loop_launches += 1;
+    *out = c->loop_ev[slot];
+    return PROT_OK;
+}
+
 int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk, int64_t T,
              const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
              int32_t *y_b, int64_t K, bool cooperative = false,
@@ -521,7 +542,9 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
     if (cooperative) HIP_TRY(c, prot::launch_clear_err(c->ctl, c->stream, 16));
     HIP_TRY(c, prot::launch_init(a, warm, mate_a, mate_b, y_a, c->stream));
     if (c->rtime) HIP_TRY(c, prot::launch_clear_times(c->rtime, c->stream));
-    HIP_TRY(c, prot::launch_loop(a, grid, c->stream, c->ev[2], c->ev[3]));
+    hipEvent_t *le = nullptr;
+    if (int r = next_loop_events(c, &le)) return r;
+    HIP_TRY(c, prot::launch_loop(a, grid, c->stream, le[0], le[1]));
     const int32_t complete = (o && o->no_completion) ? 0 : 1;
     HIP_TRY(c, prot::launch_finish(a, warm, complete, mate_a, mate_b, y_a, c->lists, c->stream));
     return PROT_OK;
@@ -598,7 +621,10 @@ int collect(prot_ctx *c, prot_stats *st, int64_t T, double eps_int, int cost_kin
     float ms = 0.0f;
     if (timed_build && hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess)
         st->ms_build = ms;
-    if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) st->ms_loop_kernel = ms;
+    if (c->loop_slot >= 0 &&
+        hipEventElapsedTime(&ms, c->loop_ev[c->loop_slot][0], c->loop_ev[c->loop_slot][1]) ==
+            hipSuccess)
+        st->ms_loop_kernel = ms;
     if (hipEventElapsedTime(&ms, c->ev[timed_build ? 0 : 1], c->ev[4]) == hipSuccess)
         st->ms_total = ms;
     return PROT_OK;
@@ -997,6 +1023,9 @@ int prot_ctx_destroy(prot_ctx *c)
     if (c->stage) (void)hipHostFree(c->stage);
     for (int i = 0; i < 5; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    for (auto &pair : c->loop_ev)
+        for (hipEvent_t e : pair)
+            if (e) (void)hipEventDestroy(e);
     delete c;
     return PROT_OK;
 }
@@ -1590,7 +1619,9 @@ int prot_ot_solve_clustered(prot_ctx *c, const float *C, int64_t n_b, int64_t n_
         if (cap >= 0) A.lds_bytes = std::min<int64_t>(A.lds_bytes, lds_fixed + 2 * cap);
     }
     HIP_TRY(c, prot::launch_cluster_init(A, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    hipEvent_t *le = nullptr;
+    if ((rc = next_loop_events(c, &le))) return rc;
+    HIP_TRY(c, hipEventRecord(le[0], c->stream));
     int grid = 1;
     HIP_TRY(c, prot::cluster_grid(A.n_b, &grid));
     if (const char *e = std::getenv("PROT_CLUSTER_GRID")) {
@@ -1598,7 +1629,7 @@ int prot_ot_solve_clustered(prot_ctx *c, const float *C, int64_t n_b, int64_t n_
         if (g >= 1 && g < grid) grid = g;
     }
     HIP_TRY(c, prot::launch_cluster_loop(A, grid, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+    HIP_TRY(c, hipEventRecord(le[1], c->stream));
     HIP_TRY(c, prot::launch_cluster_counts(A, w.cnt, c->part_k, 1, c->stream));
     prot::OtPlanArgs pa{};
     pa.cnt = w.cnt;
@@ -2039,6 +2070,24 @@ int64_t prot_get_round_times(prot_ctx *c, int64_t *out, int64_t cap)
         hipStreamSynchronize(c->stream) != hipSuccess)
         return PROT_E_HIP;
     return m;
+}
+
+int32_t prot_loop_times(prot_ctx *c, float *ms_out, int32_t count)
+{
+    if (!c || count < 0 || (count > 0 && !ms_out)) return PROT_E_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return PROT_E_HIP;
+    int64_t m = std::min<int64_t>({(int64_t)count, c->loop_launches,
+                                   (int64_t)prot_ctx::kLoopEvents});
+    for (int64_t i = 0; i < m; ++i) {
+        // oldest first: the latest launch goes last
+        const int slot = (int)((c->loop_slot - (m - 1 - i) + 2 * prot_ctx::kLoopEvents) %
+                               prot_ctx::kLoopEvents);
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->loop_ev[slot][0], c->loop_ev[slot][1]) != hipSuccess)
+            return fail(c, PROT_E_HIP, "prot_loop_times: an event was not recorded");
+        ms_out[i] = ms;
+    }
+    return (int32_t)m;
 }
 
 int64_t prot_get_trace(prot_ctx *c, int64_t *out, int64_t cap)
