@@ -1280,7 +1280,9 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
     if (!rc) rc = ensure_thresholds(c, ei);
     if (rc) return rc;
     int16_t *kmat = on_the_fly ? nullptr : c->kmat;
-    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    // the build's and the whole solve's timing events only when statistics
+    // are asked for (each event record holds the next launch back a few us)
+    if (!enqueue_only) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
     prot::PointsJob j = points_job(c, X, Y, n_b, d, ei, kmat, ldk, n_a);
     j.no_matrix = on_the_fly ? 1 : 0;
     j.k8 = k8;
@@ -1288,7 +1290,7 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
     if ((rc = setup_prune(c, j, n_max))) return rc;
     if ((rc = setup_l1(c, j, n_b, n_a))) return rc;
     HIP_TRY(c, prot::launch_points(j, n_max, ldk, c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    if (!enqueue_only) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
     OnTheFly otf;
     if (on_the_fly) {
         otf.d = d;
@@ -1309,7 +1311,7 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
             HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, points_cost_kind(c),
                                              nullptr, 0, X, Y, d, c->part_k, c->part_c,
                                              c->stream, nullptr, 0.0, nullptr, k8));
-        HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+        if (!enqueue_only) HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
         return PROT_OK;
     };
     if ((rc = enqueue(false))) return rc;
