@@ -448,7 +448,6 @@ struct OnTheFly {
     double eps = 0.0;
 };
 
-// n rows (B), n_a >= n columns (A).
 // Copies of the transport reduction: row b reads cost row rmap[b]; ymax holds
 // the largest dual of each point's copies.
 struct Copies {
@@ -456,9 +455,6 @@ struct Copies {
     unsigned long long *ymax = nullptr;
 };
 
-// K: the largest rounded cost (for the watchdog and the warm-start check).
-// cooperative: launch the loop cooperatively (the retry after the gate
-// admitted too few workgroups).
 // The events of the next phase-loop launch: the ring's next slot (its
 // events created on first use).
 int next_loop_events(prot_ctx *c, hipEvent_t **out)
@@ -473,6 +469,10 @@ int next_loop_events(prot_ctx *c, hipEvent_t **out)
     return PROT_OK;
 }
 
+// The phase loop on n rows (B) and n_a >= n columns (A), with its init and
+// finish kernels. K: the largest rounded cost (for the watchdog and the
+// warm-start check). cooperative: launch the loop cooperatively (the retry after the gate
+// admitted too few workgroups).
 int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk, int64_t T,
              const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
              int32_t *y_b, int64_t K, bool cooperative = false,
