@@ -30,16 +30,17 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "n=10k ε=.01 solve ms + phase-scan HBM GB/s; batched solves/s vs plain loop"
 
 
-TRAFFIC_FILES = {(10000, 2): "traffic_points_n10000_d2_eps0.01.json",
-                 (50000, 3): "traffic_points_n50000_d3_eps0.005.json"}
+TRAFFIC_FILES = {(10000, 2, "auto"): "traffic_points_n10000_d2_eps0.01.json",
+                 (50000, 3, "auto"): "traffic_points_n50000_d3_eps0.005.json",
+                 (50000, 3, "matrix"): "traffic_points_n50000_d3_eps0.005_matrix.json"}
 
 
-def measured_traffic(n, d, kernel):
+def measured_traffic(n, d, kernel, storage="auto"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of this workload, or None when there is none or the kernel
     sources have changed since the counters were taken."""
     import hashlib
-    name = TRAFFIC_FILES.get((n, d))
+    name = TRAFFIC_FILES.get((n, d, storage))
     path = os.path.join(ROOT, "profiles", name) if name else None
     if not path or not os.path.exists(path):
         return None
@@ -216,6 +217,11 @@ def bench_large_matrix(prot, synth, torch, reps=5):
             "ms_per_solve": round(ms, 4), "ms_build": round(bm, 4), "ms_loop": round(lm, 4),
             "phases": st["phases"], "rounds": st["rounds"], "scanned": st["scanned"],
             "loop_scan_GBps": round(scan_gbs, 1), "loop_frac_of_hbm_peak": round(scan_gbs / HBM_PEAK_GBS, 4),
+            # HBM bytes per loop launch from the committed counters (null if
+            # the kernel sources changed since), against 2 B per entry examined
+            "loop_traffic_bytes": measured_traffic(
+                50000, 3, "phase_loop_kernel<false, 0, false, false, false>", "matrix"),
+            "loop_algorithmic_bytes": 2 * st["scanned"],
             "build_write_GBps": round(write_gbs, 1), "cost": st["cost"]}
 
 
@@ -479,8 +485,8 @@ def main():
     ap.add_argument("--phase-report", action="store_true",
                     help="print a per-phase table of the phase loop instead of the bench line")
     ap.add_argument("--storage", default="auto", choices=["auto", "matrix", "on_the_fly"],
-                    help="rounded costs of --phase-report: as the library chooses, the stored "
-                         "matrix, or recomputed in the scan")
+                    help="rounded costs of the timed solves (and of --phase-report): as the "
+                         "library chooses, the stored matrix, or recomputed in the scan")
     ap.add_argument("--only", default=None,
                     choices=["batched", "ot_loss", "uniform_costs", "large", "large_matrix",
                              "unbalanced", "transport", "transport_clustered",
@@ -527,8 +533,9 @@ def main():
     ctx = prot.Context(0)
     ctx.reserve(n, with_matrix=True)
 
+    storage = args.storage
     for _ in range(args.warmup):
-        ctx.solve_points(Xd, Yd, eps)
+        ctx.solve_points(Xd, Yd, eps, storage=storage)
     torch.cuda.synchronize()
 
     # The timed steps are enqueued back to back (stats=False: each solve's
@@ -538,7 +545,7 @@ def main():
     timing = "enqueued back to back"
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.solve_points(Xd, Yd, eps, stats=False)
+        ctx.solve_points(Xd, Yd, eps, storage=storage, stats=False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     try:
@@ -553,7 +560,7 @@ def main():
         timing = "one synchronised solve at a time"
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ctx.solve_points(Xd, Yd, eps)
+            ctx.solve_points(Xd, Yd, eps, storage=storage)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
@@ -566,7 +573,7 @@ def main():
     build_ms, scanned = [], []
     t0 = time.perf_counter()
     for _ in range(n_sync):
-        res = ctx.solve_points(Xd, Yd, eps)
+        res = ctx.solve_points(Xd, Yd, eps, storage=storage)
         build_ms.append(res.stats["ms_build"])
         scanned.append(res.stats["scanned"])
     torch.cuda.synchronize()
@@ -577,10 +584,16 @@ def main():
     loop_bytes = 2.0 * float(np.mean(scanned))
     build_bytes = 2.0 * n * prot.pitch(n) + 2 * 2 * n * d * 4
     mean_loop, mean_build = float(np.mean(loop_ms)), float(np.mean(build_ms))
-    # names as the kernel trace shows them
+    # names as the kernel trace shows them (the library recomputes the costs
+    # in the scan, for d = 2, 3, when asked or when the int16 matrix would
+    # exceed 256 MiB)
+    on_the_fly = storage == "on_the_fly" or (
+        storage == "auto" and d in (2, 3) and 2 * n * prot.pitch(n) > (256 << 20))
+    loop_name = f"phase_loop_kernel<false, {d if on_the_fly else 0}, false, false, false>"
+    if on_the_fly:
+        build_bytes = 2 * 2 * n * d * 4  # the points only
     kernels = {
-        "phase_loop_kernel<false, 0, false, false, false>": {"bound": "hbm", "ms": mean_loop,
-                                                             "bytes": loop_bytes},
+        loop_name: {"bound": "hbm", "ms": mean_loop, "bytes": loop_bytes},
         "cost_build": {"bound": "hbm", "ms": mean_build, "bytes": build_bytes},
     }
     dom_name = max(kernels, key=lambda k: kernels[k]["ms"])
@@ -588,7 +601,7 @@ def main():
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     roofline = {"bound": dom["bound"], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(n, d, dom_name), "kernel": dom_name,
+                "traffic": measured_traffic(n, d, dom_name, storage), "kernel": dom_name,
                 "algorithmic_bytes": round(dom["bytes"], 1)}
 
     out = {
@@ -606,7 +619,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"assignment n={n} points U[0,1]^{d} squared-Euclidean "
                                f"eps={eps} seed={args.seed}",
-                   "n": n, "d": d, "eps": eps, "parallelism": "single-gpu"},
+                   "n": n, "d": d, "eps": eps, "storage": storage, "parallelism": "single-gpu"},
         "solves_per_s": round(1e3 / ms_per_step, 3),
         # steps enqueued back to back; a solve that also reads its
         # statistics back (one host synchronisation per solve) takes this
