@@ -64,12 +64,17 @@ typedef struct {
     /* 1: skip the arbitrary completion (Section 2.1), return the phase-loop
      * matching as is. */
     int32_t no_completion;
-    /* Point-set solves: where the rounded costs live. PROT_COSTS_AUTO picks;
-     * PROT_COSTS_MATRIX builds the n x n int16 matrix and scans it;
-     * PROT_COSTS_ON_THE_FLY (d = 2, 3) builds only the maximum and the
-     * threshold table and lets the greedy step recompute each k it examines
-     * from the points with the build's own operations (identical integers,
-     * no n^2 memory). */
+    /* Point-set solves: where the rounded costs live. PROT_COSTS_MATRIX
+     * builds the n x n int16 matrix and scans it; PROT_COSTS_ON_THE_FLY
+     * (d = 2, 3) builds only the maximum and the threshold table and lets
+     * the greedy step recompute each k it examines from the points with the
+     * build's own operations (identical integers, no n^2 memory);
+     * PROT_COSTS_AUTO stores a matrix of up to 256 MiB and otherwise
+     * recomputes, and a solve that returns statistics then hands over to the
+     * stored matrix (up to 16 GiB, if it can be allocated) once the loop has
+     * run about twice as long as writing the matrix would take: the loop
+     * stops at a phase start and resumes on the matrix from the state
+     * reached, with the same results (two loop launches). */
     int32_t cost_storage;
     /* Element type of the rounded-cost matrix that solve_cost / solve_points
      * store: PROT_KTYPE_AUTO (= int16), PROT_KTYPE_INT16, PROT_KTYPE_UINT8

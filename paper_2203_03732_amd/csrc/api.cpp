@@ -446,6 +446,7 @@ struct OnTheFly {
     int32_t d = 0;
     const float *X = nullptr, *Y = nullptr;
     double eps = 0.0;
+    uint32_t switch_round = 0;  // hand over to the stored matrix (LoopArgs)
 };
 
 // Copies of the transport reduction: row b reads cost row rmap[b]; ymax holds
@@ -476,7 +477,8 @@ int next_loop_events(prot_ctx *c, hipEvent_t **out)
 int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk, int64_t T,
              const prot_opts *o, int32_t warm, int32_t *mate_a, int32_t *mate_b, int32_t *y_a,
              int32_t *y_b, int64_t K, bool cooperative = false,
-             const OnTheFly &otf = OnTheFly(), const Copies &cp = Copies(), int k8 = 0)
+             const OnTheFly &otf = OnTheFly(), const Copies &cp = Copies(), int k8 = 0,
+             int64_t trace_off = 0)
 {
     int rc = ensure_loop(c, n_a);
     if (rc) return rc;
@@ -515,7 +517,14 @@ int run_loop(prot_ctx *c, const int16_t *k, int64_t n, int64_t n_a, int64_t ldk,
         a.pm = &c->ctl->m;
         a.pth = c->th;
         a.peps = otf.eps;
+        a.switch_round = otf.switch_round;
     }
+    // a continuation records its phases after those of the launch before
+    // (when the watchdog bounds them within the trace)
+    if (trace_off > 0)
+        a.trace = a.phase_bound > 0 && trace_off + a.phase_bound <= prot::kTraceCap
+                      ? c->trace + 4 * trace_off
+                      : nullptr;
     if (warm) {
         // (I1), Lemma 3.2's bound on the duals and the matching structure of
         // the given state, O(n); on request (I2), O(n_b n_a).
@@ -1242,6 +1251,76 @@ int prot_solve_cost(prot_ctx *c, const float *C, int64_t n, int64_t ldc, double 
     return prot_solve_cost_rect(c, C, n, n, ldc, eps, o, mate_a, mate_b, y_a, y_b, st);
 }
 
+// The rest of a point-set solve whose loop recomputed its costs and stopped
+// to hand over (status 3): the matrix is built, the loop resumes from the
+// state in the outputs (a warm start, the same trajectory as one run) and
+// the statistics of both parts are added up.
+static int hand_over_to_matrix(prot_ctx *c, const float *X, int64_t n_b, const float *Y,
+                               int64_t n_a, int32_t d, double ei, int64_t T, int64_t n_max,
+                               int64_t ldk, const prot_opts *o, int32_t *mate_a, int32_t *mate_b,
+                               int32_t *y_a, int32_t *y_b, prot_stats *st)
+{
+    const prot_stats first = *st;
+    int k8 = 0;
+    int rc = choose_k8(c, o, ei, &k8);
+    // no room for the matrix: the loop resumes recomputing its costs
+    // (PROT_HANDOVER_NO_MATRIX takes that path on purpose, for tests)
+    const bool matrix = !std::getenv("PROT_HANDOVER_NO_MATRIX") && !rc && !ensure_matrix(c, n_b, n_a);
+    if (!matrix) {
+        k8 = 0;
+        (void)hipGetLastError();  // (a failed allocation leaves its error behind)
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    if (matrix) {
+        prot::PointsJob j = points_job(c, X, Y, n_b, d, ei, c->kmat, ldk, n_a);
+        j.k8 = k8;
+        if ((rc = setup_prune(c, j, n_max))) return rc;
+        HIP_TRY(c, prot::launch_points(j, n_max, ldk, c->stream));
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+    OnTheFly otf;
+    if (!matrix) {
+        otf.d = d;
+        otf.X = X;
+        otf.Y = Y;
+        otf.eps = ei;
+    }
+    prot_opts o2{};
+    if (o) o2 = *o;
+    o2.max_phases = 0;
+    o2.check_warm = 0;
+    // the watchdog bounds both parts together
+    const int64_t K = (int64_t)std::floor(1.0 / ei);
+    const int64_t pb = phase_bound_for(o, n_b, n_a, K, T);
+    o2.phase_bound = pb > 0 ? std::max<int64_t>(1, pb - first.phases) : -1;
+    rc = run_loop(c, matrix ? c->kmat : nullptr, n_b, n_a, matrix ? ldk : round_up(n_a, 8), T,
+                  &o2, 1, mate_a, mate_b, y_a, y_b, K, false, otf, Copies(), k8, first.phases);
+    if (rc) return rc;
+    if (matrix)
+        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, c->kmat, ldk, points_cost_kind(c), nullptr,
+                                         0, X, Y, d, c->part_k, c->part_c, c->stream, nullptr, 0.0,
+                                         nullptr, k8));
+    else
+        HIP_TRY(c, prot::launch_finalize(n_b, mate_b, nullptr, 0, 2, nullptr, 0, X, Y, d,
+                                         c->part_k, c->part_c, c->stream, &c->ctl->m, ei, c->th));
+    HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+    rc = collect(c, st, T, ei, matrix ? points_cost_kind(c) : 2, true);
+    // the phase count the trace reports covers both parts
+    const int64_t phases = first.phases + st->phases;
+    HIP_TRY(c, hipMemcpyAsync(&c->ctl->phases, &phases, sizeof(int64_t), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    st->phases = phases;
+    st->sum_free += first.sum_free;
+    st->rounds += first.rounds;
+    st->max_rounds = std::max(st->max_rounds, first.max_rounds);
+    st->scanned += first.scanned;
+    st->ms_build += first.ms_build;
+    st->ms_loop_kernel += first.ms_loop_kernel;
+    st->ms_total += first.ms_total;
+    return rc;
+}
+
 int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float *Y,
                            int64_t n_a, int32_t d, double eps, const prot_opts *o,
                            int32_t *mate_a, int32_t *mate_b, int32_t *y_a, int32_t *y_b,
@@ -1280,6 +1359,23 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
     if (!rc) rc = ensure_thresholds(c, ei);
     if (rc) return rc;
     int16_t *kmat = on_the_fly ? nullptr : c->kmat;
+    // A loop that recomputes its costs because the matrix would exceed the
+    // Infinity Cache hands over to the stored matrix once it has run about
+    // twice as many rounds (~10 us each at least) as writing the matrix
+    // costs: a long solve pays for the build, a short one never sees it.
+    // Only for solves that read their statistics (the host takes the
+    // hand-over) and matrices up to 16 GiB (beyond that the recomputation is
+    // there for capacity); PROT_AUTO_SWITCH_ROUNDS sets the round (tests).
+    uint32_t switch_round = 0;
+    const double mat_bytes = 2.0 * (double)n_b * (double)prot_pitch(n_a);
+    if (on_the_fly && !enqueue_only && (!o || o->max_phases == 0)) {
+        if (const char *e = std::getenv("PROT_AUTO_SWITCH_ROUNDS")) {
+            switch_round = (uint32_t)std::max(0, std::atoi(e));
+        } else if (storage == PROT_COSTS_AUTO && mat_bytes <= (double)(16ll << 30)) {
+            const double build_us = mat_bytes / 3.5e6;
+            switch_round = (uint32_t)std::max(16.0, 2.0 * build_us / 10.0);
+        }
+    }
     // the build's and the whole solve's timing events only when statistics
     // are asked for (each event record holds the next launch back a few us)
     if (!enqueue_only) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
@@ -1297,6 +1393,7 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
         otf.X = X;
         otf.Y = Y;
         otf.eps = ei;
+        otf.switch_round = switch_round;
     }
     const int64_t K = (int64_t)std::floor(1.0 / ei);
     auto enqueue = [&](bool coop) -> int {
@@ -1322,6 +1419,10 @@ int prot_solve_points_rect(prot_ctx *c, const float *X, int64_t n_b, const float
         if ((rc = enqueue(true))) return rc;
         rc = collect(c, st, T, ei, kind, true);
     }
+    if (rc == PROT_OK && st->status == PROT_PARTIAL && c->stage->ctl.status == 3 &&
+        !(c->stage->ctl.err & 1))
+        rc = hand_over_to_matrix(c, X, n_b, Y, n_a, d, ei, T, n_max, ldk, o, mate_a, mate_b, y_a,
+                                 y_b, st);
     if (rc) return rc;
     fill_match_counts(c, n_b, st, o);
     if (c->stage->ctl.err & 1) return fail(c, PROT_E_RANGE, "a point coordinate is not finite");

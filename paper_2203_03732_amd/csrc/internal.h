@@ -70,7 +70,10 @@ struct LoopArgs {
     int32_t wide;           // 1: rows travel in 18 bits (n > 131,071; duals <= 16,383)
     int64_t T;
     int32_t origin;         // 0: diagonal, 1: zero
-    int32_t pad;
+    // stop with status 3 at the first phase start from this round on (0:
+    // never): a loop that recomputes its costs hands over to the stored
+    // matrix once it has run long enough to pay for building it
+    uint32_t switch_round;
     int64_t max_phases;
     int64_t phase_bound;      // watchdog: stop with status 2 after this many phases (0: none)
     int64_t barrier_ticks;    // bounded round-barrier wait, 100 MHz ticks (0: the default)

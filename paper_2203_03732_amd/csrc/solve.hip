@@ -524,7 +524,8 @@ __global__ void loop_reset_kernel(LoopArgs a)
     c->status = 0;
     c->phases = c->sum_free = c->rounds = c->max_rounds = 0;
     c->free_after = 0;
-    for (int i = 0; i < 4; ++i) a.trace[i] = 0;
+    if (a.trace)
+        for (int i = 0; i < 4; ++i) a.trace[i] = 0;
 }
 
 
@@ -546,7 +547,8 @@ __global__ void init_kernel(LoopArgs a, int32_t warm, const int32_t *mate_a,
         c->status = 0;
         c->phases = c->sum_free = c->rounds = c->max_rounds = 0;
         c->free_after = 0;
-        for (int i = 0; i < 4; ++i) a.trace[i] = 0;
+        if (a.trace)
+            for (int i = 0; i < 4; ++i) a.trace[i] = 0;
     }
     const int n = a.n, na = a.n_a;  // rows, columns
     const int lane = threadIdx.x & 63;
@@ -818,6 +820,11 @@ phase_loop_kernel(LoopArgs A0, const LoopArgs *__restrict__ arr, int team, int32
         if ((int64_t)n_i <= A.T) break;
         if (A.max_phases > 0 && p >= A.max_phases) {
             if (leader) ctl->status = 1;
+            break;
+        }
+        // (r and p are the same in every workgroup, so all leave together)
+        if (A.switch_round > 0 && p > 0 && r >= A.switch_round) {
+            if (leader) ctl->status = 3;
             break;
         }
         // the watchdog: no run of the method needs more phases than this
